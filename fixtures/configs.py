@@ -1,0 +1,83 @@
+"""The workloads, as seeded synthetic inputs.
+
+tiny      16 patterns at 64^2, orientations uniform in SO(3), pattern centre
+          (0.5, 0.5, 0.6) with a uniform +-3 px in-plane offset per pattern,
+          Poisson noise at 100 counts/px; library of 500 orientations uniform
+          in the cubic fundamental zone.
+map       a 100 x 100 map (10,000 patterns) at 128^2: 20 Voronoi grains with
+          uniform orientations and <= 1 deg intragranular spread, +-5 px
+          pattern-centre offsets, Poisson (1000 counts) plus Gaussian noise at
+          SNR 5; library of 4,000 fundamental-zone orientations.  Its scale
+          mirrors the paper's deformed alpha-iron map (9,130 patterns at
+          128^2, section "Deformed alpha-Fe Dataset").
+map256    the same map at 256^2.
+ragged    20,000 patterns with sizes drawn from {64, 96, 128, 160} (25 % each,
+          shuffled), otherwise as `map`; library of 8,000.
+
+Every generator takes smaller sizes for tests; `seed` fixes everything.
+"""
+
+import numpy as np
+import torch
+
+from .master import band_master
+from .orient import random_quats, random_fz_quats, perturb_quats, voronoi_map
+from .simulate import simulate_patterns
+
+PCZ = 0.6
+
+
+def _offsets(rng, p, max_px, n, integer=False):
+    off = rng.uniform(-max_px, max_px, size=(p, 2))
+    if integer:
+        off = np.round(off)
+    pcs = np.empty((p, 3))
+    pcs[:, 0] = 0.5 + off[:, 0] / n
+    pcs[:, 1] = 0.5 + off[:, 1] / n
+    pcs[:, 2] = PCZ
+    return pcs, off
+
+
+def tiny(seed=1, p=16, n=64, l=500, integer_offsets=False, device="cpu"):
+    rng = np.random.default_rng(seed)
+    master = band_master()
+    true_q = random_quats(rng, p)
+    pcs, off = _offsets(rng, p, 3.0, n, integer_offsets)
+    lib_q = random_fz_quats(rng, l)
+    pats = simulate_patterns(true_q, n, pcs, ("poisson", 100.0), seed=seed + 1000, device=device)
+    return dict(master=master, patterns=pats, pcs=pcs, offsets=off, true_q=true_q, lib_q=lib_q,
+                n=n, pc=(0.5, 0.5, PCZ))
+
+
+def map_grid(seed=2, rows=100, cols=100, n=128, l=4000, n_grains=20, device="cpu",
+             noise=("poisson_gauss", 1000.0, 5.0), dtype=torch.float64):
+    rng = np.random.default_rng(seed)
+    master = band_master()
+    gid = voronoi_map(rng, rows, cols, n_grains)
+    grain_q = random_quats(rng, n_grains)
+    true_q = perturb_quats(rng, grain_q[gid], 1.0)
+    p = rows * cols
+    pcs, off = _offsets(rng, p, 5.0, n)
+    lib_q = random_fz_quats(rng, l)
+    pats = simulate_patterns(true_q, n, pcs, noise, seed=seed + 1000, device=device, dtype=dtype)
+    return dict(master=master, patterns=pats, pcs=pcs, offsets=off, true_q=true_q, lib_q=lib_q,
+                n=n, pc=(0.5, 0.5, PCZ), grain=gid)
+
+
+def ragged(seed=4, p=20000, l=8000, sizes=(64, 96, 128, 160), device="cpu"):
+    rng = np.random.default_rng(seed)
+    master = band_master()
+    ns = np.repeat(np.array(sizes), int(np.ceil(p / len(sizes))))[:p]
+    rng.shuffle(ns)
+    true_q = random_quats(rng, p)
+    off = rng.uniform(-5.0, 5.0, size=(p, 2))
+    pcs = np.stack([0.5 + off[:, 0] / ns, 0.5 + off[:, 1] / ns, np.full(p, PCZ)], axis=1)
+    lib_q = random_fz_quats(rng, l)
+    pats = []
+    for s in sizes:
+        idx = np.nonzero(ns == s)[0]
+        if idx.size:
+            pats.append((idx, simulate_patterns(true_q[idx], int(s), pcs[idx],
+                                                ("poisson_gauss", 1000.0, 5.0), seed=seed + s, device=device)))
+    return dict(master=master, sizes=ns, pattern_sets=pats, pcs=pcs, true_q=true_q, lib_q=lib_q,
+                pc=(0.5, 0.5, PCZ))
