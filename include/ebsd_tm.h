@@ -1,0 +1,231 @@
+/*
+ * ebsd_tm.h -- C ABI of the MI355X (gfx950) hot path of refined template
+ * matching for EBSD indexing (Foden, Collins, Wilkinson & Britton, arXiv
+ * 1807.11313).
+ *
+ * The problem (Introduction and section "Method Overview"): experimental
+ * patterns are compared with a library of templates, each a gnomonic
+ * projection of a spherical master pattern for one crystal orientation; the
+ * comparison is the normalised cross-correlation of filtered images,
+ * evaluated for every relative shift through the Fourier domain (Equations
+ * 2-4); the best match is the template with the highest correlation peak,
+ * and its peak position gives the pattern shift.  One library is projected
+ * at one nominal pattern centre.  Section "Orientation and Pattern Centre
+ * Refinement" then refines each best match: the measured shift gives the
+ * rotation about the detector x and y axes (Equation 7, angle = shift /
+ * detector distance), a log-polar resampling gives the rotation about the
+ * detector normal, and the template is re-projected at the pattern's own
+ * pattern centre, about two iterations.  The correlation peak height is the
+ * per-pattern quality output (section "Demonstrations").
+ *
+ * Conventions (the paper defers these to a reference it cites):
+ *   image      row-major [row j][col i], float32, square n x n;
+ *   PC         (pcx, pcy, pcz) in screen widths: pcx from the left edge,
+ *              pcy from the top edge, pcz = source-to-screen distance /
+ *              screen width (footnote 2 of section "Fast Fourier Transform");
+ *   frame      detector x = +column, y = +row, z = source to screen; pixel
+ *              ray d = normalise((i+1/2)/n - pcx, (j+1/2)/n - pcy, pcz);
+ *   orientation unit quaternion (w, x, y, z), w >= 0, float64, of the
+ *              rotation R with crystal direction c = R d;
+ *   master     equirectangular float32 [H][W]: row r at polar angle
+ *              (r + 1/2) pi / H from crystal +z, column q at azimuth
+ *              2 pi q / W from +x toward +y;
+ *   shift      (s_x, s_y) px with E(x) ~ T(x - s): the pattern is the
+ *              template moved by +s;
+ *   peak h     normalised correlation in [-1, 1].
+ *
+ * Memory: every array pointer is a DEVICE pointer (hipMalloc / torch CUDA
+ * tensors), contiguous, at least 16-byte aligned; structs are host memory.
+ * The caller owns all buffers.  The library keeps no caller pointer after a
+ * call returns; its scratch is allocated and freed stream-ordered on the
+ * caller's stream (hipMallocAsync / hipFreeAsync).
+ *
+ * Execution: asynchronous on `stream` (a hipStream_t; NULL = null stream).
+ * Outputs are valid once the stream has been synchronised.
+ *
+ * Errors: every function returns EBSD_OK (0) or a negative code; on an
+ * argument error nothing is enqueued and no output is written.
+ * ebsd_last_error() returns a thread-local description of the last error.
+ *
+ * Supported pattern sizes: n in {64, 96, 128, 160}.
+ */
+#ifndef EBSD_TM_H
+#define EBSD_TM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EBSD_OK 0
+#define EBSD_E_INVALID (-1)     /* null pointer, bad size or parameter      */
+#define EBSD_E_NOMEM (-2)       /* device allocation failed                 */
+#define EBSD_E_DEVICE (-3)      /* HIP runtime or launch error              */
+#define EBSD_E_UNSUPPORTED (-4) /* valid request this build does not serve  */
+
+#define EBSD_PREC_FP32 0
+
+#define EBSD_FORM_AUTO 0
+#define EBSD_FORM_FFT 1
+
+/* A batch of P square patterns of side n, pattern p at data + p n n. */
+typedef struct {
+  const float* data;
+  int64_t P;
+  int32_t n;
+} ebsd_batch;
+
+/* Equirectangular master pattern, H rows x W columns. */
+typedef struct {
+  const float* data;
+  int32_t H, W;
+} ebsd_master;
+
+/* Nominal pattern centre, and optionally one per pattern (device [P][3]). */
+typedef struct {
+  double pcx, pcy, pcz;
+  const double* pc_per;
+} ebsd_geometry;
+
+/*
+ * Method parameters.  The paper leaves window, filter, upsampling and the
+ * log-polar grid unspecified; the defaults (ebsd_params_default) are:
+ *   window        1: separable Hann w_i = sin^2(pi (i + 1/2) / n); 0: none
+ *   sigma_hp      2.0 cycles/image: high pass 1 - exp(-rho^2 / 2 sigma_hp^2)
+ *   sigma_lp_frac 0.125: low pass exp(-rho^2 / 2 (frac n)^2)
+ *   rho_max_frac  0.375: filter is zero for rho > frac n (must be <= 0.375)
+ *   max_shift     -1: every cyclic shift; k >= 0: |s_x|, |s_y| <= k
+ *   upsample      100: sub-pixel step 1/upsample over +-0.75 px
+ *   n_iter        2 refinement iterations (fixed, no early exit)
+ *   n_rho, n_eta  0, 0: log-polar grid n/2 radii x 2n angles
+ *   precision     EBSD_PREC_FP32
+ *   form          EBSD_FORM_AUTO (= FFT)
+ */
+typedef struct {
+  uint32_t struct_size; /* sizeof(ebsd_params) */
+  int32_t window;
+  double sigma_hp, sigma_lp_frac, rho_max_frac;
+  int32_t max_shift;
+  int32_t upsample;
+  int32_t n_iter;
+  int32_t n_rho, n_eta;
+  int32_t precision;
+  int32_t form;
+} ebsd_params;
+
+/* Fills *p with the defaults above. */
+void ebsd_params_default(ebsd_params* p);
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int ebsd_version(void);
+
+/* Thread-local text of the last error ("" if none). */
+const char* ebsd_last_error(void);
+
+/*
+ * Index every pattern against every library orientation (section "Method
+ * Overview", Figure 1 B-C; Equations 2-5).
+ *   pats      P patterns of side n (device float32 [P][n][n])
+ *   mp        master pattern (device float32 [H][W])
+ *   geo       nominal pattern centre; geo->pc_per is ignored (one library)
+ *   lib_q     L library orientations (device float64 [L][4], unit, w >= 0)
+ *   prm       parameters (NULL: defaults)
+ * Outputs (device):
+ *   best_idx  int32 [P]   template with the largest integer correlation
+ *                         peak, ties to the smallest index
+ *   best_q    float64 [P][4]  lib_q[best_idx]        (may be NULL)
+ *   peak_h    float32 [P] upsampled peak height of the winner
+ *   shift     float32 [P][2] upsampled (s_x, s_y) px of the winner
+ *   scores    float32 [P][L] integer peak of every pair (may be NULL)
+ */
+int ebsd_index_patterns(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo,
+                        const double* lib_q, int64_t L, const ebsd_params* prm, int32_t* best_idx,
+                        double* best_q, float* peak_h, float* shift, float* scores, void* stream);
+
+/*
+ * Refine starting orientations (section "Orientation and Pattern Centre
+ * Refinement"): n_iter times { project the template at (R, PC_p); measure
+ * the upsampled shift s; R <- R (Ry(beta) Rx(alpha))^T with beta =
+ * atan(s_x / DD), alpha = -atan(s_y / DD), DD = pcz n px; re-project; measure
+ * the log-polar eta shift d; R <- R Rz(gamma)^T, gamma = 2 pi d / n_eta };
+ * then a final projection and correlation give peak_h and shift.
+ *   geo->pc_per  per-pattern pattern centres (device [P][3]) or NULL for
+ *                the nominal one
+ *   q_init       device float64 [P][4]
+ * Outputs (device): q_out float64 [P][4] (may alias q_init), peak_h float32
+ * [P], shift float32 [P][2].
+ */
+int ebsd_refine_orientations(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo,
+                             const double* q_init, const ebsd_params* prm, double* q_out, float* peak_h,
+                             float* shift, void* stream);
+
+/* ---- stage entry points (the same kernels, exposed for stage-by-stage checks) ---- */
+
+/*
+ * Gnomonic projection (section "SO(3) Library Generation"): K templates of
+ * side n for orientations q (device float64 [K][4]) at geo's pattern centre
+ * (or geo->pc_per[k]); out: device float32 [K][n][n], raw master intensities.
+ */
+int ebsd_project_templates(const ebsd_master* mp, const double* q, int64_t K, int32_t n,
+                           const ebsd_geometry* geo, float* out, void* stream);
+
+/*
+ * Filtered unit-energy spectra of K images of side n (device float32
+ * [K][n][n]): contrast normalised, windowed, 2-D DFT (Equation 4 without
+ * the unitary factor), band-passed, scaled to unit energy.
+ * spec: device complex64 (interleaved float32 pairs) [K][B+1][2B+1],
+ * B = 3n/8, element [v][kk] = X(u, v) with u = kk (kk <= B) or kk - 2B - 1;
+ * energy: device float64 [K], the pre-scaling energy sum |X'|^2 over the
+ * full spectrum (may be NULL).
+ */
+int ebsd_pattern_spectra(const float* imgs, int64_t K, int32_t n, const ebsd_params* prm, float* spec,
+                         double* energy, void* stream);
+
+/* Number of float32 values (2 per complex) of one stored spectrum of side n, or -1. */
+int64_t ebsd_spectrum_floats(int32_t n);
+
+/*
+ * Integer correlation peak of K (pattern, template) spectrum pairs
+ * (spec_p[pi[k]], spec_l[li[k]]): h_int float32 [K], s_int int32 [K][2]
+ * (s_x, s_y signed in [-n/2, n/2)), and optionally the full map float32
+ * [K][n][n] indexed [s_y mod n][s_x mod n] (map may be NULL).
+ */
+int ebsd_xcf_peak(const float* spec_p, const float* spec_l, const int32_t* pi, const int32_t* li,
+                  int64_t K, int32_t n, const ebsd_params* prm, float* h_int, int32_t* s_int, float* map,
+                  void* stream);
+
+/* Score matrix h_int[p][l] of P pattern spectra against L template spectra. */
+int ebsd_xcf_scores(const float* spec_p, int64_t P, const float* spec_l, int64_t L, int32_t n,
+                    const ebsd_params* prm, float* scores, void* stream);
+
+/* Upsampled peak around s_int for K pairs: h_sub float32 [K], s_sub float32 [K][2] (x, y). */
+int ebsd_xcf_subpixel(const float* spec_p, const float* spec_l, const int32_t* pi, const int32_t* li,
+                      int64_t K, int32_t n, const int32_t* s_int, const ebsd_params* prm, float* h_sub,
+                      float* s_sub, void* stream);
+
+/*
+ * Log-polar rotation measurement: gamma float64 [K] (radians) of pattern k
+ * relative to template k (both device float32 [K][n][n]); positive gamma
+ * means the pattern is the template rotated by +gamma in
+ * eta = atan2(row - c, col - c).
+ */
+int ebsd_measure_rotation(const float* pats, const float* tmpls, int64_t K, int32_t n,
+                          const ebsd_params* prm, double* gamma, void* stream);
+
+/*
+ * Instrumentation.  While enabled, every launch of the correlation search
+ * kernel (the dominant kernel of ebsd_index_patterns and ebsd_xcf_scores)
+ * is bracketed by a pair of HIP events recorded on the caller's stream.
+ * ebsd_timing_read (after the stream has been synchronised) returns the
+ * summed elapsed time in ms and the number of launches, and clears the
+ * record.  Not for concurrent use from several threads.
+ */
+int ebsd_timing_enable(int enable);
+int ebsd_timing_read(double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EBSD_TM_H */

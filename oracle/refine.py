@@ -89,6 +89,18 @@ def eta_correlation(lp_e, lp_t):
     return c / norm
 
 
+def eta_value(c, t):
+    """Real trigonometric interpolant of the cyclic sequence c at points t
+    (the Nyquist term enters as cos(pi t))."""
+    n = c.size
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    cf = np.fft.fft(c)
+    q = np.arange(1, n // 2)
+    return (cf[0].real
+            + 2 * np.real(cf[q][None, :] * np.exp(2j * np.pi * np.outer(t, q) / n)).sum(axis=1)
+            + cf[n // 2].real * np.cos(np.pi * t)) / n
+
+
 def eta_peak(c, kappa=100, box=0.75):
     """Integer argmax (ties to the smallest index), then the maximum of the
     trigonometric interpolant of c over D_int + a / kappa, |a| <= ceil(box kappa)
@@ -96,24 +108,24 @@ def eta_peak(c, kappa=100, box=0.75):
     n = c.size
     k = int(np.argmax(c))
     d_int = k - n if k >= n // 2 else k
-    cf = np.fft.fft(c)
     m = int(np.ceil(box * kappa))
     t = d_int + np.arange(-m, m + 1) / kappa
-    q = np.arange(1, n // 2)
-    val = (cf[0].real
-           + 2 * np.real(cf[q][None, :] * np.exp(2j * np.pi * np.outer(t, q) / n)).sum(axis=1)
-           + cf[n // 2].real * np.cos(np.pi * t)) / n
+    val = eta_value(c, t)
     j = int(np.argmax(val))
     return float(val[j]), float(t[j])
 
 
-def measure_gamma(pattern, template, prm):
+def eta_correlation_of(pattern, template, prm):
     n = pattern.shape[0]
-    n_rho, n_eta = prm.nrho(n), prm.neta(n)
-    le = logpolar(spectra.normalise(pattern), n_rho, n_eta)
-    lt = logpolar(spectra.normalise(template), n_rho, n_eta)
-    _, d = eta_peak(eta_correlation(le, lt), prm.upsample)
-    return 2 * np.pi * d / n_eta
+    le = logpolar(spectra.normalise(pattern), prm.nrho(n), prm.neta(n))
+    lt = logpolar(spectra.normalise(template), prm.nrho(n), prm.neta(n))
+    return eta_correlation(le, lt)
+
+
+def measure_gamma(pattern, template, prm):
+    c = eta_correlation_of(pattern, template, prm)
+    _, d = eta_peak(c, prm.upsample)
+    return 2 * np.pi * d / c.size
 
 
 def measure_shift(pattern, template, prm):

@@ -1,0 +1,287 @@
+"""Python binding of libebsd_tm.so, the gfx950 hot path of refined template
+matching for EBSD indexing (arXiv 1807.11313).
+
+Argument marshalling only: every step runs in the HIP kernels behind the C
+ABI of ``include/ebsd_tm.h``.  Tensors must be contiguous CUDA (HIP) tensors
+of the stated dtype; work is enqueued on torch's current stream.  There is no
+CPU fallback: if the shared library is missing or fails to load, importing
+the binding functions raises.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["lib", "Params", "index_patterns", "refine_orientations", "project_templates",
+           "pattern_spectra", "spectrum_floats", "xcf_peak", "xcf_scores", "xcf_subpixel",
+           "measure_rotation", "params_default", "version", "LIB_PATH", "EXPORTS"]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libebsd_tm.so")
+
+# Every function the header declares.
+EXPORTS = ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_index_patterns",
+           "ebsd_refine_orientations", "ebsd_project_templates", "ebsd_pattern_spectra",
+           "ebsd_spectrum_floats", "ebsd_xcf_peak", "ebsd_xcf_scores", "ebsd_xcf_subpixel",
+           "ebsd_measure_rotation", "ebsd_timing_enable", "ebsd_timing_read")
+
+EBSD_OK = 0
+ERRORS = {-1: "EBSD_E_INVALID", -2: "EBSD_E_NOMEM", -3: "EBSD_E_DEVICE", -4: "EBSD_E_UNSUPPORTED"}
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("P", ctypes.c_int64), ("n", ctypes.c_int32)]
+
+
+class Master(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("pcx", ctypes.c_double), ("pcy", ctypes.c_double), ("pcz", ctypes.c_double),
+                ("pc_per", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("window", ctypes.c_int32),
+                ("sigma_hp", ctypes.c_double), ("sigma_lp_frac", ctypes.c_double),
+                ("rho_max_frac", ctypes.c_double), ("max_shift", ctypes.c_int32),
+                ("upsample", ctypes.c_int32), ("n_iter", ctypes.c_int32), ("n_rho", ctypes.c_int32),
+                ("n_eta", ctypes.c_int32), ("precision", ctypes.c_int32), ("form", ctypes.c_int32)]
+
+
+class EbsdError(RuntimeError):
+    def __init__(self, code, func, msg):
+        super().__init__("%s failed: %s (%d): %s" % (func, ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Loads the shared library (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libebsd_tm.so is not built at %s; run paper_1807_11313_amd/build.py" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER
+    L.ebsd_params_default.argtypes = [dp(Params)]
+    L.ebsd_params_default.restype = None
+    L.ebsd_version.restype = ctypes.c_int
+    L.ebsd_last_error.restype = ctypes.c_char_p
+    L.ebsd_spectrum_floats.argtypes = [i32]
+    L.ebsd_spectrum_floats.restype = i64
+    L.ebsd_index_patterns.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, i64, dp(Params), vp, vp, vp, vp,
+                                      vp, vp]
+    L.ebsd_refine_orientations.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, dp(Params), vp, vp, vp, vp]
+    L.ebsd_project_templates.argtypes = [dp(Master), vp, i64, i32, dp(Geometry), vp, vp]
+    L.ebsd_pattern_spectra.argtypes = [vp, i64, i32, dp(Params), vp, vp, vp]
+    L.ebsd_xcf_peak.argtypes = [vp, vp, vp, vp, i64, i32, dp(Params), vp, vp, vp, vp]
+    L.ebsd_xcf_scores.argtypes = [vp, i64, vp, i64, i32, dp(Params), vp, vp]
+    L.ebsd_xcf_subpixel.argtypes = [vp, vp, vp, vp, i64, i32, vp, dp(Params), vp, vp, vp]
+    L.ebsd_measure_rotation.argtypes = [vp, vp, i64, i32, dp(Params), vp, vp]
+    L.ebsd_timing_enable.argtypes = [ctypes.c_int]
+    L.ebsd_timing_read.argtypes = [dp(ctypes.c_double), dp(ctypes.c_int64)]
+    for name in EXPORTS:
+        if name not in ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_spectrum_floats"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def params_default(**kw):
+    p = Params()
+    lib().ebsd_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def version():
+    return lib().ebsd_version()
+
+
+def spectrum_floats(n):
+    return lib().ebsd_spectrum_floats(n)
+
+
+def _check(rc, func):
+    if rc != EBSD_OK:
+        raise EbsdError(rc, func, lib().ebsd_last_error().decode())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _master(master):
+    import torch
+    return Master(_ptr(master, torch.float32, "master").value, master.shape[0], master.shape[1])
+
+
+def _geo(pc, pc_per=None):
+    import torch
+    return Geometry(float(pc[0]), float(pc[1]), float(pc[2]),
+                    None if pc_per is None else _ptr(pc_per, torch.float64, "pc_per").value)
+
+
+def _params(prm):
+    return ctypes.byref(prm) if prm is not None else None
+
+
+def index_patterns(patterns, master, pc, lib_q, prm=None, scores=False):
+    """Returns dict(best_idx, best_q, peak_h, shift[, scores]) as CUDA tensors."""
+    import torch
+    p, n = patterns.shape[0], patterns.shape[-1]
+    dev = patterns.device
+    out = dict(best_idx=torch.empty(p, dtype=torch.int32, device=dev),
+               best_q=torch.empty((p, 4), dtype=torch.float64, device=dev),
+               peak_h=torch.empty(p, dtype=torch.float32, device=dev),
+               shift=torch.empty((p, 2), dtype=torch.float32, device=dev))
+    if scores:
+        out["scores"] = torch.empty((p, lib_q.shape[0]), dtype=torch.float32, device=dev)
+    batch = Batch(_ptr(patterns, torch.float32, "patterns").value, p, n)
+    rc = lib().ebsd_index_patterns(ctypes.byref(batch), ctypes.byref(_master(master)), ctypes.byref(_geo(pc)),
+                                   _ptr(lib_q, torch.float64, "lib_q"), lib_q.shape[0], _params(prm),
+                                   _ptr(out["best_idx"]), _ptr(out["best_q"]), _ptr(out["peak_h"]),
+                                   _ptr(out["shift"]), _ptr(out.get("scores")), _stream())
+    _check(rc, "ebsd_index_patterns")
+    return out
+
+
+def refine_orientations(patterns, master, pc, q_init, pc_per=None, prm=None):
+    """Returns dict(q, peak_h, shift) as CUDA tensors."""
+    import torch
+    p, n = patterns.shape[0], patterns.shape[-1]
+    dev = patterns.device
+    out = dict(q=torch.empty((p, 4), dtype=torch.float64, device=dev),
+               peak_h=torch.empty(p, dtype=torch.float32, device=dev),
+               shift=torch.empty((p, 2), dtype=torch.float32, device=dev))
+    batch = Batch(_ptr(patterns, torch.float32, "patterns").value, p, n)
+    rc = lib().ebsd_refine_orientations(ctypes.byref(batch), ctypes.byref(_master(master)),
+                                        ctypes.byref(_geo(pc, pc_per)), _ptr(q_init, torch.float64, "q_init"),
+                                        _params(prm), _ptr(out["q"]), _ptr(out["peak_h"]), _ptr(out["shift"]),
+                                        _stream())
+    _check(rc, "ebsd_refine_orientations")
+    return out
+
+
+def project_templates(master, q, n, pc, pc_per=None):
+    import torch
+    out = torch.empty((q.shape[0], n, n), dtype=torch.float32, device=q.device)
+    rc = lib().ebsd_project_templates(ctypes.byref(_master(master)), _ptr(q, torch.float64, "q"), q.shape[0], n,
+                                      ctypes.byref(_geo(pc, pc_per)), _ptr(out), _stream())
+    _check(rc, "ebsd_project_templates")
+    return out
+
+
+def pattern_spectra(imgs, prm=None, energy=False):
+    """Unit-energy band spectra [K][B+1][2B+1] complex64 (and FP64 energies)."""
+    import torch
+    k, n = imgs.shape[0], imgs.shape[-1]
+    nf = spectrum_floats(n)
+    if nf < 0:
+        raise ValueError("unsupported size %d" % n)
+    spec = torch.empty((k, nf), dtype=torch.float32, device=imgs.device)
+    en = torch.empty(k, dtype=torch.float64, device=imgs.device) if energy else None
+    rc = lib().ebsd_pattern_spectra(_ptr(imgs, torch.float32, "imgs"), k, n, _params(prm), _ptr(spec), _ptr(en),
+                                    _stream())
+    _check(rc, "ebsd_pattern_spectra")
+    return (spec, en) if energy else spec
+
+
+def xcf_peak(spec_p, spec_l, pi, li, n, prm=None, want_map=False):
+    import torch
+    k = pi.shape[0] if pi is not None else spec_p.shape[0]
+    dev = spec_p.device
+    h = torch.empty(k, dtype=torch.float32, device=dev)
+    s = torch.empty((k, 2), dtype=torch.int32, device=dev)
+    mp = torch.empty((k, n, n), dtype=torch.float32, device=dev) if want_map else None
+    rc = lib().ebsd_xcf_peak(_ptr(spec_p, torch.float32), _ptr(spec_l, torch.float32),
+                             _ptr(pi, torch.int32, "pi"), _ptr(li, torch.int32, "li"), k, n, _params(prm),
+                             _ptr(h), _ptr(s), _ptr(mp), _stream())
+    _check(rc, "ebsd_xcf_peak")
+    return (h, s, mp) if want_map else (h, s)
+
+
+def xcf_scores(spec_p, spec_l, n, prm=None):
+    import torch
+    p, l = spec_p.shape[0], spec_l.shape[0]
+    out = torch.empty((p, l), dtype=torch.float32, device=spec_p.device)
+    rc = lib().ebsd_xcf_scores(_ptr(spec_p, torch.float32), p, _ptr(spec_l, torch.float32), l, n, _params(prm),
+                               _ptr(out), _stream())
+    _check(rc, "ebsd_xcf_scores")
+    return out
+
+
+def xcf_subpixel(spec_p, spec_l, pi, li, s_int, n, prm=None):
+    import torch
+    k = s_int.shape[0]
+    h = torch.empty(k, dtype=torch.float32, device=spec_p.device)
+    s = torch.empty((k, 2), dtype=torch.float32, device=spec_p.device)
+    rc = lib().ebsd_xcf_subpixel(_ptr(spec_p, torch.float32), _ptr(spec_l, torch.float32),
+                                 _ptr(pi, torch.int32, "pi"), _ptr(li, torch.int32, "li"), k, n,
+                                 _ptr(s_int, torch.int32, "s_int"), _params(prm), _ptr(h), _ptr(s), _stream())
+    _check(rc, "ebsd_xcf_subpixel")
+    return h, s
+
+
+def measure_rotation(pats, tmpls, prm=None):
+    import torch
+    k, n = pats.shape[0], pats.shape[-1]
+    g = torch.empty(k, dtype=torch.float64, device=pats.device)
+    rc = lib().ebsd_measure_rotation(_ptr(pats, torch.float32, "pats"), _ptr(tmpls, torch.float32, "tmpls"), k, n,
+                                     _params(prm), _ptr(g), _stream())
+    _check(rc, "ebsd_measure_rotation")
+    return g
+
+
+def timing_enable(on=True):
+    lib().ebsd_timing_enable(1 if on else 0)
+
+
+def timing_read():
+    """(total ms, launches) of the search kernel since the last read."""
+    ms, cnt = ctypes.c_double(), ctypes.c_int64()
+    _check(lib().ebsd_timing_read(ctypes.byref(ms), ctypes.byref(cnt)), "ebsd_timing_read")
+    return ms.value, cnt.value
+
+
+def spectra_to_complex(spec, n):
+    """View a [K][floats] spectrum tensor as complex [K][B+1][2B+1] (host numpy)."""
+    b = 3 * n // 8
+    a = spec.detach().cpu().numpy().reshape(spec.shape[0], b + 1, 2 * b + 1, 2)
+    return a[..., 0] + 1j * a[..., 1]
+
+
+def band_to_full(band, n):
+    """Place a [.., B+1, 2B+1] band spectrum onto the full n x n grid X[u, v]
+    (Hermitian completion for v < 0); used to compare with full-grid spectra."""
+    b = 3 * n // 8
+    full = np.zeros(band.shape[:-2] + (n, n), dtype=np.complex128)
+    u = np.concatenate([np.arange(0, b + 1), np.arange(-b, 0)]) % n
+    for v in range(b + 1):
+        full[..., u, v] = band[..., v, :]
+        if v > 0:
+            full[..., (-u) % n, n - v] = np.conj(band[..., v, :])
+    return full

@@ -1,0 +1,421 @@
+// C-ABI layer: argument validation, stream-ordered scratch, and the kernel
+// sequence of each entry point (declared and documented in include/ebsd_tm.h).
+#include "../../include/ebsd_tm.h"
+#include "ebsd_internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace ebsd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return EBSD_E_DEVICE;
+}
+
+#define EBSD_TRY(expr, where)                      \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return fail_hip(e_, where); \
+  } while (0)
+
+// Scratch allocated in stream order on the caller's stream and released in
+// stream order when the call returns; the device memory pool keeps it for
+// the next call, so repeated calls do not reach the driver.
+class Scratch {
+ public:
+  explicit Scratch(hipStream_t s) : stream_(s) {}
+  ~Scratch() {
+    for (void* p : ptrs_) (void)hipFreeAsync(p, stream_);
+  }
+  template <class T>
+  T* get(size_t count, hipError_t* err) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    *err = hipMallocAsync(&p, count * sizeof(T), stream_);
+    if (*err != hipSuccess) return nullptr;
+    ptrs_.push_back(p);
+    return static_cast<T*>(p);
+  }
+
+ private:
+  hipStream_t stream_;
+  std::vector<void*> ptrs_;
+};
+
+#define EBSD_ALLOC(var, T, count, scratch)                                   \
+  T* var = nullptr;                                                          \
+  do {                                                                       \
+    hipError_t e_ = hipSuccess;                                              \
+    var = (scratch).template get<T>((size_t)(count), &e_);                   \
+    if (e_ != hipSuccess) return fail(EBSD_E_NOMEM, "device allocation failed: " #var); \
+  } while (0)
+
+constexpr size_t kParamsV1 = offsetof(ebsd_params, form) + sizeof(int32_t);
+
+// Copies the caller's parameter block (of any size >= the first version)
+// over the defaults and validates it.
+int resolve_params(const ebsd_params* in, int n, ebsd_params* out) {
+  ebsd_params_default(out);
+  if (in) {
+    if (in->struct_size < kParamsV1) return fail(EBSD_E_INVALID, "ebsd_params.struct_size too small");
+    const size_t sz = in->struct_size < sizeof(ebsd_params) ? in->struct_size : sizeof(ebsd_params);
+    std::memcpy(out, in, sz);
+    out->struct_size = sizeof(ebsd_params);
+  }
+  if (!(out->sigma_hp > 0.0) || !(out->sigma_lp_frac > 0.0) || !(out->rho_max_frac > 0.0))
+    return fail(EBSD_E_INVALID, "filter parameters must be positive");
+  if (out->rho_max_frac > 0.375 + 1e-12)
+    return fail(EBSD_E_UNSUPPORTED, "rho_max_frac above 3/8 is outside the stored band");
+  if (out->upsample < 1 || out->upsample > 128) return fail(EBSD_E_INVALID, "upsample must be in [1, 128]");
+  if (out->n_iter < 0 || out->n_iter > 64) return fail(EBSD_E_INVALID, "n_iter must be in [0, 64]");
+  if (out->n_rho == 0) out->n_rho = n / 2;
+  if (out->n_eta == 0) out->n_eta = 2 * n;
+  if (out->n_rho < 2 || out->n_rho > 4096) return fail(EBSD_E_INVALID, "n_rho must be in [2, 4096]");
+  if (out->n_eta < 4 || out->n_eta > 1024 || (out->n_eta & 1))
+    return fail(EBSD_E_INVALID, "n_eta must be even and in [4, 1024]");
+  if (out->precision != EBSD_PREC_FP32) return fail(EBSD_E_UNSUPPORTED, "precision not built");
+  if (out->form != EBSD_FORM_AUTO && out->form != EBSD_FORM_FFT) return fail(EBSD_E_UNSUPPORTED, "form not built");
+  if (out->max_shift < -1) return fail(EBSD_E_INVALID, "max_shift must be >= -1");
+  return EBSD_OK;
+}
+
+FilterParams filter_of(const ebsd_params& p, int n) {
+  FilterParams f;
+  f.window = p.window;
+  f.sigma_hp = (float)p.sigma_hp;
+  f.sigma_lp = (float)(p.sigma_lp_frac * n);
+  f.rho_max = (float)(p.rho_max_frac * n);
+  return f;
+}
+
+int64_t spec_complex(int n) {
+  const int b = band_of(n);
+  return b < 0 ? -1 : (int64_t)(b + 1) * (2 * b + 1);
+}
+
+int check_size(int n) {
+  if (!size_supported(n)) return fail(EBSD_E_UNSUPPORTED, "pattern size not supported (64, 96, 128, 160)");
+  return EBSD_OK;
+}
+
+int check_master(const ebsd_master* mp) {
+  if (!mp || !mp->data) return fail(EBSD_E_INVALID, "null master");
+  if (mp->H < 4 || mp->W < 4) return fail(EBSD_E_INVALID, "master must be at least 4 x 4");
+  return EBSD_OK;
+}
+
+int check_geometry(const ebsd_geometry* geo) {
+  if (!geo) return fail(EBSD_E_INVALID, "null geometry");
+  if (!(geo->pcz > 0.0) || !std::isfinite(geo->pcx) || !std::isfinite(geo->pcy))
+    return fail(EBSD_E_INVALID, "pattern centre must be finite with pcz > 0");
+  return EBSD_OK;
+}
+
+// Event pairs around the search kernel while timing is enabled.
+bool g_timing = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
+
+hipError_t timed_scores(int n, const float2* sp, int64_t p, const float2* sl, int64_t l, int max_shift,
+                        float* out, hipStream_t st) {
+  if (!g_timing) return launch_xcf_scores(n, sp, p, sl, l, max_shift, out, st);
+  hipEvent_t a, b;
+  hipError_t e;
+  if ((e = hipEventCreate(&a)) != hipSuccess) return e;
+  if ((e = hipEventCreate(&b)) != hipSuccess) return e;
+  if ((e = hipEventRecord(a, st)) != hipSuccess) return e;
+  if ((e = launch_xcf_scores(n, sp, p, sl, l, max_shift, out, st)) != hipSuccess) return e;
+  if ((e = hipEventRecord(b, st)) != hipSuccess) return e;
+  g_events.emplace_back(a, b);
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ebsd_timing_enable(int enable) {
+  g_timing = enable != 0;
+  return EBSD_OK;
+}
+
+int ebsd_timing_read(double* total_ms, int64_t* launches) {
+  double tot = 0.0;
+  int64_t cnt = 0;
+  int rc = EBSD_OK;
+  for (auto& ev : g_events) {
+    float ms = 0.0f;
+    hipError_t e = hipEventElapsedTime(&ms, ev.first, ev.second);
+    if (e != hipSuccess) rc = fail_hip(e, "timing_read");
+    tot += ms;
+    ++cnt;
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  g_events.clear();
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = cnt;
+  return rc;
+}
+
+void ebsd_params_default(ebsd_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(ebsd_params);
+  p->window = 1;
+  p->sigma_hp = 2.0;
+  p->sigma_lp_frac = 0.125;
+  p->rho_max_frac = 0.375;
+  p->max_shift = -1;
+  p->upsample = 100;
+  p->n_iter = 2;
+  p->n_rho = 0;
+  p->n_eta = 0;
+  p->precision = EBSD_PREC_FP32;
+  p->form = EBSD_FORM_AUTO;
+}
+
+int ebsd_version(void) { return 100; }
+
+const char* ebsd_last_error(void) { return g_last_error.c_str(); }
+
+int64_t ebsd_spectrum_floats(int32_t n) {
+  const int64_t c = spec_complex(n);
+  return c < 0 ? -1 : 2 * c;
+}
+
+int ebsd_project_templates(const ebsd_master* mp, const double* q, int64_t K, int32_t n,
+                           const ebsd_geometry* geo, float* out, void* stream) {
+  g_last_error.clear();
+  int rc;
+  if ((rc = check_master(mp)) || (rc = check_geometry(geo))) return rc;
+  if (n < 4 || n > 4096) return fail(EBSD_E_INVALID, "n must be in [4, 4096]");
+  if (K < 0) return fail(EBSD_E_INVALID, "K must be >= 0");
+  if (K == 0) return EBSD_OK;
+  if (!q || !out) return fail(EBSD_E_INVALID, "null pointer");
+  EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, q, K, geo->pc_per, geo->pcx, geo->pcy, geo->pcz, out,
+                          (hipStream_t)stream),
+           "project");
+  return EBSD_OK;
+}
+
+int ebsd_pattern_spectra(const float* imgs, int64_t K, int32_t n, const ebsd_params* prm, float* spec,
+                         double* energy, void* stream) {
+  g_last_error.clear();
+  int rc;
+  ebsd_params p;
+  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p))) return rc;
+  if (K < 0) return fail(EBSD_E_INVALID, "K must be >= 0");
+  if (K == 0) return EBSD_OK;
+  if (!imgs || !spec) return fail(EBSD_E_INVALID, "null pointer");
+  EBSD_TRY(launch_spectra(n, imgs, (int64_t)n * n, K, filter_of(p, n), (float2*)spec, energy,
+                          (hipStream_t)stream),
+           "spectra");
+  return EBSD_OK;
+}
+
+int ebsd_xcf_peak(const float* spec_p, const float* spec_l, const int32_t* pi, const int32_t* li, int64_t K,
+                  int32_t n, const ebsd_params* prm, float* h_int, int32_t* s_int, float* map, void* stream) {
+  g_last_error.clear();
+  int rc;
+  ebsd_params p;
+  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p))) return rc;
+  if (K < 0) return fail(EBSD_E_INVALID, "K must be >= 0");
+  if (K == 0) return EBSD_OK;
+  if (!spec_p || !spec_l || !h_int || !s_int) return fail(EBSD_E_INVALID, "null pointer");
+  if (K > 0x7fffffffLL) return fail(EBSD_E_INVALID, "K too large");
+  EBSD_TRY(launch_xcf_peak(n, (const float2*)spec_p, (const float2*)spec_l, pi, li, K, p.max_shift, h_int, s_int,
+                           map, (hipStream_t)stream),
+           "xcf_peak");
+  return EBSD_OK;
+}
+
+int ebsd_xcf_scores(const float* spec_p, int64_t P, const float* spec_l, int64_t L, int32_t n,
+                    const ebsd_params* prm, float* scores, void* stream) {
+  g_last_error.clear();
+  int rc;
+  ebsd_params p;
+  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p))) return rc;
+  if (P < 0 || L < 0) return fail(EBSD_E_INVALID, "P and L must be >= 0");
+  if (P == 0 || L == 0) return EBSD_OK;
+  if (!spec_p || !spec_l || !scores) return fail(EBSD_E_INVALID, "null pointer");
+  EBSD_TRY(timed_scores(n, (const float2*)spec_p, P, (const float2*)spec_l, L, p.max_shift, scores,
+                        (hipStream_t)stream),
+           "xcf_scores");
+  return EBSD_OK;
+}
+
+int ebsd_xcf_subpixel(const float* spec_p, const float* spec_l, const int32_t* pi, const int32_t* li, int64_t K,
+                      int32_t n, const int32_t* s_int, const ebsd_params* prm, float* h_sub, float* s_sub,
+                      void* stream) {
+  g_last_error.clear();
+  int rc;
+  ebsd_params p;
+  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p))) return rc;
+  if (K < 0) return fail(EBSD_E_INVALID, "K must be >= 0");
+  if (K == 0) return EBSD_OK;
+  if (!spec_p || !spec_l || !s_int || !h_sub || !s_sub) return fail(EBSD_E_INVALID, "null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  const int kn = p.upsample * n;
+  EBSD_ALLOC(roots, float2, kn, ws);
+  EBSD_TRY(launch_roots(kn, roots, st), "roots");
+  EBSD_TRY(launch_subpixel(n, (const float2*)spec_p, (const float2*)spec_l, pi, li, K, s_int, p.upsample, roots,
+                           h_sub, s_sub, st),
+           "subpixel");
+  return EBSD_OK;
+}
+
+int ebsd_measure_rotation(const float* pats, const float* tmpls, int64_t K, int32_t n, const ebsd_params* prm,
+                          double* gamma, void* stream) {
+  g_last_error.clear();
+  int rc;
+  ebsd_params p;
+  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p))) return rc;
+  if (K < 0) return fail(EBSD_E_INVALID, "K must be >= 0");
+  if (K == 0) return EBSD_OK;
+  if (!pats || !tmpls || !gamma) return fail(EBSD_E_INVALID, "null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  const size_t lp = (size_t)p.n_rho * p.n_eta;
+  EBSD_ALLOC(lp_e, float, lp * K, ws);
+  EBSD_ALLOC(lp_t, float, lp * K, ws);
+  EBSD_TRY(launch_logpolar(n, pats, K, p.n_rho, p.n_eta, lp_e, st), "logpolar");
+  EBSD_TRY(launch_logpolar(n, tmpls, K, p.n_rho, p.n_eta, lp_t, st), "logpolar");
+  EBSD_TRY(launch_eta_peak(lp_e, lp_t, K, p.n_rho, p.n_eta, p.upsample, gamma, st), "eta_peak");
+  return EBSD_OK;
+}
+
+int ebsd_index_patterns(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo,
+                        const double* lib_q, int64_t L, const ebsd_params* prm, int32_t* best_idx, double* best_q,
+                        float* peak_h, float* shift, float* scores, void* stream) {
+  g_last_error.clear();
+  int rc;
+  if (!pats) return fail(EBSD_E_INVALID, "null batch");
+  const int n = pats->n;
+  ebsd_params p;
+  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p)) || (rc = check_master(mp)) ||
+      (rc = check_geometry(geo)))
+    return rc;
+  const int64_t P = pats->P;
+  if (P < 0) return fail(EBSD_E_INVALID, "P must be >= 0");
+  if (L < 1) return fail(EBSD_E_INVALID, "library must hold at least one orientation");
+  if (L > 0x7fffffffLL || P > 0x7fffffffLL) return fail(EBSD_E_INVALID, "P and L must fit in int32");
+  if (!lib_q) return fail(EBSD_E_INVALID, "null library");
+  if (P == 0) return EBSD_OK;
+  if (!pats->data || !best_idx || !peak_h || !shift) return fail(EBSD_E_INVALID, "null pointer");
+
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  const int64_t sc = spec_complex(n);
+  const int64_t npix = (int64_t)n * n;
+  const FilterParams fp = filter_of(p, n);
+  EBSD_ALLOC(tmpl, float, npix * L, ws);
+  EBSD_ALLOC(spec_l, float2, sc * L, ws);
+  EBSD_ALLOC(spec_p, float2, sc * P, ws);
+  float* sc_out = scores;
+  if (!sc_out) {
+    EBSD_ALLOC(tmp_scores, float, P * L, ws);
+    sc_out = tmp_scores;
+  }
+  EBSD_ALLOC(h_int, float, P, ws);
+  EBSD_ALLOC(s_int, int32_t, 2 * P, ws);
+  EBSD_ALLOC(h_tmp, float, P, ws);
+  const int kn = p.upsample * n;
+  EBSD_ALLOC(roots, float2, kn, ws);
+
+  EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, lib_q, L, nullptr, geo->pcx, geo->pcy, geo->pcz, tmpl, st),
+           "project");
+  EBSD_TRY(launch_spectra(n, tmpl, npix, L, fp, spec_l, nullptr, st), "spectra(templates)");
+  EBSD_TRY(launch_spectra(n, pats->data, npix, P, fp, spec_p, nullptr, st), "spectra(patterns)");
+  EBSD_TRY(timed_scores(n, spec_p, P, spec_l, L, p.max_shift, sc_out, st), "xcf_scores");
+  EBSD_TRY(launch_library_argmax(sc_out, P, L, best_idx, h_int, st), "library_argmax");
+  EBSD_TRY(launch_xcf_peak(n, spec_p, spec_l, nullptr, best_idx, P, p.max_shift, h_tmp, s_int, nullptr, st),
+           "xcf_peak");
+  EBSD_TRY(launch_roots(kn, roots, st), "roots");
+  EBSD_TRY(launch_subpixel(n, spec_p, spec_l, nullptr, best_idx, P, s_int, p.upsample, roots, peak_h, shift, st),
+           "subpixel");
+  if (best_q) EBSD_TRY(launch_gather_q(lib_q, best_idx, P, best_q, st), "gather_q");
+  return EBSD_OK;
+}
+
+int ebsd_refine_orientations(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo,
+                             const double* q_init, const ebsd_params* prm, double* q_out, float* peak_h,
+                             float* shift, void* stream) {
+  g_last_error.clear();
+  int rc;
+  if (!pats) return fail(EBSD_E_INVALID, "null batch");
+  const int n = pats->n;
+  ebsd_params p;
+  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p)) || (rc = check_master(mp)) ||
+      (rc = check_geometry(geo)))
+    return rc;
+  const int64_t P = pats->P;
+  if (P < 0) return fail(EBSD_E_INVALID, "P must be >= 0");
+  if (P > 0x7fffffffLL) return fail(EBSD_E_INVALID, "P must fit in int32");
+  if (P == 0) return EBSD_OK;
+  if (!pats->data || !q_init || !q_out || !peak_h || !shift) return fail(EBSD_E_INVALID, "null pointer");
+
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  const int64_t sc = spec_complex(n);
+  const int64_t npix = (int64_t)n * n;
+  const FilterParams fp = filter_of(p, n);
+  const int64_t lp = (int64_t)p.n_rho * p.n_eta;
+  EBSD_ALLOC(tmpl, float, npix * P, ws);
+  EBSD_ALLOC(spec_p, float2, sc * P, ws);
+  EBSD_ALLOC(spec_t, float2, sc * P, ws);
+  EBSD_ALLOC(lp_e, float, lp * P, ws);
+  EBSD_ALLOC(lp_t, float, lp * P, ws);
+  EBSD_ALLOC(h_int, float, P, ws);
+  EBSD_ALLOC(h_sub, float, P, ws);
+  EBSD_ALLOC(s_int, int32_t, 2 * P, ws);
+  EBSD_ALLOC(s_sub, float, 2 * P, ws);
+  EBSD_ALLOC(gam, double, P, ws);
+  const int kn = p.upsample * n;
+  EBSD_ALLOC(roots, float2, kn, ws);
+
+  if (q_out != q_init) EBSD_TRY(hipMemcpyAsync(q_out, q_init, sizeof(double) * 4 * P, hipMemcpyDeviceToDevice, st), "copy q");
+  EBSD_TRY(launch_roots(kn, roots, st), "roots");
+  EBSD_TRY(launch_spectra(n, pats->data, npix, P, fp, spec_p, nullptr, st), "spectra(patterns)");
+  EBSD_TRY(launch_logpolar(n, pats->data, P, p.n_rho, p.n_eta, lp_e, st), "logpolar(patterns)");
+  const double* pcp = geo->pc_per;
+  auto measure_shift = [&](float* h_out, float* s_out) -> int {
+    EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, q_out, P, pcp, geo->pcx, geo->pcy, geo->pcz, tmpl, st),
+             "project");
+    EBSD_TRY(launch_spectra(n, tmpl, npix, P, fp, spec_t, nullptr, st), "spectra(templates)");
+    EBSD_TRY(launch_xcf_peak(n, spec_p, spec_t, nullptr, nullptr, P, p.max_shift, h_int, s_int, nullptr, st),
+             "xcf_peak");
+    EBSD_TRY(launch_subpixel(n, spec_p, spec_t, nullptr, nullptr, P, s_int, p.upsample, roots, h_out, s_out, st),
+             "subpixel");
+    return EBSD_OK;
+  };
+  for (int it = 0; it < p.n_iter; ++it) {
+    if ((rc = measure_shift(h_sub, s_sub))) return rc;
+    EBSD_TRY(launch_update_xy(q_out, s_sub, P, pcp, geo->pcz, n, st), "update_xy");
+    EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, q_out, P, pcp, geo->pcx, geo->pcy, geo->pcz, tmpl, st),
+             "project");
+    EBSD_TRY(launch_logpolar(n, tmpl, P, p.n_rho, p.n_eta, lp_t, st), "logpolar(templates)");
+    EBSD_TRY(launch_eta_peak(lp_e, lp_t, P, p.n_rho, p.n_eta, p.upsample, gam, st), "eta_peak");
+    EBSD_TRY(launch_update_z(q_out, gam, P, st), "update_z");
+  }
+  if ((rc = measure_shift(peak_h, shift))) return rc;
+  return EBSD_OK;
+}
+
+}  // extern "C"

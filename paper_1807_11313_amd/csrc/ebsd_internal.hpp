@@ -1,0 +1,74 @@
+// Internal launch interface between the C-ABI layer and the kernels.
+// Every launcher enqueues on `stream` and returns the hipError_t of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ebsd {
+
+// Band half-width of the stored spectra for a supported size (3N/8), or -1.
+int band_of(int n);
+bool size_supported(int n);
+
+struct FilterParams {
+  int window;
+  float sigma_hp, sigma_lp, rho_max;
+};
+
+// Contrast-normalise, window, forward 2-D DFT, band-pass, FP64 energy and
+// unit-energy scaling of K n x n images (image k at imgs + k * img_stride).
+// Output: spec[k][v][kk] complex64 (v in [0, B], kk in [0, 2B + 1)), energy[k].
+hipError_t launch_spectra(int n, const float* imgs, int64_t img_stride, int64_t k,
+                          const FilterParams& fp, float2* spec, double* energy,
+                          hipStream_t stream);
+
+// Integer-peak scores h[p][l] = max_s rho(p, l; s) for every pattern x template.
+hipError_t launch_xcf_scores(int n, const float2* spec_p, int64_t p, const float2* spec_l,
+                             int64_t l, int max_shift, float* scores, hipStream_t stream);
+
+// Integer peak (value, signed shift) for K explicit pairs (pi[k], li[k]),
+// and optionally the full correlation map [K][n][n] (row = s_y mod n).
+hipError_t launch_xcf_peak(int n, const float2* spec_p, const float2* spec_l,
+                           const int32_t* pi, const int32_t* li, int64_t k, int max_shift,
+                           float* h_int, int32_t* s_int, float* map, hipStream_t stream);
+
+// Upsampled peak around s_int: h_sub[k], s_sub[k] = (s_x, s_y) px.
+hipError_t launch_subpixel(int n, const float2* spec_p, const float2* spec_l,
+                           const int32_t* pi, const int32_t* li, int64_t k,
+                           const int32_t* s_int, int kappa, const float2* roots,
+                           float* h_sub, float* s_sub, hipStream_t stream);
+
+// exp(2 pi i k / m) for k in [0, m), computed in FP64 and rounded.
+hipError_t launch_roots(int m, float2* out, hipStream_t stream);
+
+// Gnomonic projection of the master for K orientations (FP64 quaternions),
+// at one pattern centre or one per orientation.
+hipError_t launch_project(int n, const float* master, int mh, int mw, const double* q,
+                          int64_t k, const double* pc_per, double pcx, double pcy, double pcz,
+                          float* out, hipStream_t stream);
+
+// Best template per pattern from the score matrix (ties: smallest index).
+hipError_t launch_library_argmax(const float* scores, int64_t p, int64_t l, int32_t* best,
+                                 float* best_h, hipStream_t stream);
+
+// best_q[p] = lib_q[best[p]]
+hipError_t launch_gather_q(const double* lib_q, const int32_t* best, int64_t p, double* best_q,
+                           hipStream_t stream);
+
+// Log-polar resampling of contrast-normalised images, rows mean-removed.
+hipError_t launch_logpolar(int n, const float* imgs, int64_t k, int n_rho, int n_eta,
+                           float* out, hipStream_t stream);
+
+// eta correlation of pattern / template log-polar images, peak refined by
+// trigonometric interpolation: gamma[k] (radians).
+hipError_t launch_eta_peak(const float* lp_e, const float* lp_t, int64_t k, int n_rho,
+                           int n_eta, int kappa, double* gamma, hipStream_t stream);
+
+// FP64 orientation updates: R <- R (Ry(beta) Rx(alpha))^T from s_sub, and
+// R <- R Rz(gamma)^T.
+hipError_t launch_update_xy(double* q, const float* s_sub, int64_t k, const double* pc_per,
+                            double pcz, int n, hipStream_t stream);
+hipError_t launch_update_z(double* q, const double* gamma, int64_t k, hipStream_t stream);
+
+}  // namespace ebsd

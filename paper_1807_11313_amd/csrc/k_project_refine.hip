@@ -1,0 +1,532 @@
+// Template projection, sub-pixel peak, library argmax and refinement kernels (gfx950).
+#include "ebsd_common.hpp"
+#include "ebsd_internal.hpp"
+
+#include <math.h>
+
+namespace ebsd {
+
+// ---------------------------------------------------------------------------
+// Gnomonic projection (section "SO(3) Library Generation"): pixel (i, j) of an
+// n x n screen looks along d = normalise((i + 1/2)/n - PCx, (j + 1/2)/n - PCy, PCz)
+// (detector frame x = +column, y = +row, z = source to screen; PC in screen
+// widths); the crystal direction c = R d is looked up in the equirectangular
+// master (row r at polar angle (r + 1/2) pi / H, column q at azimuth 2 pi q / W)
+// with Keys cubic convolution (a = -0.5), periodic in azimuth, rows clamped.
+__device__ __forceinline__ void keys4(float t, float* w) {
+  // weights of taps at offsets -1, 0, 1, 2 for fractional position t in [0, 1)
+  const float a = -0.5f;
+  const float t2 = t * t, t3 = t2 * t;
+  w[0] = a * (t3 - 2.0f * t2 + t);
+  w[1] = (a + 2.0f) * t3 - (a + 3.0f) * t2 + 1.0f;
+  const float s = 1.0f - t, s2 = s * s, s3 = s2 * s;
+  w[2] = (a + 2.0f) * s3 - (a + 3.0f) * s2 + 1.0f;
+  w[3] = a * (s3 - 2.0f * s2 + s);
+}
+
+__global__ __launch_bounds__(256) void k_project(const float* __restrict__ master, int mh, int mw,
+                                                 const double* __restrict__ q,
+                                                 const double* __restrict__ pc_per, double pcx,
+                                                 double pcy, double pcz, int n,
+                                                 float* __restrict__ out) {
+  const int64_t k = blockIdx.y;
+  const int pix = blockIdx.x * 256 + threadIdx.x;
+  if (pix >= n * n) return;
+  const double qw = q[4 * k], qx = q[4 * k + 1], qy = q[4 * k + 2], qz = q[4 * k + 3];
+  const float r00 = (float)(1 - 2 * (qy * qy + qz * qz)), r01 = (float)(2 * (qx * qy - qw * qz)),
+              r02 = (float)(2 * (qx * qz + qw * qy));
+  const float r10 = (float)(2 * (qx * qy + qw * qz)), r11 = (float)(1 - 2 * (qx * qx + qz * qz)),
+              r12 = (float)(2 * (qy * qz - qw * qx));
+  const float r20 = (float)(2 * (qx * qz - qw * qy)), r21 = (float)(2 * (qy * qz + qw * qx)),
+              r22 = (float)(1 - 2 * (qx * qx + qy * qy));
+  if (pc_per) {
+    pcx = pc_per[3 * k];
+    pcy = pc_per[3 * k + 1];
+    pcz = pc_per[3 * k + 2];
+  }
+  const int j = pix / n, i = pix - j * n;
+  const float inv_n = 1.0f / (float)n;
+  const float dx = ((float)i + 0.5f) * inv_n - (float)pcx;
+  const float dy = ((float)j + 0.5f) * inv_n - (float)pcy;
+  const float dz = (float)pcz;
+  const float rn = rsqrtf(dx * dx + dy * dy + dz * dz);
+  const float ux = dx * rn, uy = dy * rn, uz = dz * rn;
+  const float cx = r00 * ux + r01 * uy + r02 * uz;
+  const float cy = r10 * ux + r11 * uy + r12 * uz;
+  const float cz = r20 * ux + r21 * uy + r22 * uz;
+  const float theta = atan2f(sqrtf(cx * cx + cy * cy), cz);
+  float phi = atan2f(cy, cx);
+  if (phi < 0.0f) phi += 6.28318530717958647692f;
+  float v = theta * ((float)mh * 0.318309886183790671538f) - 0.5f;
+  const float u = phi * ((float)mw * 0.159154943091895335769f);
+  v = fminf(fmaxf(v, 0.0f), (float)(mh - 1));
+  const float v0f = floorf(v), u0f = floorf(u);
+  float wv[4], wu[4];
+  keys4(v - v0f, wv);
+  keys4(u - u0f, wu);
+  const int v0 = (int)v0f, u0 = (int)u0f;
+  float acc = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int row = min(max(v0 + a - 1, 0), mh - 1);
+    const float* mrow = master + (int64_t)row * mw;
+    float ra = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int col = (u0 + b - 1) % mw;
+      if (col < 0) col += mw;
+      ra = __fmaf_rn(wu[b], mrow[col], ra);
+    }
+    acc = __fmaf_rn(wv[a], ra, acc);
+  }
+  out[k * (int64_t)n * n + pix] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// exp(2 pi i k / m), k in [0, m), FP64 evaluation.
+__global__ void k_roots(int m, float2* out) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= m) return;
+  double s, c;
+  sincospi(2.0 * (double)k / (double)m, &s, &c);
+  out[k] = make_float2((float)c, (float)s);
+}
+
+// ---------------------------------------------------------------------------
+// Upsampled peak (Equation 5 and the peak upsampling of section "Fast Fourier
+// Transform"): rho evaluated exactly (matrix DFT over the band) at
+// s_int + (a, b) / kappa for |a|, |b| <= ceil(0.75 kappa); the largest real
+// value wins, ties to the smallest (b, a) row-major.  Phases are looked up
+// in a table of the kappa N-th roots of unity at exact integer indices.
+__global__ __launch_bounds__(256) void k_subpixel(int n, int bnd, const cf* __restrict__ spec_p,
+                                                  const cf* __restrict__ spec_l,
+                                                  const int32_t* __restrict__ pi,
+                                                  const int32_t* __restrict__ li,
+                                                  const int32_t* __restrict__ s_int, int kappa,
+                                                  const cf* __restrict__ roots,
+                                                  float* __restrict__ h_sub,
+                                                  float* __restrict__ s_sub) {
+  extern __shared__ cf sm[];
+  const int nv = bnd + 1, nk = 2 * bnd + 1, spec = nv * nk;
+  const int m = (3 * kappa + 3) / 4;  // ceil(0.75 kappa)
+  const int msz = 2 * m + 1;
+  const int kn = kappa * n;
+  cf* z = sm;            // [nv][nk]
+  cf* g = sm + spec;     // [msz][nv]
+  const int tid = threadIdx.x;
+  const int64_t k = blockIdx.x;
+  const cf* E = spec_p + (pi ? (int64_t)pi[k] : k) * spec;
+  const cf* T = spec_l + (li ? (int64_t)li[k] : k) * spec;
+  const int x0 = s_int[2 * k], y0 = s_int[2 * k + 1];
+  for (int t = tid; t < spec; t += 256) z[t] = cmulc(E[t], T[t]);
+  __syncthreads();
+  // G(b, v) = sum_u Z(u, v) exp(2 pi i u (y0 + (b - m)/kappa) / n)
+  for (int t = tid; t < msz * nv; t += 256) {
+    const int b = t / nv, v = t - b * nv;
+    const int ph = kappa * y0 + b - m;
+    float ar = 0.0f, ai = 0.0f;
+    for (int kk = 0; kk < nk; ++kk) {
+      const int u = kk <= bnd ? kk : kk - nk;
+      int idx = (u * ph) % kn;
+      if (idx < 0) idx += kn;
+      const cf w = roots[idx];
+      const cf zz = z[v * nk + kk];
+      ar = __fmaf_rn(zz.x, w.x, __fmaf_rn(-zz.y, w.y, ar));
+      ai = __fmaf_rn(zz.x, w.y, __fmaf_rn(zz.y, w.x, ai));
+    }
+    g[b * nv + v] = cf{ar, ai};
+  }
+  __syncthreads();
+  // rho(b, a) = Re G(b, 0) + 2 Re sum_{v >= 1} G(b, v) exp(2 pi i v (x0 + (a - m)/kappa) / n)
+  float best = -INFINITY;
+  int bi = 0x7fffffff;
+  for (int t = tid; t < msz * msz; t += 256) {
+    const int b = t / msz, a = t - b * msz;
+    const int ph = kappa * x0 + a - m;
+    float acc = 0.0f;
+    for (int v = 1; v < nv; ++v) {
+      int idx = (v * ph) % kn;
+      if (idx < 0) idx += kn;
+      const cf w = roots[idx];
+      const cf gg = g[b * nv + v];
+      acc = __fmaf_rn(gg.x, w.x, __fmaf_rn(-gg.y, w.y, acc));
+    }
+    const float val = g[b * nv].x + 2.0f * acc;
+    argmax_merge(best, bi, val, t);
+  }
+  wave_argmax(best, bi);
+  __shared__ float rv[4];
+  __shared__ int ri[4];
+  if ((tid & 63) == 0) {
+    rv[tid >> 6] = best;
+    ri[tid >> 6] = bi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 4; ++w) argmax_merge(best, bi, rv[w], ri[w]);
+    const int b = bi / msz, a = bi - b * msz;
+    h_sub[k] = best;
+    s_sub[2 * k] = (float)x0 + (float)(a - m) / (float)kappa;
+    s_sub[2 * k + 1] = (float)y0 + (float)(b - m) / (float)kappa;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Library argmax (section "Method Overview": best match = highest coefficient),
+// ties to the smallest template index.
+__global__ __launch_bounds__(256) void k_library_argmax(const float* __restrict__ scores, int64_t l,
+                                                        int32_t* __restrict__ best,
+                                                        float* __restrict__ best_h) {
+  const int64_t p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const float* s = scores + p * l;
+  float bv = -INFINITY;
+  int bi = 0x7fffffff;
+  for (int64_t i = tid; i < l; i += 256) argmax_merge(bv, bi, s[i], (int)i);
+  wave_argmax(bv, bi);
+  __shared__ float rv[4];
+  __shared__ int ri[4];
+  if ((tid & 63) == 0) {
+    rv[tid >> 6] = bv;
+    ri[tid >> 6] = bi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 4; ++w) argmax_merge(bv, bi, rv[w], ri[w]);
+    if (bi < 0 || bi >= l) bi = 0;  // every score NaN: keep the index in range
+    best[p] = bi;
+    if (best_h) best_h[p] = bv;
+  }
+}
+
+__global__ void k_gather_q(const double* __restrict__ lib_q, const int32_t* __restrict__ best,
+                           int64_t p, double* __restrict__ best_q) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= p) return;
+  const int64_t l = best[i];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) best_q[4 * i + c] = lib_q[4 * l + c];
+}
+
+// ---------------------------------------------------------------------------
+// Log-polar resampling (section "Orientation and Pattern Centre Refinement"):
+// centre ((n-1)/2, (n-1)/2), n_rho radii log-spaced in [2, n/2 - 2] px, n_eta
+// angles eta_m = 2 pi m / n_eta measured from +column toward +row, bilinear
+// samples of the contrast-normalised image, each radius row mean-removed.
+__global__ __launch_bounds__(256) void k_logpolar(const float* __restrict__ imgs, int n, int n_rho,
+                                                  int n_eta, float* __restrict__ out) {
+  const int64_t k = blockIdx.x;
+  const int tid = threadIdx.x;
+  const float* img = imgs + k * (int64_t)n * n;
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = tid; i < n * n; i += 256) {
+    const double v = img[i];
+    s1 += v;
+    s2 += v * v;
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  __shared__ double red[8];
+  if ((tid & 63) == 0) {
+    red[tid >> 6] = s1;
+    red[4 + (tid >> 6)] = s2;
+  }
+  __syncthreads();
+  const double mean = (red[0] + red[1] + red[2] + red[3]) / (double)(n * n);
+  const double var = (red[4] + red[5] + red[6] + red[7]) / (double)(n * n) - mean * mean;
+  const float fmean = (float)mean, inv_std = var > 0.0 ? (float)(1.0 / sqrt(var)) : 0.0f;
+  const float c = 0.5f * (float)(n - 1);
+  const double rmin = 2.0, rmax = 0.5 * n - 2.0;
+  const int lane = tid & 63, wave = tid >> 6;
+  float* o = out + k * (int64_t)n_rho * n_eta;
+  for (int row = wave; row < n_rho; row += 4) {
+    const float r = (float)(rmin * pow(rmax / rmin, (double)row / (double)(n_rho - 1)));
+    float sum = 0.0f;
+    for (int m = lane; m < n_eta; m += 64) {
+      float sn, cs;
+      sincospif(2.0f * (float)m / (float)n_eta, &sn, &cs);
+      const float col = c + r * cs, rw = c + r * sn;
+      const float r0f = floorf(rw), c0f = floorf(col);
+      const float fr = rw - r0f, fc = col - c0f;
+      const int r0 = (int)r0f, c0 = (int)c0f;
+      const float* p = img + r0 * n + c0;
+      const float val = (1.0f - fr) * ((1.0f - fc) * p[0] + fc * p[1]) + fr * ((1.0f - fc) * p[n] + fc * p[n + 1]);
+      const float x = (val - fmean) * inv_std;
+      o[row * n_eta + m] = x;
+      sum += x;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    const float mu = sum / (float)n_eta;
+    for (int m = lane; m < n_eta; m += 64) o[row * n_eta + m] -= mu;
+  }
+}
+
+// eta correlation c(D) = sum_k w_k sum_m Le[k][m] Lt[k][m - D] (Hann weights
+// over radius), normalised; integer argmax (ties to the smallest D), then the
+// maximum of its trigonometric interpolant over D_int + a / kappa,
+// |a| <= ceil(0.75 kappa) (ties to the smallest a); gamma = 2 pi D / n_eta.
+__global__ __launch_bounds__(256) void k_eta_peak(const float* __restrict__ lp_e,
+                                                  const float* __restrict__ lp_t, int n_rho,
+                                                  int n_eta, int kappa, double* __restrict__ gamma) {
+  extern __shared__ float fsm[];
+  constexpr int RC = 8;  // radius rows staged per step
+  float* le = fsm;                     // [RC][n_eta]
+  float* lt = fsm + RC * n_eta;        // [RC][n_eta]
+  float* cc = fsm + 2 * RC * n_eta;    // [n_eta]
+  float* cq = cc + n_eta;              // [2][n_eta / 2 + 1]
+  const int64_t k = blockIdx.x;
+  const int tid = threadIdx.x;
+  const float* E = lp_e + k * (int64_t)n_rho * n_eta;
+  const float* T = lp_t + k * (int64_t)n_rho * n_eta;
+  constexpr int DMAX = 4;  // n_eta <= 1024
+  float acc[DMAX] = {0.f, 0.f, 0.f, 0.f};
+  float ee = 0.0f, tt = 0.0f;
+  for (int r0 = 0; r0 < n_rho; r0 += RC) {
+    const int rc = min(RC, n_rho - r0);
+    __syncthreads();
+    for (int t = tid; t < rc * n_eta; t += 256) {
+      le[t] = E[r0 * n_eta + t];
+      lt[t] = T[r0 * n_eta + t];
+    }
+    __syncthreads();
+    for (int rr = 0; rr < rc; ++rr) {
+      const float s = sinpif(((float)(r0 + rr) + 0.5f) / (float)n_rho);
+      const float w = s * s;
+      const float* er = le + rr * n_eta;
+      const float* tr = lt + rr * n_eta;
+#pragma unroll
+      for (int j = 0; j < DMAX; ++j) {
+        const int d = tid + 256 * j;
+        if (d < n_eta) {
+          float a = 0.0f;
+          // m - d wraps at m = d
+          for (int m = 0; m < d; ++m) a = __fmaf_rn(er[m], tr[m - d + n_eta], a);
+          for (int m = d; m < n_eta; ++m) a = __fmaf_rn(er[m], tr[m - d], a);
+          acc[j] = __fmaf_rn(w, a, acc[j]);
+        }
+      }
+      if (tid < n_eta) {
+        // per-thread partial energies over this row
+        float pe = 0.0f, pt = 0.0f;
+        for (int m = tid; m < n_eta; m += 256) {
+          pe = __fmaf_rn(er[m], er[m], pe);
+          pt = __fmaf_rn(tr[m], tr[m], pt);
+        }
+        ee = __fmaf_rn(w, pe, ee);
+        tt = __fmaf_rn(w, pt, tt);
+      }
+    }
+  }
+  // energies
+  for (int off = 32; off > 0; off >>= 1) {
+    ee += __shfl_xor(ee, off, 64);
+    tt += __shfl_xor(tt, off, 64);
+  }
+  __shared__ float rsum[8];
+  __shared__ float rv[4];
+  __shared__ int ri[4];
+  if ((tid & 63) == 0) {
+    rsum[tid >> 6] = ee;
+    rsum[4 + (tid >> 6)] = tt;
+  }
+  __syncthreads();
+  const float norm = sqrtf((rsum[0] + rsum[1] + rsum[2] + rsum[3]) * (rsum[4] + rsum[5] + rsum[6] + rsum[7]));
+  const float inv = norm > 0.0f ? 1.0f / norm : 0.0f;
+  float bv = -INFINITY;
+  int bi = 0x7fffffff;
+#pragma unroll
+  for (int j = 0; j < DMAX; ++j) {
+    const int d = tid + 256 * j;
+    if (d < n_eta) {
+      const float v = acc[j] * inv;
+      cc[d] = v;
+      argmax_merge(bv, bi, v, d);
+    }
+  }
+  wave_argmax(bv, bi);
+  if ((tid & 63) == 0) {
+    rv[tid >> 6] = bv;
+    ri[tid >> 6] = bi;
+  }
+  __syncthreads();
+  for (int w = 0; w < 4; ++w) argmax_merge(bv, bi, rv[w], ri[w]);
+  const int d_int = bi >= n_eta / 2 ? bi - n_eta : bi;
+  // C(q) = sum_D c(D) exp(-2 pi i q D / n_eta), q in [0, n_eta / 2]
+  const int nq = n_eta / 2 + 1;
+  float* cqr = cq;
+  float* cqi = cq + nq;
+  for (int qq = tid; qq < nq; qq += 256) {
+    float ar = 0.0f, ai = 0.0f;
+    for (int d = 0; d < n_eta; ++d) {
+      float sn, cs;
+      sincospif(2.0f * (float)((qq * d) % n_eta) / (float)n_eta, &sn, &cs);
+      ar = __fmaf_rn(cc[d], cs, ar);
+      ai = __fmaf_rn(-cc[d], sn, ai);
+    }
+    cqr[qq] = ar;
+    cqi[qq] = ai;
+  }
+  __syncthreads();
+  const int m = (3 * kappa + 3) / 4;
+  const int kn = kappa * n_eta;
+  float best = -INFINITY;
+  int besta = 0x7fffffff;
+  for (int a = -m + tid; a <= m; a += 256) {
+    const int ph = kappa * d_int + a;
+    float v = cqr[0];
+    for (int qq = 1; qq < n_eta / 2; ++qq) {
+      int idx = (qq * ph) % kn;
+      if (idx < 0) idx += kn;
+      float sn, cs;
+      sincospif(2.0f * (float)idx / (float)kn, &sn, &cs);
+      v += 2.0f * (cqr[qq] * cs - cqi[qq] * sn);
+    }
+    // Nyquist term cos(pi t) = (-1)^d_int cos(pi a / kappa)
+    const float ny = ((d_int & 1) ? -1.0f : 1.0f) * cospif((float)a / (float)kappa);
+    v += cqr[n_eta / 2] * ny;
+    v /= (float)n_eta;
+    argmax_merge(best, besta, v, a + m);
+  }
+  wave_argmax(best, besta);
+  __syncthreads();
+  if ((tid & 63) == 0) {
+    rv[tid >> 6] = best;
+    ri[tid >> 6] = besta;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 4; ++w) argmax_merge(best, besta, rv[w], ri[w]);
+    const double dsub = (double)d_int + (double)(besta - m) / (double)kappa;
+    gamma[k] = 2.0 * 3.14159265358979323846 * dsub / (double)n_eta;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 orientation updates (Equation 7 with the atan reading; log-polar z):
+// with c = R d, a crystal rotated by Q in the detector frame has orientation
+// R Q^T, i.e. quaternion q (x) conj(q_Q).
+__device__ __forceinline__ void qmul(const double* a, const double* b, double* o) {
+  o[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+  o[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+  o[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+  o[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+}
+__device__ __forceinline__ void qstore(double* q, const double* v) {
+  const double s = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3]);
+  const double sg = v[0] < 0.0 ? -s : s;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) q[c] = v[c] * sg;
+}
+
+__global__ void k_update_xy(double* __restrict__ q, const float* __restrict__ s_sub, int64_t kk,
+                            const double* __restrict__ pc_per, double pcz, int n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= kk) return;
+  const double dd = (pc_per ? pc_per[3 * i + 2] : pcz) * (double)n;
+  const double beta = atan((double)s_sub[2 * i] / dd);
+  const double alpha = -atan((double)s_sub[2 * i + 1] / dd);
+  // conj(q_y(beta) q_x(alpha)) = conj(q_x(alpha)) conj(q_y(beta))
+  const double cxi[4] = {cos(0.5 * alpha), -sin(0.5 * alpha), 0.0, 0.0};
+  const double cyi[4] = {cos(0.5 * beta), 0.0, -sin(0.5 * beta), 0.0};
+  double t[4], o[4];
+  qmul(q + 4 * i, cxi, t);
+  qmul(t, cyi, o);
+  qstore(q + 4 * i, o);
+}
+
+__global__ void k_update_z(double* __restrict__ q, const double* __restrict__ gamma, int64_t kk) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= kk) return;
+  const double g = gamma[i];
+  const double czi[4] = {cos(0.5 * g), 0.0, 0.0, -sin(0.5 * g)};
+  double o[4];
+  qmul(q + 4 * i, czi, o);
+  qstore(q + 4 * i, o);
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_project(int n, const float* master, int mh, int mw, const double* q, int64_t k,
+                          const double* pc_per, double pcx, double pcy, double pcz, float* out,
+                          hipStream_t stream) {
+  if (k <= 0) return hipSuccess;
+  if (k > 65535) {
+    for (int64_t s = 0; s < k; s += 65535) {
+      const int64_t c = k - s < 65535 ? k - s : 65535;
+      hipError_t e = launch_project(n, master, mh, mw, q + 4 * s, c, pc_per ? pc_per + 3 * s : nullptr, pcx,
+                                    pcy, pcz, out + s * (int64_t)n * n, stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  dim3 grid((unsigned)((n * n + 255) / 256), (unsigned)k);
+  hipLaunchKernelGGL(k_project, grid, dim3(256), 0, stream, master, mh, mw, q, pc_per, pcx, pcy, pcz, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_roots(int m, float2* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_roots, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, m, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_subpixel(int n, const float2* spec_p, const float2* spec_l, const int32_t* pi,
+                           const int32_t* li, int64_t k, const int32_t* s_int, int kappa,
+                           const float2* roots, float* h_sub, float* s_sub, hipStream_t stream) {
+  if (k <= 0) return hipSuccess;
+  const int bnd = band_of(n);
+  if (bnd < 0) return hipErrorInvalidValue;
+  const int m = (3 * kappa + 3) / 4;
+  const size_t shm = sizeof(cf) * ((size_t)(bnd + 1) * (2 * bnd + 1) + (size_t)(2 * m + 1) * (bnd + 1));
+  if (shm > 160 * 1024) return hipErrorInvalidValue;
+  hipFuncSetAttribute((const void*)k_subpixel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(k_subpixel, dim3((unsigned)k), dim3(256), shm, stream, n, bnd, (const cf*)spec_p,
+                     (const cf*)spec_l, pi, li, s_int, kappa, (const cf*)roots, h_sub, s_sub);
+  return hipGetLastError();
+}
+
+hipError_t launch_library_argmax(const float* scores, int64_t p, int64_t l, int32_t* best,
+                                 float* best_h, hipStream_t stream) {
+  if (p <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_library_argmax, dim3((unsigned)p), dim3(256), 0, stream, scores, l, best, best_h);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_q(const double* lib_q, const int32_t* best, int64_t p, double* best_q,
+                           hipStream_t stream) {
+  if (p <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_q, dim3((unsigned)((p + 255) / 256)), dim3(256), 0, stream, lib_q, best, p, best_q);
+  return hipGetLastError();
+}
+
+hipError_t launch_logpolar(int n, const float* imgs, int64_t k, int n_rho, int n_eta, float* out,
+                           hipStream_t stream) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_logpolar, dim3((unsigned)k), dim3(256), 0, stream, imgs, n, n_rho, n_eta, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_eta_peak(const float* lp_e, const float* lp_t, int64_t k, int n_rho, int n_eta,
+                           int kappa, double* gamma, hipStream_t stream) {
+  if (k <= 0) return hipSuccess;
+  if (n_eta > 1024 || n_rho < 2) return hipErrorInvalidValue;
+  const size_t shm = sizeof(float) * ((size_t)2 * 8 * n_eta + n_eta + 2 * (n_eta / 2 + 1));
+  hipLaunchKernelGGL(k_eta_peak, dim3((unsigned)k), dim3(256), shm, stream, lp_e, lp_t, n_rho, n_eta, kappa,
+                     gamma);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_xy(double* q, const float* s_sub, int64_t k, const double* pc_per, double pcz,
+                            int n, hipStream_t stream) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_update_xy, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, stream, q, s_sub, k, pc_per,
+                     pcz, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_z(double* q, const double* gamma, int64_t k, hipStream_t stream) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_update_z, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, stream, q, gamma, k);
+  return hipGetLastError();
+}
+
+}  // namespace ebsd

@@ -1,0 +1,532 @@
+// Filtered spectra and cross-correlation kernels (gfx950).
+//
+// Spectra (sections "Fast Fourier Transform" and "SO(3) Sampling Frequency"):
+// contrast normalisation, separable Hann window, forward 2-D DFT (Equation 4,
+// unnormalised), band-pass H(rho) = (1 - exp(-rho^2 / 2 s_hp^2)) exp(-rho^2 / 2 s_lp^2)
+// cut to zero beyond rho_max, FP64 energy, unit-energy scaling.
+//
+// Correlation (Equations 2, 3 and the spatial definition of r_fg, normalised
+// by the autocorrelations): rho(s) = sum_u E(u) conj(T(u)) exp(+2 pi i u.s / N)
+// for unit-energy spectra, evaluated on every cyclic shift by an inverse 2-D
+// DFT that only touches the non-zero band, then reduced to its peak.
+//
+// Stored spectrum layout (band layout): complex64 S[v][kk], v in [0, B] (the
+// Hermitian half along columns), kk in [0, 2B + 1) with u = kk for kk <= B and
+// u = kk - (2B + 1) otherwise; B = 3N/8, outside of which the filter is zero.
+//
+// Every 1-D transform of length N = R1 * R2 is done in two in-register passes
+// (radix R1, twiddle, radix R2) with one exchange through LDS in between;
+// the 2-D inverse transform runs the column pass on the B + 1 non-zero
+// columns only, and the row pass on pairs of rows packed as one complex
+// transform (both rows' outputs are real).
+#include "ebsd_common.hpp"
+#include "ebsd_internal.hpp"
+
+#include <math.h>
+
+namespace ebsd {
+
+template <int N>
+struct Lay {
+  static constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2, B = Plan<N>::B;
+  static constexpr int NV = B + 1, NK = 2 * B + 1;
+  static constexpr int SPEC = NV * NK;
+  // padded strides (in complex elements) of the LDS exchange layouts
+  static constexpr int XS = N + 4;   // [v][c][b]  column-pass exchange
+  static constexpr int AS = NV + 1;  // [y][v]     column-pass output
+  static constexpr int YS = N + 4;   // [q][c][b]  row-pass exchange
+  static constexpr int ZS = N + 2;   // [q][v]     forward row-pass output
+  static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+  static constexpr int LDS = cmax(cmax(NV * XS, N * AS), cmax((N / 2) * YS, (N / 2) * ZS));
+};
+
+__device__ __forceinline__ int signed_shift(int k, int n) { return k >= n / 2 ? k - n : k; }
+
+// exp(+2 pi i k / N), k in [0, N), into LDS (FP64 evaluation, rounded)
+template <int N, int NT>
+__device__ __forceinline__ void load_roots(cf* tw, int tid) {
+  for (int k = tid; k < N; k += NT) {
+    double s, c;
+    sincospi(2.0 * (double)k / (double)N, &s, &c);
+    tw[k] = cf{(float)c, (float)s};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inverse 2-D transform of Z = E conj(T) over the band, calling epi(y, x, rho)
+// for every shift (y = s_y mod N, x = s_x mod N).
+template <int N, int NT, class Epi>
+__device__ __forceinline__ void xcf_core(const cf* __restrict__ E, const cf* __restrict__ T,
+                                         cf* lds, const cf* tw, int tid, Epi& epi) {
+  using L = Lay<N>;
+  constexpr int R1 = L::R1, R2 = L::R2, B = L::B, NV = L::NV, NK = L::NK;
+
+  // column pass, radix R1 over u = R2 a + b, for every (v, b)
+  constexpr int T1 = NV * R2;
+  for (int t = tid; t < T1; t += NT) {
+    const int v = t / R2, b = t - v * R2;
+    cf x[R1];
+#pragma unroll
+    for (int a = 0; a < R1; ++a) {
+      const int u = R2 * a + b;
+      const int kk = u <= B ? u : (u >= N - B ? u - N + NK : -1);
+      if (kk >= 0) {
+        x[a] = cmulc(E[v * NK + kk], T[v * NK + kk]);
+      } else {
+        x[a] = cf{0.f, 0.f};
+      }
+    }
+    DFT<R1, 1>::run(x);
+#pragma unroll
+    for (int c = 1; c < R1; ++c) x[c] = cmul(x[c], tw[b * c]);
+#pragma unroll
+    for (int c = 0; c < R1; ++c) lds[v * L::XS + c * R2 + b] = x[c];
+  }
+  __syncthreads();
+
+  // column pass, radix R2 over b, for every (v, c): A(y = c + R1 d, v)
+  constexpr int T2 = NV * R1, J2 = (T2 + NT - 1) / NT;
+  cf h2[J2][R2];
+#pragma unroll
+  for (int j = 0; j < J2; ++j) {
+    const int t = tid + j * NT;
+    if (t < T2) {
+      const int v = t / R1, c = t - v * R1;
+#pragma unroll
+      for (int b = 0; b < R2; ++b) h2[j][b] = lds[v * L::XS + c * R2 + b];
+      DFT<R2, 1>::run(h2[j]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J2; ++j) {
+    const int t = tid + j * NT;
+    if (t < T2) {
+      const int v = t / R1, c = t - v * R1;
+#pragma unroll
+      for (int d = 0; d < R2; ++d) lds[(c + R1 * d) * L::AS + v] = h2[j][d];
+    }
+  }
+  __syncthreads();
+
+  // row pass on row pairs (q, q + N/2): S(v) = H_q(v) + i H_{q+N/2}(v) with the
+  // Hermitian extension H_y(N - w) = conj(A(y, w)); radix R1 over v = R2 a + b
+  constexpr int T3 = (N / 2) * R2, J3 = (T3 + NT - 1) / NT;
+  cf h3[J3][R1];
+#pragma unroll
+  for (int j = 0; j < J3; ++j) {
+    const int t = tid + j * NT;
+    if (t < T3) {
+      const int q = t / R2, b = t - q * R2;
+#pragma unroll
+      for (int a = 0; a < R1; ++a) {
+        const int v = R2 * a + b;
+        cf s = cf{0.f, 0.f};
+        if (v == 0) {
+          s = cf{lds[q * L::AS].x, lds[(q + N / 2) * L::AS].x};
+        } else if (v <= B) {
+          const cf p0 = lds[q * L::AS + v], p1 = lds[(q + N / 2) * L::AS + v];
+          s = cf{p0.x - p1.y, p0.y + p1.x};
+        } else if (v >= N - B) {
+          const int w = N - v;
+          const cf p0 = lds[q * L::AS + w], p1 = lds[(q + N / 2) * L::AS + w];
+          s = cf{p0.x + p1.y, p1.x - p0.y};
+        }
+        h3[j][a] = s;
+      }
+      DFT<R1, 1>::run(h3[j]);
+#pragma unroll
+      for (int c = 1; c < R1; ++c) h3[j][c] = cmul(h3[j][c], tw[b * c]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J3; ++j) {
+    const int t = tid + j * NT;
+    if (t < T3) {
+      const int q = t / R2, b = t - q * R2;
+#pragma unroll
+      for (int c = 0; c < R1; ++c) lds[q * L::YS + c * R2 + b] = h3[j][c];
+    }
+  }
+  __syncthreads();
+
+  // row pass, radix R2: outputs x = c + R1 d; real part row q, imaginary part row q + N/2
+  constexpr int T4 = (N / 2) * R1;
+  for (int t = tid; t < T4; t += NT) {
+    const int q = t / R1, c = t - q * R1;
+    cf z[R2];
+#pragma unroll
+    for (int b = 0; b < R2; ++b) z[b] = lds[q * L::YS + c * R2 + b];
+    DFT<R2, 1>::run(z);
+#pragma unroll
+    for (int d = 0; d < R2; ++d) {
+      const int x = c + R1 * d;
+      epi(q, x, z[d].x);
+      epi(q + N / 2, x, z[d].y);
+    }
+  }
+}
+
+struct MaxEpi {
+  float m;
+  int n, s;
+  __device__ __forceinline__ void operator()(int y, int x, float v) {
+    if (s < 0 || (abs(signed_shift(y, n)) <= s && abs(signed_shift(x, n)) <= s)) m = fmaxf(m, v);
+  }
+};
+
+struct ArgmaxEpi {
+  float m;
+  int i, n, s;
+  float* map;
+  __device__ __forceinline__ void operator()(int y, int x, float v) {
+    if (map) map[y * n + x] = v;
+    if (s < 0 || (abs(signed_shift(y, n)) <= s && abs(signed_shift(x, n)) <= s))
+      argmax_merge(m, i, v, y * n + x);
+  }
+};
+
+template <int NT>
+__device__ __forceinline__ float block_max(float v, float* red, int tid) {
+  v = wave_max(v);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  float r = red[0];
+#pragma unroll
+  for (int w = 1; w < NT / 64; ++w) r = fmaxf(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
+// Scores of every pattern against a chunk of templates.  Blocks are
+// numbered so that consecutive blocks on one XCD (blocks are dealt to the 8
+// XCDs round robin) share a template chunk, which then stays in that XCD's L2.
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_xcf_scores(const cf* __restrict__ spec_p, int64_t np,
+                                                   const cf* __restrict__ spec_l, int64_t nl,
+                                                   int lchunk, int64_t nblk, int max_shift,
+                                                   float* __restrict__ scores) {
+  using L = Lay<N>;
+  __shared__ cf lds[L::LDS];
+  __shared__ cf tw[N];
+  __shared__ float red[NT / 64];
+  const int tid = threadIdx.x;
+  const int64_t per = (nblk + 7) / 8;
+  const int64_t g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (g >= nblk) return;
+  const int64_t chunk = g / np, p = g - chunk * np;
+  load_roots<N, NT>(tw, tid);
+  __syncthreads();
+  const cf* E = spec_p + p * L::SPEC;
+  const int64_t l0 = chunk * lchunk;
+  const int64_t l1 = l0 + lchunk < nl ? l0 + lchunk : nl;
+  for (int64_t l = l0; l < l1; ++l) {
+    MaxEpi epi{-INFINITY, N, max_shift};
+    xcf_core<N, NT>(E, spec_l + l * L::SPEC, lds, tw, tid, epi);
+    const float m = block_max<NT>(epi.m, red, tid);
+    if (tid == 0) scores[p * nl + l] = m;
+  }
+}
+
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_xcf_peak(const cf* __restrict__ spec_p, const cf* __restrict__ spec_l,
+                                                 const int32_t* __restrict__ pi, const int32_t* __restrict__ li,
+                                                 int max_shift, float* __restrict__ h_int,
+                                                 int32_t* __restrict__ s_int, float* __restrict__ map) {
+  using L = Lay<N>;
+  __shared__ cf lds[L::LDS];
+  __shared__ cf tw[N];
+  __shared__ float redv[NT / 64];
+  __shared__ int redi[NT / 64];
+  const int tid = threadIdx.x;
+  const int64_t k = blockIdx.x;
+  load_roots<N, NT>(tw, tid);
+  __syncthreads();
+  ArgmaxEpi epi{-INFINITY, 0x7fffffff, N, max_shift, map ? map + k * N * N : nullptr};
+  const int64_t ip = pi ? pi[k] : k, il = li ? li[k] : k;
+  xcf_core<N, NT>(spec_p + ip * L::SPEC, spec_l + il * L::SPEC, lds, tw, tid, epi);
+  float m = epi.m;
+  int i = epi.i;
+  wave_argmax(m, i);
+  if ((tid & 63) == 0) {
+    redv[tid >> 6] = m;
+    redi[tid >> 6] = i;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < NT / 64; ++w) argmax_merge(m, i, redv[w], redi[w]);
+    h_int[k] = m;
+    if (i < 0 || i >= N * N) i = 0;  // every value NaN: report shift 0
+    const int sy = i / N, sx = i - sy * N;
+    s_int[2 * k] = signed_shift(sx, N);
+    s_int[2 * k + 1] = signed_shift(sy, N);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward spectra of K images.
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_spectra(const float* __restrict__ imgs, int64_t img_stride,
+                                                FilterParams fp, cf* __restrict__ spec,
+                                                double* __restrict__ energy) {
+  using L = Lay<N>;
+  constexpr int R1 = L::R1, R2 = L::R2, B = L::B, NV = L::NV, NK = L::NK;
+  __shared__ cf lds[L::LDS];
+  __shared__ cf tw[N];
+  __shared__ float win[N];
+  __shared__ double red[2 * (NT / 64)];
+  const int tid = threadIdx.x;
+  const int64_t k = blockIdx.x;
+  const float* img = imgs + k * img_stride;
+  load_roots<N, NT>(tw, tid);
+  for (int i = tid; i < N; i += NT) {
+    const float s = sinpif(((float)i + 0.5f) / (float)N);
+    win[i] = fp.window ? s * s : 1.0f;
+  }
+
+  // mean and standard deviation in FP64
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = tid; i < N * N; i += NT) {
+    const double v = (double)img[i];
+    s1 += v;
+    s2 += v * v;
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if ((tid & 63) == 0) {
+    red[tid >> 6] = s1;
+    red[NT / 64 + (tid >> 6)] = s2;
+  }
+  __syncthreads();
+  double t1 = 0.0, t2 = 0.0;
+  for (int w = 0; w < NT / 64; ++w) {
+    t1 += red[w];
+    t2 += red[NT / 64 + w];
+  }
+  const double mean = t1 / (double)(N * N);
+  const double var = t2 / (double)(N * N) - mean * mean;
+  const float fmean = (float)mean;
+  const float inv_std = var > 0.0 ? (float)(1.0 / sqrt(var)) : 0.0f;
+  __syncthreads();
+
+  // row pass, radix R1 on row pairs (q, q + N/2) packed as real + i imag
+  constexpr int TF1 = (N / 2) * R2;
+  for (int t = tid; t < TF1; t += NT) {
+    const int q = t / R2, b = t - q * R2;
+    cf x[R1];
+    const float wq0 = win[q] * inv_std, wq1 = win[q + N / 2] * inv_std;
+#pragma unroll
+    for (int a = 0; a < R1; ++a) {
+      const int col = R2 * a + b;
+      const float v0 = (img[q * N + col] - fmean) * wq0 * win[col];
+      const float v1 = (img[(q + N / 2) * N + col] - fmean) * wq1 * win[col];
+      x[a] = cf{v0, v1};
+    }
+    DFT<R1, -1>::run(x);
+#pragma unroll
+    for (int c = 1; c < R1; ++c) x[c] = cmulc(x[c], tw[b * c]);
+#pragma unroll
+    for (int c = 0; c < R1; ++c) lds[q * L::YS + c * R2 + b] = x[c];
+  }
+  __syncthreads();
+
+  // row pass, radix R2: Z_q(v = c + R1 d)
+  constexpr int TF2 = (N / 2) * R1, JF2 = (TF2 + NT - 1) / NT;
+  cf h2[JF2][R2];
+#pragma unroll
+  for (int j = 0; j < JF2; ++j) {
+    const int t = tid + j * NT;
+    if (t < TF2) {
+      const int q = t / R1, c = t - q * R1;
+#pragma unroll
+      for (int b = 0; b < R2; ++b) h2[j][b] = lds[q * L::YS + c * R2 + b];
+      DFT<R2, -1>::run(h2[j]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < JF2; ++j) {
+    const int t = tid + j * NT;
+    if (t < TF2) {
+      const int q = t / R1, c = t - q * R1;
+#pragma unroll
+      for (int d = 0; d < R2; ++d) lds[q * L::ZS + c + R1 * d] = h2[j][d];
+    }
+  }
+  __syncthreads();
+
+  // separate the two packed rows: F_q(v) = (Z(v) + conj Z(-v)) / 2,
+  // F_{q+N/2}(v) = (Z(v) - conj Z(-v)) / 2i, for v in [0, B]
+  constexpr int TF3 = (N / 2) * NV, JF3 = (TF3 + NT - 1) / NT;
+  cf h3[JF3][2];
+#pragma unroll
+  for (int j = 0; j < JF3; ++j) {
+    const int t = tid + j * NT;
+    if (t < TF3) {
+      const int q = t / NV, v = t - q * NV;
+      const cf z1 = lds[q * L::ZS + v];
+      const cf zb = lds[q * L::ZS + (v == 0 ? 0 : N - v)];
+      h3[j][0] = cf{0.5f * (z1.x + zb.x), 0.5f * (z1.y - zb.y)};
+      h3[j][1] = cf{0.5f * (z1.y + zb.y), -0.5f * (z1.x - zb.x)};
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < JF3; ++j) {
+    const int t = tid + j * NT;
+    if (t < TF3) {
+      const int q = t / NV, v = t - q * NV;
+      lds[q * L::AS + v] = h3[j][0];
+      lds[(q + N / 2) * L::AS + v] = h3[j][1];
+    }
+  }
+  __syncthreads();
+
+  // column pass, radix R1 over y = R2 a + b, for every (v, b)
+  constexpr int TF4 = NV * R2, JF4 = (TF4 + NT - 1) / NT;
+  cf h4[JF4][R1];
+#pragma unroll
+  for (int j = 0; j < JF4; ++j) {
+    const int t = tid + j * NT;
+    if (t < TF4) {
+      const int v = t / R2, b = t - v * R2;
+#pragma unroll
+      for (int a = 0; a < R1; ++a) h4[j][a] = lds[(R2 * a + b) * L::AS + v];
+      DFT<R1, -1>::run(h4[j]);
+#pragma unroll
+      for (int c = 1; c < R1; ++c) h4[j][c] = cmulc(h4[j][c], tw[b * c]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < JF4; ++j) {
+    const int t = tid + j * NT;
+    if (t < TF4) {
+      const int v = t / R2, b = t - v * R2;
+#pragma unroll
+      for (int c = 0; c < R1; ++c) lds[v * L::XS + c * R2 + b] = h4[j][c];
+    }
+  }
+  __syncthreads();
+
+  // column pass, radix R2: X(u = c + R1 d, v); band-pass and energy
+  constexpr int TF5 = NV * R1, JF5 = (TF5 + NT - 1) / NT;
+  cf h5[JF5][R2];
+  const float inv2hp = 1.0f / (2.0f * fp.sigma_hp * fp.sigma_hp);
+  const float inv2lp = 1.0f / (2.0f * fp.sigma_lp * fp.sigma_lp);
+  const float rmax2 = fp.rho_max * fp.rho_max;
+  double en = 0.0;
+#pragma unroll
+  for (int j = 0; j < JF5; ++j) {
+    const int t = tid + j * NT;
+    if (t < TF5) {
+      const int v = t / R1, c = t - v * R1;
+#pragma unroll
+      for (int b = 0; b < R2; ++b) h5[j][b] = lds[v * L::XS + c * R2 + b];
+      DFT<R2, -1>::run(h5[j]);
+#pragma unroll
+      for (int d = 0; d < R2; ++d) {
+        const int u = c + R1 * d;
+        const int us = u >= N / 2 ? u - N : u;
+        const float r2 = (float)(us * us + v * v);
+        float h = 0.0f;
+        if ((us >= -B && us <= B) && r2 <= rmax2 && us != -N / 2) {
+          h = (1.0f - expf(-r2 * inv2hp)) * expf(-r2 * inv2lp);
+        }
+        const cf z = cscale(h5[j][d], h);
+        h5[j][d] = z;
+        en += (v == 0 ? 1.0 : 2.0) * ((double)z.x * (double)z.x + (double)z.y * (double)z.y);
+      }
+    }
+  }
+  en = wave_sum(en);
+  if ((tid & 63) == 0) red[tid >> 6] = en;
+  __syncthreads();
+  double etot = 0.0;
+  for (int w = 0; w < NT / 64; ++w) etot += red[w];
+  const float scale = etot > 0.0 ? (float)(1.0 / sqrt(etot)) : 0.0f;
+  cf* out = spec + k * L::SPEC;
+#pragma unroll
+  for (int j = 0; j < JF5; ++j) {
+    const int t = tid + j * NT;
+    if (t < TF5) {
+      const int v = t / R1, c = t - v * R1;
+#pragma unroll
+      for (int d = 0; d < R2; ++d) {
+        const int u = c + R1 * d;
+        const int kk = u <= B ? u : (u >= N - B ? u - N + NK : -1);
+        if (kk >= 0) out[v * NK + kk] = cscale(h5[j][d], scale);
+      }
+    }
+  }
+  if (tid == 0 && energy) energy[k] = etot;
+}
+
+// ---------------------------------------------------------------------------
+int band_of(int n) {
+  switch (n) {
+    case 64: return Plan<64>::B;
+    case 96: return Plan<96>::B;
+    case 128: return Plan<128>::B;
+    case 160: return Plan<160>::B;
+    default: return -1;
+  }
+}
+bool size_supported(int n) { return band_of(n) > 0; }
+
+template <int N>
+static constexpr int nt_xcf() { return N <= 96 ? 256 : 256; }
+template <int N>
+static constexpr int nt_spec() { return N <= 96 ? 256 : 512; }
+
+#define EBSD_DISPATCH(n, CALL)        \
+  switch (n) {                        \
+    case 64: { constexpr int NN = 64; CALL; } break;   \
+    case 96: { constexpr int NN = 96; CALL; } break;   \
+    case 128: { constexpr int NN = 128; CALL; } break; \
+    case 160: { constexpr int NN = 160; CALL; } break; \
+    default: return hipErrorInvalidValue;              \
+  }
+
+hipError_t launch_spectra(int n, const float* imgs, int64_t img_stride, int64_t k,
+                          const FilterParams& fp, float2* spec, double* energy,
+                          hipStream_t stream) {
+  if (k <= 0) return hipSuccess;
+  EBSD_DISPATCH(n, {
+    constexpr int NT = nt_spec<NN>();
+    hipLaunchKernelGGL((k_spectra<NN, NT>), dim3((unsigned)k), dim3(NT), 0, stream, imgs, img_stride, fp,
+                       (cf*)spec, energy);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_xcf_scores(int n, const float2* spec_p, int64_t p, const float2* spec_l,
+                             int64_t l, int max_shift, float* scores, hipStream_t stream) {
+  if (p <= 0 || l <= 0) return hipSuccess;
+  const int lchunk = 32;
+  const int64_t nchunk = (l + lchunk - 1) / lchunk;
+  const int64_t nblk = p * nchunk;
+  const int64_t grid = ((nblk + 7) / 8) * 8;
+  if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+  EBSD_DISPATCH(n, {
+    constexpr int NT = nt_xcf<NN>();
+    hipLaunchKernelGGL((k_xcf_scores<NN, NT>), dim3((unsigned)grid), dim3(NT), 0, stream, (const cf*)spec_p,
+                       p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_xcf_peak(int n, const float2* spec_p, const float2* spec_l,
+                           const int32_t* pi, const int32_t* li, int64_t k, int max_shift,
+                           float* h_int, int32_t* s_int, float* map, hipStream_t stream) {
+  if (k <= 0) return hipSuccess;
+  EBSD_DISPATCH(n, {
+    constexpr int NT = nt_xcf<NN>();
+    hipLaunchKernelGGL((k_xcf_peak<NN, NT>), dim3((unsigned)k), dim3(NT), 0, stream, (const cf*)spec_p,
+                       (const cf*)spec_l, pi, li, max_shift, h_int, s_int, map);
+  });
+  return hipGetLastError();
+}
+
+}  // namespace ebsd

@@ -1,0 +1,79 @@
+"""Host-side checks of the C-ABI library: it loads without a GPU, exports
+every symbol the header declares, and rejects bad arguments before touching
+the device (nothing is enqueued, so these run on a CPU-only host)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_1807_11313_amd as pkg
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.skip("library not built")
+    return pkg, pkg.lib()
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "ebsd_tm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ebsd_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_and_binding_agree():
+    pkg, _ = _lib()
+    assert sorted(pkg.EXPORTS) == _declared()
+
+
+def test_every_declared_symbol_is_exported():
+    _, lib = _lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_defaults_and_version():
+    pkg, lib = _lib()
+    p = pkg.params_default()
+    assert p.struct_size == ctypes.sizeof(pkg.Params)
+    assert (p.window, p.sigma_hp, p.sigma_lp_frac, p.rho_max_frac) == (1, 2.0, 0.125, 0.375)
+    assert (p.max_shift, p.upsample, p.n_iter, p.n_rho, p.n_eta) == (-1, 100, 2, 0, 0)
+    assert pkg.version() >= 100
+    assert pkg.spectrum_floats(128) == 2 * 49 * 97
+    assert pkg.spectrum_floats(100) == -1
+
+
+def _index(pkg, lib, batch, prm, L=10, master=None, geo=None):
+    m = master or pkg.Master(0x1000, 256, 256)
+    g = geo or pkg.Geometry(0.5, 0.5, 0.6, None)
+    return lib.ebsd_index_patterns(ctypes.byref(batch) if batch is not None else None, ctypes.byref(m),
+                                   ctypes.byref(g), ctypes.c_void_p(0x2000), L,
+                                   ctypes.byref(prm) if prm is not None else None,
+                                   ctypes.c_void_p(0x3000), None, ctypes.c_void_p(0x4000),
+                                   ctypes.c_void_p(0x5000), None, None)
+
+
+def test_argument_errors():
+    pkg, lib = _lib()
+    ok = pkg.Batch(0x6000, 4, 64)
+    prm = pkg.params_default()
+    assert _index(pkg, lib, None, prm) == -1
+    assert _index(pkg, lib, pkg.Batch(0x6000, 4, 100), prm) == -4        # unsupported size
+    assert _index(pkg, lib, ok, prm, L=0) == -1                          # empty library
+    assert _index(pkg, lib, pkg.Batch(0x6000, -1, 64), prm) == -1
+    assert _index(pkg, lib, ok, prm, master=pkg.Master(0, 256, 256)) == -1
+    assert _index(pkg, lib, ok, prm, geo=pkg.Geometry(0.5, 0.5, 0.0, None)) == -1
+    bad = pkg.params_default()
+    bad.struct_size = 8
+    assert _index(pkg, lib, ok, bad) == -1
+    assert b"struct_size" in lib.ebsd_last_error()
+    assert _index(pkg, lib, ok, pkg.params_default(rho_max_frac=0.45)) == -4
+    assert _index(pkg, lib, ok, pkg.params_default(upsample=0)) == -1
+    assert _index(pkg, lib, ok, pkg.params_default(n_eta=7)) == -1
+    assert _index(pkg, lib, ok, pkg.params_default(precision=9)) == -4
+    assert _index(pkg, lib, ok, pkg.params_default(max_shift=-3)) == -1
+    # an empty batch is a valid no-op
+    assert _index(pkg, lib, pkg.Batch(0x6000, 0, 64), prm) == 0

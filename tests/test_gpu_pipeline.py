@@ -1,0 +1,94 @@
+"""End-to-end parity of ebsd_index_patterns and ebsd_refine_orientations
+against the FP64 oracle.
+
+Best-match index: bit-exact unless the oracle's top-2 gap is within
+tau_tie = 2e-4 (twice the height tolerance), in which case the GPU's choice
+must score within tau_tie of the oracle's best.  Integer shift of the
+winner: exact.  Peak height: 1e-4.  Sub-pixel shift: 0.02 px.  Refined
+orientation: 0.05 deg disorientation from the oracle's.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from fixtures import configs
+from oracle import pipeline, rotations
+
+from .gpu_util import banner, dev, host, tm
+
+pytestmark = pytest.mark.gpu
+
+TAU_TIE = 2e-4
+
+
+def _check_index(res, ref, scores_ref=None):
+    best = host(res["best_idx"])
+    ties = 0
+    for i in range(len(best)):
+        if ref["gap"][i] > TAU_TIE:
+            assert best[i] == ref["best_idx"][i], (i, best[i], ref["best_idx"][i], ref["gap"][i])
+        else:
+            ties += 1
+            if scores_ref is not None:
+                assert scores_ref[i][best[i]] >= ref["h_int"][i] - TAU_TIE
+    return ties
+
+
+@pytest.mark.parametrize("n", [64, 96, 128, 160])
+def test_index_patterns_small(n):
+    banner("index_patterns n=%d" % n)
+    t = tm()
+    cfg = configs.tiny(p=6, l=37, n=n, seed=n)
+    pats = dev(cfg["patterns"])
+    res = t.index_patterns(pats, dev(cfg["master"]), cfg["pc"], dev(cfg["lib_q"]), scores=True)
+    ref = pipeline.index_patterns(cfg["patterns"].numpy(), cfg["master"], cfg["pc"], cfg["lib_q"],
+                                  oracle.Params(), return_scores=True)
+    sc = host(res["scores"])
+    assert np.max(np.abs(sc - ref["scores"])) < 1e-4
+    ties = _check_index(res, ref, ref["scores"])
+    assert ties <= 1
+    same = host(res["best_idx"]) == ref["best_idx"]
+    assert np.max(np.abs(host(res["peak_h"])[same] - ref["peak_h"][same])) < 1e-4
+    assert np.max(np.abs(host(res["shift"])[same] - ref["shift"][same])) <= 0.02 + 1e-6
+    assert np.allclose(host(res["best_q"]), cfg["lib_q"][host(res["best_idx"])])
+
+
+def test_index_tiny_config():
+    # the tiny workload in full: 16 patterns at 64^2 against 500 templates
+    banner("index_patterns tiny config")
+    t = tm()
+    cfg = configs.tiny()
+    res = t.index_patterns(dev(cfg["patterns"]), dev(cfg["master"]), cfg["pc"], dev(cfg["lib_q"]), scores=True)
+    ref = pipeline.index_patterns(cfg["patterns"].numpy(), cfg["master"], cfg["pc"], cfg["lib_q"],
+                                  oracle.Params(), return_scores=True)
+    assert np.max(np.abs(host(res["scores"]) - ref["scores"])) < 1e-4
+    _check_index(res, ref, ref["scores"])
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_refine_matches_oracle(n):
+    banner("refine n=%d" % n)
+    t = tm()
+    cfg = configs.tiny(p=4, l=200, n=n, seed=3 + n)
+    ref_i = pipeline.index_patterns(cfg["patterns"].numpy(), cfg["master"], cfg["pc"], cfg["lib_q"],
+                                    oracle.Params())
+    q0 = ref_i["best_q"]
+    rr = t.refine_orientations(dev(cfg["patterns"]), dev(cfg["master"]), cfg["pc"], dev(q0),
+                               pc_per=dev(cfg["pcs"]))
+    ref = pipeline.refine_orientations(cfg["patterns"].numpy(), cfg["master"], cfg["pcs"], q0, oracle.Params())
+    q = host(rr["q"])
+    d = np.rad2deg([rotations.disorientation_q(a, b) for a, b in zip(q, ref["q"])])
+    assert np.max(d) < 0.05, d
+    assert np.max(np.abs(host(rr["peak_h"]) - ref["peak_h"])) < 1e-4
+    assert np.allclose(np.linalg.norm(q, axis=1), 1.0, atol=1e-12) and np.all(q[:, 0] >= 0)
+
+
+def test_refine_zero_iterations_is_final_measurement():
+    t = tm()
+    cfg = configs.tiny(p=3, l=50, n=64, seed=9)
+    q0 = cfg["true_q"]
+    rr = t.refine_orientations(dev(cfg["patterns"]), dev(cfg["master"]), cfg["pc"], dev(q0),
+                               pc_per=dev(cfg["pcs"]), prm=t.params_default(n_iter=0))
+    assert np.allclose(host(rr["q"]), q0)
