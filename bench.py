@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--patterns", type=int, default=10000, help="map size (must be a square)")
     ap.add_argument("--library", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one elementwise copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path has no multi-GPU form in this build "
@@ -87,6 +89,13 @@ def main():
     side = int(round(args.patterns ** 0.5))
     n = 128
     dev = torch.device("cuda:0")
+    if args.copy_calibration_mib > 0:
+        # one read and one write of exactly this many bytes, as a single kernel
+        src = torch.ones(args.copy_calibration_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     print("[bench] generating map workload %dx%d patterns at %d^2, library %d" % (side, side, n, args.library),
           file=sys.stderr, flush=True)
     cfg = configs.map_grid(rows=side, cols=side, n=n, l=args.library, device=dev, dtype=torch.float32)

@@ -174,8 +174,8 @@ int ebsd_project_templates(const ebsd_master* mp, const double* q, int64_t K, in
  * Filtered unit-energy spectra of K images of side n (device float32
  * [K][n][n]): contrast normalised, windowed, 2-D DFT (Equation 4 without
  * the unitary factor), band-passed, scaled to unit energy.
- * spec: device complex64 (interleaved float32 pairs) [K][B+1][2B+1],
- * B = 3n/8, element [v][kk] = X(u, v) with u = kk (kk <= B) or kk - 2B - 1;
+ * spec: device complex64 (interleaved float32 pairs) [K][2B+1][B+1],
+ * B = 3n/8, element [kk][v] = X(u, v) with u = kk (kk <= B) or kk - 2B - 1;
  * energy: device float64 [K], the pre-scaling energy sum |X'|^2 over the
  * full spectrum (may be NULL).
  */

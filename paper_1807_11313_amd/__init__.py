@@ -268,10 +268,10 @@ def timing_read():
 
 
 def spectra_to_complex(spec, n):
-    """View a [K][floats] spectrum tensor as complex [K][B+1][2B+1] (host numpy)."""
+    """Host copy of a [K][floats] spectrum tensor (stored [kk][v]) as complex [K][v][kk]."""
     b = 3 * n // 8
-    a = spec.detach().cpu().numpy().reshape(spec.shape[0], b + 1, 2 * b + 1, 2)
-    return a[..., 0] + 1j * a[..., 1]
+    a = spec.detach().cpu().numpy().reshape(spec.shape[0], 2 * b + 1, b + 1, 2)
+    return np.swapaxes(a[..., 0] + 1j * a[..., 1], 1, 2)
 
 
 def band_to_full(band, n):

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k_subpixel(int n, int bnd, const cf* __re
   const int m = (3 * kappa + 3) / 4;  // ceil(0.75 kappa)
   const int msz = 2 * m + 1;
   const int kn = kappa * n;
-  cf* z = sm;            // [nv][nk]
+  cf* z = sm;            // [nk][nv]
   cf* g = sm + spec;     // [msz][nv]
   const int tid = threadIdx.x;
   const int64_t k = blockIdx.x;
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void k_subpixel(int n, int bnd, const cf* __re
       int idx = (u * ph) % kn;
       if (idx < 0) idx += kn;
       const cf w = roots[idx];
-      const cf zz = z[v * nk + kk];
+      const cf zz = z[kk * nv + v];
       ar = __fmaf_rn(zz.x, w.x, __fmaf_rn(-zz.y, w.y, ar));
       ai = __fmaf_rn(zz.x, w.y, __fmaf_rn(zz.y, w.x, ai));
     }

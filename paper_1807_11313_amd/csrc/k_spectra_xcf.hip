@@ -10,9 +10,10 @@
 // for unit-energy spectra, evaluated on every cyclic shift by an inverse 2-D
 // DFT that only touches the non-zero band, then reduced to its peak.
 //
-// Stored spectrum layout (band layout): complex64 S[v][kk], v in [0, B] (the
-// Hermitian half along columns), kk in [0, 2B + 1) with u = kk for kk <= B and
-// u = kk - (2B + 1) otherwise; B = 3N/8, outside of which the filter is zero.
+// Stored spectrum layout (band layout): complex64 S[kk][v], kk in [0, 2B + 1)
+// with u = kk for kk <= B and u = kk - (2B + 1) otherwise (rows), v in [0, B]
+// (the Hermitian half along columns, contiguous); B = 3N/8, outside of which
+// the filter is zero.
 //
 // Every 1-D transform of length N = R1 * R2 is done in two in-register passes
 // (radix R1, twiddle, radix R2) with one exchange through LDS in between;
@@ -71,7 +72,7 @@ __device__ __forceinline__ void xcf_core(const cf* __restrict__ E, const cf* __r
       const int u = R2 * a + b;
       const int kk = u <= B ? u : (u >= N - B ? u - N + NK : -1);
       if (kk >= 0) {
-        x[a] = cmulc(E[v * NK + kk], T[v * NK + kk]);
+        x[a] = cmulc(E[kk * NV + v], T[kk * NV + v]);
       } else {
         x[a] = cf{0.f, 0.f};
       }
@@ -261,6 +262,165 @@ __global__ __launch_bounds__(NT) void k_xcf_peak(const cf* __restrict__ spec_p, 
     const int sy = i / N, sx = i - sy * N;
     s_int[2 * k] = signed_shift(sx, N);
     s_int[2 * k + 1] = signed_shift(sy, N);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Search kernel for N = 128 (R1 = 16, R2 = 8, B = 48), 8 waves per block.
+// Every phase gives each wave one radix position, so the band tests, the
+// spectrum row indices and the inter-pass twiddles are wave-uniform (scalar),
+// and lanes run along the spectrum column v or the row pair q, so every LDS
+// access is lane-contiguous.  The pattern's spectrum stays in registers
+// while the block streams its chunk of templates.
+//   phase 1  wave b, lane v:  radix 16 over u = 8a + b of E conj(T), twiddle
+//   phase 2  wave c, lane v:  radix 8 over b -> A(y = c + 16 d, v)
+//   phase 3  wave b, lane q:  radix 16 over v = 8a + b of the packed row pair
+//                             (q, q + 64), twiddle
+//   phase 4  wave c, lane q:  radix 8 over b -> rho(row q and q + 64, x = c + 16 d)
+template <int N>
+struct RootTable {
+  cf w[N];
+  constexpr RootTable() : w() {
+    for (int k = 0; k < N; ++k) {
+      w[k].x = (float)cx::cos2pi(k, N);
+      w[k].y = (float)cx::sin2pi(k, N);
+    }
+  }
+};
+__constant__ RootTable<128> c_roots128 = RootTable<128>();
+
+template <bool WINDOW>
+__global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__ spec_p, int64_t np,
+                                                          const cf* __restrict__ spec_l, int64_t nl,
+                                                          int lchunk, int64_t nblk, int max_shift,
+                                                          float* __restrict__ scores) {
+  constexpr int N = 128, R1 = 16, R2 = 8, B = 48, NV = 49;
+  constexpr int SPEC = NV * (2 * B + 1);
+  constexpr int AV = N + 1;  // A[v][y] row stride (odd: the phase-2 writes spread over banks)
+  // X [c][b][v] (R1*R2*NV), A [v][y] (NV*AV), Y [c][b][q] (R1*R2*64) share one buffer
+  constexpr int LDSN = (R1 * R2 * 64 > NV * AV) ? R1 * R2 * 64 : NV * AV;
+  __shared__ cf lds[LDSN];
+  __shared__ float red[8];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t per = (nblk + 7) / 8;
+  const int64_t g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (g >= nblk) return;
+  const int64_t chunk = g / np, p = g - chunk * np;
+  const bool vlane = lane < NV;
+
+  // inter-pass twiddles w^(wave c), c = 1..15: the same set in phases 1 and 3
+  cf tw[R1];
+#pragma unroll
+  for (int c = 0; c < R1; ++c) tw[c] = c_roots128.w[(wave * c) & (N - 1)];
+
+  // pattern spectrum values used by this lane in phase 1
+  const cf* E = spec_p + p * SPEC;
+  cf ev[R1];
+#pragma unroll
+  for (int a = 0; a < R1; ++a) {
+    const int u = R2 * a + wave;
+    const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : -1);
+    ev[a] = (kk >= 0 && vlane) ? E[kk * NV + lane] : cf{0.f, 0.f};
+  }
+
+  const int64_t l0 = chunk * lchunk;
+  const int64_t l1 = l0 + lchunk < nl ? l0 + lchunk : nl;
+  for (int64_t l = l0; l < l1; ++l) {
+    const cf* T = spec_l + l * SPEC;
+    // phase 1
+    {
+      cf x[R1];
+#pragma unroll
+      for (int a = 0; a < R1; ++a) {
+        const int u = R2 * a + wave;
+        const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : -1);
+        x[a] = (kk >= 0 && vlane) ? cmulc(ev[a], T[kk * NV + lane]) : cf{0.f, 0.f};
+      }
+      DFT<R1, 1>::run(x);
+#pragma unroll
+      for (int c = 1; c < R1; ++c) x[c] = cmul(x[c], tw[c]);
+      if (vlane) {
+#pragma unroll
+        for (int c = 0; c < R1; ++c) lds[(c * R2 + wave) * NV + lane] = x[c];
+      }
+    }
+    __syncthreads();
+    // phase 2: waves take c = wave and c = wave + 8
+    cf h[2][R2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = wave + 8 * j;
+#pragma unroll
+      for (int b = 0; b < R2; ++b) h[j][b] = vlane ? lds[(c * R2 + b) * NV + lane] : cf{0.f, 0.f};
+      DFT<R2, 1>::run(h[j]);
+    }
+    __syncthreads();
+    if (vlane) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int c = wave + 8 * j;
+#pragma unroll
+        for (int d = 0; d < R2; ++d) lds[lane * AV + c + R1 * d] = h[j][d];
+      }
+    }
+    __syncthreads();
+    // phase 3: wave b, lane q: packed rows q and q + 64
+    cf s[R1];
+#pragma unroll
+    for (int a = 0; a < R1; ++a) {
+      const int v = R2 * a + wave;
+      if (v == 0) {
+        s[a] = cf{lds[lane].x, lds[lane + 64].x};
+      } else if (v <= B) {
+        const cf p0 = lds[v * AV + lane], p1 = lds[v * AV + lane + 64];
+        s[a] = cf{p0.x - p1.y, p0.y + p1.x};
+      } else if (v >= N - B) {
+        const int w = N - v;
+        const cf p0 = lds[w * AV + lane], p1 = lds[w * AV + lane + 64];
+        s[a] = cf{p0.x + p1.y, p1.x - p0.y};
+      } else {
+        s[a] = cf{0.f, 0.f};
+      }
+    }
+    DFT<R1, 1>::run(s);
+#pragma unroll
+    for (int c = 1; c < R1; ++c) s[c] = cmul(s[c], tw[c]);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < R1; ++c) lds[(c * R2 + wave) * 64 + lane] = s[c];
+    __syncthreads();
+    // phase 4: waves take c = wave and c = wave + 8; outputs x = c + 16 d
+    float m = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = wave + 8 * j;
+      cf z[R2];
+#pragma unroll
+      for (int b = 0; b < R2; ++b) z[b] = lds[(c * R2 + b) * 64 + lane];
+      DFT<R2, 1>::run(z);
+#pragma unroll
+      for (int d = 0; d < R2; ++d) {
+        if constexpr (WINDOW) {
+          const int x = c + R1 * d;
+          const bool okx = abs(signed_shift(x, N)) <= max_shift;
+          if (okx && abs(signed_shift(lane, N)) <= max_shift) m = fmaxf(m, z[d].x);
+          if (okx && abs(signed_shift(lane + 64, N)) <= max_shift) m = fmaxf(m, z[d].y);
+        } else {
+          m = fmaxf(m, fmaxf(z[d].x, z[d].y));
+        }
+      }
+    }
+    m = wave_max(m);
+    if (lane == 0) red[wave] = m;
+    __syncthreads();
+    if (tid == 0) {
+      float r = red[0];
+#pragma unroll
+      for (int w = 1; w < 8; ++w) r = fmaxf(r, red[w]);
+      scores[p * nl + l] = r;
+    }
   }
 }
 
@@ -456,7 +616,7 @@ __global__ __launch_bounds__(NT) void k_spectra(const float* __restrict__ imgs, 
       for (int d = 0; d < R2; ++d) {
         const int u = c + R1 * d;
         const int kk = u <= B ? u : (u >= N - B ? u - N + NK : -1);
-        if (kk >= 0) out[v * NK + kk] = cscale(h5[j][d], scale);
+        if (kk >= 0) out[kk * NV + v] = cscale(h5[j][d], scale);
       }
     }
   }
@@ -509,6 +669,15 @@ hipError_t launch_xcf_scores(int n, const float2* spec_p, int64_t p, const float
   const int64_t nblk = p * nchunk;
   const int64_t grid = ((nblk + 7) / 8) * 8;
   if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (n == 128) {
+    if (max_shift < 0)
+      hipLaunchKernelGGL((k_xcf_scores128<false>), dim3((unsigned)grid), dim3(512), 0, stream, (const cf*)spec_p, p,
+                         (const cf*)spec_l, l, lchunk, nblk, max_shift, scores);
+    else
+      hipLaunchKernelGGL((k_xcf_scores128<true>), dim3((unsigned)grid), dim3(512), 0, stream, (const cf*)spec_p, p,
+                         (const cf*)spec_l, l, lchunk, nblk, max_shift, scores);
+    return hipGetLastError();
+  }
   EBSD_DISPATCH(n, {
     constexpr int NT = nt_xcf<NN>();
     hipLaunchKernelGGL((k_xcf_scores<NN, NT>), dim3((unsigned)grid), dim3(NT), 0, stream, (const cf*)spec_p,
