@@ -83,6 +83,8 @@ int resolve_params(const ebsd_params* in, int n, ebsd_params* out) {
   if (out->rho_max_frac > 0.375 + 1e-12)
     return fail(EBSD_E_UNSUPPORTED, "rho_max_frac above 3/8 is outside the stored band");
   if (out->upsample < 1 || out->upsample > 128) return fail(EBSD_E_INVALID, "upsample must be in [1, 128]");
+  if (size_supported(n) && subpixel_lds_bytes(n, out->upsample) > 160 * 1024)
+    return fail(EBSD_E_UNSUPPORTED, "upsample too large for this pattern size");
   if (out->n_iter < 0 || out->n_iter > 64) return fail(EBSD_E_INVALID, "n_iter must be in [0, 64]");
   if (out->n_rho == 0) out->n_rho = n / 2;
   if (out->n_eta == 0) out->n_eta = 2 * n;
@@ -272,9 +274,8 @@ int ebsd_xcf_subpixel(const float* spec_p, const float* spec_l, const int32_t* p
   if (!spec_p || !spec_l || !s_int || !h_sub || !s_sub) return fail(EBSD_E_INVALID, "null pointer");
   hipStream_t st = (hipStream_t)stream;
   Scratch ws(st);
-  const int kn = p.upsample * n;
-  EBSD_ALLOC(roots, float2, kn, ws);
-  EBSD_TRY(launch_roots(kn, roots, st), "roots");
+  EBSD_ALLOC(roots, float2, subpixel_table_size(n, p.upsample), ws);
+  EBSD_TRY(launch_subpixel_tables(n, p.upsample, roots, st), "subpixel tables");
   EBSD_TRY(launch_subpixel(n, (const float2*)spec_p, (const float2*)spec_l, pi, li, K, s_int, p.upsample, roots,
                            h_sub, s_sub, st),
            "subpixel");
@@ -336,8 +337,7 @@ int ebsd_index_patterns(const ebsd_batch* pats, const ebsd_master* mp, const ebs
   EBSD_ALLOC(h_int, float, P, ws);
   EBSD_ALLOC(s_int, int32_t, 2 * P, ws);
   EBSD_ALLOC(h_tmp, float, P, ws);
-  const int kn = p.upsample * n;
-  EBSD_ALLOC(roots, float2, kn, ws);
+  EBSD_ALLOC(roots, float2, subpixel_table_size(n, p.upsample), ws);
 
   EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, lib_q, L, nullptr, geo->pcx, geo->pcy, geo->pcz, tmpl, st),
            "project");
@@ -347,7 +347,7 @@ int ebsd_index_patterns(const ebsd_batch* pats, const ebsd_master* mp, const ebs
   EBSD_TRY(launch_library_argmax(sc_out, P, L, best_idx, h_int, st), "library_argmax");
   EBSD_TRY(launch_xcf_peak(n, spec_p, spec_l, nullptr, best_idx, P, p.max_shift, h_tmp, s_int, nullptr, st),
            "xcf_peak");
-  EBSD_TRY(launch_roots(kn, roots, st), "roots");
+  EBSD_TRY(launch_subpixel_tables(n, p.upsample, roots, st), "subpixel tables");
   EBSD_TRY(launch_subpixel(n, spec_p, spec_l, nullptr, best_idx, P, s_int, p.upsample, roots, peak_h, shift, st),
            "subpixel");
   if (best_q) EBSD_TRY(launch_gather_q(lib_q, best_idx, P, best_q, st), "gather_q");
@@ -387,11 +387,10 @@ int ebsd_refine_orientations(const ebsd_batch* pats, const ebsd_master* mp, cons
   EBSD_ALLOC(s_int, int32_t, 2 * P, ws);
   EBSD_ALLOC(s_sub, float, 2 * P, ws);
   EBSD_ALLOC(gam, double, P, ws);
-  const int kn = p.upsample * n;
-  EBSD_ALLOC(roots, float2, kn, ws);
+  EBSD_ALLOC(roots, float2, subpixel_table_size(n, p.upsample), ws);
 
   if (q_out != q_init) EBSD_TRY(hipMemcpyAsync(q_out, q_init, sizeof(double) * 4 * P, hipMemcpyDeviceToDevice, st), "copy q");
-  EBSD_TRY(launch_roots(kn, roots, st), "roots");
+  EBSD_TRY(launch_subpixel_tables(n, p.upsample, roots, st), "subpixel tables");
   EBSD_TRY(launch_spectra(n, pats->data, npix, P, fp, spec_p, nullptr, st), "spectra(patterns)");
   EBSD_TRY(launch_logpolar(n, pats->data, P, p.n_rho, p.n_eta, lp_e, st), "logpolar(patterns)");
   const double* pcp = geo->pc_per;

@@ -33,10 +33,16 @@ hipError_t launch_xcf_peak(int n, const float2* spec_p, const float2* spec_l,
                            const int32_t* pi, const int32_t* li, int64_t k, int max_shift,
                            float* h_int, int32_t* s_int, float* map, hipStream_t stream);
 
+// Phase tables of the upsampled peak for (n, kappa): size in complex
+// elements, their construction, and the LDS one block of the kernel needs.
+int subpixel_table_size(int n, int kappa);
+size_t subpixel_lds_bytes(int n, int kappa);
+hipError_t launch_subpixel_tables(int n, int kappa, float2* tab, hipStream_t stream);
+
 // Upsampled peak around s_int: h_sub[k], s_sub[k] = (s_x, s_y) px.
 hipError_t launch_subpixel(int n, const float2* spec_p, const float2* spec_l,
                            const int32_t* pi, const int32_t* li, int64_t k,
-                           const int32_t* s_int, int kappa, const float2* roots,
+                           const int32_t* s_int, int kappa, const float2* tab,
                            float* h_sub, float* s_sub, hipStream_t stream);
 
 // exp(2 pi i k / m) for k in [0, m), computed in FP64 and rounded.
