@@ -130,6 +130,18 @@ def main():
     flops_launch = P * L * pair_flops(n)
     achieved = flops_launch / xcf_avg_s
 
+    # HBM traffic of the search kernel, from the committed counter profile,
+    # only while the kernel source is the one the counters were taken on
+    traffic = None
+    try:
+        import hashlib
+        prof = json.load(open(os.path.join(ROOT, "profiles", "xcf_search_128_map.json")))
+        src = open(os.path.join(ROOT, prof["source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest()[:16] == prof["source_sha256_prefix"] and (P, L, n) == (10000, 4000, 128):
+            traffic = prof["fetch_bytes_per_launch"] + prof["write_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        traffic = None
+
     # accuracy of the last step against the simulated truth (context, not parity)
     from oracle import rotations
     q = out["q"].cpu().numpy()
@@ -149,7 +161,9 @@ def main():
         "xcf_pairs_per_s_whole_step": P * L / (ms_per_step / 1e3),
         "roofline": {"bound": "alu", "kernel": "k_xcf_scores<128>", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
-                     "traffic": None, "avg_launch_ms": xcf_avg_s * 1e3,
+                     "traffic": traffic, "traffic_unit": "bytes per launch (HBM, counters)",
+                     "algorithmic_bytes": (P + L) * 2 * 49 * 97 * 4 + P * L * 4,
+                     "avg_launch_ms": xcf_avg_s * 1e3,
                      "flops_per_launch": flops_launch, "flops_per_pair": pair_flops(n)},
         "accuracy": {"refined_misorientation_deg_median": float(np.median(mis)),
                      "refined_misorientation_deg_p95": float(np.percentile(mis, 95)),
