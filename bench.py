@@ -68,6 +68,11 @@ def main():
     ap.add_argument("--patterns", type=int, default=10000, help="map size (must be a square)")
     ap.add_argument("--library", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the windowed / split-precision comparison")
+    ap.add_argument("--search-precision", type=int, default=0,
+                    help="precision of the timed step's search (0 FP32 FFT, 1 FP16x2, 2 BF16x2, 3 BF16)")
+    ap.add_argument("--search-max-shift", type=int, default=-1, help="shift window of the timed step (-1: all)")
+    ap.add_argument("--form-steps", type=int, default=3)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one elementwise copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -106,8 +111,10 @@ def main():
     P, L = pats.shape[0], lib_q.shape[0]
     torch.cuda.synchronize()
 
+    main_prm = tm.params_default(precision=args.search_precision, max_shift=args.search_max_shift)
+
     def step():
-        r = tm.index_patterns(pats, master, cfg["pc"], lib_q)
+        r = tm.index_patterns(pats, master, cfg["pc"], lib_q, prm=main_prm)
         return tm.refine_orientations(pats, master, cfg["pc"], r["best_q"], pc_per=pc_per), r
 
     for i in range(args.warmup):
@@ -169,10 +176,64 @@ def main():
                      "refined_misorientation_deg_p95": float(np.percentile(mis, 95)),
                      "sample": "200 map points vs simulated truth"},
     }
+    if not args.no_forms:
+        line["forms"] = compare_forms(tm, pats, master, cfg, lib_q, pc_per, idx["best_idx"], out["q"], args.form_steps)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(cfg, n, L, P)
     print(json.dumps(line), flush=True)
+
+
+def compare_forms(tm, pats, master, cfg, lib_q, pc_per, best_ref, q_ref, steps):
+    """The same step with the search in other forms: the FP32 FFT form and the
+    split-precision DFT-GEMM forms with a +-15 px shift window (the map's
+    pattern-centre offsets are within +-5 px and a library step moves the
+    pattern by <= ~6 px).  Indexing accuracy is compared with the exhaustive
+    FP32 step: agreement of the best template, and the refined orientation's
+    misorientation from the exhaustive one and from the simulated truth."""
+    import numpy as np
+    import torch
+    from oracle import rotations
+
+    P, L = pats.shape[0], lib_q.shape[0]
+    best_ref = best_ref.cpu().numpy()
+    q_ref = q_ref.cpu().numpy()
+    sample = np.linspace(0, P - 1, 200).astype(int)
+    res = {}
+    for name, kw in (("fft_fp32_window15", dict(precision=0, max_shift=15)),
+                     ("dftgemm_fp16x2_window15", dict(precision=1, max_shift=15)),
+                     ("dftgemm_bf16x2_window15", dict(precision=2, max_shift=15)),
+                     ("dftgemm_bf16_window15", dict(precision=3, max_shift=15))):
+        prm = tm.params_default(**kw)
+
+        def step():
+            r = tm.index_patterns(pats, master, cfg["pc"], lib_q, prm=prm)
+            return tm.refine_orientations(pats, master, cfg["pc"], r["best_q"], pc_per=pc_per), r
+
+        step()
+        torch.cuda.synchronize()
+        tm.timing_read()
+        tm.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out, idx = step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tm.timing_enable(False)
+        ms, cnt = tm.timing_read()
+        q = out["q"].cpu().numpy()
+        best = idx["best_idx"].cpu().numpy()
+        vs_ref = np.rad2deg([rotations.disorientation_q(q[i], q_ref[i]) for i in sample])
+        vs_true = np.rad2deg([rotations.disorientation_q(q[i], cfg["true_q"][i]) for i in sample])
+        res[name] = {"patterns_per_s": P * steps / (t1 - t0),
+                     "xcf_pairs_per_s": P * L / (ms / 1e3 / max(cnt, 1)),
+                     "search_ms": ms / max(cnt, 1),
+                     "best_index_agreement_with_exhaustive_fp32": float(np.mean(best == best_ref)),
+                     "refined_vs_exhaustive_deg_p99": float(np.percentile(vs_ref, 99)),
+                     "refined_vs_truth_deg_median": float(np.median(vs_true)),
+                     "refined_vs_truth_deg_p95": float(np.percentile(vs_true, 95))}
+        print("[bench] form %s: %.0f patterns/s" % (name, res[name]["patterns_per_s"]), file=sys.stderr, flush=True)
+    return res
 
 
 if __name__ == "__main__":

@@ -64,10 +64,26 @@ extern "C" {
 #define EBSD_E_DEVICE (-3)      /* HIP runtime or launch error              */
 #define EBSD_E_UNSUPPORTED (-4) /* valid request this build does not serve  */
 
+/* Arithmetic of the correlation search (the library ranking):
+ *   FP32    FP32 FFT form (every cyclic shift, or a window)
+ *   FP16X2  DFT-GEMMs on MFMA, operands split into FP16 hi + lo halves,
+ *           products hi*hi + hi*lo + lo*hi accumulated in FP32
+ *   BF16X2  the same with BF16 halves
+ *   BF16    BF16 operands, one product (reported, not parity-bound)
+ * The winner's integer peak, sub-pixel peak and the refinement always run
+ * in FP32. */
 #define EBSD_PREC_FP32 0
+#define EBSD_PREC_FP16X2 1
+#define EBSD_PREC_BF16X2 2
+#define EBSD_PREC_BF16 3
 
+/* Form of the search: AUTO picks FFT for FP32 and DFTGEMM otherwise.
+ * DFTGEMM evaluates only the shift window |s_x|, |s_y| <= max_shift
+ * (max_shift >= 0 required; the window's 2 max_shift + 1 shifts are padded
+ * to a multiple of 16 and must fit the on-chip constant operands). */
 #define EBSD_FORM_AUTO 0
 #define EBSD_FORM_FFT 1
+#define EBSD_FORM_DFTGEMM 2
 
 /* A batch of P square patterns of side n, pattern p at data + p n n. */
 typedef struct {
@@ -99,8 +115,8 @@ typedef struct {
  *   upsample      100: sub-pixel step 1/upsample over +-0.75 px
  *   n_iter        2 refinement iterations (fixed, no early exit)
  *   n_rho, n_eta  0, 0: log-polar grid n/2 radii x 2n angles
- *   precision     EBSD_PREC_FP32
- *   form          EBSD_FORM_AUTO (= FFT)
+ *   precision     EBSD_PREC_FP32 (see above)
+ *   form          EBSD_FORM_AUTO
  */
 typedef struct {
   uint32_t struct_size; /* sizeof(ebsd_params) */

@@ -91,9 +91,19 @@ int resolve_params(const ebsd_params* in, int n, ebsd_params* out) {
   if (out->n_rho < 2 || out->n_rho > 4096) return fail(EBSD_E_INVALID, "n_rho must be in [2, 4096]");
   if (out->n_eta < 4 || out->n_eta > 1024 || (out->n_eta & 1))
     return fail(EBSD_E_INVALID, "n_eta must be even and in [4, 1024]");
-  if (out->precision != EBSD_PREC_FP32) return fail(EBSD_E_UNSUPPORTED, "precision not built");
-  if (out->form != EBSD_FORM_AUTO && out->form != EBSD_FORM_FFT) return fail(EBSD_E_UNSUPPORTED, "form not built");
+  if (out->precision < EBSD_PREC_FP32 || out->precision > EBSD_PREC_BF16)
+    return fail(EBSD_E_UNSUPPORTED, "unknown precision");
+  if (out->form < EBSD_FORM_AUTO || out->form > EBSD_FORM_DFTGEMM) return fail(EBSD_E_UNSUPPORTED, "unknown form");
   if (out->max_shift < -1) return fail(EBSD_E_INVALID, "max_shift must be >= -1");
+  if (out->form == EBSD_FORM_AUTO) out->form = out->precision == EBSD_PREC_FP32 ? EBSD_FORM_FFT : EBSD_FORM_DFTGEMM;
+  if (out->form == EBSD_FORM_FFT && out->precision != EBSD_PREC_FP32)
+    return fail(EBSD_E_UNSUPPORTED, "the FFT form runs in FP32 only");
+  if (out->form == EBSD_FORM_DFTGEMM) {
+    if (out->precision == EBSD_PREC_FP32) return fail(EBSD_E_UNSUPPORTED, "the DFT-GEMM form runs in 16-bit halves");
+    if (out->max_shift < 0) return fail(EBSD_E_INVALID, "the DFT-GEMM form needs a shift window (max_shift >= 0)");
+    if (size_supported(n) && !gemm_supported(n, out->max_shift))
+      return fail(EBSD_E_UNSUPPORTED, "shift window too large for the DFT-GEMM form at this size");
+  }
   return EBSD_OK;
 }
 
@@ -133,15 +143,23 @@ int check_geometry(const ebsd_geometry* geo) {
 bool g_timing = false;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
 
-hipError_t timed_scores(int n, const float2* sp, int64_t p, const float2* sl, int64_t l, int max_shift,
-                        float* out, hipStream_t st) {
-  if (!g_timing) return launch_xcf_scores(n, sp, p, sl, l, max_shift, out, st);
+// The search in the requested form: FFT (FP32) or split-precision DFT-GEMM.
+hipError_t launch_search(int n, const ebsd_params& prm, const float2* sp, int64_t p, const float2* sl, int64_t l,
+                         unsigned short* frag, float* out, hipStream_t st) {
+  if (prm.form == EBSD_FORM_DFTGEMM)
+    return launch_xcf_gemm(n, prm.precision - 1, sp, p, sl, l, prm.max_shift, frag, out, st);
+  return launch_xcf_scores(n, sp, p, sl, l, prm.max_shift, out, st);
+}
+
+hipError_t timed_scores(int n, const ebsd_params& prm, const float2* sp, int64_t p, const float2* sl, int64_t l,
+                        unsigned short* frag, float* out, hipStream_t st) {
+  if (!g_timing) return launch_search(n, prm, sp, p, sl, l, frag, out, st);
   hipEvent_t a, b;
   hipError_t e;
   if ((e = hipEventCreate(&a)) != hipSuccess) return e;
   if ((e = hipEventCreate(&b)) != hipSuccess) return e;
   if ((e = hipEventRecord(a, st)) != hipSuccess) return e;
-  if ((e = launch_xcf_scores(n, sp, p, sl, l, max_shift, out, st)) != hipSuccess) return e;
+  if ((e = launch_search(n, prm, sp, p, sl, l, frag, out, st)) != hipSuccess) return e;
   if ((e = hipEventRecord(b, st)) != hipSuccess) return e;
   g_events.emplace_back(a, b);
   return hipSuccess;
@@ -256,9 +274,14 @@ int ebsd_xcf_scores(const float* spec_p, int64_t P, const float* spec_l, int64_t
   if (P < 0 || L < 0) return fail(EBSD_E_INVALID, "P and L must be >= 0");
   if (P == 0 || L == 0) return EBSD_OK;
   if (!spec_p || !spec_l || !scores) return fail(EBSD_E_INVALID, "null pointer");
-  EBSD_TRY(timed_scores(n, (const float2*)spec_p, P, (const float2*)spec_l, L, p.max_shift, scores,
-                        (hipStream_t)stream),
-           "xcf_scores");
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  unsigned short* frag = nullptr;
+  if (p.form == EBSD_FORM_DFTGEMM) {
+    EBSD_ALLOC(f, unsigned short, gemm_frag_bytes(n, p.max_shift) / 2, ws);
+    frag = f;
+  }
+  EBSD_TRY(timed_scores(n, p, (const float2*)spec_p, P, (const float2*)spec_l, L, frag, scores, st), "xcf_scores");
   return EBSD_OK;
 }
 
@@ -343,7 +366,12 @@ int ebsd_index_patterns(const ebsd_batch* pats, const ebsd_master* mp, const ebs
            "project");
   EBSD_TRY(launch_spectra(n, tmpl, npix, L, fp, spec_l, nullptr, st), "spectra(templates)");
   EBSD_TRY(launch_spectra(n, pats->data, npix, P, fp, spec_p, nullptr, st), "spectra(patterns)");
-  EBSD_TRY(timed_scores(n, spec_p, P, spec_l, L, p.max_shift, sc_out, st), "xcf_scores");
+  unsigned short* frag = nullptr;
+  if (p.form == EBSD_FORM_DFTGEMM) {
+    EBSD_ALLOC(f, unsigned short, gemm_frag_bytes(n, p.max_shift) / 2, ws);
+    frag = f;
+  }
+  EBSD_TRY(timed_scores(n, p, spec_p, P, spec_l, L, frag, sc_out, st), "xcf_scores");
   EBSD_TRY(launch_library_argmax(sc_out, P, L, best_idx, h_int, st), "library_argmax");
   EBSD_TRY(launch_xcf_peak(n, spec_p, spec_l, nullptr, best_idx, P, p.max_shift, h_tmp, s_int, nullptr, st),
            "xcf_peak");

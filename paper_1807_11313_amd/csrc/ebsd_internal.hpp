@@ -54,6 +54,14 @@ hipError_t launch_project(int n, const float* master, int mh, int mw, const doub
                           int64_t k, const double* pc_per, double pcx, double pcy, double pcz,
                           float* out, hipStream_t stream);
 
+// Windowed search as split-precision DFT-GEMMs on MFMA (precision 0: FP16
+// hi + lo, 1: BF16 hi + lo, 2: BF16), |s_x|, |s_y| <= max_shift.  `frag` is
+// scratch of gemm_frag_bytes(n, max_shift) bytes for the constant operands.
+bool gemm_supported(int n, int max_shift);
+size_t gemm_frag_bytes(int n, int max_shift);
+hipError_t launch_xcf_gemm(int n, int precision, const float2* spec_p, int64_t p, const float2* spec_l,
+                           int64_t l, int max_shift, unsigned short* frag, float* scores, hipStream_t stream);
+
 // Best template per pattern from the score matrix (ties: smallest index).
 hipError_t launch_library_argmax(const float* scores, int64_t p, int64_t l, int32_t* best,
                                  float* best_h, hipStream_t stream);
