@@ -47,7 +47,10 @@
  * argument error nothing is enqueued and no output is written.
  * ebsd_last_error() returns a thread-local description of the last error.
  *
- * Supported pattern sizes: n in {64, 96, 128, 160}.
+ * Supported pattern sizes: n in {64, 96, 128, 160, 256}.  At n = 256 the
+ * FFT form of the search and the full correlation map are not built: the
+ * search runs in the DFT-GEMM form and every integer peak needs a shift
+ * window (max_shift >= 0); other calls return EBSD_E_UNSUPPORTED.
  */
 #ifndef EBSD_TM_H
 #define EBSD_TM_H

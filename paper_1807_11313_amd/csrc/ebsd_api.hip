@@ -116,13 +116,42 @@ FilterParams filter_of(const ebsd_params& p, int n) {
   return f;
 }
 
+// Spectra of K contiguous images: one kernel up to 160, three passes through
+// stream-ordered scratch at 256.
+int do_spectra(int n, const float* imgs, int64_t k, const FilterParams& fp, float2* spec, double* energy,
+               Scratch& ws, hipStream_t st) {
+  if (n == 256) {
+    EBSD_ALLOC(s256, unsigned char, spectra256_scratch_bytes(k), ws);
+    EBSD_TRY(launch_spectra256(imgs, k, fp, spec, energy, s256, st), "spectra256");
+    return EBSD_OK;
+  }
+  EBSD_TRY(launch_spectra(n, imgs, (int64_t)n * n, k, fp, spec, energy, st), "spectra");
+  return EBSD_OK;
+}
+
+// Integer peak of explicit pairs: the full-map FFT form where it exists,
+// otherwise the exact shift-window evaluation (needs max_shift >= 0).
+int do_peak(int n, const ebsd_params& p, const float2* sp, const float2* sl, const int32_t* pi, const int32_t* li,
+            int64_t k, float* h, int32_t* s, Scratch& ws, hipStream_t st) {
+  if (fft_supported(n)) {
+    EBSD_TRY(launch_xcf_peak(n, sp, sl, pi, li, k, p.max_shift, h, s, nullptr, st), "xcf_peak");
+    return EBSD_OK;
+  }
+  if (!window_peak_supported(n, p.max_shift))
+    return fail(EBSD_E_UNSUPPORTED, "this size needs a shift window (max_shift >= 0) for the integer peak");
+  EBSD_ALLOC(tab, float2, window_table_size(n, p.max_shift), ws);
+  EBSD_TRY(launch_window_tables(n, p.max_shift, tab, st), "window tables");
+  EBSD_TRY(launch_window_peak(n, sp, sl, pi, li, k, p.max_shift, tab, h, s, st), "window peak");
+  return EBSD_OK;
+}
+
 int64_t spec_complex(int n) {
   const int b = band_of(n);
   return b < 0 ? -1 : (int64_t)(b + 1) * (2 * b + 1);
 }
 
 int check_size(int n) {
-  if (!size_supported(n)) return fail(EBSD_E_UNSUPPORTED, "pattern size not supported (64, 96, 128, 160)");
+  if (!size_supported(n)) return fail(EBSD_E_UNSUPPORTED, "pattern size not supported (64, 96, 128, 160, 256)");
   return EBSD_OK;
 }
 
@@ -243,10 +272,9 @@ int ebsd_pattern_spectra(const float* imgs, int64_t K, int32_t n, const ebsd_par
   if (K < 0) return fail(EBSD_E_INVALID, "K must be >= 0");
   if (K == 0) return EBSD_OK;
   if (!imgs || !spec) return fail(EBSD_E_INVALID, "null pointer");
-  EBSD_TRY(launch_spectra(n, imgs, (int64_t)n * n, K, filter_of(p, n), (float2*)spec, energy,
-                          (hipStream_t)stream),
-           "spectra");
-  return EBSD_OK;
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  return do_spectra(n, imgs, K, filter_of(p, n), (float2*)spec, energy, ws, st);
 }
 
 int ebsd_xcf_peak(const float* spec_p, const float* spec_l, const int32_t* pi, const int32_t* li, int64_t K,
@@ -259,10 +287,16 @@ int ebsd_xcf_peak(const float* spec_p, const float* spec_l, const int32_t* pi, c
   if (K == 0) return EBSD_OK;
   if (!spec_p || !spec_l || !h_int || !s_int) return fail(EBSD_E_INVALID, "null pointer");
   if (K > 0x7fffffffLL) return fail(EBSD_E_INVALID, "K too large");
-  EBSD_TRY(launch_xcf_peak(n, (const float2*)spec_p, (const float2*)spec_l, pi, li, K, p.max_shift, h_int, s_int,
-                           map, (hipStream_t)stream),
-           "xcf_peak");
-  return EBSD_OK;
+  if (map) {
+    if (!fft_supported(n)) return fail(EBSD_E_UNSUPPORTED, "the full correlation map is not built at this size");
+    EBSD_TRY(launch_xcf_peak(n, (const float2*)spec_p, (const float2*)spec_l, pi, li, K, p.max_shift, h_int, s_int,
+                             map, (hipStream_t)stream),
+             "xcf_peak");
+    return EBSD_OK;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  return do_peak(n, p, (const float2*)spec_p, (const float2*)spec_l, pi, li, K, h_int, s_int, ws, st);
 }
 
 int ebsd_xcf_scores(const float* spec_p, int64_t P, const float* spec_l, int64_t L, int32_t n,
@@ -274,6 +308,8 @@ int ebsd_xcf_scores(const float* spec_p, int64_t P, const float* spec_l, int64_t
   if (P < 0 || L < 0) return fail(EBSD_E_INVALID, "P and L must be >= 0");
   if (P == 0 || L == 0) return EBSD_OK;
   if (!spec_p || !spec_l || !scores) return fail(EBSD_E_INVALID, "null pointer");
+  if (p.form == EBSD_FORM_FFT && !fft_supported(n))
+    return fail(EBSD_E_UNSUPPORTED, "the FFT search is not built at this size; use the DFT-GEMM form");
   hipStream_t st = (hipStream_t)stream;
   Scratch ws(st);
   unsigned short* frag = nullptr;
@@ -343,6 +379,10 @@ int ebsd_index_patterns(const ebsd_batch* pats, const ebsd_master* mp, const ebs
   if (!lib_q) return fail(EBSD_E_INVALID, "null library");
   if (P == 0) return EBSD_OK;
   if (!pats->data || !best_idx || !peak_h || !shift) return fail(EBSD_E_INVALID, "null pointer");
+  if (p.form == EBSD_FORM_FFT && !fft_supported(n))
+    return fail(EBSD_E_UNSUPPORTED, "the FFT search is not built at this size; use the DFT-GEMM form");
+  if (!fft_supported(n) && !window_peak_supported(n, p.max_shift))
+    return fail(EBSD_E_UNSUPPORTED, "at this size the peak needs a shift window (max_shift >= 0)");
 
   hipStream_t st = (hipStream_t)stream;
   Scratch ws(st);
@@ -364,8 +404,8 @@ int ebsd_index_patterns(const ebsd_batch* pats, const ebsd_master* mp, const ebs
 
   EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, lib_q, L, nullptr, geo->pcx, geo->pcy, geo->pcz, tmpl, st),
            "project");
-  EBSD_TRY(launch_spectra(n, tmpl, npix, L, fp, spec_l, nullptr, st), "spectra(templates)");
-  EBSD_TRY(launch_spectra(n, pats->data, npix, P, fp, spec_p, nullptr, st), "spectra(patterns)");
+  if (int e = do_spectra(n, tmpl, L, fp, spec_l, nullptr, ws, st)) return e;
+  if (int e = do_spectra(n, pats->data, P, fp, spec_p, nullptr, ws, st)) return e;
   unsigned short* frag = nullptr;
   if (p.form == EBSD_FORM_DFTGEMM) {
     EBSD_ALLOC(f, unsigned short, gemm_frag_bytes(n, p.max_shift) / 2, ws);
@@ -373,8 +413,7 @@ int ebsd_index_patterns(const ebsd_batch* pats, const ebsd_master* mp, const ebs
   }
   EBSD_TRY(timed_scores(n, p, spec_p, P, spec_l, L, frag, sc_out, st), "xcf_scores");
   EBSD_TRY(launch_library_argmax(sc_out, P, L, best_idx, h_int, st), "library_argmax");
-  EBSD_TRY(launch_xcf_peak(n, spec_p, spec_l, nullptr, best_idx, P, p.max_shift, h_tmp, s_int, nullptr, st),
-           "xcf_peak");
+  if (int e = do_peak(n, p, spec_p, spec_l, nullptr, best_idx, P, h_tmp, s_int, ws, st)) return e;
   EBSD_TRY(launch_subpixel_tables(n, p.upsample, roots, st), "subpixel tables");
   EBSD_TRY(launch_subpixel(n, spec_p, spec_l, nullptr, best_idx, P, s_int, p.upsample, roots, peak_h, shift, st),
            "subpixel");
@@ -398,6 +437,8 @@ int ebsd_refine_orientations(const ebsd_batch* pats, const ebsd_master* mp, cons
   if (P > 0x7fffffffLL) return fail(EBSD_E_INVALID, "P must fit in int32");
   if (P == 0) return EBSD_OK;
   if (!pats->data || !q_init || !q_out || !peak_h || !shift) return fail(EBSD_E_INVALID, "null pointer");
+  if (!fft_supported(n) && !window_peak_supported(n, p.max_shift))
+    return fail(EBSD_E_UNSUPPORTED, "at this size the peak needs a shift window (max_shift >= 0)");
 
   hipStream_t st = (hipStream_t)stream;
   Scratch ws(st);
@@ -419,15 +460,14 @@ int ebsd_refine_orientations(const ebsd_batch* pats, const ebsd_master* mp, cons
 
   if (q_out != q_init) EBSD_TRY(hipMemcpyAsync(q_out, q_init, sizeof(double) * 4 * P, hipMemcpyDeviceToDevice, st), "copy q");
   EBSD_TRY(launch_subpixel_tables(n, p.upsample, roots, st), "subpixel tables");
-  EBSD_TRY(launch_spectra(n, pats->data, npix, P, fp, spec_p, nullptr, st), "spectra(patterns)");
+  if ((rc = do_spectra(n, pats->data, P, fp, spec_p, nullptr, ws, st))) return rc;
   EBSD_TRY(launch_logpolar(n, pats->data, P, p.n_rho, p.n_eta, lp_e, st), "logpolar(patterns)");
   const double* pcp = geo->pc_per;
   auto measure_shift = [&](float* h_out, float* s_out) -> int {
     EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, q_out, P, pcp, geo->pcx, geo->pcy, geo->pcz, tmpl, st),
              "project");
-    EBSD_TRY(launch_spectra(n, tmpl, npix, P, fp, spec_t, nullptr, st), "spectra(templates)");
-    EBSD_TRY(launch_xcf_peak(n, spec_p, spec_t, nullptr, nullptr, P, p.max_shift, h_int, s_int, nullptr, st),
-             "xcf_peak");
+    if (int e = do_spectra(n, tmpl, P, fp, spec_t, nullptr, ws, st)) return e;
+    if (int e = do_peak(n, p, spec_p, spec_t, nullptr, nullptr, P, h_int, s_int, ws, st)) return e;
     EBSD_TRY(launch_subpixel(n, spec_p, spec_t, nullptr, nullptr, P, s_int, p.upsample, roots, h_out, s_out, st),
              "subpixel");
     return EBSD_OK;

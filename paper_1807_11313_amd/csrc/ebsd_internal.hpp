@@ -7,18 +7,38 @@
 
 namespace ebsd {
 
-// Band half-width of the stored spectra for a supported size (3N/8), or -1.
-int band_of(int n);
-bool size_supported(int n);
-
 struct FilterParams {
   int window;
   float sigma_hp, sigma_lp, rho_max;
 };
 
+// Band half-width of the stored spectra for a supported size (3N/8), or -1.
+// Sizes 64, 96, 128, 160 run every stage; 256 runs the spectra, the
+// DFT-GEMM search and the shift-window peaks (its full-map FFT does not fit
+// one block's LDS).
+int band_of(int n);
+bool size_supported(int n);
+bool fft_supported(int n);
+
+// Spectra at 256 x 256 (three passes through a scratch of
+// spectra256_scratch_bytes(k) bytes); images contiguous.
+size_t spectra256_scratch_bytes(int64_t k);
+hipError_t launch_spectra256(const float* imgs, int64_t k, const FilterParams& fp, float2* spec, double* energy,
+                             void* scratch, hipStream_t stream);
+
+// Integer peak inside the shift window |s_x|, |s_y| <= max_shift, evaluated
+// exactly in FP32 on the band (any supported size); tables of
+// window_table_size complex elements built by launch_window_tables.
+bool window_peak_supported(int n, int max_shift);
+int window_table_size(int n, int max_shift);
+hipError_t launch_window_tables(int n, int max_shift, float2* tab, hipStream_t stream);
+hipError_t launch_window_peak(int n, const float2* spec_p, const float2* spec_l, const int32_t* pi,
+                              const int32_t* li, int64_t k, int max_shift, const float2* tab, float* h_int,
+                              int32_t* s_int, hipStream_t stream);
+
 // Contrast-normalise, window, forward 2-D DFT, band-pass, FP64 energy and
 // unit-energy scaling of K n x n images (image k at imgs + k * img_stride).
-// Output: spec[k][v][kk] complex64 (v in [0, B], kk in [0, 2B + 1)), energy[k].
+// Output: spec[k][kk][v] complex64 (kk in [0, 2B + 1), v in [0, B]), energy[k].
 hipError_t launch_spectra(int n, const float* imgs, int64_t img_stride, int64_t k,
                           const FilterParams& fp, float2* spec, double* energy,
                           hipStream_t stream);

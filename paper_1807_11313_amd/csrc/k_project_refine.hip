@@ -93,190 +93,6 @@ __global__ void k_roots(int m, float2* out) {
 }
 
 // ---------------------------------------------------------------------------
-// Upsampled peak (Equation 5 and the peak upsampling of section "Fast Fourier
-// Transform"): rho evaluated exactly (a matrix DFT over the band) at
-// s_int + (a, b) / kappa for |a|, |b| <= m = ceil(0.75 kappa); the largest
-// real value wins, ties to the smallest (b, a) row-major.
-//
-// With the integer part of the shift applied as an exact phase ramp,
-//   Z'(u, v)  = Z(u, v) exp(2 pi i u y0 / n)
-//   G(b, v)   = sum_u F1(u, b) Z'(u, v),     F1(u, b) = exp(2 pi i u (b - m) / (kappa n))
-//   G'(b, v)  = G(b, v) exp(2 pi i v x0 / n) w_v   (w_0 = 1, w_v = 2: Hermitian half)
-//   rho(b, a) = Re sum_v G'(b, v) F2(v, a),  F2(v, a) = exp(2 pi i v (a - m) / (kappa n))
-// so both stages are products with pattern-independent phase matrices, tiled
-// through LDS.  Table layout (complex): F1 [2B+1][M], F2 [B+1][M], roots_n [n].
-int subpixel_table_size(int n, int kappa) {
-  const int b = band_of(n);
-  const int msz = 2 * ((3 * kappa + 3) / 4) + 1;
-  return (3 * b + 2) * msz + n;
-}
-
-__global__ void k_subpixel_tables(int n, int bnd, int kappa, float2* tab) {
-  const int m = (3 * kappa + 3) / 4, msz = 2 * m + 1;
-  const int nk = 2 * bnd + 1, nv = bnd + 1;
-  const long kn = (long)kappa * n;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const int total = (nk + nv) * msz + n;
-  if (i >= total) return;
-  long idx;
-  double den;
-  if (i < nk * msz) {
-    const int kk = i / msz, b = i - kk * msz;
-    const int u = kk <= bnd ? kk : kk - nk;
-    idx = (long)u * (b - m);
-    den = (double)kn;
-  } else if (i < (nk + nv) * msz) {
-    const int j = i - nk * msz;
-    const int v = j / msz, a = j - v * msz;
-    idx = (long)v * (a - m);
-    den = (double)kn;
-  } else {
-    idx = i - (nk + nv) * msz;
-    den = (double)n;
-  }
-  const long md = (long)den;
-  idx %= md;
-  if (idx < 0) idx += md;
-  double s, c;
-  sincospi(2.0 * (double)idx / den, &s, &c);
-  tab[i] = make_float2((float)c, (float)s);
-}
-
-template <int MB>
-__global__ __launch_bounds__(256) void k_subpixel(int n, int bnd, const cf* __restrict__ spec_p,
-                                                  const cf* __restrict__ spec_l,
-                                                  const int32_t* __restrict__ pi,
-                                                  const int32_t* __restrict__ li,
-                                                  const int32_t* __restrict__ s_int, int kappa,
-                                                  const cf* __restrict__ tab,
-                                                  float* __restrict__ h_sub,
-                                                  float* __restrict__ s_sub) {
-  // MB = ceil(M / 16): b (and a) values per thread
-  extern __shared__ cf sm[];
-  constexpr int UC = 16;  // rows of the phase matrices staged per step
-  const int nv = bnd + 1, nk = 2 * bnd + 1, spec = nv * nk;
-  const int m = (3 * kappa + 3) / 4, msz = 2 * m + 1;
-  cf* zs = sm;                     // Z' [nk][nv]
-  cf* fc = sm + spec;              // staged phase-matrix rows [UC][msz]
-  cf* g = fc + UC * msz;           // G [msz][nv]
-  const cf* F1 = tab;
-  const cf* F2 = tab + nk * msz;
-  const cf* rn = tab + (nk + nv) * msz;
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  const int64_t k = blockIdx.x;
-  const cf* E = spec_p + (pi ? (int64_t)pi[k] : k) * spec;
-  const cf* T = spec_l + (li ? (int64_t)li[k] : k) * spec;
-  const int x0 = s_int[2 * k], y0 = s_int[2 * k + 1];
-  for (int t = tid; t < spec; t += 256) {
-    const int kk = t / nv;
-    const int u = kk <= bnd ? kk : kk - nk;
-    int r = (u * y0) % n;
-    if (r < 0) r += n;
-    zs[t] = cmul(cmulc(E[t], T[t]), rn[r]);
-  }
-  // stage 1: thread (ty, tx) accumulates G(b = ty + 16 i, v = tx + 16 j)
-  cf acc[MB][4];
-#pragma unroll
-  for (int i = 0; i < MB; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = cf{0.f, 0.f};
-  for (int u0 = 0; u0 < nk; u0 += UC) {
-    const int uc = min(UC, nk - u0);
-    __syncthreads();
-    for (int t = tid; t < uc * msz; t += 256) fc[t] = F1[u0 * msz + t];
-    __syncthreads();
-    for (int uu = 0; uu < uc; ++uu) {
-      cf zv[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int v = tx + 16 * j;
-        zv[j] = v < nv ? zs[(u0 + uu) * nv + v] : cf{0.f, 0.f};
-      }
-#pragma unroll
-      for (int i = 0; i < MB; ++i) {
-        const int b = ty + 16 * i;
-        const cf f = b < msz ? fc[uu * msz + b] : cf{0.f, 0.f};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[i][j].x = __fmaf_rn(f.x, zv[j].x, __fmaf_rn(-f.y, zv[j].y, acc[i][j].x));
-          acc[i][j].y = __fmaf_rn(f.x, zv[j].y, __fmaf_rn(f.y, zv[j].x, acc[i][j].y));
-        }
-      }
-    }
-  }
-  // G'(b, v) = G(b, v) exp(2 pi i v x0 / n) w_v
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int v = tx + 16 * j;
-    if (v < nv) {
-      int r = (v * x0) % n;
-      if (r < 0) r += n;
-      const cf w = cscale(rn[r], v == 0 ? 1.0f : 2.0f);
-#pragma unroll
-      for (int i = 0; i < MB; ++i) {
-        const int b = ty + 16 * i;
-        if (b < msz) g[b * nv + v] = cmul(acc[i][j], w);
-      }
-    }
-  }
-  // stage 2: thread (ty, tx) accumulates rho(b = ty + 16 i, a = tx + 16 j)
-  float rho[MB][MB];
-#pragma unroll
-  for (int i = 0; i < MB; ++i)
-#pragma unroll
-    for (int j = 0; j < MB; ++j) rho[i][j] = 0.0f;
-  for (int v0 = 0; v0 < nv; v0 += UC) {
-    const int vc = min(UC, nv - v0);
-    __syncthreads();
-    for (int t = tid; t < vc * msz; t += 256) fc[t] = F2[v0 * msz + t];
-    __syncthreads();
-    for (int vv = 0; vv < vc; ++vv) {
-      cf gv[MB], fv[MB];
-#pragma unroll
-      for (int i = 0; i < MB; ++i) {
-        const int b = ty + 16 * i;
-        gv[i] = b < msz ? g[b * nv + v0 + vv] : cf{0.f, 0.f};
-        const int a = tx + 16 * i;
-        fv[i] = a < msz ? fc[vv * msz + a] : cf{0.f, 0.f};
-      }
-#pragma unroll
-      for (int i = 0; i < MB; ++i)
-#pragma unroll
-        for (int j = 0; j < MB; ++j)
-          rho[i][j] = __fmaf_rn(gv[i].x, fv[j].x, __fmaf_rn(-gv[i].y, fv[j].y, rho[i][j]));
-    }
-  }
-  float best = -INFINITY;
-  int bi = 0x7fffffff;
-#pragma unroll
-  for (int i = 0; i < MB; ++i) {
-    const int b = ty + 16 * i;
-#pragma unroll
-    for (int j = 0; j < MB; ++j) {
-      const int a = tx + 16 * j;
-      if (b < msz && a < msz) argmax_merge(best, bi, rho[i][j], b * msz + a);
-    }
-  }
-  wave_argmax(best, bi);
-  __shared__ float rv[4];
-  __shared__ int ri[4];
-  if ((tid & 63) == 0) {
-    rv[tid >> 6] = best;
-    ri[tid >> 6] = bi;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int w = 1; w < 4; ++w) argmax_merge(best, bi, rv[w], ri[w]);
-    if (bi < 0 || bi >= msz * msz) bi = m * msz + m;
-    const int b = bi / msz, a = bi - b * msz;
-    h_sub[k] = best;
-    s_sub[2 * k] = (float)x0 + (float)(a - m) / (float)kappa;
-    s_sub[2 * k + 1] = (float)y0 + (float)(b - m) / (float)kappa;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Library argmax (section "Method Overview": best match = highest coefficient),
 // ties to the smallest template index.
 __global__ __launch_bounds__(256) void k_library_argmax(const float* __restrict__ scores, int64_t l,
@@ -571,46 +387,6 @@ hipError_t launch_project(int n, const float* master, int mh, int mw, const doub
 
 hipError_t launch_roots(int m, float2* out, hipStream_t stream) {
   hipLaunchKernelGGL(k_roots, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, m, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_subpixel_tables(int n, int kappa, float2* tab, hipStream_t stream) {
-  const int bnd = band_of(n);
-  if (bnd < 0) return hipErrorInvalidValue;
-  const int total = subpixel_table_size(n, kappa);
-  hipLaunchKernelGGL(k_subpixel_tables, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, n, bnd, kappa,
-                     tab);
-  return hipGetLastError();
-}
-
-size_t subpixel_lds_bytes(int n, int kappa) {
-  const int bnd = band_of(n);
-  const int msz = 2 * ((3 * kappa + 3) / 4) + 1;
-  return sizeof(cf) * ((size_t)(bnd + 1) * (2 * bnd + 1) + (size_t)16 * msz + (size_t)msz * (bnd + 1));
-}
-
-hipError_t launch_subpixel(int n, const float2* spec_p, const float2* spec_l, const int32_t* pi,
-                           const int32_t* li, int64_t k, const int32_t* s_int, int kappa,
-                           const float2* tab, float* h_sub, float* s_sub, hipStream_t stream) {
-  if (k <= 0) return hipSuccess;
-  const int bnd = band_of(n);
-  if (bnd < 0 || bnd + 1 > 64) return hipErrorInvalidValue;
-  const int msz = 2 * ((3 * kappa + 3) / 4) + 1;
-  const size_t shm = subpixel_lds_bytes(n, kappa);
-  if (shm > 160 * 1024) return hipErrorInvalidValue;
-  const int mb = (msz + 15) / 16;
-#define EBSD_SUB(MBV)                                                                                         \
-  do {                                                                                                        \
-    hipFuncSetAttribute((const void*)k_subpixel<MBV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); \
-    hipLaunchKernelGGL(k_subpixel<MBV>, dim3((unsigned)k), dim3(256), shm, stream, n, bnd, (const cf*)spec_p,  \
-                       (const cf*)spec_l, pi, li, s_int, kappa, (const cf*)tab, h_sub, s_sub);               \
-  } while (0)
-  if (mb <= 4) EBSD_SUB(4);
-  else if (mb <= 7) EBSD_SUB(7);
-  else if (mb <= 10) EBSD_SUB(10);
-  else if (mb <= 13) EBSD_SUB(13);
-  else return hipErrorInvalidValue;
-#undef EBSD_SUB
   return hipGetLastError();
 }
 

@@ -630,10 +630,12 @@ int band_of(int n) {
     case 96: return Plan<96>::B;
     case 128: return Plan<128>::B;
     case 160: return Plan<160>::B;
+    case 256: return Plan<256>::B;
     default: return -1;
   }
 }
 bool size_supported(int n) { return band_of(n) > 0; }
+bool fft_supported(int n) { return n == 64 || n == 96 || n == 128 || n == 160; }
 
 template <int N>
 static constexpr int nt_xcf() { return N <= 96 ? 256 : 256; }
