@@ -29,6 +29,20 @@ def pair_flops(n):
 
 
 PEAK_FP32_VALU = 157.3e12   # MI355X fp32 vector, FLOP/s (published)
+PEAK_MFMA_16BIT = 2.5e15    # MI355X dense FP16 / BF16 matrix, FLOP/s (published)
+
+
+# Algorithmic matrix flops per pair of the windowed DFT-GEMM search with
+# |s_x|, |s_y| <= S: stage 1 a complex product over the band (2B + 1 rows,
+# B + 1 columns, 2S + 1 shifts, 8 flops per complex multiply-add), stage 2
+# the real part of a complex product (4 flops per term) over B + 1 columns
+# and (2S + 1)^2 shifts; times 3 for the hi*hi + hi*lo + lo*hi products of
+# the split forms.
+def gemm_pair_flops(n, s, precision):
+    b = 3 * n // 8
+    w = 2 * s + 1
+    one = 8 * (2 * b + 1) * (b + 1) * w + 4 * (b + 1) * w * w
+    return one * (1 if precision == 3 else 3)
 
 
 def cpu_baseline(cfg, n, l_full, p_full):
@@ -73,6 +87,10 @@ def main():
                     help="precision of the timed step's search (0 FP32 FFT, 1 FP16x2, 2 BF16x2, 3 BF16)")
     ap.add_argument("--search-max-shift", type=int, default=-1, help="shift window of the timed step (-1: all)")
     ap.add_argument("--form-steps", type=int, default=3)
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the split-precision search on the same map at 256^2")
+    ap.add_argument("--precision-patterns", type=int, default=10000)
+    ap.add_argument("--precision-steps", type=int, default=2)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one elementwise copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -178,9 +196,16 @@ def main():
     }
     if not args.no_forms:
         line["forms"] = compare_forms(tm, pats, master, cfg, lib_q, pc_per, idx["best_idx"], out["q"], args.form_steps)
+    # the oracle's sample, on the host, before the 128^2 map is released
+    cpu_cfg = {"patterns": cfg["patterns"][:3].cpu(), "lib_q": cfg["lib_q"][:400], "master": cfg["master"],
+               "pc": cfg["pc"], "pcs": cfg["pcs"][:2], "true_q": cfg["true_q"][:2]}
+    if not args.no_precision:
+        del pats, cfg, out, idx
+        torch.cuda.empty_cache()
+        line["precision256"] = precision_256(tm, args.precision_patterns, args.library, args.precision_steps)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(cfg, n, L, P)
+        line["cpu_baseline"] = cpu_baseline(cpu_cfg, n, L, P)
     print(json.dumps(line), flush=True)
 
 
@@ -233,6 +258,114 @@ def compare_forms(tm, pats, master, cfg, lib_q, pc_per, best_ref, q_ref, steps):
                      "refined_vs_truth_deg_median": float(np.median(vs_true)),
                      "refined_vs_truth_deg_p95": float(np.percentile(vs_true, 95))}
         print("[bench] form %s: %.0f patterns/s" % (name, res[name]["patterns_per_s"]), file=sys.stderr, flush=True)
+    return res
+
+
+def precision_256(tm, patterns, library, steps, window=15, sample=3, n_sub=96):
+    """The map at 256 x 256 with the search as split-precision DFT-GEMMs on
+    MFMA (the FFT form is not built at this size), +-15 px window, followed
+    by the same refinement.  Per precision: patterns/s, pairs/s and the MFMA
+    roofline of the search kernel, agreement of the best template with the
+    FP16 hi + lo form, accuracy against the simulated truth, and the error
+    against the FP64 oracle on a sample of patterns: scores over a random
+    subset of the library plus the GPU's pick, the winner's sub-pixel peak
+    height and shift, and the refined orientation from the same start."""
+    import numpy as np
+    import torch
+    import oracle
+    from fixtures import configs
+    from oracle import geometry, pipeline, rotations, spectra, xcf
+
+    n = 256
+    side = int(round(patterns ** 0.5))
+    dev = torch.device("cuda:0")
+    print("[bench] generating map workload %dx%d patterns at %d^2, library %d" % (side, side, n, library),
+          file=sys.stderr, flush=True)
+    cfg = configs.map_grid(rows=side, cols=side, n=n, l=library, device=dev, dtype=torch.float32)
+    pats = cfg["patterns"].contiguous()
+    master = torch.as_tensor(cfg["master"], device=dev).contiguous()
+    lib_q = torch.as_tensor(cfg["lib_q"], device=dev).contiguous()
+    pc_per = torch.as_tensor(cfg["pcs"], device=dev).contiguous()
+    P, L = pats.shape[0], lib_q.shape[0]
+    pts = np.linspace(0, P - 1, 200).astype(int)
+    smp = np.linspace(0, P - 1, sample + 2).astype(int)[1:-1]
+    rng = np.random.default_rng(7)
+    sub = np.sort(rng.choice(L, size=min(n_sub, L), replace=False))
+
+    # oracle side of the error sample (independent of the precision)
+    oprm = oracle.Params(max_shift=window)
+    pats_h = cfg["patterns"][smp].cpu().numpy().astype(np.float64)
+    o_pat = [spectra.unit_spectrum(pats_h[i], oprm) for i in range(len(smp))]
+    o_lib = {}
+
+    def o_spec(j):
+        if j not in o_lib:
+            img = geometry.project(cfg["master"], rotations.quat_to_matrix(cfg["lib_q"][j]), n, cfg["pc"])
+            o_lib[j] = spectra.unit_spectrum(img, oprm)
+        return o_lib[j]
+
+    res = {"workload": "map: %d patterns (%dx%d grid, 20 grains) at %dx%d fp32 vs %d-orientation cubic library, "
+                       "DFT-GEMM search |s| <= %d px + 2-iteration refinement" % (P, side, side, n, n, L, window),
+           "error_sample": "%d patterns x %d random templates (+ the GPU's pick) against the FP64 oracle"
+                           % (len(smp), len(sub))}
+    ref_best = None
+    for name, prec in (("fp16x2", 1), ("bf16x2", 2), ("bf16", 3)):
+        prm = tm.params_default(precision=prec, max_shift=window)
+
+        def step():
+            r = tm.index_patterns(pats, master, cfg["pc"], lib_q, prm=prm)
+            return tm.refine_orientations(pats, master, cfg["pc"], r["best_q"], pc_per=pc_per, prm=prm), r
+
+        step()
+        torch.cuda.synchronize()
+        tm.timing_read()
+        tm.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out, idx = step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tm.timing_enable(False)
+        ms, cnt = tm.timing_read()
+        search_s = ms / 1e3 / max(cnt, 1)
+        flops = P * L * gemm_pair_flops(n, window, prec)
+        best = idx["best_idx"].cpu().numpy()
+        if ref_best is None:
+            ref_best = best
+        q = out["q"].cpu().numpy()
+        vs_true = np.rad2deg([rotations.disorientation_q(q[i], cfg["true_q"][i]) for i in pts])
+
+        # error against the FP64 oracle on the sample
+        sc = tm.index_patterns(pats[smp], master, cfg["pc"], lib_q, prm=prm, scores=True)
+        sc_h = sc["scores"].cpu().numpy()
+        d_score = d_h = d_s = 0.0
+        for a in range(len(smp)):
+            cols = sorted(set(sub.tolist()) | {int(best[smp[a]])})
+            ref = xcf.library_scores(o_pat[a], [o_spec(j) for j in cols], max_shift=window)
+            d_score = max(d_score, float(np.max(np.abs(sc_h[a, cols] - ref))))
+            b = int(sc["best_idx"][a])
+            ho, so = xcf.subpixel_peak(o_pat[a], o_spec(b),
+                                       xcf.integer_peak(xcf.xcf_map(o_pat[a], o_spec(b)), window)[1], oprm.upsample)
+            d_h = max(d_h, abs(float(sc["peak_h"][a]) - ho))
+            sg = sc["shift"][a].cpu().numpy()
+            d_s = max(d_s, abs(sg[0] - so[1]), abs(sg[1] - so[0]))
+        q0 = idx["best_q"].cpu().numpy()[smp]
+        rr = pipeline.refine_orientations(pats_h, cfg["master"], cfg["pcs"][smp], q0, oprm)
+        d_q = max(np.rad2deg(rotations.disorientation_q(q[smp[a]], rr["q"][a])) for a in range(len(smp)))
+        res[name] = {"patterns_per_s": P * steps / (t1 - t0), "xcf_pairs_per_s": P * L / search_s,
+                     "search_ms": search_s * 1e3,
+                     "roofline": {"bound": "mfma", "kernel": "k_xcf_gemm<256>", "achieved": flops / search_s / 1e12,
+                                  "peak": PEAK_MFMA_16BIT / 1e12, "unit": "TFLOP/s",
+                                  "frac": flops / search_s / PEAK_MFMA_16BIT,
+                                  "flops_per_pair": gemm_pair_flops(n, window, prec)},
+                     "best_index_agreement_with_fp16x2": float(np.mean(best == ref_best)),
+                     "refined_vs_truth_deg_median": float(np.median(vs_true)),
+                     "refined_vs_truth_deg_p95": float(np.percentile(vs_true, 95)),
+                     "vs_oracle": {"max_abs_score": d_score, "max_abs_peak_h": d_h, "max_abs_shift_px": float(d_s),
+                                   "max_refined_misorientation_deg": float(d_q)}}
+        print("[bench] 256 %s: %.0f patterns/s, %.3g pairs/s, oracle |dh| %.2g"
+              % (name, res[name]["patterns_per_s"], res[name]["xcf_pairs_per_s"], d_score),
+              file=sys.stderr, flush=True)
     return res
 
 
