@@ -81,3 +81,26 @@ def ragged(seed=4, p=20000, l=8000, sizes=(64, 96, 128, 160), device="cpu"):
                                                 ("poisson_gauss", 1000.0, 5.0), seed=seed + s, device=device)))
     return dict(master=master, sizes=ns, pattern_sets=pats, pcs=pcs, true_q=true_q, lib_q=lib_q,
                 pc=(0.5, 0.5, PCZ))
+
+
+def pack_ragged(cfg, device="cpu", dtype=torch.float32):
+    """Packs a ragged workload into one flat buffer in pattern order:
+    returns (data [sum n_p^2], offsets [P] int64 element offsets, sizes [P])."""
+    ns = np.asarray(cfg["sizes"], dtype=np.int64)
+    offsets = np.concatenate([[0], np.cumsum(ns * ns)[:-1]]).astype(np.int64)
+    data = torch.empty(int((ns * ns).sum()), dtype=dtype, device=device)
+    for idx, pats in cfg["pattern_sets"]:
+        s = int(ns[idx[0]])
+        flat = pats.to(device=device, dtype=dtype).reshape(len(idx), s * s)
+        pos = torch.as_tensor(offsets[idx], device=device)[:, None] + torch.arange(s * s, device=device)[None, :]
+        data[pos.reshape(-1)] = flat.reshape(-1)
+    return data, offsets, ns.astype(np.int32)
+
+
+def ragged_pattern(cfg, i):
+    """Pattern i of a ragged workload as a host array."""
+    for idx, pats in cfg["pattern_sets"]:
+        j = np.nonzero(idx == i)[0]
+        if j.size:
+            return pats[int(j[0])].cpu().numpy()
+    raise IndexError(i)
