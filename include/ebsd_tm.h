@@ -243,6 +243,55 @@ int ebsd_measure_rotation(const float* pats, const float* tmpls, int64_t K, int3
 int ebsd_timing_enable(int enable);
 int ebsd_timing_read(double* total_ms, int64_t* launches);
 
+/*
+ * Ragged batches (patterns of several detector binnings in one call).
+ *
+ * A plan fixes the batch layout: P patterns, pattern p of side n_per[p]
+ * (64, 96, 128 or 160) stored row-major at element offset offset[p] of one
+ * packed float32 buffer; both arrays are HOST memory, read during the call.
+ * It also fixes the library size L and the parameters (the FP32 FFT form;
+ * max_shift, filter and upsampling as in ebsd_params).  Creating a plan
+ * allocates all device memory the runs need, and times candidate tiles of
+ * the persistent search kernel for every size present (the number of
+ * templates each work item correlates and the persistent grid), keeping the
+ * fastest (EBSD_RAGGED_NO_AUTOTUNE keeps 16 templates and the resident
+ * capacity).
+ *
+ * ebsd_ragged_run indexes the batch against the library (method of
+ * ebsd_index_patterns, each pattern against templates projected at its own
+ * size and the nominal pattern centre) and, with EBSD_RAGGED_STENCIL, then
+ * evaluates around each pattern's best template the 27 orientations
+ * R Q(a, b, c)^T, Q = Rz(c) Ry(b) Rx(a), a, b, c in {-d, 0, +d} with
+ * d = stencil_step_deg (numbered 9 i_a + 3 i_b + i_c, i = 0, 1, 2 for -d,
+ * 0, +d), each projected at the pattern's own pattern centre (geo->pc_per
+ * [P][3] device, or the nominal one), keeps the candidate with the largest
+ * integer correlation peak (ties: smaller number) and upsamples its peak;
+ * this grid search is the coarse alternative to the refinement that the
+ * paper's closing discussion mentions.
+ * Outputs in pattern order (device): best_idx [P] library index (may be
+ * NULL), q_out [P][4] final orientation, peak_h [P], shift [P][2] (x, y) of
+ * the final template, stencil_idx [P] chosen candidate number (-1 without
+ * the stencil; may be NULL).  The first run captures the whole sequence into
+ * one HIP graph; later runs with the same pointers and geometry replay it
+ * (EBSD_RAGGED_EAGER enqueues the kernels directly instead).  A plan serves
+ * one run at a time: runs of one plan on different streams race.
+ */
+typedef struct ebsd_ragged_plan_s* ebsd_ragged_plan;
+#define EBSD_RAGGED_STENCIL 1
+#define EBSD_RAGGED_EAGER 2
+#define EBSD_RAGGED_NO_AUTOTUNE 4
+
+int ebsd_ragged_plan_create(const int32_t* n_per, const int64_t* offset, int64_t P, int64_t L,
+                            const ebsd_params* prm, double stencil_step_deg, int32_t flags,
+                            ebsd_ragged_plan* plan);
+int ebsd_ragged_run(ebsd_ragged_plan plan, const float* data, const ebsd_master* mp, const ebsd_geometry* geo,
+                    const double* lib_q, int32_t* best_idx, double* q_out, float* peak_h, float* shift,
+                    int32_t* stencil_idx, void* stream);
+/* Chosen tiles: for each size present, tiles[4 k ..] = (n, patterns,
+ * templates per work item, persistent grid blocks); *count sizes (<= 4). */
+int ebsd_ragged_plan_tiles(ebsd_ragged_plan plan, int32_t* tiles, int32_t* count);
+int ebsd_ragged_plan_destroy(ebsd_ragged_plan plan);
+
 #ifdef __cplusplus
 }
 #endif

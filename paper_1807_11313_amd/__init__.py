@@ -15,7 +15,7 @@ import numpy as np
 
 __all__ = ["lib", "Params", "index_patterns", "refine_orientations", "project_templates",
            "pattern_spectra", "spectrum_floats", "xcf_peak", "xcf_scores", "xcf_subpixel",
-           "measure_rotation", "params_default", "version", "LIB_PATH", "EXPORTS"]
+           "measure_rotation", "params_default", "version", "RaggedPlan", "LIB_PATH", "EXPORTS"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libebsd_tm.so")
@@ -24,7 +24,10 @@ LIB_PATH = os.path.join(HERE, "libebsd_tm.so")
 EXPORTS = ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_index_patterns",
            "ebsd_refine_orientations", "ebsd_project_templates", "ebsd_pattern_spectra",
            "ebsd_spectrum_floats", "ebsd_xcf_peak", "ebsd_xcf_scores", "ebsd_xcf_subpixel",
-           "ebsd_measure_rotation", "ebsd_timing_enable", "ebsd_timing_read")
+           "ebsd_measure_rotation", "ebsd_timing_enable", "ebsd_timing_read", "ebsd_ragged_plan_create",
+           "ebsd_ragged_run", "ebsd_ragged_plan_tiles", "ebsd_ragged_plan_destroy")
+
+RAGGED_STENCIL, RAGGED_EAGER, RAGGED_NO_AUTOTUNE = 1, 2, 4
 
 EBSD_OK = 0
 ERRORS = {-1: "EBSD_E_INVALID", -2: "EBSD_E_NOMEM", -3: "EBSD_E_DEVICE", -4: "EBSD_E_UNSUPPORTED"}
@@ -86,6 +89,10 @@ def lib():
     L.ebsd_measure_rotation.argtypes = [vp, vp, i64, i32, dp(Params), vp, vp]
     L.ebsd_timing_enable.argtypes = [ctypes.c_int]
     L.ebsd_timing_read.argtypes = [dp(ctypes.c_double), dp(ctypes.c_int64)]
+    L.ebsd_ragged_plan_create.argtypes = [vp, vp, i64, i64, dp(Params), ctypes.c_double, i32, dp(vp)]
+    L.ebsd_ragged_run.argtypes = [vp, vp, dp(Master), dp(Geometry), vp, vp, vp, vp, vp, vp, vp]
+    L.ebsd_ragged_plan_tiles.argtypes = [vp, vp, dp(i32)]
+    L.ebsd_ragged_plan_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_spectrum_floats"):
             getattr(L, name).restype = ctypes.c_int
@@ -285,3 +292,67 @@ def band_to_full(band, n):
         if v > 0:
             full[..., (-u) % n, n - v] = np.conj(band[..., v, :])
     return full
+
+
+class RaggedPlan:
+    """A ragged batch layout (ebsd_ragged_plan_create): pattern p of side
+    sizes[p] at element offset offsets[p] of one packed float32 buffer
+    (host arrays), a library of L orientations and the parameters."""
+
+    def __init__(self, sizes, offsets, L, prm=None, stencil=True, step_deg=0.5, eager=False, autotune=True):
+        sizes = np.ascontiguousarray(sizes, dtype=np.int32)
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        if sizes.shape != offsets.shape or sizes.ndim != 1:
+            raise ValueError("sizes and offsets must be 1-D arrays of equal length")
+        self.P, self.L = int(sizes.shape[0]), int(L)
+        flags = (RAGGED_STENCIL if stencil else 0) | (RAGGED_EAGER if eager else 0) | \
+            (0 if autotune else RAGGED_NO_AUTOTUNE)
+        h = ctypes.c_void_p()
+        _check(lib().ebsd_ragged_plan_create(sizes.ctypes.data_as(ctypes.c_void_p),
+                                             offsets.ctypes.data_as(ctypes.c_void_p), self.P, self.L,
+                                             _params(prm), float(step_deg), flags, ctypes.byref(h)),
+               "ebsd_ragged_plan_create")
+        self._h = h
+
+    def run(self, data, master, pc, lib_q, pc_per=None, stencil_idx=True):
+        import torch
+        dev = data.device
+        p = self.P
+        out = dict(best_idx=torch.empty(p, dtype=torch.int32, device=dev),
+                   q=torch.empty((p, 4), dtype=torch.float64, device=dev),
+                   peak_h=torch.empty(p, dtype=torch.float32, device=dev),
+                   shift=torch.empty((p, 2), dtype=torch.float32, device=dev))
+        if stencil_idx:
+            out["stencil_idx"] = torch.empty(p, dtype=torch.int32, device=dev)
+        self.run_into(data, master, pc, lib_q, out, pc_per)
+        return out
+
+    def run_into(self, data, master, pc, lib_q, out, pc_per=None):
+        import torch
+        if lib_q.shape[0] != self.L:
+            raise ValueError("library size differs from the plan's")
+        m, g = _master(master), _geo(pc, pc_per)
+        _check(lib().ebsd_ragged_run(self._h, _ptr(data, torch.float32, "data"), ctypes.byref(m), ctypes.byref(g),
+                                     _ptr(lib_q, torch.float64, "lib_q"), _ptr(out.get("best_idx")),
+                                     _ptr(out["q"]), _ptr(out["peak_h"]), _ptr(out["shift"]),
+                                     _ptr(out.get("stencil_idx")), _stream()),
+               "ebsd_ragged_run")
+        return out
+
+    def tiles(self):
+        t = (ctypes.c_int32 * 16)()
+        c = ctypes.c_int32()
+        _check(lib().ebsd_ragged_plan_tiles(self._h, t, ctypes.byref(c)), "ebsd_ragged_plan_tiles")
+        return [dict(n=t[4 * k], patterns=t[4 * k + 1], templates_per_item=t[4 * k + 2], grid=t[4 * k + 3])
+                for k in range(c.value)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ebsd_ragged_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -2,6 +2,7 @@
 // sequence of each entry point (declared and documented in include/ebsd_tm.h).
 #include "../../include/ebsd_tm.h"
 #include "ebsd_internal.hpp"
+#include "api_util.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -14,7 +15,8 @@
 
 using namespace ebsd;
 
-namespace {
+namespace ebsd {
+namespace api {
 
 thread_local std::string g_last_error;
 
@@ -194,7 +196,10 @@ hipError_t timed_scores(int n, const ebsd_params& prm, const float2* sp, int64_t
   return hipSuccess;
 }
 
-}  // namespace
+}  // namespace api
+}  // namespace ebsd
+
+using namespace ebsd::api;
 
 extern "C" {
 

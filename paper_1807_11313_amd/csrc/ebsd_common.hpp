@@ -274,4 +274,20 @@ __device__ __forceinline__ void wave_argmax(float& v, int& i) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 quaternions (w, x, y, z): Hamilton product and storage normalised
+// with w >= 0.
+__device__ __forceinline__ void qmul(const double* a, const double* b, double* o) {
+  o[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+  o[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+  o[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+  o[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+}
+__device__ __forceinline__ void qstore(double* q, const double* v) {
+  const double s = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3]);
+  const double sg = v[0] < 0.0 ? -s : s;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) q[c] = v[c] * sg;
+}
+
 }  // namespace ebsd

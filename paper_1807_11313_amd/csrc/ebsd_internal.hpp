@@ -43,6 +43,20 @@ hipError_t launch_spectra(int n, const float* imgs, int64_t img_stride, int64_t 
                           const FilterParams& fp, float2* spec, double* energy,
                           hipStream_t stream);
 
+// Spectra of K images at element offsets img_off[k] of imgs.
+hipError_t launch_spectra_gather(int n, const float* imgs, const int64_t* img_off, int64_t k,
+                                 const FilterParams& fp, float2* spec, double* energy, hipStream_t stream);
+
+// Persistent form of the search (sizes 64 to 160): `grid` blocks take
+// (pattern, chunk of lchunk templates) items from the device counter *queue,
+// which must be zero when the kernel starts.  Block size and the resident
+// blocks per CU of the kernel that serves size n.
+int xcf_block_threads(int n);
+hipError_t xcf_persistent_occupancy(int n, int max_shift, int* blocks_per_cu);
+hipError_t launch_xcf_scores_persistent(int n, const float2* spec_p, int64_t p, const float2* spec_l, int64_t l,
+                                        int max_shift, float* scores, int lchunk, int grid, int* queue,
+                                        hipStream_t stream);
+
 // Integer-peak scores h[p][l] = max_s rho(p, l; s) for every pattern x template.
 hipError_t launch_xcf_scores(int n, const float2* spec_p, int64_t p, const float2* spec_l,
                              int64_t l, int max_shift, float* scores, hipStream_t stream);

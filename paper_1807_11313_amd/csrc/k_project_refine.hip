@@ -327,19 +327,6 @@ __global__ __launch_bounds__(256) void k_eta_peak(const float* __restrict__ lp_e
 // FP64 orientation updates (Equation 7 with the atan reading; log-polar z):
 // with c = R d, a crystal rotated by Q in the detector frame has orientation
 // R Q^T, i.e. quaternion q (x) conj(q_Q).
-__device__ __forceinline__ void qmul(const double* a, const double* b, double* o) {
-  o[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
-  o[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
-  o[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
-  o[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
-}
-__device__ __forceinline__ void qstore(double* q, const double* v) {
-  const double s = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3]);
-  const double sg = v[0] < 0.0 ? -s : s;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) q[c] = v[c] * sg;
-}
-
 __global__ void k_update_xy(double* __restrict__ q, const float* __restrict__ s_sub, int64_t kk,
                             const double* __restrict__ pc_per, double pcz, int n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;

@@ -203,30 +203,50 @@ __device__ __forceinline__ float block_max(float v, float* red, int tid) {
 // Scores of every pattern against a chunk of templates.  Blocks are
 // numbered so that consecutive blocks on one XCD (blocks are dealt to the 8
 // XCDs round robin) share a template chunk, which then stays in that XCD's L2.
-template <int N, int NT>
+//
+// PERSIST: the grid is sized to the resident capacity and every block takes
+// work items (pattern, template chunk) from the device counter *queue (zero
+// at launch) until all nblk items are taken; items are numbered chunk-major
+// as the block numbers are, so concurrently running blocks share a chunk.
+template <int N, int NT, bool PERSIST>
 __global__ __launch_bounds__(NT) void k_xcf_scores(const cf* __restrict__ spec_p, int64_t np,
                                                    const cf* __restrict__ spec_l, int64_t nl,
                                                    int lchunk, int64_t nblk, int max_shift,
-                                                   float* __restrict__ scores) {
+                                                   float* __restrict__ scores, int* __restrict__ queue) {
   using L = Lay<N>;
   __shared__ cf lds[L::LDS];
   __shared__ cf tw[N];
   __shared__ float red[NT / 64];
+  __shared__ int item;
   const int tid = threadIdx.x;
-  const int64_t per = (nblk + 7) / 8;
-  const int64_t g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  int64_t g;
+  if constexpr (PERSIST) {
+    if (tid == 0) item = atomicAdd(queue, 1);
+    __syncthreads();
+    g = item;
+  } else {
+    const int64_t per = (nblk + 7) / 8;
+    g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  }
   if (g >= nblk) return;
-  const int64_t chunk = g / np, p = g - chunk * np;
   load_roots<N, NT>(tw, tid);
   __syncthreads();
-  const cf* E = spec_p + p * L::SPEC;
-  const int64_t l0 = chunk * lchunk;
-  const int64_t l1 = l0 + lchunk < nl ? l0 + lchunk : nl;
-  for (int64_t l = l0; l < l1; ++l) {
-    MaxEpi epi{-INFINITY, N, max_shift};
-    xcf_core<N, NT>(E, spec_l + l * L::SPEC, lds, tw, tid, epi);
-    const float m = block_max<NT>(epi.m, red, tid);
-    if (tid == 0) scores[p * nl + l] = m;
+  while (g < nblk) {
+    const int64_t chunk = g / np, p = g - chunk * np;
+    const cf* E = spec_p + p * L::SPEC;
+    const int64_t l0 = chunk * lchunk;
+    const int64_t l1 = l0 + lchunk < nl ? l0 + lchunk : nl;
+    for (int64_t l = l0; l < l1; ++l) {
+      MaxEpi epi{-INFINITY, N, max_shift};
+      xcf_core<N, NT>(E, spec_l + l * L::SPEC, lds, tw, tid, epi);
+      const float m = block_max<NT>(epi.m, red, tid);
+      if (tid == 0) scores[p * nl + l] = m;
+    }
+    if constexpr (!PERSIST) break;
+    __syncthreads();
+    if (tid == 0) item = atomicAdd(queue, 1);
+    __syncthreads();
+    g = item;
   }
 }
 
@@ -289,11 +309,11 @@ struct RootTable {
 };
 __constant__ RootTable<128> c_roots128 = RootTable<128>();
 
-template <bool WINDOW>
+template <bool WINDOW, bool PERSIST>
 __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__ spec_p, int64_t np,
                                                           const cf* __restrict__ spec_l, int64_t nl,
                                                           int lchunk, int64_t nblk, int max_shift,
-                                                          float* __restrict__ scores) {
+                                                          float* __restrict__ scores, int* __restrict__ queue) {
   constexpr int N = 128, R1 = 16, R2 = 8, B = 48, NV = 49;
   constexpr int SPEC = NV * (2 * B + 1);
   constexpr int AV = N + 1;  // A[v][y] row stride (odd: the phase-2 writes spread over banks)
@@ -304,10 +324,17 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t per = (nblk + 7) / 8;
-  const int64_t g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  __shared__ int item;
+  int64_t g;
+  if constexpr (PERSIST) {
+    if (tid == 0) item = atomicAdd(queue, 1);
+    __syncthreads();
+    g = item;
+  } else {
+    const int64_t per = (nblk + 7) / 8;
+    g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  }
   if (g >= nblk) return;
-  const int64_t chunk = g / np, p = g - chunk * np;
   const bool vlane = lane < NV;
 
   // inter-pass twiddles w^(wave c), c = 1..15: the same set in phases 1 and 3
@@ -315,6 +342,8 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
 #pragma unroll
   for (int c = 0; c < R1; ++c) tw[c] = c_roots128.w[(wave * c) & (N - 1)];
 
+  while (g < nblk) {
+  const int64_t chunk = g / np, p = g - chunk * np;
   // pattern spectrum values used by this lane in phase 1
   const cf* E = spec_p + p * SPEC;
   cf ev[R1];
@@ -422,14 +451,20 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
       scores[p * nl + l] = r;
     }
   }
+  if constexpr (!PERSIST) break;
+  __syncthreads();
+  if (tid == 0) item = atomicAdd(queue, 1);
+  __syncthreads();
+  g = item;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Forward spectra of K images.
 template <int N, int NT>
 __global__ __launch_bounds__(NT) void k_spectra(const float* __restrict__ imgs, int64_t img_stride,
-                                                FilterParams fp, cf* __restrict__ spec,
-                                                double* __restrict__ energy) {
+                                                const int64_t* __restrict__ img_off, FilterParams fp,
+                                                cf* __restrict__ spec, double* __restrict__ energy) {
   using L = Lay<N>;
   constexpr int R1 = L::R1, R2 = L::R2, B = L::B, NV = L::NV, NK = L::NK;
   __shared__ cf lds[L::LDS];
@@ -438,7 +473,7 @@ __global__ __launch_bounds__(NT) void k_spectra(const float* __restrict__ imgs, 
   __shared__ double red[2 * (NT / 64)];
   const int tid = threadIdx.x;
   const int64_t k = blockIdx.x;
-  const float* img = imgs + k * img_stride;
+  const float* img = imgs + (img_off ? img_off[k] : k * img_stride);
   load_roots<N, NT>(tw, tid);
   for (int i = tid; i < N; i += NT) {
     const float s = sinpif(((float)i + 0.5f) / (float)N);
@@ -657,8 +692,19 @@ hipError_t launch_spectra(int n, const float* imgs, int64_t img_stride, int64_t 
   if (k <= 0) return hipSuccess;
   EBSD_DISPATCH(n, {
     constexpr int NT = nt_spec<NN>();
-    hipLaunchKernelGGL((k_spectra<NN, NT>), dim3((unsigned)k), dim3(NT), 0, stream, imgs, img_stride, fp,
-                       (cf*)spec, energy);
+    hipLaunchKernelGGL((k_spectra<NN, NT>), dim3((unsigned)k), dim3(NT), 0, stream, imgs, img_stride,
+                       (const int64_t*)nullptr, fp, (cf*)spec, energy);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_spectra_gather(int n, const float* imgs, const int64_t* img_off, int64_t k,
+                                 const FilterParams& fp, float2* spec, double* energy, hipStream_t stream) {
+  if (k <= 0) return hipSuccess;
+  EBSD_DISPATCH(n, {
+    constexpr int NT = nt_spec<NN>();
+    hipLaunchKernelGGL((k_spectra<NN, NT>), dim3((unsigned)k), dim3(NT), 0, stream, imgs, (int64_t)0, img_off,
+                       fp, (cf*)spec, energy);
   });
   return hipGetLastError();
 }
@@ -673,17 +719,66 @@ hipError_t launch_xcf_scores(int n, const float2* spec_p, int64_t p, const float
   if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
   if (n == 128) {
     if (max_shift < 0)
-      hipLaunchKernelGGL((k_xcf_scores128<false>), dim3((unsigned)grid), dim3(512), 0, stream, (const cf*)spec_p, p,
-                         (const cf*)spec_l, l, lchunk, nblk, max_shift, scores);
+      hipLaunchKernelGGL((k_xcf_scores128<false, false>), dim3((unsigned)grid), dim3(512), 0, stream,
+                         (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, nullptr);
     else
-      hipLaunchKernelGGL((k_xcf_scores128<true>), dim3((unsigned)grid), dim3(512), 0, stream, (const cf*)spec_p, p,
-                         (const cf*)spec_l, l, lchunk, nblk, max_shift, scores);
+      hipLaunchKernelGGL((k_xcf_scores128<true, false>), dim3((unsigned)grid), dim3(512), 0, stream,
+                         (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, nullptr);
     return hipGetLastError();
   }
   EBSD_DISPATCH(n, {
     constexpr int NT = nt_xcf<NN>();
-    hipLaunchKernelGGL((k_xcf_scores<NN, NT>), dim3((unsigned)grid), dim3(NT), 0, stream, (const cf*)spec_p,
-                       p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores);
+    hipLaunchKernelGGL((k_xcf_scores<NN, NT, false>), dim3((unsigned)grid), dim3(NT), 0, stream,
+                       (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, nullptr);
+  });
+  return hipGetLastError();
+}
+
+int xcf_block_threads(int n) {
+  if (n == 128) return 512;
+  switch (n) {
+    case 64: return nt_xcf<64>();
+    case 96: return nt_xcf<96>();
+    case 160: return nt_xcf<160>();
+    default: return 0;
+  }
+}
+
+hipError_t xcf_persistent_occupancy(int n, int max_shift, int* blocks_per_cu) {
+  *blocks_per_cu = 0;
+  if (n == 128) {
+    return max_shift < 0
+               ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_xcf_scores128<false, true>, 512, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_xcf_scores128<true, true>, 512, 0);
+  }
+  EBSD_DISPATCH(n, {
+    constexpr int NT = nt_xcf<NN>();
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_xcf_scores<NN, NT, true>, NT, 0);
+  });
+  return hipSuccess;
+}
+
+hipError_t launch_xcf_scores_persistent(int n, const float2* spec_p, int64_t p, const float2* spec_l, int64_t l,
+                                        int max_shift, float* scores, int lchunk, int grid, int* queue,
+                                        hipStream_t stream) {
+  if (p <= 0 || l <= 0) return hipSuccess;
+  if (lchunk < 1 || grid < 1) return hipErrorInvalidValue;
+  const int64_t nchunk = (l + lchunk - 1) / lchunk;
+  const int64_t nblk = p * nchunk;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (n == 128) {
+    if (max_shift < 0)
+      hipLaunchKernelGGL((k_xcf_scores128<false, true>), dim3((unsigned)grid), dim3(512), 0, stream,
+                         (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, queue);
+    else
+      hipLaunchKernelGGL((k_xcf_scores128<true, true>), dim3((unsigned)grid), dim3(512), 0, stream,
+                         (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, queue);
+    return hipGetLastError();
+  }
+  EBSD_DISPATCH(n, {
+    constexpr int NT = nt_xcf<NN>();
+    hipLaunchKernelGGL((k_xcf_scores<NN, NT, true>), dim3((unsigned)grid), dim3(NT), 0, stream,
+                       (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, queue);
   });
   return hipGetLastError();
 }

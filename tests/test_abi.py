@@ -77,3 +77,30 @@ def test_argument_errors():
     assert _index(pkg, lib, ok, pkg.params_default(max_shift=-3)) == -1
     # an empty batch is a valid no-op
     assert _index(pkg, lib, pkg.Batch(0x6000, 0, 64), prm) == 0
+
+
+def test_ragged_plan_argument_errors():
+    # every rejection below happens before the library touches the device
+    pkg, lib = _lib()
+    import numpy as np
+    sizes = np.array([64, 96, 128, 160], np.int32)
+    offs = np.array([0, 4096, 4096 + 9216, 4096 + 9216 + 16384], np.int64)
+    h = ctypes.c_void_p()
+
+    def create(sz, off, P=4, L=10, prm=None, step=0.5, flags=1, plan=True):
+        return lib.ebsd_ragged_plan_create(None if sz is None else sz.ctypes.data_as(ctypes.c_void_p),
+                                           None if off is None else off.ctypes.data_as(ctypes.c_void_p), P, L,
+                                           ctypes.byref(prm) if prm is not None else None, step, flags,
+                                           ctypes.byref(h) if plan else None)
+
+    assert create(sizes, offs, plan=False) == -1
+    assert create(None, offs) == -1
+    assert create(sizes, offs, L=0) == -1
+    assert create(sizes, offs, P=0) == -1
+    assert create(sizes, offs, step=0.0) == -1
+    assert create(sizes, offs, flags=64) == -1
+    assert create(np.array([64, 96, 128, 256], np.int32), offs) == -4          # 256 is not a ragged size
+    assert create(sizes, np.array([0, -1, 5, 6], np.int64)) == -1
+    assert create(sizes, offs, prm=pkg.params_default(precision=1, max_shift=5)) == -4
+    assert h.value is None
+    assert lib.ebsd_ragged_plan_destroy(None) == 0
