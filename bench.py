@@ -91,6 +91,11 @@ def main():
                     help="skip the split-precision search on the same map at 256^2")
     ap.add_argument("--precision-patterns", type=int, default=10000)
     ap.add_argument("--precision-steps", type=int, default=2)
+    ap.add_argument("--no-ragged", action="store_true",
+                    help="skip the ragged batch (binnings 64-160, 27-point stencil, one graph launch)")
+    ap.add_argument("--ragged-patterns", type=int, default=20000)
+    ap.add_argument("--ragged-library", type=int, default=8000)
+    ap.add_argument("--ragged-steps", type=int, default=2)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one elementwise copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -203,6 +208,9 @@ def main():
         del pats, cfg, out, idx
         torch.cuda.empty_cache()
         line["precision256"] = precision_256(tm, args.precision_patterns, args.library, args.precision_steps)
+    if not args.no_ragged:
+        torch.cuda.empty_cache()
+        line["ragged"] = ragged_batch(tm, args.ragged_patterns, args.ragged_library, args.ragged_steps)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(cpu_cfg, n, L, P)
@@ -366,6 +374,74 @@ def precision_256(tm, patterns, library, steps, window=15, sample=3, n_sub=96):
         print("[bench] 256 %s: %.0f patterns/s, %.3g pairs/s, oracle |dh| %.2g"
               % (name, res[name]["patterns_per_s"], res[name]["xcf_pairs_per_s"], d_score),
               file=sys.stderr, flush=True)
+    return res
+
+
+def ragged_batch(tm, patterns, library, steps, sample_per_size=1):
+    """Patterns of binnings 64, 96, 128 and 160 (25 % each, shuffled) against
+    one library, followed by the 27-point +-0.5 deg stencil, as one graph
+    launch per step (plan built once, tiles autotuned at plan creation).
+    Reports patterns/s and library pairs/s of the whole step, the chosen
+    tiles, accuracy against the simulated truth, and agreement of the
+    stencil's choice with the FP64 oracle from the same start on a sample."""
+    import numpy as np
+    import torch
+    import oracle
+    from fixtures import configs
+    from oracle import rotations, stencil
+
+    dev = torch.device("cuda:0")
+    print("[bench] generating ragged workload: %d patterns, library %d" % (patterns, library),
+          file=sys.stderr, flush=True)
+    cfg = configs.ragged(p=patterns, l=library, device=dev)
+    data, offs, ns = configs.pack_ragged(cfg, device=dev)
+    cfg["pattern_sets"] = [(idx, pats.cpu()) for idx, pats in cfg["pattern_sets"]]
+    master = torch.as_tensor(cfg["master"], device=dev).contiguous()
+    lib_q = torch.as_tensor(cfg["lib_q"], device=dev).contiguous()
+    pc_per = torch.as_tensor(cfg["pcs"], device=dev).contiguous()
+    P, L = len(ns), len(cfg["lib_q"])
+    t0 = time.perf_counter()
+    plan = tm.RaggedPlan(ns, offs, L, stencil=True)
+    t_plan = time.perf_counter() - t0
+    out = plan.run(data, master, cfg["pc"], lib_q, pc_per=pc_per)       # capture + first run
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run_into(data, master, cfg["pc"], lib_q, out, pc_per)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    q = out["q"].cpu().numpy()
+    best = out["best_idx"].cpu().numpy()
+    sidx = out["stencil_idx"].cpu().numpy()
+    pts = np.linspace(0, P - 1, 200).astype(int)
+    vs_true = np.rad2deg([rotations.disorientation_q(q[i], cfg["true_q"][i]) for i in pts])
+    lib_true = np.rad2deg([rotations.disorientation_q(cfg["lib_q"][best[i]], cfg["true_q"][i]) for i in pts])
+    # the stencil's choice against the oracle's from the same library pick
+    agree, dh, total = 0, 0.0, 0
+    prm = oracle.Params()
+    for n in (64, 96, 128, 160):
+        for i in np.nonzero(ns == n)[0][:sample_per_size]:
+            st = stencil.stencil_refine([configs.ragged_pattern(cfg, i)], cfg["master"], cfg["pcs"][i:i + 1],
+                                        cfg["lib_q"][best[i]][None], prm)
+            total += 1
+            if st["idx"][0] == sidx[i]:
+                agree += 1
+                dh = max(dh, abs(float(out["peak_h"][i]) - st["peak_h"][0]))
+    res = {"workload": "ragged: %d patterns, binnings 64/96/128/160 (25%% each, shuffled), %d-orientation cubic "
+                       "library, exhaustive FFT XCF + 27-point +-0.5 deg stencil, one graph launch per step"
+                       % (P, L),
+           "patterns_per_s": P / dt, "ms_per_step": dt * 1e3, "library_pairs_per_s_whole_step": P * L / dt,
+           "stencil_candidates_per_step": 27 * P, "plan_create_s_incl_autotune": t_plan,
+           "tiles": plan.tiles(), "steps": steps,
+           "library_pick_vs_truth_deg_median": float(np.median(lib_true)),
+           "stencil_vs_truth_deg_median": float(np.median(vs_true)),
+           "stencil_vs_truth_deg_p95": float(np.percentile(vs_true, 95)),
+           "stencil_vs_oracle": {"agreement": agree / max(total, 1), "sample": total,
+                                 "max_abs_peak_h": dh}}
+    print("[bench] ragged: %.0f patterns/s, %.3g library pairs/s" % (res["patterns_per_s"],
+                                                                      res["library_pairs_per_s_whole_step"]),
+          file=sys.stderr, flush=True)
+    plan.close()
     return res
 
 
