@@ -292,6 +292,69 @@ int ebsd_ragged_run(ebsd_ragged_plan plan, const float* data, const ebsd_master*
 int ebsd_ragged_plan_tiles(ebsd_ragged_plan plan, int32_t* tiles, int32_t* count);
 int ebsd_ragged_plan_destroy(ebsd_ragged_plan plan);
 
+/*
+ * Learned proposal.  The paper ranks every template by correlation; here a
+ * small convolutional network ranks the library orientations first and the
+ * correlation runs only on its top k, with the exhaustive search as the
+ * fallback for every pattern whose best peak height stays below a threshold
+ * (the peak height is the paper's quality measure, section "Deformed
+ * alpha-Fe Dataset").  Network: the pattern binned by block means to
+ * 64 x 64 and normalised to zero mean, unit variance; four 3 x 3
+ * convolutions (zero padding, bias, ReLU) with 32, 64, 128, 128 channels,
+ * each followed by a 2 x 2 max pool; a fully connected layer from the
+ * 128 x 4 x 4 features to the L library orientations; softmax
+ * cross-entropy against the library orientation nearest (cubic
+ * disorientation) to the true one.  FP32 throughout.  Parameters are one
+ * flat float vector: conv_i.w [co][ci][3][3], conv_i.b [co] for i = 1..4,
+ * fc.w [L][2048], fc.b [L].  A network object owns its parameters, Adam
+ * state and workspace on the device it was created on.
+ */
+typedef struct ebsd_cnn_s* ebsd_cnn;
+
+/* Number of parameters for L classes (-1 for L < 1). */
+int64_t ebsd_cnn_param_count(int32_t n_classes);
+/* He-normal weights from a Philox4x32-10 stream keyed by seed, zero biases. */
+int ebsd_cnn_create(int32_t n_classes, uint64_t seed, ebsd_cnn* out, void* stream);
+int ebsd_cnn_destroy(ebsd_cnn cnn);
+/* Copy the parameter vector out of / into the network (device [count]);
+ * setting parameters also resets the Adam state. */
+int ebsd_cnn_get_params(ebsd_cnn cnn, float* out, void* stream);
+int ebsd_cnn_set_params(ebsd_cnn cnn, const float* in, void* stream);
+/* Network inputs x [P][64][64] from patterns [P][n][n], n a multiple of 64. */
+int ebsd_cnn_input(const float* pats, int64_t P, int32_t n, float* x, void* stream);
+/* Scores over the library, logits [B][L]. */
+int ebsd_cnn_forward(ebsd_cnn cnn, const float* x, int64_t B, float* logits, void* stream);
+/* Mean cross-entropy of the batch (device float *loss) and its gradient
+ * (device [count], parameter order); B in [1, 4096]. */
+int ebsd_cnn_gradients(ebsd_cnn cnn, const float* x, const int32_t* labels, int64_t B, float* grad, float* loss,
+                       void* stream);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8) on the batch's gradient. */
+int ebsd_cnn_train_step(ebsd_cnn cnn, const float* x, const int32_t* labels, int64_t B, float lr, float* loss,
+                        void* stream);
+/* Training data made on the device: sample s in [first, first + B) gets a
+ * uniform random orientation and an in-plane pattern-centre offset of up to
+ * +-max_offset_px (Philox4x32-10 keyed by seed, counter s), is projected at
+ * n x n from the master, scaled to `counts` mean counts with Poisson noise
+ * (normal approximation) plus Gaussian noise for the given SNR, and binned
+ * into x [B][64][64]; labels [B] (optional) is its nearest library
+ * orientation, q_true [B][4] (optional) its orientation. */
+int ebsd_cnn_make_batch(const ebsd_master* mp, const ebsd_geometry* geo, const double* lib_q, int64_t L, int32_t n,
+                        int64_t B, int64_t first, uint64_t seed, double max_offset_px, double counts, double snr,
+                        float* x, int32_t* labels, double* q_true, void* stream);
+/* The k best library indices per row of logits [rows][L], best first (ties:
+ * smaller index). */
+int ebsd_cnn_topk(const float* logits, int64_t rows, int32_t L, int32_t k, int32_t* idx, void* stream);
+/* ebsd_index_patterns with the search pruned to the network's top_k
+ * orientations per pattern (n = 64 or 128, FP32 FFT form): the best
+ * candidate by integer peak height (ties: smaller library index); patterns
+ * whose best stays below fallback_tau are searched exhaustively, and
+ * fallback [P] (optional) marks them.  Outputs as ebsd_index_patterns.  The
+ * call waits for the stream once, to learn how many patterns fall back. */
+int ebsd_index_proposed(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo,
+                        const double* lib_q, int64_t L, ebsd_cnn cnn, int32_t top_k, float fallback_tau,
+                        const ebsd_params* prm, int32_t* best_idx, double* best_q, float* peak_h, float* shift,
+                        int32_t* fallback, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

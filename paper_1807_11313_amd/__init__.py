@@ -15,7 +15,8 @@ import numpy as np
 
 __all__ = ["lib", "Params", "index_patterns", "refine_orientations", "project_templates",
            "pattern_spectra", "spectrum_floats", "xcf_peak", "xcf_scores", "xcf_subpixel",
-           "measure_rotation", "params_default", "version", "RaggedPlan", "LIB_PATH", "EXPORTS"]
+           "measure_rotation", "params_default", "version", "RaggedPlan", "Cnn", "cnn_make_batch", "cnn_topk",
+           "index_proposed", "LIB_PATH", "EXPORTS"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libebsd_tm.so")
@@ -25,7 +26,10 @@ EXPORTS = ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_index
            "ebsd_refine_orientations", "ebsd_project_templates", "ebsd_pattern_spectra",
            "ebsd_spectrum_floats", "ebsd_xcf_peak", "ebsd_xcf_scores", "ebsd_xcf_subpixel",
            "ebsd_measure_rotation", "ebsd_timing_enable", "ebsd_timing_read", "ebsd_ragged_plan_create",
-           "ebsd_ragged_run", "ebsd_ragged_plan_tiles", "ebsd_ragged_plan_destroy")
+           "ebsd_ragged_run", "ebsd_ragged_plan_tiles", "ebsd_ragged_plan_destroy", "ebsd_cnn_param_count",
+           "ebsd_cnn_create", "ebsd_cnn_destroy", "ebsd_cnn_get_params", "ebsd_cnn_set_params", "ebsd_cnn_input",
+           "ebsd_cnn_forward", "ebsd_cnn_gradients", "ebsd_cnn_train_step", "ebsd_cnn_make_batch", "ebsd_cnn_topk",
+           "ebsd_index_proposed")
 
 RAGGED_STENCIL, RAGGED_EAGER, RAGGED_NO_AUTOTUNE = 1, 2, 4
 
@@ -93,8 +97,25 @@ def lib():
     L.ebsd_ragged_run.argtypes = [vp, vp, dp(Master), dp(Geometry), vp, vp, vp, vp, vp, vp, vp]
     L.ebsd_ragged_plan_tiles.argtypes = [vp, vp, dp(i32)]
     L.ebsd_ragged_plan_destroy.argtypes = [vp]
+    u64, f32, f64 = ctypes.c_uint64, ctypes.c_float, ctypes.c_double
+    L.ebsd_cnn_param_count.argtypes = [i32]
+    L.ebsd_cnn_param_count.restype = i64
+    L.ebsd_cnn_create.argtypes = [i32, u64, dp(vp), vp]
+    L.ebsd_cnn_destroy.argtypes = [vp]
+    L.ebsd_cnn_get_params.argtypes = [vp, vp, vp]
+    L.ebsd_cnn_set_params.argtypes = [vp, vp, vp]
+    L.ebsd_cnn_input.argtypes = [vp, i64, i32, vp, vp]
+    L.ebsd_cnn_forward.argtypes = [vp, vp, i64, vp, vp]
+    L.ebsd_cnn_gradients.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.ebsd_cnn_train_step.argtypes = [vp, vp, vp, i64, f32, vp, vp]
+    L.ebsd_cnn_make_batch.argtypes = [dp(Master), dp(Geometry), vp, i64, i32, i64, i64, u64, f64, f64, f64, vp, vp,
+                                      vp, vp]
+    L.ebsd_cnn_topk.argtypes = [vp, i64, i32, i32, vp, vp]
+    L.ebsd_index_proposed.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, i64, vp, i32, f32, dp(Params), vp,
+                                      vp, vp, vp, vp, vp]
     for name in EXPORTS:
-        if name not in ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_spectrum_floats"):
+        if name not in ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_spectrum_floats",
+                        "ebsd_cnn_param_count"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -356,3 +377,116 @@ class RaggedPlan:
             self.close()
         except Exception:
             pass
+
+
+class Cnn:
+    """The proposal network (ebsd_cnn_*): parameters, Adam state and
+    workspace on the current device."""
+
+    def __init__(self, n_classes, seed=0):
+        self.n_classes = int(n_classes)
+        h = ctypes.c_void_p()
+        _check(lib().ebsd_cnn_create(self.n_classes, int(seed), ctypes.byref(h), _stream()), "ebsd_cnn_create")
+        self._h = h
+
+    @property
+    def param_count(self):
+        return lib().ebsd_cnn_param_count(self.n_classes)
+
+    def get_params(self):
+        import torch
+        out = torch.empty(self.param_count, dtype=torch.float32, device="cuda")
+        _check(lib().ebsd_cnn_get_params(self._h, _ptr(out), _stream()), "ebsd_cnn_get_params")
+        return out
+
+    def set_params(self, t):
+        import torch
+        if t.numel() != self.param_count:
+            raise ValueError("expected %d parameters" % self.param_count)
+        _check(lib().ebsd_cnn_set_params(self._h, _ptr(t, torch.float32, "params"), _stream()),
+               "ebsd_cnn_set_params")
+
+    @staticmethod
+    def input(patterns):
+        import torch
+        p, n = patterns.shape[0], patterns.shape[-1]
+        x = torch.empty((p, 64, 64), dtype=torch.float32, device=patterns.device)
+        _check(lib().ebsd_cnn_input(_ptr(patterns, torch.float32, "patterns"), p, n, _ptr(x), _stream()),
+               "ebsd_cnn_input")
+        return x
+
+    def forward(self, x):
+        import torch
+        out = torch.empty((x.shape[0], self.n_classes), dtype=torch.float32, device=x.device)
+        _check(lib().ebsd_cnn_forward(self._h, _ptr(x, torch.float32, "x"), x.shape[0], _ptr(out), _stream()),
+               "ebsd_cnn_forward")
+        return out
+
+    def gradients(self, x, labels):
+        import torch
+        g = torch.empty(self.param_count, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _check(lib().ebsd_cnn_gradients(self._h, _ptr(x, torch.float32, "x"), _ptr(labels, torch.int32, "labels"),
+                                        x.shape[0], _ptr(g), _ptr(loss), _stream()), "ebsd_cnn_gradients")
+        return g, loss
+
+    def train_step(self, x, labels, lr, loss=None):
+        import torch
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _check(lib().ebsd_cnn_train_step(self._h, _ptr(x, torch.float32, "x"), _ptr(labels, torch.int32, "labels"),
+                                         x.shape[0], float(lr), _ptr(loss), _stream()), "ebsd_cnn_train_step")
+        return loss
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ebsd_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cnn_make_batch(master, pc, lib_q, n, batch, first, seed, max_offset_px=5.0, counts=1000.0, snr=5.0,
+                   x=None, labels=None, q_true=None):
+    import torch
+    dev = master.device
+    x = x if x is not None else torch.empty((batch, 64, 64), dtype=torch.float32, device=dev)
+    m, g = _master(master), _geo(pc)
+    L = lib_q.shape[0] if lib_q is not None else 0
+    _check(lib().ebsd_cnn_make_batch(ctypes.byref(m), ctypes.byref(g), _ptr(lib_q, torch.float64, "lib_q"), L, n,
+                                     batch, first, int(seed), float(max_offset_px), float(counts), float(snr),
+                                     _ptr(x), _ptr(labels, torch.int32, "labels"),
+                                     _ptr(q_true, torch.float64, "q_true"), _stream()),
+           "ebsd_cnn_make_batch")
+    return x
+
+
+def cnn_topk(logits, k):
+    import torch
+    idx = torch.empty((logits.shape[0], k), dtype=torch.int32, device=logits.device)
+    _check(lib().ebsd_cnn_topk(_ptr(logits, torch.float32, "logits"), logits.shape[0], logits.shape[1], k, _ptr(idx),
+                               _stream()), "ebsd_cnn_topk")
+    return idx
+
+
+def index_proposed(patterns, master, pc, lib_q, cnn, top_k=32, fallback_tau=0.0, prm=None):
+    import torch
+    p, n = patterns.shape[0], patterns.shape[-1]
+    dev = patterns.device
+    out = dict(best_idx=torch.empty(p, dtype=torch.int32, device=dev),
+               best_q=torch.empty((p, 4), dtype=torch.float64, device=dev),
+               peak_h=torch.empty(p, dtype=torch.float32, device=dev),
+               shift=torch.empty((p, 2), dtype=torch.float32, device=dev),
+               fallback=torch.empty(p, dtype=torch.int32, device=dev))
+    b = Batch(_ptr(patterns, torch.float32, "patterns").value, p, n)
+    m, g = _master(master), _geo(pc)
+    _check(lib().ebsd_index_proposed(ctypes.byref(b), ctypes.byref(m), ctypes.byref(g),
+                                     _ptr(lib_q, torch.float64, "lib_q"), lib_q.shape[0], cnn._h, top_k,
+                                     float(fallback_tau), _params(prm), _ptr(out["best_idx"]), _ptr(out["best_q"]),
+                                     _ptr(out["peak_h"]), _ptr(out["shift"]), _ptr(out["fallback"]), _stream()),
+           "ebsd_index_proposed")
+    return out

@@ -1,0 +1,742 @@
+// Kernels of the proposal network (FP32): convolution and fully connected
+// layers as tiled GEMMs whose operands are read through index maps (the
+// convolution's im2col never exists in memory), pooling, softmax
+// cross-entropy, Adam, and the on-device training-data generator (random
+// orientations, projection noise, binning, nearest-library labels).
+#include "cnn_internal.hpp"
+#include "ebsd_common.hpp"
+
+#include <math.h>
+
+namespace ebsd {
+namespace cnn {
+
+// ---------------------------------------------------------------------------
+// Tiled FP32 GEMM: C(m, n) = sum_k A(m, k) B(k, n) over k in the block's
+// slice [z * kslice, (z + 1) * kslice) of [0, K).  64 x 64 tiles, 16-deep
+// K steps through LDS, 4 x 4 outputs per thread at (ty + 16 i, tx + 16 j).
+// A::KFAST / B::KFAST choose which index runs along consecutive threads when
+// the tile is loaded (the one that is contiguous in memory).
+template <class A, class Bm, class Out>
+__global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N, int K, int kslice) {
+  __shared__ float as[16][64 + 1];
+  __shared__ float bs[16][64 + 1];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int kb = blockIdx.z * kslice;
+  const int ke = min(K, kb + kslice);
+  float acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0f;
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int idx = tid + 256 * r;
+      int mm, kk;
+      if constexpr (A::KFAST) {
+        kk = idx & 15;
+        mm = idx >> 4;
+      } else {
+        mm = idx & 63;
+        kk = idx >> 6;
+      }
+      const int m = m0 + mm, k = k0 + kk;
+      as[kk][mm] = (m < M && k < ke) ? a(m, k) : 0.0f;
+      int nn;
+      if constexpr (Bm::KFAST) {
+        kk = idx & 15;
+        nn = idx >> 4;
+      } else {
+        nn = idx & 63;
+        kk = idx >> 6;
+      }
+      const int n = n0 + nn, k2 = k0 + kk;
+      bs[kk][nn] = (n < N && k2 < ke) ? b(k2, n) : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      float ar[4], br[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ar[i] = as[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) br[j] = bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __fmaf_rn(ar[i], br[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
+      if (m < M && n < N) out(m, n, acc[i][j], blockIdx.z);
+    }
+}
+
+// --- operand maps ---------------------------------------------------------
+// Images are NCHW with H = W = 1 << lw.
+
+// forward convolution, A(m = (b, y, x), k = (c, r)): input pixel under tap r
+struct ConvFwdA {
+  static constexpr bool KFAST = false;
+  const float* in;
+  int ci, lw;
+  __device__ float operator()(int m, int k) const {
+    const int w = 1 << lw;
+    const int x = m & (w - 1), y = (m >> lw) & (w - 1), bb = m >> (2 * lw);
+    const int c = k / 9, r = k - 9 * c;
+    const int yy = y + r / 3 - 1, xx = x + r % 3 - 1;
+    if ((unsigned)yy >= (unsigned)w || (unsigned)xx >= (unsigned)w) return 0.0f;
+    return in[(((size_t)bb * ci + c) << (2 * lw)) + (yy << lw) + xx];
+  }
+};
+// B(k, n) = w[n][k] (weights [co][ci * 9])
+struct WeightT {
+  static constexpr bool KFAST = true;
+  const float* w;
+  int k_len;
+  __device__ float operator()(int k, int n) const { return w[(size_t)n * k_len + k]; }
+};
+// out[b][n][y][x] = max(acc + bias[n], 0)
+struct ConvReluOut {
+  float* out;
+  const float* bias;
+  int co, lw;
+  __device__ void operator()(int m, int n, float v, int) const {
+    const int hw = 1 << (2 * lw);
+    const int bb = m >> (2 * lw), p = m & (hw - 1);
+    out[((size_t)bb * co + n) * hw + p] = fmaxf(v + bias[n], 0.0f);
+  }
+};
+
+// data gradient, A(m = (b, y, x), k = (o, r)) = g[b][o][y - dy + 1][x - dx + 1]
+struct ConvBwdDataA {
+  static constexpr bool KFAST = false;
+  const float* g;
+  int co, lw;
+  __device__ float operator()(int m, int k) const {
+    const int w = 1 << lw;
+    const int x = m & (w - 1), y = (m >> lw) & (w - 1), bb = m >> (2 * lw);
+    const int o = k / 9, r = k - 9 * o;
+    const int yy = y - r / 3 + 1, xx = x - r % 3 + 1;
+    if ((unsigned)yy >= (unsigned)w || (unsigned)xx >= (unsigned)w) return 0.0f;
+    return g[(((size_t)bb * co + o) << (2 * lw)) + (yy << lw) + xx];
+  }
+};
+// B(k = (o, r), n = c) = w[o][c][r]
+struct WeightBwdData {
+  static constexpr bool KFAST = false;
+  const float* w;
+  int ci;
+  __device__ float operator()(int k, int n) const {
+    const int o = k / 9, r = k - 9 * o;
+    return w[((size_t)o * ci + n) * 9 + r];
+  }
+};
+// out[b][n][y][x] = acc
+struct NchwOut {
+  float* out;
+  int c, lw;
+  __device__ void operator()(int m, int n, float v, int) const {
+    const int hw = 1 << (2 * lw);
+    const int bb = m >> (2 * lw), p = m & (hw - 1);
+    out[((size_t)bb * c + n) * hw + p] = v;
+  }
+};
+
+// weight gradient, A(m = o, k = (b, y, x)) = g[b][o][y][x]
+struct ConvBwdWA {
+  static constexpr bool KFAST = true;
+  const float* g;
+  int co, lw;
+  __device__ float operator()(int m, int k) const {
+    const int hw = 1 << (2 * lw);
+    const int bb = k >> (2 * lw), p = k & (hw - 1);
+    return g[((size_t)bb * co + m) * hw + p];
+  }
+};
+// B(k = (b, y, x), n = (c, r)) = in[b][c][y + dy - 1][x + dx - 1]
+struct ConvBwdWB {
+  static constexpr bool KFAST = true;
+  const float* in;
+  int ci, lw;
+  __device__ float operator()(int k, int n) const {
+    const int w = 1 << lw;
+    const int x = k & (w - 1), y = (k >> lw) & (w - 1), bb = k >> (2 * lw);
+    const int c = n / 9, r = n - 9 * c;
+    const int yy = y + r / 3 - 1, xx = x + r % 3 - 1;
+    if ((unsigned)yy >= (unsigned)w || (unsigned)xx >= (unsigned)w) return 0.0f;
+    return in[(((size_t)bb * ci + c) << (2 * lw)) + (yy << lw) + xx];
+  }
+};
+// partial[z][m][n] = acc (split K, summed in a fixed order afterwards)
+struct SplitOut {
+  float* part;
+  int M, N;
+  __device__ void operator()(int m, int n, float v, int z) const { part[((size_t)z * M + m) * N + n] = v; }
+};
+
+// row-major matrices
+struct RowK {  // A(m, k) = p[m * ld + k]
+  static constexpr bool KFAST = true;
+  const float* p;
+  int ld;
+  __device__ float operator()(int m, int k) const { return p[(size_t)m * ld + k]; }
+};
+struct ColK {  // A(m, k) = p[k * ld + m]
+  static constexpr bool KFAST = false;
+  const float* p;
+  int ld;
+  __device__ float operator()(int m, int k) const { return p[(size_t)k * ld + m]; }
+};
+struct BRowN {  // B(k, n) = p[k * ld + n]
+  static constexpr bool KFAST = false;
+  const float* p;
+  int ld;
+  __device__ float operator()(int k, int n) const { return p[(size_t)k * ld + n]; }
+};
+struct RowOut {  // C[m * ld + n] = acc (+ bias[n])
+  float* out;
+  const float* bias;
+  int ld;
+  __device__ void operator()(int m, int n, float v, int) const {
+    out[(size_t)m * ld + n] = bias ? v + bias[n] : v;
+  }
+};
+
+template <class A, class Bm, class Out>
+static hipError_t gemm(A a, Bm b, Out out, int M, int N, int K, int splits, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  splits = splits < 1 ? 1 : splits;
+  int kslice = (K + splits - 1) / splits;
+  kslice = (kslice + 15) & ~15;
+  const int z = (K + kslice - 1) / kslice;
+  dim3 grid((N + 63) / 64, (M + 63) / 64, z < 1 ? 1 : z);
+  hipLaunchKernelGGL((k_tgemm<A, Bm, Out>), grid, dim3(256), 0, st, a, b, out, M, N, K, kslice);
+  return hipGetLastError();
+}
+
+// part [z][M][N] -> out [M][N] (+= when accumulate)
+__global__ void k_split_sum(const float* __restrict__ part, int z, int64_t mn, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= mn) return;
+  float s = 0.0f;
+  for (int k = 0; k < z; ++k) s += part[(size_t)k * mn + i];
+  out[i] = s;
+}
+
+// sum over (b, pixel) of g[b][c][pixel] for every channel c (bias gradient)
+__global__ __launch_bounds__(256) void k_channel_sum(const float* __restrict__ g, int bsz, int c, int hw,
+                                                     float* __restrict__ out) {
+  const int ch = blockIdx.x;
+  double s = 0.0;
+  for (int bb = 0; bb < bsz; ++bb) {
+    const float* p = g + ((size_t)bb * c + ch) * hw;
+    for (int i = threadIdx.x; i < hw; i += 256) s += p[i];
+  }
+  s = wave_sum(s);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[ch] = (float)(red[0] + red[1] + red[2] + red[3]);
+}
+
+// column sums of a [rows][cols] matrix
+__global__ void k_col_sum(const float* __restrict__ a, int rows, int cols, float* __restrict__ out) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= cols) return;
+  float s = 0.0f;
+  for (int r = 0; r < rows; ++r) s += a[(size_t)r * cols + j];
+  out[j] = s;
+}
+
+// 2 x 2 max pool of [planes][2h][2w] -> [planes][h][w]
+__global__ void k_pool_fwd(const float* __restrict__ in, int64_t planes, int lw_out, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int wo = 1 << lw_out;
+  if (i >= planes * wo * wo) return;
+  const int64_t pl = i >> (2 * lw_out);
+  const int y = (int)((i >> lw_out) & (wo - 1)), x = (int)(i & (wo - 1));
+  const float* p = in + (pl << (2 * lw_out + 2)) + (size_t)(2 * y) * (2 * wo) + 2 * x;
+  out[i] = fmaxf(fmaxf(p[0], p[1]), fmaxf(p[2 * wo], p[2 * wo + 1]));
+}
+
+// gradient through the pool (first maximal input) and the ReLU (r > 0)
+__global__ void k_pool_bwd(const float* __restrict__ r, const float* __restrict__ pooled,
+                           const float* __restrict__ dpool, int64_t planes, int lw_out, float* __restrict__ g) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int wo = 1 << lw_out;
+  if (i >= planes * wo * wo) return;
+  const int64_t pl = i >> (2 * lw_out);
+  const int y = (int)((i >> lw_out) & (wo - 1)), x = (int)(i & (wo - 1));
+  const size_t base = (pl << (2 * lw_out + 2)) + (size_t)(2 * y) * (2 * wo) + 2 * x;
+  const size_t off[4] = {0, 1, (size_t)(2 * wo), (size_t)(2 * wo + 1)};
+  const float m = pooled[i], d = dpool[i];
+  bool done = false;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const float v = r[base + off[t]];
+    const bool hit = !done && v == m;
+    done = done || hit;
+    g[base + off[t]] = (hit && v > 0.0f) ? d : 0.0f;
+  }
+}
+
+// softmax cross-entropy per row: loss_row[b], dz = (softmax - onehot) / B
+__global__ __launch_bounds__(256) void k_softmax_xent(const float* __restrict__ z, const int32_t* __restrict__ y,
+                                                      int l, int bsz, float* __restrict__ dz,
+                                                      double* __restrict__ loss_row) {
+  const int bb = blockIdx.x;
+  const float* zr = z + (size_t)bb * l;
+  __shared__ float redf[4];
+  __shared__ double redd[4];
+  float mx = -INFINITY;
+  for (int i = threadIdx.x; i < l; i += 256) mx = fmaxf(mx, zr[i]);
+  mx = wave_max(mx);
+  if ((threadIdx.x & 63) == 0) redf[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  mx = fmaxf(fmaxf(redf[0], redf[1]), fmaxf(redf[2], redf[3]));
+  double s = 0.0;
+  for (int i = threadIdx.x; i < l; i += 256) s += exp((double)(zr[i] - mx));
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) redd[threadIdx.x >> 6] = s;
+  __syncthreads();
+  s = redd[0] + redd[1] + redd[2] + redd[3];
+  const int lab = y[bb];
+  const float inv = 1.0f / (float)bsz;
+  for (int i = threadIdx.x; i < l; i += 256) {
+    const float p = (float)(exp((double)(zr[i] - mx)) / s);
+    dz[(size_t)bb * l + i] = (p - (i == lab ? 1.0f : 0.0f)) * inv;
+  }
+  if (threadIdx.x == 0) loss_row[bb] = log(s) - (double)(zr[lab] - mx);
+}
+
+__global__ void k_mean_loss(const double* __restrict__ loss_row, int bsz, float* __restrict__ loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < bsz; ++i) s += loss_row[i];
+  *loss = (float)(s / bsz);
+}
+
+// Adam (Kingma and Ba), bias-corrected step sizes precomputed on the host
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr_t, float b1, float b2, float eps_t) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr_t * mi / (sqrtf(vi) + eps_t);
+}
+
+// ---------------------------------------------------------------------------
+// Counter-based random numbers: Philox4x32-10 (Salmon, Moraes, Dror and
+// Shaw, SC 2011), counter (i_lo, i_hi, stream, 0), key (seed_lo, seed_hi).
+__device__ __forceinline__ uint4 philox(uint64_t i, uint32_t stream, uint64_t seed) {
+  uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32), c2 = stream, c3 = 0u;
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+// uniform in (0, 1)
+__device__ __forceinline__ double unit(uint32_t a, uint32_t b) {
+  const uint64_t x = ((uint64_t)a << 21) ^ (uint64_t)(b >> 11);  // 53 bits
+  return ((double)(x & ((1ull << 53) - 1)) + 0.5) * (1.0 / 9007199254740992.0);
+}
+__device__ __forceinline__ float2 normal2(uint4 r) {
+  const double u1 = unit(r.x, r.y), u2 = unit(r.z, r.w);
+  const double rad = sqrt(-2.0 * log(u1));
+  double s, c;
+  sincospi(2.0 * u2, &s, &c);
+  return make_float2((float)(rad * c), (float)(rad * s));
+}
+
+// He-normal initial weights (biases zero): std sqrt(2 / fan_in)
+__global__ void k_init_params(float* __restrict__ w, int64_t begin, int64_t count, float stdv, uint64_t seed,
+                              uint32_t stream) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const float2 z = normal2(philox((uint64_t)i, stream, seed));
+  w[begin + i] = stdv * z.x;
+}
+
+// random orientation (Shoemake's uniform quaternion) and in-plane pattern
+// centre offset for sample index s
+__global__ void k_sample_setup(int64_t first, int64_t bsz, uint64_t seed, double pcx, double pcy, double pcz,
+                               double max_off_frac, double* __restrict__ q, double* __restrict__ pc) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= bsz) return;
+  const uint64_t s = (uint64_t)(first + j);
+  const uint4 r0 = philox(s, 1u, seed), r1 = philox(s, 2u, seed);
+  const double u1 = unit(r0.x, r0.y), u2 = unit(r0.z, r0.w), u3 = unit(r1.x, r1.y);
+  double s2, c2, s3, c3;
+  sincospi(2.0 * u2, &s2, &c2);
+  sincospi(2.0 * u3, &s3, &c3);
+  const double a = sqrt(1.0 - u1), b = sqrt(u1);
+  double v[4] = {b * c3, a * s2, a * c2, b * s3};
+  qstore(q + 4 * j, v);
+  const double ox = (2.0 * unit(r1.z, r1.w) - 1.0) * max_off_frac;
+  const uint4 r2 = philox(s, 3u, seed);
+  const double oy = (2.0 * unit(r2.x, r2.y) - 1.0) * max_off_frac;
+  pc[3 * j] = pcx + ox;
+  pc[3 * j + 1] = pcy + oy;
+  pc[3 * j + 2] = pcz;
+}
+
+// Noise (when `noisy`: the pattern scaled to a mean count level, Poisson by
+// its normal approximation, plus Gaussian read noise fixing the pattern's
+// SNR), f x f block-mean binning to 64 x 64 (f = n / 64) and
+// (x - mean) / std.  One block per pattern.
+__global__ __launch_bounds__(256) void k_noise_bin(const float* __restrict__ clean, int n, int64_t first,
+                                                   uint64_t seed, float counts, float snr, int noisy,
+                                                   float* __restrict__ x) {
+  __shared__ float bin[64 * 64];
+  __shared__ double red[8];
+  const int64_t j = blockIdx.x;
+  const int tid = threadIdx.x;
+  const float* img = clean + (size_t)j * n * n;
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = tid; i < n * n; i += 256) {
+    const double v = img[i];
+    s1 += v;
+    s2 += v * v;
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if ((tid & 63) == 0) {
+    red[tid >> 6] = s1;
+    red[4 + (tid >> 6)] = s2;
+  }
+  __syncthreads();
+  const double mean = (red[0] + red[1] + red[2] + red[3]) / ((double)n * n);
+  const double var = (red[4] + red[5] + red[6] + red[7]) / ((double)n * n) - mean * mean;
+  const double ct = var > 0.0 && mean > 0.0 ? sqrt(var) / mean : 0.0;
+  double var_g = ct > 0.0 ? (counts * ct / snr) * (counts * ct / snr) - counts : 0.0;
+  double c_eff = counts;
+  if (var_g < 0.0) {
+    c_eff = ct > 0.0 ? (snr / ct) * (snr / ct) : counts;
+    var_g = 0.0;
+  }
+  const float scale = !noisy ? 1.0f : (mean > 0.0 ? (float)(c_eff / mean) : 0.0f);
+  const float sg = (float)sqrt(var_g);
+  const int f = n / 64;
+  const uint64_t s = (uint64_t)(first + j);
+  __syncthreads();
+  for (int o = tid; o < 64 * 64; o += 256) {
+    const int by = o >> 6, bx = o & 63;
+    float acc = 0.0f;
+    for (int dy = 0; dy < f; ++dy)
+      for (int dx = 0; dx < f; ++dx) {
+        const int pix = (by * f + dy) * n + bx * f + dx;
+        float v = img[pix] * scale;
+        if (noisy) {
+          const float2 z = normal2(philox((s << 20) ^ (uint64_t)pix, 4u, seed));
+          v += sqrtf(fmaxf(v, 0.0f)) * z.x + sg * z.y;
+        }
+        acc += v;
+      }
+    bin[o] = acc / (float)(f * f);
+  }
+  __syncthreads();
+  s1 = 0.0;
+  s2 = 0.0;
+  for (int o = tid; o < 64 * 64; o += 256) {
+    const double v = bin[o];
+    s1 += v;
+    s2 += v * v;
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  __syncthreads();
+  if ((tid & 63) == 0) {
+    red[tid >> 6] = s1;
+    red[4 + (tid >> 6)] = s2;
+  }
+  __syncthreads();
+  const double m2 = (red[0] + red[1] + red[2] + red[3]) / 4096.0;
+  const double v2 = (red[4] + red[5] + red[6] + red[7]) / 4096.0 - m2 * m2;
+  const float fm = (float)m2, is = v2 > 0.0 ? (float)(1.0 / sqrt(v2)) : 0.0f;
+  for (int o = tid; o < 64 * 64; o += 256) x[(size_t)j * 4096 + o] = (bin[o] - fm) * is;
+}
+
+// The 24 proper rotations of the cubic point group as quaternions.
+__constant__ double c_cubic_q[24][4] = {
+    {1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1},
+    {0.70710678118654752, 0.70710678118654752, 0, 0}, {0.70710678118654752, -0.70710678118654752, 0, 0},
+    {0.70710678118654752, 0, 0.70710678118654752, 0}, {0.70710678118654752, 0, -0.70710678118654752, 0},
+    {0.70710678118654752, 0, 0, 0.70710678118654752}, {0.70710678118654752, 0, 0, -0.70710678118654752},
+    {0.5, 0.5, 0.5, 0.5}, {0.5, 0.5, 0.5, -0.5}, {0.5, 0.5, -0.5, 0.5}, {0.5, 0.5, -0.5, -0.5},
+    {0.5, -0.5, 0.5, 0.5}, {0.5, -0.5, 0.5, -0.5}, {0.5, -0.5, -0.5, 0.5}, {0.5, -0.5, -0.5, -0.5},
+    {0, 0.70710678118654752, 0.70710678118654752, 0}, {0, 0.70710678118654752, -0.70710678118654752, 0},
+    {0, 0.70710678118654752, 0, 0.70710678118654752}, {0, 0.70710678118654752, 0, -0.70710678118654752},
+    {0, 0, 0.70710678118654752, 0.70710678118654752}, {0, 0, 0.70710678118654752, -0.70710678118654752}};
+
+// label[j] = library orientation of smallest cubic disorientation from q[j]
+// (largest |<q, s (x) q_l>|; ties: smallest index).  One block per sample.
+__global__ __launch_bounds__(256) void k_nearest_library(const double* __restrict__ q, const double* __restrict__ lib,
+                                                         int l, int32_t* __restrict__ label) {
+  const int64_t j = blockIdx.x;
+  const double a[4] = {q[4 * j], q[4 * j + 1], q[4 * j + 2], q[4 * j + 3]};
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int i = threadIdx.x; i < l; i += 256) {
+    const double* b = lib + 4 * (size_t)i;
+    double m = 0.0;
+    for (int s = 0; s < 24; ++s) {
+      double sb[4];
+      qmul(c_cubic_q[s], b, sb);
+      m = fmax(m, fabs(a[0] * sb[0] + a[1] * sb[1] + a[2] * sb[2] + a[3] * sb[3]));
+    }
+    if (m > best) {  // i increases: ties keep the smaller index
+      best = m;
+      bi = i;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double b2 = __shfl_xor(best, off, 64);
+    const int i2 = __shfl_xor(bi, off, 64);
+    if (b2 > best || (b2 == best && i2 < bi)) {
+      best = b2;
+      bi = i2;
+    }
+  }
+  __shared__ double rv[4];
+  __shared__ int ri[4];
+  if ((threadIdx.x & 63) == 0) {
+    rv[threadIdx.x >> 6] = best;
+    ri[threadIdx.x >> 6] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w)
+      if (rv[w] > best || (rv[w] == best && ri[w] < bi)) {
+        best = rv[w];
+        bi = ri[w];
+      }
+    label[j] = bi;
+  }
+}
+
+// The k largest scores of each row, in decreasing order (ties: smaller
+// index first; NaN scores count as -inf).  One block per row; the row is
+// staged in LDS.
+__global__ __launch_bounds__(256) void k_topk(const float* __restrict__ z, int l, int k, int32_t* __restrict__ idx) {
+  extern __shared__ float row[];
+  const int64_t b = blockIdx.x;
+  for (int i = threadIdx.x; i < l; i += 256) {
+    const float v = z[(size_t)b * l + i];
+    row[i] = v != v ? -INFINITY : v;
+  }
+  __shared__ float rv[4];
+  __shared__ int ri[4];
+  __shared__ int pick;
+  __syncthreads();
+  for (int t = 0; t < k; ++t) {
+    float best = -INFINITY;
+    int bi = 0x7fffffff;
+    for (int i = threadIdx.x; i < l; i += 256) argmax_merge(best, bi, row[i], i);
+    wave_argmax(best, bi);
+    if ((threadIdx.x & 63) == 0) {
+      rv[threadIdx.x >> 6] = best;
+      ri[threadIdx.x >> 6] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < 4; ++w) argmax_merge(best, bi, rv[w], ri[w]);
+      pick = bi;
+      idx[b * k + t] = bi;
+    }
+    __syncthreads();
+    // a taken entry becomes NaN, which never wins a comparison (k <= l)
+    if (threadIdx.x == 0) row[pick] = __int_as_float(0x7fc00000);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+namespace {
+inline unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
+inline int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+}  // namespace
+
+Layout layout_of(int n_classes) {
+  Layout lay;
+  int64_t off = 0;
+  int ci = 1;
+  for (int i = 0; i < 4; ++i) {
+    lay.conv_w[i] = off;
+    off += (int64_t)kChannels[i] * ci * 9;
+    lay.conv_b[i] = off;
+    off += kChannels[i];
+    ci = kChannels[i];
+  }
+  lay.fc_w = off;
+  off += (int64_t)n_classes * kFeatures;
+  lay.fc_b = off;
+  off += n_classes;
+  lay.total = off;
+  lay.classes = n_classes;
+  return lay;
+}
+
+hipError_t init_params(float* params, const Layout& lay, uint64_t seed, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(params, 0, sizeof(float) * lay.total, st);
+  if (e != hipSuccess) return e;
+  int ci = 1;
+  for (int i = 0; i < 4; ++i) {
+    const int64_t cnt = (int64_t)kChannels[i] * ci * 9;
+    hipLaunchKernelGGL(k_init_params, dim3(nb(cnt)), dim3(256), 0, st, params, lay.conv_w[i], cnt,
+                       (float)sqrt(2.0 / (ci * 9)), seed, (uint32_t)(10 + i));
+    ci = kChannels[i];
+  }
+  const int64_t cnt = (int64_t)lay.classes * kFeatures;
+  hipLaunchKernelGGL(k_init_params, dim3(nb(cnt)), dim3(256), 0, st, params, lay.fc_w, cnt,
+                     (float)sqrt(1.0 / kFeatures), seed, 20u);
+  return hipGetLastError();
+}
+
+// forward; act holds r_i, p_i (i = 0..3) and the logits
+hipError_t forward(const float* params, const Layout& lay, const float* x, int64_t bsz, const Acts& act,
+                   hipStream_t st) {
+  const float* a = x;
+  int ci = 1, w = kInSize;
+  hipError_t e;
+  for (int i = 0; i < 4; ++i) {
+    const int co = kChannels[i], lw = ilog2(w);
+    const int M = (int)(bsz * w * w), K = ci * 9;
+    e = gemm(ConvFwdA{a, ci, lw}, WeightT{params + lay.conv_w[i], K},
+             ConvReluOut{act.r[i], params + lay.conv_b[i], co, lw}, M, co, K, 1, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pool_fwd, dim3(nb(bsz * co * (w / 2) * (w / 2))), dim3(256), 0, st, act.r[i],
+                       (int64_t)(bsz * co), lw - 1, act.p[i]);
+    a = act.p[i];
+    ci = co;
+    w /= 2;
+  }
+  return gemm(RowK{a, kFeatures}, WeightT{params + lay.fc_w, kFeatures},
+              RowOut{act.logits, params + lay.fc_b, lay.classes}, (int)bsz, lay.classes, kFeatures, 1, st);
+}
+
+static int splits_for(int64_t k_len, int64_t tiles) {
+  // enough blocks to fill the chip, slices of at least 1024
+  int64_t s = (1024 + tiles - 1) / tiles;
+  const int64_t maxs = (k_len + 1023) / 1024;
+  if (s > maxs) s = maxs;
+  if (s < 1) s = 1;
+  return (int)s;
+}
+
+hipError_t backward(const float* params, const Layout& lay, const float* x, const int32_t* labels, int64_t bsz,
+                    const Acts& act, float* grad, float* part, size_t part_floats, double* loss_row, float* loss,
+                    hipStream_t st) {
+  hipError_t e;
+  const int L = lay.classes;
+  hipLaunchKernelGGL(k_softmax_xent, dim3((unsigned)bsz), dim3(256), 0, st, act.logits, labels, L, (int)bsz,
+                     act.dz, loss_row);
+  hipLaunchKernelGGL(k_mean_loss, dim3(1), dim3(64), 0, st, loss_row, (int)bsz, loss);
+  // fc: dW = dz^T f, db = column sums of dz, df = dz W
+  e = gemm(ColK{act.dz, L}, BRowN{act.p[3], kFeatures}, RowOut{grad + lay.fc_w, nullptr, kFeatures}, L, kFeatures,
+           (int)bsz, 1, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_col_sum, dim3(nb(L)), dim3(256), 0, st, act.dz, (int)bsz, L, grad + lay.fc_b);
+  e = gemm(RowK{act.dz, L}, BRowN{params + lay.fc_w, kFeatures}, RowOut{act.dp[3], nullptr, kFeatures}, (int)bsz,
+           kFeatures, L, 1, st);
+  if (e != hipSuccess) return e;
+  int w = kInSize >> 3;  // conv4 input side (8)
+  for (int i = 3; i >= 0; --i) {
+    const int co = kChannels[i], ci = i ? kChannels[i - 1] : 1, lw = ilog2(w);
+    const float* in = i ? act.p[i - 1] : x;
+    hipLaunchKernelGGL(k_pool_bwd, dim3(nb(bsz * co * (w / 2) * (w / 2))), dim3(256), 0, st, act.r[i], act.p[i],
+                       act.dp[i], (int64_t)(bsz * co), lw - 1, act.g[i]);
+    // weight gradient, split over (b, y, x)
+    const int K = (int)(bsz * w * w), N = ci * 9;
+    const int64_t tiles = (int64_t)((co + 63) / 64) * ((N + 63) / 64);
+    int s = splits_for(K, tiles);
+    while ((size_t)s * co * N > part_floats && s > 1) s = (s + 1) / 2;
+    int kslice = ((K + s - 1) / s + 15) & ~15;
+    const int z = (K + kslice - 1) / kslice;
+    e = gemm(ConvBwdWA{act.g[i], co, lw}, ConvBwdWB{in, ci, lw}, SplitOut{part, co, N}, co, N, K, s, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_split_sum, dim3(nb((int64_t)co * N)), dim3(256), 0, st, part, z, (int64_t)co * N,
+                       grad + lay.conv_w[i]);
+    hipLaunchKernelGGL(k_channel_sum, dim3(co), dim3(256), 0, st, act.g[i], (int)bsz, co, w * w,
+                       grad + lay.conv_b[i]);
+    if (i > 0) {
+      e = gemm(ConvBwdDataA{act.g[i], co, lw}, WeightBwdData{params + lay.conv_w[i], ci},
+               NchwOut{act.dp[i - 1], ci, lw}, (int)(bsz * w * w), ci, co * 9, 1, st);
+      if (e != hipSuccess) return e;
+    }
+    w *= 2;
+  }
+  return hipGetLastError();
+}
+
+hipError_t adam(float* params, const float* grad, float* m, float* v, int64_t n, int64_t step, float lr,
+                hipStream_t st) {
+  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  const double c1 = 1.0 - pow(b1, (double)step), c2 = 1.0 - pow(b2, (double)step);
+  const float lr_t = (float)(lr * sqrt(c2) / c1);
+  const float eps_t = (float)(eps * sqrt(c2));
+  hipLaunchKernelGGL(k_adam, dim3(nb(n)), dim3(256), 0, st, params, grad, m, v, n, lr_t, (float)b1, (float)b2,
+                     eps_t);
+  return hipGetLastError();
+}
+
+hipError_t sample_setup(int64_t first, int64_t bsz, uint64_t seed, double pcx, double pcy, double pcz,
+                        double max_off_frac, double* q, double* pc, hipStream_t st) {
+  hipLaunchKernelGGL(k_sample_setup, dim3(nb(bsz)), dim3(256), 0, st, first, bsz, seed, pcx, pcy, pcz,
+                     max_off_frac, q, pc);
+  return hipGetLastError();
+}
+
+hipError_t noise_bin(const float* clean, int n, int64_t bsz, int64_t first, uint64_t seed, float counts, float snr,
+                     int noisy, float* x, hipStream_t st) {
+  if (n % kInSize != 0 || n < kInSize) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_noise_bin, dim3((unsigned)bsz), dim3(256), 0, st, clean, n, first, seed, counts, snr, noisy,
+                     x);
+  return hipGetLastError();
+}
+
+hipError_t nearest_library(const double* q, int64_t bsz, const double* lib, int l, int32_t* label,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_nearest_library, dim3((unsigned)bsz), dim3(256), 0, st, q, lib, l, label);
+  return hipGetLastError();
+}
+
+hipError_t topk(const float* z, int64_t rows, int l, int k, int32_t* idx, hipStream_t st) {
+  const size_t shm = sizeof(float) * (size_t)l;
+  if (shm > 160 * 1024) return hipErrorInvalidValue;
+  const hipError_t e = hipFuncSetAttribute((const void*)k_topk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_topk, dim3((unsigned)rows), dim3(256), shm, st, z, l, k, idx);
+  return hipGetLastError();
+}
+
+}  // namespace cnn
+}  // namespace ebsd
