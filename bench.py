@@ -96,6 +96,12 @@ def main():
     ap.add_argument("--ragged-patterns", type=int, default=20000)
     ap.add_argument("--ragged-library", type=int, default=8000)
     ap.add_argument("--ragged-steps", type=int, default=2)
+    ap.add_argument("--no-proposal", action="store_true",
+                    help="skip the learned proposal (CNN trained on the GPU, top-32 search with fallback)")
+    ap.add_argument("--proposal-library", type=int, default=8000)
+    ap.add_argument("--proposal-train", type=int, default=200000, help="distinct training patterns")
+    ap.add_argument("--proposal-epochs", type=float, default=2.0)
+    ap.add_argument("--proposal-test", type=int, default=50000)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one elementwise copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -211,6 +217,10 @@ def main():
     if not args.no_ragged:
         torch.cuda.empty_cache()
         line["ragged"] = ragged_batch(tm, args.ragged_patterns, args.ragged_library, args.ragged_steps)
+    if not args.no_proposal:
+        torch.cuda.empty_cache()
+        line["proposal"] = learned_proposal(tm, args.proposal_library, args.proposal_train, args.proposal_epochs,
+                                            args.proposal_test)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(cpu_cfg, n, L, P)
@@ -442,6 +452,136 @@ def ragged_batch(tm, patterns, library, steps, sample_per_size=1):
                                                                       res["library_pairs_per_s_whole_step"]),
           file=sys.stderr, flush=True)
     plan.close()
+    return res
+
+
+def cnn_flops_per_sample(n_classes):
+    """Multiply-adds x 2 of one forward pass (four 3 x 3 convolutions, the
+    fully connected layer); a training step is counted as 3 forward passes."""
+    macs, ci, w = 0, 1, 64
+    for co in (32, 64, 128, 128):
+        macs += w * w * co * ci * 9
+        ci, w = co, w // 2
+    return 2 * (macs + 2048 * n_classes)
+
+
+def learned_proposal(tm, library, n_train, epochs, n_test, k=32, bsz=256, n=128):
+    """The network trained on the GPU on projected noisy patterns (fixed set
+    of n_train sample counters, fresh noise per epoch), then the pruned search
+    (top-k correlation + exhaustive fallback below tau) against the
+    exhaustive FP32 search on n_test simulated 128 x 128 patterns.  tau is the
+    1st percentile of the exhaustive peak height on a validation set."""
+    import numpy as np
+    import torch
+    from fixtures import band_master, random_fz_quats, random_quats, simulate_patterns
+    from oracle import rotations
+
+    dev = torch.device("cuda:0")
+    lib = random_fz_quats(np.random.default_rng(11), library)
+    master = torch.as_tensor(band_master(), device=dev).contiguous()
+    lq = torch.as_tensor(lib, device=dev).contiguous()
+    pc = (0.5, 0.5, 0.6)
+
+    def patterns(p, seed):
+        rng = np.random.default_rng(seed)
+        q = random_quats(rng, p)
+        off = rng.uniform(-5, 5, size=(p, 2))
+        pcs = np.stack([0.5 + off[:, 0] / n, 0.5 + off[:, 1] / n, np.full(p, 0.6)], 1)
+        return q, pcs, simulate_patterns(q, n, pcs, ("poisson_gauss", 1000.0, 5.0), seed=seed, device=dev,
+                                         dtype=torch.float32).contiguous()
+
+    print("[bench] proposal: training on %d patterns x %.1f epochs, library %d" % (n_train, epochs, library),
+          file=sys.stderr, flush=True)
+    net = tm.Cnn(library, seed=5)
+    x = torch.empty((bsz, 64, 64), device=dev)
+    y = torch.empty(bsz, dtype=torch.int32, device=dev)
+    loss = torch.empty(1, device=dev)
+    steps = int(epochs * n_train / bsz)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        first = (s * bsz) % n_train
+        tm.cnn_make_batch(master, pc, lq, n, bsz, first, 1000 + (s * bsz) // n_train, x=x, labels=y)
+        net.train_step(x, y, 1e-3, loss)
+        if s % 500 == 0:
+            print("[bench]   step %d/%d loss %.3f" % (s, steps, float(loss.item())), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    final_loss = float(loss.item())
+    # network throughput alone (forward + backward + Adam) on one batch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        net.train_step(x, y, 1e-3, loss)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / 20
+    train_flops = 3 * cnn_flops_per_sample(library) * bsz
+
+    _, _, val = patterns(10000, 31)
+    tau = float(np.percentile(tm.index_patterns(val, master, pc, lq)["peak_h"].cpu().numpy(), 1.0))
+    del val
+    q_test, pcs_test, test = patterns(n_test, 32)
+    pc_per = torch.as_tensor(pcs_test, device=dev).contiguous()
+
+    def timed(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t1) / reps
+
+    ex, t_ex = timed(lambda: tm.index_patterns(test, master, pc, lq))
+    pr, t_pr = timed(lambda: tm.index_proposed(test, master, pc, lq, net, top_k=k, fallback_tau=tau))
+    x_test = tm.Cnn.input(test[:bsz * 8])
+    _, t_fwd = timed(lambda: net.forward(x_test), reps=5)
+    # both picks refined the same way (the library pick is only the start)
+    rf_ex, t_rf = timed(lambda: tm.refine_orientations(test, master, pc, ex["best_q"], pc_per=pc_per), reps=1)
+    rf_pr, _ = timed(lambda: tm.refine_orientations(test, master, pc, pr["best_q"], pc_per=pc_per), reps=1)
+    b_ex, b_pr = ex["best_idx"].cpu().numpy(), pr["best_idx"].cpu().numpy()
+    fb = pr["fallback"].cpu().numpy().astype(bool)
+    q_ex, q_pr = rf_ex["q"].cpu().numpy(), rf_pr["q"].cpu().numpy()
+    pts = np.linspace(0, n_test - 1, 500).astype(int)
+    mis_ex = np.rad2deg([rotations.disorientation_q(lib[b_ex[i]], q_test[i]) for i in pts])
+    mis_pr = np.rad2deg([rotations.disorientation_q(lib[b_pr[i]], q_test[i]) for i in pts])
+    rex = np.rad2deg([rotations.disorientation_q(q_ex[i], q_test[i]) for i in pts])
+    rpr = np.rad2deg([rotations.disorientation_q(q_pr[i], q_test[i]) for i in pts])
+    rpe = np.rad2deg([rotations.disorientation_q(q_pr[i], q_ex[i]) for i in pts])
+    pairs_pr = n_test * k + int(fb.sum()) * library
+    res = {"workload": "proposal: CNN (4 conv 32-128 ch on 64x64 binned input, fc to %d) trained on the GPU on "
+                       "%d projected noisy patterns x %.1f epochs; %d test patterns at 128x128 fp32, top-%d "
+                       "correlation with exhaustive fallback below tau" % (library, n_train, epochs, n_test, k),
+           "train_s": t_train, "train_steps": steps, "batch": bsz, "final_loss": final_loss,
+           "train_samples_per_s": steps * bsz / t_train,
+           "train_step_roofline": {"bound": "alu", "achieved": train_flops / t_step / 1e12,
+                                   "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                                   "frac": train_flops / t_step / PEAK_FP32_VALU,
+                                   "flops_per_sample_forward": cnn_flops_per_sample(library)},
+           "forward_patterns_per_s": bsz * 8 / t_fwd,
+           "tau": tau,
+           "refine_s": t_rf,
+           "exhaustive": {"search_patterns_per_s": n_test / t_ex, "patterns_per_s_with_refinement":
+                          n_test / (t_ex + t_rf), "pairs": n_test * library,
+                          "pick_vs_truth_deg_median": float(np.median(mis_ex)),
+                          "refined_vs_truth_deg_median": float(np.median(rex)),
+                          "refined_vs_truth_deg_p95": float(np.percentile(rex, 95))},
+           "pruned": {"search_patterns_per_s": n_test / t_pr, "patterns_per_s_with_refinement":
+                      n_test / (t_pr + t_rf), "pairs": pairs_pr, "fallback_fraction": float(fb.mean()),
+                      "pick_agreement_with_exhaustive": float(np.mean(b_pr == b_ex)),
+                      "pick_vs_truth_deg_median": float(np.median(mis_pr)),
+                      "refined_vs_truth_deg_median": float(np.median(rpr)),
+                      "refined_vs_truth_deg_p95": float(np.percentile(rpr, 95)),
+                      "refined_vs_exhaustive_refined_deg_median": float(np.median(rpe)),
+                      "refined_within_0.1deg_of_exhaustive": float(np.mean(rpe <= 0.1))},
+           "accuracy_sample": "500 test patterns",
+           "search_speedup": t_ex / t_pr}
+    print("[bench] proposal: exhaustive %.0f patterns/s, pruned %.0f patterns/s (search), refined within 0.1 deg "
+          "%.4f, fallback %.3f" % (res["exhaustive"]["search_patterns_per_s"], res["pruned"]["search_patterns_per_s"],
+                                   res["pruned"]["refined_within_0.1deg_of_exhaustive"],
+                                   res["pruned"]["fallback_fraction"]),
+          file=sys.stderr, flush=True)
+    net.close()
     return res
 
 

@@ -717,6 +717,7 @@ hipError_t sample_setup(int64_t first, int64_t bsz, uint64_t seed, double pcx, d
 
 hipError_t noise_bin(const float* clean, int n, int64_t bsz, int64_t first, uint64_t seed, float counts, float snr,
                      int noisy, float* x, hipStream_t st) {
+  if (bsz > (int64_t(1) << 31) / 256) return hipErrorInvalidValue;  // one dispatch below 2^31 items
   if (n % kInSize != 0 || n < kInSize) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_noise_bin, dim3((unsigned)bsz), dim3(256), 0, st, clean, n, first, seed, counts, snr, noisy,
                      x);
@@ -725,11 +726,13 @@ hipError_t noise_bin(const float* clean, int n, int64_t bsz, int64_t first, uint
 
 hipError_t nearest_library(const double* q, int64_t bsz, const double* lib, int l, int32_t* label,
                            hipStream_t st) {
+  if (bsz > (int64_t(1) << 31) / 256) return hipErrorInvalidValue;  // one dispatch below 2^31 items
   hipLaunchKernelGGL(k_nearest_library, dim3((unsigned)bsz), dim3(256), 0, st, q, lib, l, label);
   return hipGetLastError();
 }
 
 hipError_t topk(const float* z, int64_t rows, int l, int k, int32_t* idx, hipStream_t st) {
+  if (rows > (int64_t(1) << 31) / 256) return hipErrorInvalidValue;  // one dispatch below 2^31 items
   const size_t shm = sizeof(float) * (size_t)l;
   if (shm > 160 * 1024) return hipErrorInvalidValue;
   const hipError_t e = hipFuncSetAttribute((const void*)k_topk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);

@@ -265,6 +265,18 @@ static hipError_t launch_grid(int n, const float2* spec_p, const float2* spec_l,
   if (k <= 0) return hipSuccess;
   const int bnd = band_of(n);
   if (bnd < 0 || grid_lds_bytes(n, m) > 160 * 1024) return hipErrorInvalidValue;
+  const int64_t kmax = (int64_t(1) << 31) / 256;  // blocks x threads of one dispatch below 2^31
+  if (k > kmax) {
+    const int64_t sc = (int64_t)(bnd + 1) * (2 * bnd + 1);
+    for (int64_t s0 = 0; s0 < k; s0 += kmax) {
+      const hipError_t e = launch_grid(n, pi ? spec_p : spec_p + s0 * sc, li ? spec_l : spec_l + s0 * sc,
+                                       pi ? pi + s0 : nullptr, li ? li + s0 : nullptr, k - s0 < kmax ? k - s0 : kmax,
+                                       centre ? centre + 2 * s0 : nullptr, kappa, m, int_keys, tab, h + s0,
+                                       s ? s + 2 * s0 : nullptr, si ? si + 2 * s0 : nullptr, stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   if (bnd + 1 <= 64)
     return grid_vj<4>(n, bnd, spec_p, spec_l, pi, li, k, centre, kappa, m, int_keys, tab, h, s, si, stream);
   if (bnd + 1 <= 112)

@@ -380,8 +380,15 @@ hipError_t launch_roots(int m, float2* out, hipStream_t stream) {
 hipError_t launch_library_argmax(const float* scores, int64_t p, int64_t l, int32_t* best,
                                  float* best_h, hipStream_t stream) {
   if (p <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_library_argmax, dim3((unsigned)p), dim3(256), 0, stream, scores, l, best, best_h);
-  return hipGetLastError();
+  const int64_t pmax = (int64_t(1) << 31) / 256;  // blocks x threads of one dispatch below 2^31
+  for (int64_t s = 0; s < p; s += pmax) {
+    const int64_t pc = p - s < pmax ? p - s : pmax;
+    hipLaunchKernelGGL(k_library_argmax, dim3((unsigned)pc), dim3(256), 0, stream, scores + s * l, l, best + s,
+                       best_h + s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_gather_q(const double* lib_q, const int32_t* best, int64_t p, double* best_q,
@@ -394,6 +401,7 @@ hipError_t launch_gather_q(const double* lib_q, const int32_t* best, int64_t p, 
 hipError_t launch_logpolar(int n, const float* imgs, int64_t k, int n_rho, int n_eta, float* out,
                            hipStream_t stream) {
   if (k <= 0) return hipSuccess;
+  if (k > (int64_t(1) << 31) / 256) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_logpolar, dim3((unsigned)k), dim3(256), 0, stream, imgs, n, n_rho, n_eta, out);
   return hipGetLastError();
 }
@@ -401,7 +409,7 @@ hipError_t launch_logpolar(int n, const float* imgs, int64_t k, int n_rho, int n
 hipError_t launch_eta_peak(const float* lp_e, const float* lp_t, int64_t k, int n_rho, int n_eta,
                            int kappa, double* gamma, hipStream_t stream) {
   if (k <= 0) return hipSuccess;
-  if (n_eta > 1024 || n_rho < 2) return hipErrorInvalidValue;
+  if (n_eta > 1024 || n_rho < 2 || k > (int64_t(1) << 31) / 256) return hipErrorInvalidValue;
   const size_t shm = sizeof(float) * ((size_t)2 * 8 * n_eta + n_eta + 2 * (n_eta / 2 + 1));
   hipLaunchKernelGGL(k_eta_peak, dim3((unsigned)k), dim3(256), shm, stream, lp_e, lp_t, n_rho, n_eta, kappa,
                      gamma);

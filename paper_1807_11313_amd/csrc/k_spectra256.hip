@@ -186,6 +186,7 @@ size_t spectra256_scratch_bytes(int64_t k) {
 hipError_t launch_spectra256(const float* imgs, int64_t k, const FilterParams& fp, float2* spec, double* energy,
                              void* scratch, hipStream_t stream) {
   if (k <= 0) return hipSuccess;
+  if (k * CGROUPS > (int64_t(1) << 31) / 256) return hipErrorInvalidValue;  // one dispatch below 2^31 items
   float2* st = (float2*)scratch;
   cf* v = (cf*)((char*)scratch + (size_t)k * sizeof(float2));
   double* part = (double*)((char*)v + (size_t)k * N * NV * sizeof(cf));

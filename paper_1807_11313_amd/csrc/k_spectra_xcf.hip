@@ -686,10 +686,24 @@ static constexpr int nt_spec() { return N <= 96 ? 256 : 512; }
     default: return hipErrorInvalidValue;              \
   }
 
+// One dispatch holds fewer than 2^32 work-items per grid dimension; every
+// launcher below keeps its 1-D grids under 2^31 by splitting the items.
+constexpr int64_t kMaxItems = int64_t(1) << 31;
+
 hipError_t launch_spectra(int n, const float* imgs, int64_t img_stride, int64_t k,
                           const FilterParams& fp, float2* spec, double* energy,
                           hipStream_t stream) {
   if (k <= 0) return hipSuccess;
+  const int64_t kmax = kMaxItems / 512;
+  if (k > kmax) {
+    const int64_t sc = (int64_t)(band_of(n) + 1) * (2 * band_of(n) + 1);
+    for (int64_t s = 0; s < k; s += kmax) {
+      const hipError_t e = launch_spectra(n, imgs + s * img_stride, img_stride, k - s < kmax ? k - s : kmax, fp,
+                                          spec + s * sc, energy ? energy + s : nullptr, stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   EBSD_DISPATCH(n, {
     constexpr int NT = nt_spec<NN>();
     hipLaunchKernelGGL((k_spectra<NN, NT>), dim3((unsigned)k), dim3(NT), 0, stream, imgs, img_stride,
@@ -701,6 +715,16 @@ hipError_t launch_spectra(int n, const float* imgs, int64_t img_stride, int64_t 
 hipError_t launch_spectra_gather(int n, const float* imgs, const int64_t* img_off, int64_t k,
                                  const FilterParams& fp, float2* spec, double* energy, hipStream_t stream) {
   if (k <= 0) return hipSuccess;
+  const int64_t kmax = kMaxItems / 512;
+  if (k > kmax) {
+    const int64_t sc = (int64_t)(band_of(n) + 1) * (2 * band_of(n) + 1);
+    for (int64_t s = 0; s < k; s += kmax) {
+      const hipError_t e = launch_spectra_gather(n, imgs, img_off + s, k - s < kmax ? k - s : kmax, fp,
+                                                 spec + s * sc, energy ? energy + s : nullptr, stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   EBSD_DISPATCH(n, {
     constexpr int NT = nt_spec<NN>();
     hipLaunchKernelGGL((k_spectra<NN, NT>), dim3((unsigned)k), dim3(NT), 0, stream, imgs, (int64_t)0, img_off,
@@ -714,9 +738,20 @@ hipError_t launch_xcf_scores(int n, const float2* spec_p, int64_t p, const float
   if (p <= 0 || l <= 0) return hipSuccess;
   const int lchunk = 32;
   const int64_t nchunk = (l + lchunk - 1) / lchunk;
+  // patterns per dispatch so that blocks x threads stays below 2^31
+  const int64_t pmax = (kMaxItems / 512 - 8) / nchunk;
+  if (pmax < 1) return hipErrorInvalidValue;
+  if (p > pmax) {
+    const int64_t sc = (int64_t)(band_of(n) + 1) * (2 * band_of(n) + 1);
+    for (int64_t s = 0; s < p; s += pmax) {
+      const hipError_t e = launch_xcf_scores(n, spec_p + s * sc, p - s < pmax ? p - s : pmax, spec_l, l, max_shift,
+                                             scores + s * l, stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   const int64_t nblk = p * nchunk;
   const int64_t grid = ((nblk + 7) / 8) * 8;
-  if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
   if (n == 128) {
     if (max_shift < 0)
       hipLaunchKernelGGL((k_xcf_scores128<false, false>), dim3((unsigned)grid), dim3(512), 0, stream,
@@ -787,6 +822,19 @@ hipError_t launch_xcf_peak(int n, const float2* spec_p, const float2* spec_l,
                            const int32_t* pi, const int32_t* li, int64_t k, int max_shift,
                            float* h_int, int32_t* s_int, float* map, hipStream_t stream) {
   if (k <= 0) return hipSuccess;
+  const int64_t kmax = kMaxItems / 256;
+  if (k > kmax) {
+    const int64_t sc = (int64_t)(band_of(n) + 1) * (2 * band_of(n) + 1);
+    for (int64_t s = 0; s < k; s += kmax) {
+      // without index lists, pair k is (pattern k, template k)
+      const hipError_t e = launch_xcf_peak(n, pi ? spec_p : spec_p + s * sc, li ? spec_l : spec_l + s * sc,
+                                           pi ? pi + s : nullptr, li ? li + s : nullptr, k - s < kmax ? k - s : kmax,
+                                           max_shift, h_int + s, s_int + 2 * s,
+                                           map ? map + s * (int64_t)n * n : nullptr, stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   EBSD_DISPATCH(n, {
     constexpr int NT = nt_xcf<NN>();
     hipLaunchKernelGGL((k_xcf_peak<NN, NT>), dim3((unsigned)k), dim3(NT), 0, stream, (const cf*)spec_p,

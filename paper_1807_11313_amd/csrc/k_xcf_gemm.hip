@@ -455,12 +455,20 @@ static hipError_t run_gemm(const float2* spec_p, int64_t p, const float2* spec_l
   hipLaunchKernelGGL((k_gemm_consts<N, ST, PREC>), dim3((nthr + 255) / 256), dim3(256), 0, stream, frag);
   const int lchunk = 32;
   const int64_t nchunk = (l + lchunk - 1) / lchunk;
-  const int64_t nblk = p * nchunk;
-  const int64_t grid = ((nblk + 7) / 8) * 8;
-  if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_xcf_gemm<N, ST, PREC>), dim3((unsigned)grid), dim3(512), 0, stream, (const cf*)spec_p, p,
-                     (const cf*)spec_l, l, lchunk, nblk, max_shift, frag, scores);
-  return hipGetLastError();
+  // patterns per dispatch so that blocks x threads stays below 2^31
+  const int64_t pmax = ((int64_t(1) << 31) / 512 - 8) / nchunk;
+  if (pmax < 1) return hipErrorInvalidValue;
+  for (int64_t s = 0; s < p; s += pmax) {
+    const int64_t pc = p - s < pmax ? p - s : pmax;
+    const int64_t nblk = pc * nchunk;
+    const int64_t grid = ((nblk + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_xcf_gemm<N, ST, PREC>), dim3((unsigned)grid), dim3(512), 0, stream,
+                       (const cf*)spec_p + s * G::SPEC, pc, (const cf*)spec_l, l, lchunk, nblk, max_shift, frag,
+                       scores + s * l);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
   }
 }
 

@@ -182,3 +182,22 @@ def test_empty_inputs_are_noops():
     lq = dev(random_quats(np.random.default_rng(0), 3))
     r = t.index_patterns(e, master, (0.5, 0.5, 0.6), lq)
     assert r["best_idx"].numel() == 0
+
+
+def test_search_larger_than_one_dispatch():
+    # 34,000 patterns x 8,000 templates at 128^2 needs more than 2^32
+    # work-items as one dispatch of the search kernel: the launcher splits it,
+    # and every row must equal the same rows searched on their own
+    banner("search split over dispatches")
+    t = tm()
+    n, p, l = 128, 34000, 8000
+    f = t.spectrum_floats(n)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(3)
+    sp = torch.randn((p, f), generator=g, device="cuda:0") * 1e-2
+    sl = torch.randn((l, f), generator=g, device="cuda:0") * 1e-2
+    full = t.xcf_scores(sp, sl, n)
+    for rows in (slice(0, 64), slice(p - 64, p), slice(20000, 20064)):
+        part = t.xcf_scores(sp[rows].contiguous(), sl, n)
+        assert torch.equal(full[rows], part), rows
+    del full
