@@ -460,6 +460,233 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// The same wave-uniform search for N = R1 x R2 with R2 waves per block
+// (64 = 8 x 8, 96 = 12 x 8, 160 = 16 x 10).  Phases 1-2 run the column
+// transform with lanes along v (B + 1 <= 64 lanes); phases 3-4 run the row
+// transform on row pairs (q, q + N/2) packed as one complex transform, with
+// lanes along q in blocks of QB rows; where R1 is not a multiple of R2 the
+// waves past R1 idle in the second radix pass.
+__constant__ RootTable<64> c_roots64 = RootTable<64>();
+__constant__ RootTable<96> c_roots96 = RootTable<96>();
+__constant__ RootTable<160> c_roots160 = RootTable<160>();
+
+template <int N>
+__device__ __forceinline__ cf root_of(int k) {
+  if constexpr (N == 64) return c_roots64.w[k];
+  else if constexpr (N == 96) return c_roots96.w[k];
+  else if constexpr (N == 128) return c_roots128.w[k];
+  else return c_roots160.w[k];
+}
+
+template <int N>
+struct WLay {
+  static constexpr int R1 = N == 64 ? 8 : (N == 96 ? 12 : 16);
+  static constexpr int R2 = N == 160 ? 10 : 8;
+  static constexpr int B = Plan<N>::B, NV = B + 1, NK = 2 * B + 1, SPEC = NV * NK;
+  static constexpr int NQ = N / 2;                      // packed row pairs
+  static constexpr int QB = N == 160 ? 40 : NQ;         // rows per lane block
+  static constexpr int NQB = (NQ + QB - 1) / QB;
+  static constexpr int JC = (R1 + R2 - 1) / R2;         // second-pass radix positions per wave
+  static constexpr int AV = N + 1;                      // A[v][y] row stride
+  static constexpr int XN = R1 * R2 * NV, AN = NV * AV, YN = R1 * R2 * QB;
+  // SEPA: A sits after X, so the second column pass writes each radix
+  // position as soon as it is done and Y reuses X (used at 160, where X + A
+  // fit in LDS and several row blocks read A again); otherwise A and Y
+  // overwrite X and A in turn, after barriers
+  static constexpr bool SEPA = N == 160;
+  static constexpr int AOFF = SEPA ? XN : 0;
+  static constexpr int YOFF = SEPA ? 0 : (NQB > 1 ? AN : 0);
+  static constexpr int cmx(int a, int b) { return a > b ? a : b; }
+  static constexpr int LDSN = cmx(cmx(XN, AOFF + AN), YOFF + YN);
+  static constexpr int NT = R2 * 64;
+  // hold the pattern's phase-1 values in registers across the template loop
+  // (at 160 they would spill; there each template re-reads them through L1)
+  static constexpr bool ECACHE = N != 160;
+};
+
+template <int N, bool WINDOW, bool PERSIST>
+__global__ __launch_bounds__(WLay<N>::NT) void k_xcf_scoresw(const cf* __restrict__ spec_p, int64_t np,
+                                                             const cf* __restrict__ spec_l, int64_t nl, int lchunk,
+                                                             int64_t nblk, int max_shift, float* __restrict__ scores,
+                                                             int* __restrict__ queue) {
+  using L = WLay<N>;
+  constexpr int R1 = L::R1, R2 = L::R2, B = L::B, NV = L::NV, SPEC = L::SPEC, AV = L::AV;
+  constexpr int NQ = L::NQ, QB = L::QB, NQB = L::NQB, JC = L::JC;
+  __shared__ cf lds[L::LDSN];
+  __shared__ float red[R2];
+  __shared__ int item;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int64_t g;
+  if constexpr (PERSIST) {
+    if (tid == 0) item = atomicAdd(queue, 1);
+    __syncthreads();
+    g = item;
+  } else {
+    const int64_t per = (nblk + 7) / 8;
+    g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  }
+  if (g >= nblk) return;
+  const bool vlane = lane < NV;
+
+  while (g < nblk) {
+    const int64_t chunk = g / np, p = g - chunk * np;
+    const cf* E = spec_p + p * SPEC;
+    cf ev[L::ECACHE ? R1 : 1];
+    if constexpr (L::ECACHE) {
+#pragma unroll
+      for (int a = 0; a < R1; ++a) {
+        const int u = R2 * a + wave;
+        const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : -1);
+        ev[a] = (kk >= 0 && vlane) ? E[kk * NV + lane] : cf{0.f, 0.f};
+      }
+    }
+    const int64_t l0 = chunk * lchunk;
+    const int64_t l1 = l0 + lchunk < nl ? l0 + lchunk : nl;
+    for (int64_t l = l0; l < l1; ++l) {
+      const cf* T = spec_l + l * SPEC;
+      // phase 1: wave b, lane v: radix R1 over u = R2 a + b, twiddle
+      {
+        cf x[R1];
+#pragma unroll
+        for (int a = 0; a < R1; ++a) {
+          const int u = R2 * a + wave;
+          const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : -1);
+          cf e;
+          if constexpr (L::ECACHE) e = ev[a];
+          else e = (kk >= 0 && vlane) ? E[kk * NV + lane] : cf{0.f, 0.f};
+          x[a] = (kk >= 0 && vlane) ? cmulc(e, T[kk * NV + lane]) : cf{0.f, 0.f};
+        }
+        DFT<R1, 1>::run(x);
+#pragma unroll
+        for (int c = 1; c < R1; ++c) x[c] = cmul(x[c], root_of<N>((wave * c) % N));
+        if (vlane) {
+#pragma unroll
+          for (int c = 0; c < R1; ++c) lds[(c * R2 + wave) * NV + lane] = x[c];
+        }
+      }
+      __syncthreads();
+      // phase 2: wave takes c = wave + R2 j: radix R2 over b -> A(y = c + R1 d, v)
+      if constexpr (L::SEPA) {
+#pragma unroll
+        for (int j = 0; j < JC; ++j) {
+          const int c = wave + R2 * j;
+          if (c < R1) {
+            cf h[R2];
+#pragma unroll
+            for (int b = 0; b < R2; ++b) h[b] = vlane ? lds[(c * R2 + b) * NV + lane] : cf{0.f, 0.f};
+            DFT<R2, 1>::run(h);
+            if (vlane) {
+#pragma unroll
+              for (int d = 0; d < R2; ++d) lds[L::AOFF + lane * AV + c + R1 * d] = h[d];
+            }
+          }
+        }
+      } else {
+        cf h[JC][R2];
+#pragma unroll
+        for (int j = 0; j < JC; ++j) {
+          const int c = wave + R2 * j;
+          if (c < R1) {
+#pragma unroll
+            for (int b = 0; b < R2; ++b) h[j][b] = vlane ? lds[(c * R2 + b) * NV + lane] : cf{0.f, 0.f};
+            DFT<R2, 1>::run(h[j]);
+          }
+        }
+        __syncthreads();
+        if (vlane) {
+#pragma unroll
+          for (int j = 0; j < JC; ++j) {
+            const int c = wave + R2 * j;
+            if (c < R1) {
+#pragma unroll
+              for (int d = 0; d < R2; ++d) lds[lane * AV + c + R1 * d] = h[j][d];
+            }
+          }
+        }
+      }
+      __syncthreads();
+      const cf* A = lds + L::AOFF;
+      float m = -INFINITY;
+#pragma unroll
+      for (int qb = 0; qb < NQB; ++qb) {
+        const int q = qb * QB + lane;
+        const bool qlane = lane < QB && q < NQ;
+        // phase 3: wave b, lane q: radix R1 over v = R2 a + b of the packed rows (q, q + N/2)
+        cf sv[R1];
+#pragma unroll
+        for (int a = 0; a < R1; ++a) {
+          const int v = R2 * a + wave;
+          if (!qlane) {
+            sv[a] = cf{0.f, 0.f};
+          } else if (v == 0) {
+            sv[a] = cf{A[q].x, A[q + NQ].x};
+          } else if (v <= B) {
+            const cf p0 = A[v * AV + q], p1 = A[v * AV + q + NQ];
+            sv[a] = cf{p0.x - p1.y, p0.y + p1.x};
+          } else if (v >= N - B) {
+            const int w = N - v;
+            const cf p0 = A[w * AV + q], p1 = A[w * AV + q + NQ];
+            sv[a] = cf{p0.x + p1.y, p1.x - p0.y};
+          } else {
+            sv[a] = cf{0.f, 0.f};
+          }
+        }
+        DFT<R1, 1>::run(sv);
+#pragma unroll
+        for (int c = 1; c < R1; ++c) sv[c] = cmul(sv[c], root_of<N>((wave * c) % N));
+        if constexpr (!L::SEPA && NQB == 1) __syncthreads();  // Y overwrites A, which other waves may still read
+        if (lane < QB) {
+#pragma unroll
+          for (int c = 0; c < R1; ++c) lds[L::YOFF + (c * R2 + wave) * QB + lane] = sv[c];
+        }
+        __syncthreads();
+        // phase 4: wave takes c = wave + R2 j: radix R2 over b -> x = c + R1 d
+#pragma unroll
+        for (int j = 0; j < JC; ++j) {
+          const int c = wave + R2 * j;
+          if (c < R1) {
+            cf z[R2];
+#pragma unroll
+            for (int b = 0; b < R2; ++b) z[b] = lds[L::YOFF + (c * R2 + b) * QB + (lane < QB ? lane : 0)];
+            DFT<R2, 1>::run(z);
+            if (qlane) {
+#pragma unroll
+              for (int d = 0; d < R2; ++d) {
+                if constexpr (WINDOW) {
+                  const int x = c + R1 * d;
+                  const bool okx = abs(signed_shift(x, N)) <= max_shift;
+                  if (okx && abs(signed_shift(q, N)) <= max_shift) m = fmaxf(m, z[d].x);
+                  if (okx && abs(signed_shift(q + NQ, N)) <= max_shift) m = fmaxf(m, z[d].y);
+                } else {
+                  m = fmaxf(m, fmaxf(z[d].x, z[d].y));
+                }
+              }
+            }
+          }
+        }
+        if (qb + 1 < NQB) __syncthreads();
+      }
+      m = wave_max(m);
+      if (lane == 0) red[wave] = m;
+      __syncthreads();
+      if (tid == 0) {
+        float r = red[0];
+#pragma unroll
+        for (int w = 1; w < R2; ++w) r = fmaxf(r, red[w]);
+        scores[p * nl + l] = r;
+      }
+    }
+    if constexpr (!PERSIST) break;
+    __syncthreads();
+    if (tid == 0) item = atomicAdd(queue, 1);
+    __syncthreads();
+    g = item;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Forward spectra of K images.
 template <int N, int NT>
 __global__ __launch_bounds__(NT) void k_spectra(const float* __restrict__ imgs, int64_t img_stride,
@@ -739,7 +966,7 @@ hipError_t launch_xcf_scores(int n, const float2* spec_p, int64_t p, const float
   const int lchunk = 32;
   const int64_t nchunk = (l + lchunk - 1) / lchunk;
   // patterns per dispatch so that blocks x threads stays below 2^31
-  const int64_t pmax = (kMaxItems / 512 - 8) / nchunk;
+  const int64_t pmax = (kMaxItems / 1024 - 8) / nchunk;
   if (pmax < 1) return hipErrorInvalidValue;
   if (p > pmax) {
     const int64_t sc = (int64_t)(band_of(n) + 1) * (2 * band_of(n) + 1);
@@ -762,19 +989,23 @@ hipError_t launch_xcf_scores(int n, const float2* spec_p, int64_t p, const float
     return hipGetLastError();
   }
   EBSD_DISPATCH(n, {
-    constexpr int NT = nt_xcf<NN>();
-    hipLaunchKernelGGL((k_xcf_scores<NN, NT, false>), dim3((unsigned)grid), dim3(NT), 0, stream,
-                       (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, nullptr);
+    constexpr int NT = WLay<NN>::NT;
+    if (max_shift < 0)
+      hipLaunchKernelGGL((k_xcf_scoresw<NN, false, false>), dim3((unsigned)grid), dim3(NT), 0, stream,
+                         (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, nullptr);
+    else
+      hipLaunchKernelGGL((k_xcf_scoresw<NN, true, false>), dim3((unsigned)grid), dim3(NT), 0, stream,
+                         (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, nullptr);
   });
   return hipGetLastError();
 }
 
 int xcf_block_threads(int n) {
-  if (n == 128) return 512;
   switch (n) {
-    case 64: return nt_xcf<64>();
-    case 96: return nt_xcf<96>();
-    case 160: return nt_xcf<160>();
+    case 64: return WLay<64>::NT;
+    case 96: return WLay<96>::NT;
+    case 128: return 512;
+    case 160: return WLay<160>::NT;
     default: return 0;
   }
 }
@@ -787,8 +1018,10 @@ hipError_t xcf_persistent_occupancy(int n, int max_shift, int* blocks_per_cu) {
                : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_xcf_scores128<true, true>, 512, 0);
   }
   EBSD_DISPATCH(n, {
-    constexpr int NT = nt_xcf<NN>();
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_xcf_scores<NN, NT, true>, NT, 0);
+    constexpr int NT = WLay<NN>::NT;
+    return max_shift < 0
+               ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_xcf_scoresw<NN, false, true>, NT, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_xcf_scoresw<NN, true, true>, NT, 0);
   });
   return hipSuccess;
 }
@@ -811,9 +1044,13 @@ hipError_t launch_xcf_scores_persistent(int n, const float2* spec_p, int64_t p, 
     return hipGetLastError();
   }
   EBSD_DISPATCH(n, {
-    constexpr int NT = nt_xcf<NN>();
-    hipLaunchKernelGGL((k_xcf_scores<NN, NT, true>), dim3((unsigned)grid), dim3(NT), 0, stream,
-                       (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, queue);
+    constexpr int NT = WLay<NN>::NT;
+    if (max_shift < 0)
+      hipLaunchKernelGGL((k_xcf_scoresw<NN, false, true>), dim3((unsigned)grid), dim3(NT), 0, stream,
+                         (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, queue);
+    else
+      hipLaunchKernelGGL((k_xcf_scoresw<NN, true, true>), dim3((unsigned)grid), dim3(NT), 0, stream,
+                         (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, queue);
   });
   return hipGetLastError();
 }
