@@ -49,6 +49,12 @@ constexpr float kZUnscale = 1.0f / 4096.0f;
 #endif
 constexpr int kGemmELimit = EBSD_GEMM_E_LIMIT;
 
+// patterns per block of the pattern-tiled search (0: one pattern per block)
+#ifndef EBSD_GEMM_PATTERN_TILE
+#define EBSD_GEMM_PATTERN_TILE 4
+#endif
+constexpr int kGemmPatternTile = EBSD_GEMM_PATTERN_TILE;
+
 template <int N, int ST>
 struct GemmLay {
   static constexpr int B = Plan<N>::B, NV = B + 1, NK = 2 * B + 1, SPEC = NV * NK;
@@ -444,6 +450,237 @@ int gemm_slot_tiles(int max_shift) { return (2 * max_shift + 1 + 15) / 16; }
 
 #define EBSD_GEMM_SIZES(X) X(64) X(96) X(128) X(160) X(256)
 
+// One row chunk of stage 1 for one 16-slot s_y tile: Ar^T += Zr W1r + Zi (-W1i),
+// Ai^T += Zr W1i + Zi W1r, each product split into hi*hi + hi*lo + lo*hi
+// (hi*hi only for plain BF16); consecutive MFMAs go to different accumulators.
+template <int PREC, bool NEGW>
+__device__ __forceinline__ void stage1_tile(const u4v& zrh, const u4v& zrl, const u4v& zih, const u4v& zil,
+                                            const u4v* w1f, int fb, f4& ar, f4& ai) {
+  constexpr bool TWO = PREC != 2;
+  const u4v wrh = w1f[fb], wrl = w1f[fb + 64];
+  const u4v wih = w1f[fb + 128], wil = w1f[fb + 192];
+  if constexpr (NEGW) {
+    const u4v nwh = w1f[fb + 256], nwl = w1f[fb + 320];
+    ar = mfma32<PREC>(zrh, wrh, ar);
+    ai = mfma32<PREC>(zrh, wih, ai);
+    ar = mfma32<PREC>(zih, nwh, ar);
+    ai = mfma32<PREC>(zih, wrh, ai);
+    if constexpr (TWO) {
+      ar = mfma32<PREC>(zrh, wrl, ar);
+      ai = mfma32<PREC>(zrh, wil, ai);
+      ar = mfma32<PREC>(zih, nwl, ar);
+      ai = mfma32<PREC>(zih, wrl, ai);
+      ar = mfma32<PREC>(zrl, wrh, ar);
+      ai = mfma32<PREC>(zrl, wih, ai);
+      ar = mfma32<PREC>(zil, nwh, ar);
+      ai = mfma32<PREC>(zil, wrh, ai);
+    }
+  } else {
+    const u4v nzh = zih ^ 0x80008000u, nzl = zil ^ 0x80008000u;
+    ar = mfma32<PREC>(zrh, wrh, ar);
+    ai = mfma32<PREC>(zrh, wih, ai);
+    ar = mfma32<PREC>(nzh, wih, ar);
+    ai = mfma32<PREC>(zih, wrh, ai);
+    if constexpr (TWO) {
+      ar = mfma32<PREC>(zrh, wrl, ar);
+      ai = mfma32<PREC>(zrh, wil, ai);
+      ar = mfma32<PREC>(nzh, wil, ar);
+      ai = mfma32<PREC>(zih, wrl, ai);
+      ar = mfma32<PREC>(zrl, wrh, ar);
+      ai = mfma32<PREC>(zrl, wih, ai);
+      ar = mfma32<PREC>(nzl, wih, ar);
+      ai = mfma32<PREC>(zil, wrh, ai);
+    }
+  }
+}
+
+// Pattern-tiled form: a block correlates PB patterns with 8 templates (one
+// per wave).  The patterns' operand values of each (v tile, row chunk) step
+// are staged once per block in LDS (double-buffered, one barrier per step)
+// and every template value a wave loads serves PB patterns, so each pair
+// costs SPEC / PB template bytes and SPEC / 8 pattern bytes of cache traffic
+// instead of a full spectrum of each.  Blocks are numbered template-block
+// major, so the blocks running at one time on an XCD share their templates
+// in its L2 while the patterns stream.
+template <int N, int ST, int PREC, int PB>
+__global__ __launch_bounds__(512) void k_xcf_gemm_pt(const cf* __restrict__ spec_p, int64_t np,
+                                                     const cf* __restrict__ spec_l, int64_t nl, int64_t npb,
+                                                     int64_t nblk, int max_shift,
+                                                     const unsigned short* __restrict__ frag_g,
+                                                     float* __restrict__ scores) {
+  using G = GemmLay<N, ST>;
+  constexpr int VT = G::VT, KC = G::KC, NSTEP = VT * KC;
+  constexpr bool TWO = PREC != 2;
+  constexpr int EB = PB * 64 * 8;  // complex values per staging buffer
+  __shared__ __align__(16) unsigned char smem[G::FRAG_BYTES + 2 * EB * sizeof(cf)];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t per = (nblk + 7) / 8;
+  const int64_t g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (g >= nblk) return;
+  const int64_t tb = g / npb, pbk = g - tb * npb;
+  const int64_t p0 = pbk * PB;
+  const int64_t l = tb * 8 + wave;
+  const bool lok = l < nl;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(frag_g);
+    uint4* dst = reinterpret_cast<uint4*>(smem);
+    for (int i = tid; i < G::FRAG_BYTES / 16; i += 512) dst[i] = src[i];
+  }
+  const u4v* w1f = reinterpret_cast<const u4v*>(smem);
+  const u2v* cfr = reinterpret_cast<const u2v*>(smem + 2 * G::W1_HALVES);
+  cf* eb = reinterpret_cast<cf*>(smem + G::FRAG_BYTES);
+  const cf* T = spec_l + (lok ? l : 0) * G::SPEC;
+  const cf* Ew = spec_p + (p0 + wave < np ? p0 + wave : 0) * G::SPEC;  // staged by waves < PB
+  const bool ewok = wave < PB && p0 + wave < np;
+  if (wave < PB) {
+    cf vals[8];
+    load_vals<N>(Ew, 0, 0, r16, q4, vals);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) eb[(wave * 64 + lane) * 8 + j] = ewok ? cscale(vals[j], kZScale) : cf{0.f, 0.f};
+  }
+  __syncthreads();
+
+  f4 rho[PB][ST][ST];
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+    for (int a = 0; a < ST; ++a)
+#pragma unroll
+      for (int b = 0; b < ST; ++b) rho[pb][a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  cf tcur[8];
+  load_vals<N>(T, 0, 0, r16, q4, tcur);
+#pragma unroll 1
+  for (int vt = 0; vt < VT; ++vt) {
+    f4 ar[PB][ST], ai[PB][ST];
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+      for (int s = 0; s < ST; ++s) {
+        ar[pb][s] = f4{0.f, 0.f, 0.f, 0.f};
+        ai[pb][s] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll 1
+    for (int kc = 0; kc < KC; ++kc) {
+      const int step = vt * KC + kc, buf = step & 1;
+      const bool more = step + 1 < NSTEP;
+      const int kn = kc + 1 < KC ? kc + 1 : 0, vn = kc + 1 < KC ? vt : vt + 1;
+      cf tnext[8], enext[8];
+      load_vals<N>(T, more ? vn : vt, more ? kn : kc, r16, q4, tnext);
+      if (wave < PB) load_vals<N>(Ew, more ? vn : vt, more ? kn : kc, r16, q4, enext);
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb) {
+        const cf* ep = eb + ((buf * PB + pb) * 64 + lane) * 8;
+        u4v zrh, zrl, zih, zil;
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) {
+          const cf z0 = cmulc(ep[j], tcur[j]), z1 = cmulc(ep[j + 1], tcur[j + 1]);
+          unsigned h, lo;
+          split_pair<PREC>(z0.x, z1.x, h, lo);
+          zrh[j / 2] = h;
+          zrl[j / 2] = lo;
+          split_pair<PREC>(z0.y, z1.y, h, lo);
+          zih[j / 2] = h;
+          zil[j / 2] = lo;
+        }
+#pragma unroll
+        for (int s = 0; s < ST; ++s)
+          stage1_tile<PREC, G::NEGW>(zrh, zrl, zih, zil, w1f, (kc * ST + s) * 2 * G::W1_PARTS * 64 + lane, ar[pb][s],
+                                     ai[pb][s]);
+      }
+      if (wave < PB && more) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          eb[(((buf ^ 1) * PB + wave) * 64 + lane) * 8 + j] = ewok ? cscale(enext[j], kZScale) : cf{0.f, 0.f};
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < 8; ++j) tcur[j] = tnext[j];
+    }
+    // stage 2: rho^T[s_x][s_y] += Cr^T Ar^T + (-Ci)^T Ai^T
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      u2v brh[ST], brl[ST], bih[ST], bil[ST];
+#pragma unroll
+      for (int s = 0; s < ST; ++s) {
+#pragma unroll
+        for (int i = 0; i < 4; i += 2) {
+          unsigned h, lo;
+          split_pair<PREC>(ar[pb][s][i], ar[pb][s][i + 1], h, lo);
+          brh[s][i / 2] = h;
+          brl[s][i / 2] = lo;
+          split_pair<PREC>(ai[pb][s][i], ai[pb][s][i + 1], h, lo);
+          bih[s][i / 2] = h;
+          bil[s][i / 2] = lo;
+        }
+      }
+#pragma unroll
+      for (int sx = 0; sx < ST; ++sx) {
+        const int fb = (vt * ST + sx) * 4 * 64 + lane;
+        const u2v crh = cfr[fb], crl = cfr[fb + 64];
+        const u2v cih = cfr[fb + 128], cil = cfr[fb + 192];
+#pragma unroll
+        for (int sy = 0; sy < ST; ++sy) {
+          rho[pb][sx][sy] = mfma16<PREC>(crh, brh[sy], rho[pb][sx][sy]);
+          rho[pb][sx][sy] = mfma16<PREC>(cih, bih[sy], rho[pb][sx][sy]);
+          if constexpr (TWO) {
+            rho[pb][sx][sy] = mfma16<PREC>(crh, brl[sy], rho[pb][sx][sy]);
+            rho[pb][sx][sy] = mfma16<PREC>(cih, bil[sy], rho[pb][sx][sy]);
+            rho[pb][sx][sy] = mfma16<PREC>(crl, brh[sy], rho[pb][sx][sy]);
+            rho[pb][sx][sy] = mfma16<PREC>(cil, bih[sy], rho[pb][sx][sy]);
+          }
+        }
+      }
+    }
+  }
+  if (!lok) return;
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb) {
+    const int64_t p = p0 + pb;
+    if (p >= np) break;
+    const cf* E = spec_p + p * G::SPEC;
+    float cy[ST], cx4[ST][4];
+#pragma unroll
+    for (int a = 0; a < ST; ++a) {
+      cy[a] = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) cx4[a][i] = 0.0f;
+    }
+    if constexpr (G::FAST) {
+      const cf za = cmulc(E[G::B * G::NV], T[G::B * G::NV]);              // u = +B, v = 0
+      const cf zb = cmulc(E[(G::B + 1) * G::NV], T[(G::B + 1) * G::NV]);  // u = -B, v = 0
+      const cf zc = cmulc(E[G::B], T[G::B]);                                // u = 0,  v = B
+#pragma unroll
+      for (int a = 0; a < ST; ++a) {
+        const int syv = a * 16 + r16 - 8 * ST;
+        const cf w = oct_root((3 * syv) & 7);
+        cy[a] = (za.x * w.x - za.y * w.y) + (zb.x * w.x + zb.y * w.y);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int sxv = a * 16 + 4 * q4 + i - 8 * ST;
+          const cf wx = oct_root((3 * sxv) & 7);
+          cx4[a][i] = 2.0f * (zc.x * wx.x - zc.y * wx.y);
+        }
+      }
+    }
+    float m = -INFINITY;
+#pragma unroll
+    for (int sx = 0; sx < ST; ++sx)
+#pragma unroll
+      for (int sy = 0; sy < ST; ++sy)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int sxv = sx * 16 + 4 * q4 + i - 8 * ST, syv = sy * 16 + r16 - 8 * ST;
+          const float val = __fmaf_rn(rho[pb][sx][sy][i], kZUnscale, cy[sy] + cx4[sx][i]);
+          if (abs(sxv) <= max_shift && abs(syv) <= max_shift) m = fmaxf(m, val);
+        }
+    m = wave_max(m);
+    if (lane == 0) scores[p * nl + l] = m;
+  }
+}
+
 template <int N, int ST, int PREC>
 static hipError_t run_gemm(const float2* spec_p, int64_t p, const float2* spec_l, int64_t l, int max_shift,
                            unsigned short* frag, float* scores, hipStream_t stream) {
@@ -453,6 +690,27 @@ static hipError_t run_gemm(const float2* spec_p, int64_t p, const float2* spec_l
   } else {
   const int nthr = G::W1_HALVES / 2 + G::C_HALVES / 2;
   hipLaunchKernelGGL((k_gemm_consts<N, ST, PREC>), dim3((nthr + 255) / 256), dim3(256), 0, stream, frag);
+  // four patterns per block hold 32 accumulator tiles per wave at ST = 2;
+  // wider shift windows keep one pattern per block
+  constexpr int PB = ST <= 2 ? kGemmPatternTile : 0;
+  if constexpr (PB > 0 && G::FRAG_BYTES + 2 * PB * 64 * 8 * 8 <= 160 * 1024) {
+    const int64_t ntb = (l + 7) / 8;
+    // patterns per dispatch so that blocks x threads stays below 2^31
+    const int64_t pmax = (((int64_t(1) << 31) / 512 - 8) / ntb) * PB;
+    if (pmax < PB) return hipErrorInvalidValue;
+    for (int64_t s = 0; s < p; s += pmax) {
+      const int64_t pc = p - s < pmax ? p - s : pmax;
+      const int64_t npb = (pc + PB - 1) / PB;
+      const int64_t nblk = npb * ntb;
+      const int64_t grid = ((nblk + 7) / 8) * 8;
+      hipLaunchKernelGGL((k_xcf_gemm_pt<N, ST, PREC, PB>), dim3((unsigned)grid), dim3(512), 0, stream,
+                         (const cf*)spec_p + s * G::SPEC, pc, (const cf*)spec_l, l, npb, nblk, max_shift, frag,
+                         scores + s * l);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   const int lchunk = 32;
   const int64_t nchunk = (l + lchunk - 1) / lchunk;
   // patterns per dispatch so that blocks x threads stays below 2^31
