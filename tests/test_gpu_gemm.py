@@ -88,3 +88,27 @@ def test_gemm_index_patterns(prec):
             assert ref["scores"][i][best[i]] >= ref["h_int"][i] - tau
     same = best == ref["best_idx"]
     assert np.max(np.abs(host(res["peak_h"])[same] - ref["peak_h"][same])) < 1e-4
+
+
+@pytest.mark.parametrize("n", [64, 128, 256])
+@pytest.mark.parametrize("prec", [1, 2, 3])
+def test_gemm_scores_match_emulated_split(n, prec):
+    # against the oracle's emulation of the same split arithmetic in FP64:
+    # what remains is the FP32 accumulation, so the bound is far tighter than
+    # the split's own error above (which the FP64 comparison measures)
+    from oracle import split as osplit
+    banner("gemm vs emulated split n=%d precision=%d" % (n, prec))
+    t = tm()
+    pats, lq = _setup(n, 2, 20, seed=5 * n + prec)
+    tmpl = t.project_templates(dev(band_master()), dev(lq), n, (0.5, 0.5, 0.6))
+    sp, sl = t.pattern_spectra(dev(pats)), t.pattern_spectra(tmpl)
+    bp, bl = t.spectra_to_complex(sp, n), t.spectra_to_complex(sl, n)
+    name = {1: "fp16x2", 2: "bf16x2", 3: "bf16"}[prec]
+    for s in (7, 15):
+        got = host(t.xcf_scores(sp, sl, n, t.params_default(precision=prec, max_shift=s)))
+        err = 0.0
+        for i in range(len(pats)):
+            emu = osplit.emulated_scores(bp[i], bl, n, s, name)
+            err = max(err, float(np.max(np.abs(got[i] - emu))))
+        print("[gpu]   n=%d %s S=%d max |gpu - emulated| = %.3g" % (n, name, s, err), flush=True)
+        assert err < 3e-6
