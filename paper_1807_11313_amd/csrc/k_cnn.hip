@@ -231,12 +231,13 @@ __global__ void k_split_sum(const float* __restrict__ part, int z, int64_t mn, f
   out[i] = s;
 }
 
-// sum over (b, pixel) of g[b][c][pixel] for every channel c (bias gradient)
-__global__ __launch_bounds__(256) void k_channel_sum(const float* __restrict__ g, int bsz, int c, int hw,
-                                                     float* __restrict__ out) {
-  const int ch = blockIdx.x;
+// partial sums over (b, pixel) of g[b][c][pixel]: block (c, z) sums images
+// z, z + Z, ... (bias gradient, first stage)
+__global__ __launch_bounds__(256) void k_channel_part(const float* __restrict__ g, int bsz, int c, int hw,
+                                                      int zs, double* __restrict__ part) {
+  const int ch = blockIdx.x, z = blockIdx.y;
   double s = 0.0;
-  for (int bb = 0; bb < bsz; ++bb) {
+  for (int bb = z; bb < bsz; bb += zs) {
     const float* p = g + ((size_t)bb * c + ch) * hw;
     for (int i = threadIdx.x; i < hw; i += 256) s += p[i];
   }
@@ -244,7 +245,16 @@ __global__ __launch_bounds__(256) void k_channel_sum(const float* __restrict__ g
   __shared__ double red[4];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) out[ch] = (float)(red[0] + red[1] + red[2] + red[3]);
+  if (threadIdx.x == 0) part[(size_t)ch * zs + z] = red[0] + red[1] + red[2] + red[3];
+}
+
+// second stage, in a fixed order: out[c] = sum_z part[c][z]
+__global__ void k_channel_sum(const double* __restrict__ part, int c, int zs, float* __restrict__ out) {
+  const int ch = blockIdx.x * 256 + threadIdx.x;
+  if (ch >= c) return;
+  double s = 0.0;
+  for (int z = 0; z < zs; ++z) s += part[(size_t)ch * zs + z];
+  out[ch] = (float)s;
 }
 
 // column sums of a [rows][cols] matrix
@@ -665,9 +675,22 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
            (int)bsz, 1, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_col_sum, dim3(nb(L)), dim3(256), 0, st, act.dz, (int)bsz, L, grad + lay.fc_b);
-  e = gemm(RowK{act.dz, L}, BRowN{params + lay.fc_w, kFeatures}, RowOut{act.dp[3], nullptr, kFeatures}, (int)bsz,
-           kFeatures, L, 1, st);
-  if (e != hipSuccess) return e;
+  {
+    // df = dz W: few output tiles and a long K (= L), so K is split and the
+    // partials are summed in a fixed order
+    const int tiles = (int)(((bsz + 63) / 64) * ((kFeatures + 63) / 64));
+    int s = (512 + tiles - 1) / tiles;
+    const int smax = (L + 255) / 256;
+    s = s > smax ? smax : (s < 1 ? 1 : s);
+    while ((size_t)s * bsz * kFeatures > part_floats && s > 1) s = (s + 1) / 2;
+    const int kslice = ((L + s - 1) / s + 15) & ~15;
+    const int z = (L + kslice - 1) / kslice;
+    e = gemm(RowK{act.dz, L}, BRowN{params + lay.fc_w, kFeatures}, SplitOut{part, (int)bsz, kFeatures}, (int)bsz,
+             kFeatures, L, s, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_split_sum, dim3(nb(bsz * kFeatures)), dim3(256), 0, st, part, z, (int64_t)bsz * kFeatures,
+                       act.dp[3]);
+  }
   int w = kInSize >> 3;  // conv4 input side (8)
   for (int i = 3; i >= 0; --i) {
     const int co = kChannels[i], ci = i ? kChannels[i - 1] : 1, lw = ilog2(w);
@@ -685,8 +708,12 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_split_sum, dim3(nb((int64_t)co * N)), dim3(256), 0, st, part, z, (int64_t)co * N,
                        grad + lay.conv_w[i]);
-    hipLaunchKernelGGL(k_channel_sum, dim3(co), dim3(256), 0, st, act.g[i], (int)bsz, co, w * w,
-                       grad + lay.conv_b[i]);
+    {
+      const int zs = (int)(bsz < 64 ? bsz : 64);
+      double* cpart = reinterpret_cast<double*>(part);  // the weight-gradient partials are summed already
+      hipLaunchKernelGGL(k_channel_part, dim3(co, zs), dim3(256), 0, st, act.g[i], (int)bsz, co, w * w, zs, cpart);
+      hipLaunchKernelGGL(k_channel_sum, dim3(nb(co)), dim3(256), 0, st, cpart, co, zs, grad + lay.conv_b[i]);
+    }
     if (i > 0) {
       e = gemm(ConvBwdDataA{act.g[i], co, lw}, WeightBwdData{params + lay.conv_w[i], ci},
                NchwOut{act.dp[i - 1], ci, lw}, (int)(bsz * w * w), ci, co * 9, 1, st);
