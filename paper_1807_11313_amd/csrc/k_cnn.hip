@@ -1,8 +1,9 @@
 // Kernels of the proposal network (FP32): convolution and fully connected
-// layers as tiled GEMMs whose operands are read through index maps (the
-// convolution's im2col never exists in memory), pooling, softmax
-// cross-entropy, Adam, and the on-device training-data generator (random
-// orientations, projection noise, binning, nearest-library labels).
+// layers as tiled GEMMs on the FP32 matrix cores whose operands are read
+// through index maps (the convolution's im2col never exists in memory),
+// pooling, softmax cross-entropy, Adam, and the on-device training-data
+// generator (random orientations, projection noise, binning,
+// nearest-library labels).
 #include "cnn_internal.hpp"
 #include "ebsd_common.hpp"
 
@@ -12,24 +13,31 @@ namespace ebsd {
 namespace cnn {
 
 // ---------------------------------------------------------------------------
-// Tiled FP32 GEMM: C(m, n) = sum_k A(m, k) B(k, n) over k in the block's
-// slice [z * kslice, (z + 1) * kslice) of [0, K).  64 x 64 tiles, 16-deep
-// K steps through LDS, 4 x 4 outputs per thread at (ty + 16 i, tx + 16 j).
-// A::KFAST / B::KFAST choose which index runs along consecutive threads when
-// the tile is loaded (the one that is contiguous in memory).
+// Tiled FP32 GEMM on the matrix cores: C(m, n) = sum_k A(m, k) B(k, n) over k
+// in the block's slice [z * kslice, (z + 1) * kslice) of [0, K).  64 x 64
+// tiles, 16-deep K steps through LDS; wave w owns the 32 x 32 quarter
+// (w & 1, w >> 1) as 2 x 2 tiles of v_mfma_f32_16x16x4f32 (A operand: lane l
+// holds row l % 16, k = l / 16; B: k = l / 16, column l % 16; accumulator:
+// rows 4 (l / 16) + r, column l % 16).  A::KFAST / B::KFAST choose which
+// index runs along consecutive threads when the tile is loaded (the one that
+// is contiguous in memory).
+typedef float f4c __attribute__((ext_vector_type(4)));
+
 template <class A, class Bm, class Out>
 __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N, int K, int kslice) {
   __shared__ float as[16][64 + 1];
   __shared__ float bs[16][64 + 1];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int kb = blockIdx.z * kslice;
   const int ke = min(K, kb + kslice);
-  float acc[4][4];
+  f4c acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0f;
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4c{0.f, 0.f, 0.f, 0.f};
+  const int r16 = lane & 15, q4 = lane >> 4;
   for (int k0 = kb; k0 < ke; k0 += 16) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -57,26 +65,25 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      float ar[4], br[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) ar[i] = as[kk][ty + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) br[j] = bs[kk][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __fmaf_rn(ar[i], br[j], acc[i][j]);
+    for (int k4 = 0; k4 < 16; k4 += 4) {
+      const float a0 = as[k4 + q4][wm + r16], a1 = as[k4 + q4][wm + 16 + r16];
+      const float b0 = bs[k4 + q4][wn + r16], b1 = bs[k4 + q4][wn + 16 + r16];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
-      if (m < M && n < N) out(m, n, acc[i][j], blockIdx.z);
-    }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * i + 4 * q4 + r, n = n0 + wn + 16 * j + r16;
+        if (m < M && n < N) out(m, n, acc[i][j][r], blockIdx.z);
+      }
 }
 
 // --- operand maps ---------------------------------------------------------
