@@ -690,9 +690,10 @@ static hipError_t run_gemm(const float2* spec_p, int64_t p, const float2* spec_l
   } else {
   const int nthr = G::W1_HALVES / 2 + G::C_HALVES / 2;
   hipLaunchKernelGGL((k_gemm_consts<N, ST, PREC>), dim3((nthr + 255) / 256), dim3(256), 0, stream, frag);
-  // four patterns per block hold 32 accumulator tiles per wave at ST = 2;
-  // wider shift windows keep one pattern per block
-  constexpr int PB = ST <= 2 ? kGemmPatternTile : 0;
+  // four patterns per block hold 32 accumulator tiles per wave at ST = 2
+  // (at 256 the larger address arithmetic then spills, so three); wider
+  // shift windows keep one pattern per block
+  constexpr int PB = ST > 2 || kGemmPatternTile == 0 ? 0 : (N >= 256 && kGemmPatternTile > 3 ? 3 : kGemmPatternTile);
   if constexpr (PB > 0 && G::FRAG_BYTES + 2 * PB * 64 * 8 * 8 <= 160 * 1024) {
     const int64_t ntb = (l + 7) / 8;
     // patterns per dispatch so that blocks x threads stays below 2^31
