@@ -478,6 +478,9 @@ __device__ __forceinline__ cf root_of(int k) {
   else return c_roots160.w[k];
 }
 
+#ifndef EBSD_SEARCHW_MINW64
+#define EBSD_SEARCHW_MINW64 6
+#endif
 template <int N>
 struct WLay {
   static constexpr int R1 = N == 64 ? 8 : (N == 96 ? 12 : 16);
@@ -499,13 +502,17 @@ struct WLay {
   static constexpr int cmx(int a, int b) { return a > b ? a : b; }
   static constexpr int LDSN = cmx(cmx(XN, AOFF + AN), YOFF + YN);
   static constexpr int NT = R2 * 64;
+  // waves per SIMD the register allocation must allow (occupancy beats the
+  // few spills it costs): two 8-wave blocks per CU at 96 (128 VGPRs), at 64
+  // as many as EBSD_SEARCHW_MINW64 asks; at 160 LDS allows one block
+  static constexpr int MINW = N == 96 ? 4 : (N == 64 ? EBSD_SEARCHW_MINW64 : 1);
   // hold the pattern's phase-1 values in registers across the template loop
   // (at 160 they would spill; there each template re-reads them through L1)
   static constexpr bool ECACHE = N != 160;
 };
 
 template <int N, bool WINDOW, bool PERSIST>
-__global__ __launch_bounds__(WLay<N>::NT) void k_xcf_scoresw(const cf* __restrict__ spec_p, int64_t np,
+__global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(const cf* __restrict__ spec_p, int64_t np,
                                                              const cf* __restrict__ spec_l, int64_t nl, int lchunk,
                                                              int64_t nblk, int max_shift, float* __restrict__ scores,
                                                              int* __restrict__ queue) {
