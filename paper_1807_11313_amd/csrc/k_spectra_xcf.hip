@@ -461,7 +461,8 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
 
 // ---------------------------------------------------------------------------
 // The same wave-uniform search for N = R1 x R2 with R2 waves per block
-// (64 = 8 x 8, 96 = 12 x 8, 160 = 16 x 10).  Phases 1-2 run the column
+// (64 = 8 x 8, 96 = 12 x 8, 160 = 10 x 16: sixteen small-radix waves beat
+// ten radix-16 ones, whose registers allow only 2.5 waves per SIMD).  Phases 1-2 run the column
 // transform with lanes along v (B + 1 <= 64 lanes); phases 3-4 run the row
 // transform on row pairs (q, q + N/2) packed as one complex transform, with
 // lanes along q in blocks of QB rows; where R1 is not a multiple of R2 the
@@ -481,10 +482,13 @@ __device__ __forceinline__ cf root_of(int k) {
 #ifndef EBSD_SEARCHW_MINW64
 #define EBSD_SEARCHW_MINW64 6
 #endif
+#ifndef EBSD_SEARCHW_T160
+#define EBSD_SEARCHW_T160 1
+#endif
 template <int N>
 struct WLay {
-  static constexpr int R1 = N == 64 ? 8 : (N == 96 ? 12 : 16);
-  static constexpr int R2 = N == 160 ? 10 : 8;
+  static constexpr int R1 = N == 64 ? 8 : (N == 96 ? 12 : (N == 160 && EBSD_SEARCHW_T160 ? 10 : 16));
+  static constexpr int R2 = N == 160 ? (EBSD_SEARCHW_T160 ? 16 : 10) : 8;
   static constexpr int B = Plan<N>::B, NV = B + 1, NK = 2 * B + 1, SPEC = NV * NK;
   static constexpr int NQ = N / 2;                      // packed row pairs
   static constexpr int QB = N == 160 ? 40 : NQ;         // rows per lane block
