@@ -45,6 +45,20 @@ def gemm_pair_flops(n, s, precision):
     return one * (1 if precision == 3 else 3)
 
 
+def kernel_source_hash(prof):
+    """sha256 prefix of the profiled kernel's definition (from its marker to
+    the closing brace at column 0) and of the headers it includes: the byte
+    counters are used only while these are unchanged."""
+    import hashlib
+    src = open(os.path.join(ROOT, prof["source"])).read()
+    i = src.index(prof["kernel_marker"])
+    j = src.index("\n}\n", i) + 3
+    h = hashlib.sha256(src[i:j].encode())
+    for hdr in prof["headers"]:
+        h.update(open(os.path.join(ROOT, hdr), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def cpu_baseline(cfg, n, l_full, p_full):
     """Times the FP64 oracle on a bounded sample and extrapolates to the full
     workload: L template projections + spectra, P x L correlations, P
@@ -170,10 +184,8 @@ def main():
     # only while the kernel source is the one the counters were taken on
     traffic = None
     try:
-        import hashlib
         prof = json.load(open(os.path.join(ROOT, "profiles", "xcf_search_128_map.json")))
-        src = open(os.path.join(ROOT, prof["source"]), "rb").read()
-        if hashlib.sha256(src).hexdigest()[:16] == prof["source_sha256_prefix"] and (P, L, n) == (10000, 4000, 128):
+        if kernel_source_hash(prof) == prof["kernel_sha256_prefix"] and (P, L, n) == (10000, 4000, 128):
             traffic = prof["fetch_bytes_per_launch"] + prof["write_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         traffic = None
