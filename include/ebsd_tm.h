@@ -290,6 +290,8 @@ int ebsd_ragged_run(ebsd_ragged_plan plan, const float* data, const ebsd_master*
 /* Chosen tiles: for each size present, tiles[4 k ..] = (n, patterns,
  * templates per work item, persistent grid blocks); *count sizes (<= 4). */
 int ebsd_ragged_plan_tiles(ebsd_ragged_plan plan, int32_t* tiles, int32_t* count);
+/* Waits for the device (replays may still run on callers' streams), then
+ * frees the plan. */
 int ebsd_ragged_plan_destroy(ebsd_ragged_plan plan);
 
 /*

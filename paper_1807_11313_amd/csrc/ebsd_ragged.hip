@@ -537,7 +537,8 @@ int ebsd_ragged_plan_create(const int32_t* n_per, const int64_t* offset, int64_t
 
 int ebsd_ragged_plan_destroy(ebsd_ragged_plan plan) {
   if (!plan) return EBSD_OK;
-  (void)hipStreamSynchronize(plan->cap);
+  // replays run on callers' streams: wait for every one before freeing
+  (void)hipDeviceSynchronize();
   plan_free(plan);
   return EBSD_OK;
 }

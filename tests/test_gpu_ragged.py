@@ -129,3 +129,21 @@ def test_ragged_with_missing_sizes_and_tiles():
     res = _run(t, plan, cfg, data)
     assert np.all(host(res["best_idx"]) >= 0) and np.all(host(res["best_idx"]) < 33)
     plan.close()
+
+
+def test_ragged_shift_window_equals_single_size_path():
+    # the persistent searches' shift-window variants against the single-size path
+    banner("ragged with a shift window")
+    t = tm()
+    cfg, data, offs, ns = _workload(p=24, l=45, seed=9)
+    prm = t.params_default(max_shift=6)
+    plan = t.RaggedPlan(ns, offs, len(cfg["lib_q"]), prm=prm, stencil=False)
+    res = _run(t, plan, cfg, data, pcs=False)
+    best, h = host(res["best_idx"]), host(res["peak_h"])
+    for n in (64, 96, 128, 160):
+        idx = np.nonzero(ns == n)[0]
+        pats = dev(np.stack([configs.ragged_pattern(cfg, i) for i in idx]))
+        ref = t.index_patterns(pats, dev(cfg["master"]), cfg["pc"], dev(cfg["lib_q"]), prm=prm)
+        assert np.array_equal(best[idx], host(ref["best_idx"]))
+        assert np.array_equal(h[idx], host(ref["peak_h"]))
+    plan.close()
