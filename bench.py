@@ -91,8 +91,8 @@ def cpu_baseline(cfg, n, l_full, p_full):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--patterns", type=int, default=10000, help="map size (must be a square)")
     ap.add_argument("--library", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -168,13 +168,36 @@ def main():
     tm.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    step_ev = []
     for i in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
         out, idx = step()
+        e1.record()
+        step_ev.append((e0, e1))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     tm.timing_enable(False)
     xcf_ms, launches = tm.timing_read()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    step_ms = sorted(a.elapsed_time(b) for a, b in step_ev)
+    median_ms = step_ms[len(step_ms) // 2] if len(step_ms) % 2 else 0.5 * (step_ms[len(step_ms) // 2 - 1] +
+                                                                           step_ms[len(step_ms) // 2])
+
+    # the same patterns copied from pinned host memory first (reported, not the value)
+    host_pats = torch.empty(pats.shape, dtype=pats.dtype, pin_memory=True)
+    host_pats.copy_(pats)
+    dev_copy = torch.empty_like(pats)
+    torch.cuda.synchronize()
+    h0 = torch.cuda.Event(enable_timing=True)
+    h1 = torch.cuda.Event(enable_timing=True)
+    h0.record()
+    dev_copy.copy_(host_pats, non_blocking=True)
+    h1.record()
+    torch.cuda.synchronize()
+    h2d_ms = h0.elapsed_time(h1)
+    del host_pats, dev_copy
     value = P / (ms_per_step / 1e3)
     xcf_avg_s = xcf_ms / 1e3 / max(launches, 1)
     flops_launch = P * L * pair_flops(n)
@@ -205,6 +228,10 @@ def main():
                                "library, exhaustive FFT XCF + 2-iteration refinement" % (P, side, side, n, n, L),
                    "patterns": P, "library": L, "pattern_size": n, "form": "fft", "precision": "fp32",
                    "parallelism": "single GPU"},
+        "median_ms_per_step": median_ms,
+        "h2d": {"ms": h2d_ms, "bytes": pats.numel() * 4, "GB_per_s": pats.numel() * 4 / h2d_ms / 1e6,
+                "patterns_per_s_including_copy": P / ((ms_per_step + h2d_ms) / 1e3),
+                "note": "pinned host -> HBM copy of the step's patterns, timed with HIP events; not in value"},
         "xcf_pairs_per_s": P * L / xcf_avg_s,
         "xcf_pairs_per_s_whole_step": P * L / (ms_per_step / 1e3),
         "roofline": {"bound": "alu", "kernel": "k_xcf_scores<128>", "achieved": achieved / 1e12,
