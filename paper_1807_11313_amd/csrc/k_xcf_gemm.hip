@@ -100,16 +100,28 @@ __device__ __forceinline__ void split2(float x, unsigned short& hi, unsigned sho
   }
 }
 
+// x - hi for the FP16 half hi held in the low / high 16 bits of a packed
+// dword: one mixed-precision FMA (-hi * 1 + x, exact in FP32) instead of a
+// conversion and a subtraction.
+__device__ __forceinline__ float sub_half_lo(unsigned packed, float x) {
+  float r;
+  asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(packed), "v"(x));
+  return r;
+}
+__device__ __forceinline__ float sub_half_hi(unsigned packed, float x) {
+  float r;
+  asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(packed), "v"(x));
+  return r;
+}
+
 // Splits two floats into packed (hi, hi) and (lo, lo) dwords.  FP16 uses the
 // packed round-toward-zero conversion (the lo half carries the exact fp32
 // remainder x - hi, so truncation costs at most one lo ulp).
 template <int PREC>
 __device__ __forceinline__ void split_pair(float a, float b, unsigned& hi, unsigned& lo) {
   if constexpr (PREC == 0) {
-    const auto h = __builtin_amdgcn_cvt_pkrtz(a, b);
-    const float ah = (float)h[0], bh = (float)h[1];
-    hi = __builtin_bit_cast(unsigned, h);
-    lo = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(a - ah, b - bh));
+    hi = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(a, b));
+    lo = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(sub_half_lo(hi, a), sub_half_hi(hi, b)));
   } else {
     unsigned short ha, la, hb, lb;
     split2<PREC>(a, ha, la);
