@@ -54,6 +54,12 @@ constexpr int kGemmELimit = EBSD_GEMM_E_LIMIT;
 #define EBSD_GEMM_PATTERN_TILE 4
 #endif
 constexpr int kGemmPatternTile = EBSD_GEMM_PATTERN_TILE;
+#ifndef EBSD_GEMM_INTERLEAVE
+#define EBSD_GEMM_INTERLEAVE 1
+#endif
+#ifndef EBSD_GEMM_PAIRSYNC
+#define EBSD_GEMM_PAIRSYNC 1
+#endif
 
 template <int N, int ST>
 struct GemmLay {
@@ -506,10 +512,65 @@ __device__ __forceinline__ void stage1_tile(const u4v& zrh, const u4v& zrl, cons
   }
 }
 
+// Both 16-slot s_y tiles of one row chunk (ST = 2), with consecutive MFMAs
+// cycling through the four accumulators so that no MFMA waits on the one
+// just issued.
+template <int PREC, bool NEGW>
+__device__ __forceinline__ void stage1_tiles2(const u4v& zrh, const u4v& zrl, const u4v& zih, const u4v& zil,
+                                              const u4v* w1f, int fb0, int fb1, f4* ar, f4* ai) {
+  constexpr bool TWO = PREC != 2;
+  const u4v wrh0 = w1f[fb0], wrl0 = w1f[fb0 + 64], wih0 = w1f[fb0 + 128], wil0 = w1f[fb0 + 192];
+  const u4v wrh1 = w1f[fb1], wrl1 = w1f[fb1 + 64], wih1 = w1f[fb1 + 128], wil1 = w1f[fb1 + 192];
+  u4v nwh0, nwl0, nwh1, nwl1, z2h, z2l;
+  if constexpr (NEGW) {
+    nwh0 = w1f[fb0 + 256];
+    nwl0 = w1f[fb0 + 320];
+    nwh1 = w1f[fb1 + 256];
+    nwl1 = w1f[fb1 + 320];
+    z2h = zih;
+    z2l = zil;
+  } else {
+    nwh0 = wih0;
+    nwl0 = wil0;
+    nwh1 = wih1;
+    nwl1 = wil1;
+    z2h = zih ^ 0x80008000u;
+    z2l = zil ^ 0x80008000u;
+  }
+  ar[0] = mfma32<PREC>(zrh, wrh0, ar[0]);
+  ar[1] = mfma32<PREC>(zrh, wrh1, ar[1]);
+  ai[0] = mfma32<PREC>(zrh, wih0, ai[0]);
+  ai[1] = mfma32<PREC>(zrh, wih1, ai[1]);
+  ar[0] = mfma32<PREC>(z2h, nwh0, ar[0]);
+  ar[1] = mfma32<PREC>(z2h, nwh1, ar[1]);
+  ai[0] = mfma32<PREC>(zih, wrh0, ai[0]);
+  ai[1] = mfma32<PREC>(zih, wrh1, ai[1]);
+  if constexpr (TWO) {
+    ar[0] = mfma32<PREC>(zrh, wrl0, ar[0]);
+    ar[1] = mfma32<PREC>(zrh, wrl1, ar[1]);
+    ai[0] = mfma32<PREC>(zrh, wil0, ai[0]);
+    ai[1] = mfma32<PREC>(zrh, wil1, ai[1]);
+    ar[0] = mfma32<PREC>(z2h, nwl0, ar[0]);
+    ar[1] = mfma32<PREC>(z2h, nwl1, ar[1]);
+    ai[0] = mfma32<PREC>(zih, wrl0, ai[0]);
+    ai[1] = mfma32<PREC>(zih, wrl1, ai[1]);
+    ar[0] = mfma32<PREC>(zrl, wrh0, ar[0]);
+    ar[1] = mfma32<PREC>(zrl, wrh1, ar[1]);
+    ai[0] = mfma32<PREC>(zrl, wih0, ai[0]);
+    ai[1] = mfma32<PREC>(zrl, wih1, ai[1]);
+    ar[0] = mfma32<PREC>(z2l, nwh0, ar[0]);
+    ar[1] = mfma32<PREC>(z2l, nwh1, ar[1]);
+    ai[0] = mfma32<PREC>(zil, wrh0, ai[0]);
+    ai[1] = mfma32<PREC>(zil, wrh1, ai[1]);
+  }
+}
+
 // Pattern-tiled form: a block correlates PB patterns with 8 templates (one
 // per wave).  The patterns' operand values of each (v tile, row chunk) step
-// are staged once per block in LDS (double-buffered, one barrier per step)
-// and every template value a wave loads serves PB patterns, so each pair
+// are staged once per block in LDS (a four-slot ring: during an even step
+// waves w < PB stage step + 2 and the next PB waves step + 3, so one barrier
+// closes each pair of steps; with EBSD_GEMM_PAIRSYNC=0 the two-slot form
+// with a barrier per step) and every template value a wave loads serves PB patterns, so each pair
 // costs SPEC / PB template bytes and SPEC / 8 pattern bytes of cache traffic
 // instead of a full spectrum of each.  Blocks are numbered template-block
 // major, so the blocks running at one time on an XCD share their templates
@@ -524,7 +585,8 @@ __global__ __launch_bounds__(512) void k_xcf_gemm_pt(const cf* __restrict__ spec
   constexpr int VT = G::VT, KC = G::KC, NSTEP = VT * KC;
   constexpr bool TWO = PREC != 2;
   constexpr int EB = PB * 64 * 8;  // complex values per staging buffer
-  __shared__ __align__(16) unsigned char smem[G::FRAG_BYTES + 2 * EB * sizeof(cf)];
+  constexpr int NSLOT = EBSD_GEMM_PAIRSYNC ? 4 : 2;
+  __shared__ __align__(16) unsigned char smem[G::FRAG_BYTES + NSLOT * EB * sizeof(cf)];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -545,13 +607,25 @@ __global__ __launch_bounds__(512) void k_xcf_gemm_pt(const cf* __restrict__ spec
   const u2v* cfr = reinterpret_cast<const u2v*>(smem + 2 * G::W1_HALVES);
   cf* eb = reinterpret_cast<cf*>(smem + G::FRAG_BYTES);
   const cf* T = spec_l + (lok ? l : 0) * G::SPEC;
-  const cf* Ew = spec_p + (p0 + wave < np ? p0 + wave : 0) * G::SPEC;  // staged by waves < PB
-  const bool ewok = wave < PB && p0 + wave < np;
-  if (wave < PB) {
+#if EBSD_GEMM_PAIRSYNC
+  // waves w < 2 PB stage pattern p0 + w % PB of every other step (even
+  // steps by w < PB, odd ones by the next PB waves), one barrier per pair
+  const int sw = wave % PB;
+  const bool stager = wave < 2 * PB;
+  const int sodd = wave >= PB ? 1 : 0;
+#else
+  const int sw = wave;
+  const bool stager = wave < PB;
+  const int sodd = 0;
+#endif
+  const cf* Ew = spec_p + (p0 + sw < np ? p0 + sw : 0) * G::SPEC;
+  const bool ewok = stager && p0 + sw < np;
+  if (stager && sodd < NSTEP) {
     cf vals[8];
-    load_vals<N>(Ew, 0, 0, r16, q4, vals);
+    load_vals<N>(Ew, sodd / KC, sodd % KC, r16, q4, vals);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) eb[(wave * 64 + lane) * 8 + j] = ewok ? cscale(vals[j], kZScale) : cf{0.f, 0.f};
+    for (int j = 0; j < 8; ++j)
+      eb[((sodd * PB + sw) * 64 + lane) * 8 + j] = ewok ? cscale(vals[j], kZScale) : cf{0.f, 0.f};
   }
   __syncthreads();
 
@@ -576,12 +650,19 @@ __global__ __launch_bounds__(512) void k_xcf_gemm_pt(const cf* __restrict__ spec
       }
 #pragma unroll 1
     for (int kc = 0; kc < KC; ++kc) {
-      const int step = vt * KC + kc, buf = step & 1;
+      const int step = vt * KC + kc, buf = step & (NSLOT - 1);
       const bool more = step + 1 < NSTEP;
+#if EBSD_GEMM_PAIRSYNC
+      const int sstep = step + 2 + sodd;  // the step this wave stages now
+      const bool stage_now = stager && (step & 1) == 0 && sstep < NSTEP;
+#else
+      const int sstep = step + 1;
+      const bool stage_now = stager && more;
+#endif
       const int kn = kc + 1 < KC ? kc + 1 : 0, vn = kc + 1 < KC ? vt : vt + 1;
       cf tnext[8], enext[8];
       load_vals<N>(T, more ? vn : vt, more ? kn : kc, r16, q4, tnext);
-      if (wave < PB) load_vals<N>(Ew, more ? vn : vt, more ? kn : kc, r16, q4, enext);
+      if (stage_now) load_vals<N>(Ew, sstep / KC, sstep % KC, r16, q4, enext);
 #pragma unroll
       for (int pb = 0; pb < PB; ++pb) {
         const cf* ep = eb + ((buf * PB + pb) * 64 + lane) * 8;
@@ -597,17 +678,27 @@ __global__ __launch_bounds__(512) void k_xcf_gemm_pt(const cf* __restrict__ spec
           zih[j / 2] = h;
           zil[j / 2] = lo;
         }
+        if constexpr (ST == 2 && EBSD_GEMM_INTERLEAVE) {
+          stage1_tiles2<PREC, G::NEGW>(zrh, zrl, zih, zil, w1f, (kc * ST) * 2 * G::W1_PARTS * 64 + lane,
+                                       (kc * ST + 1) * 2 * G::W1_PARTS * 64 + lane, ar[pb], ai[pb]);
+        } else {
 #pragma unroll
-        for (int s = 0; s < ST; ++s)
-          stage1_tile<PREC, G::NEGW>(zrh, zrl, zih, zil, w1f, (kc * ST + s) * 2 * G::W1_PARTS * 64 + lane, ar[pb][s],
-                                     ai[pb][s]);
+          for (int s = 0; s < ST; ++s)
+            stage1_tile<PREC, G::NEGW>(zrh, zrl, zih, zil, w1f, (kc * ST + s) * 2 * G::W1_PARTS * 64 + lane,
+                                       ar[pb][s], ai[pb][s]);
+        }
       }
-      if (wave < PB && more) {
+      if (stage_now) {
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-          eb[(((buf ^ 1) * PB + wave) * 64 + lane) * 8 + j] = ewok ? cscale(enext[j], kZScale) : cf{0.f, 0.f};
+          eb[(((sstep & (NSLOT - 1)) * PB + sw) * 64 + lane) * 8 + j] =
+              ewok ? cscale(enext[j], kZScale) : cf{0.f, 0.f};
       }
+#if EBSD_GEMM_PAIRSYNC
+      if ((step & 1) || step + 1 == NSTEP) __syncthreads();
+#else
       __syncthreads();
+#endif
 #pragma unroll
       for (int j = 0; j < 8; ++j) tcur[j] = tnext[j];
     }
@@ -706,7 +797,7 @@ static hipError_t run_gemm(const float2* spec_p, int64_t p, const float2* spec_l
   // (at 256 the larger address arithmetic then spills, so three); wider
   // shift windows keep one pattern per block
   constexpr int PB = ST > 2 || kGemmPatternTile == 0 ? 0 : (N >= 256 && kGemmPatternTile > 3 ? 3 : kGemmPatternTile);
-  if constexpr (PB > 0 && G::FRAG_BYTES + 2 * PB * 64 * 8 * 8 <= 160 * 1024) {
+  if constexpr (PB > 0 && G::FRAG_BYTES + (EBSD_GEMM_PAIRSYNC ? 4 : 2) * PB * 64 * 8 * 8 <= 160 * 1024) {
     const int64_t ntb = (l + 7) / 8;
     // patterns per dispatch so that blocks x threads stays below 2^31
     const int64_t pmax = (((int64_t(1) << 31) / 512 - 8) / ntb) * PB;
