@@ -358,15 +358,21 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
   const int64_t l1 = l0 + lchunk < nl ? l0 + lchunk : nl;
   for (int64_t l = l0; l < l1; ++l) {
     const cf* T = spec_l + l * SPEC;
-    // phase 1
+    // phase 1 (ev is zero outside the band, so every lane loads from a
+    // clamped in-band address without a branch and the product stays zero:
+    // the sixteen loads are in flight together)
     {
       cf x[R1];
+      // uniform row address + one lane offset: scalar-base loads, no per-row VGPRs
+      const unsigned voff = (unsigned)(vlane ? lane : NV - 1) * (unsigned)sizeof(cf);
 #pragma unroll
       for (int a = 0; a < R1; ++a) {
         const int u = R2 * a + wave;
-        const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : -1);
-        x[a] = (kk >= 0 && vlane) ? cmulc(ev[a], T[kk * NV + lane]) : cf{0.f, 0.f};
+        const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : 0);
+        x[a] = *reinterpret_cast<const cf*>(reinterpret_cast<const char*>(T + kk * NV) + voff);
       }
+#pragma unroll
+      for (int a = 0; a < R1; ++a) x[a] = cmulc(ev[a], x[a]);
       DFT<R1, 1>::run(x);
 #pragma unroll
       for (int c = 1; c < R1; ++c) x[c] = cmul(x[c], tw[c]);
@@ -557,17 +563,31 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
     const int64_t l1 = l0 + lchunk < nl ? l0 + lchunk : nl;
     for (int64_t l = l0; l < l1; ++l) {
       const cf* T = spec_l + l * SPEC;
-      // phase 1: wave b, lane v: radix R1 over u = R2 a + b, twiddle
+      // phase 1: wave b, lane v: radix R1 over u = R2 a + b, twiddle.  With the
+      // pattern values cached (zero outside the band) every lane loads from a
+      // clamped in-band address without a branch, so all R1 loads are in
+      // flight together and the product stays zero where it must; at 160 the
+      // pattern values are re-read per template and out-of-band rows skipped
       {
         cf x[R1];
+        if constexpr (L::ECACHE) {
+          const unsigned voff = (unsigned)(vlane ? lane : NV - 1) * (unsigned)sizeof(cf);
 #pragma unroll
-        for (int a = 0; a < R1; ++a) {
-          const int u = R2 * a + wave;
-          const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : -1);
-          cf e;
-          if constexpr (L::ECACHE) e = ev[a];
-          else e = (kk >= 0 && vlane) ? E[kk * NV + lane] : cf{0.f, 0.f};
-          x[a] = (kk >= 0 && vlane) ? cmulc(e, T[kk * NV + lane]) : cf{0.f, 0.f};
+          for (int a = 0; a < R1; ++a) {
+            const int u = R2 * a + wave;
+            const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : 0);
+            x[a] = *reinterpret_cast<const cf*>(reinterpret_cast<const char*>(T + kk * NV) + voff);
+          }
+#pragma unroll
+          for (int a = 0; a < R1; ++a) x[a] = cmulc(ev[a], x[a]);
+        } else {
+#pragma unroll
+          for (int a = 0; a < R1; ++a) {
+            const int u = R2 * a + wave;
+            const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : -1);
+            const cf e = (kk >= 0 && vlane) ? E[kk * NV + lane] : cf{0.f, 0.f};
+            x[a] = (kk >= 0 && vlane) ? cmulc(e, T[kk * NV + lane]) : cf{0.f, 0.f};
+          }
         }
         DFT<R1, 1>::run(x);
 #pragma unroll

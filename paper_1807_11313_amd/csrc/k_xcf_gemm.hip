@@ -248,6 +248,15 @@ __device__ __forceinline__ cf oct_root(int k) {
   return cf{c[k], c[(k + 6) & 7]};
 }
 
+// Staged fragments of 64 lanes x 8 complex values: value j of a lane sits at
+// lane_base(frag, lane)[val_at(j)], with the 16-byte pairs (j / 2)
+// lane-contiguous, so a 128-bit LDS read of one pair by 64 lanes touches
+// consecutive addresses (lanes 64 bytes apart would put four of every eight
+// lanes on the same banks).
+template <class P>
+__device__ __forceinline__ P* lane_base(P* frags, int frag, int lane) { return frags + frag * 512 + lane * 2; }
+__device__ __forceinline__ constexpr int val_at(int j) { return (j >> 1) * 128 + (j & 1); }
+
 template <int N, int ST, int PREC>
 __global__ __launch_bounds__(512) void k_xcf_gemm(const cf* __restrict__ spec_p, int64_t np,
                                                   const cf* __restrict__ spec_l, int64_t nl, int lchunk,
@@ -278,7 +287,7 @@ __global__ __launch_bounds__(512) void k_xcf_gemm(const cf* __restrict__ spec_p,
         cf vals[8];
         load_vals<N>(E, f / KC, f % KC, r16, q4, vals);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) es[(f * 64 + lane) * 8 + j] = cscale(vals[j], kZScale);
+        for (int j = 0; j < 8; ++j) lane_base(es, f, lane)[val_at(j)] = cscale(vals[j], kZScale);
       }
     }
   }
@@ -320,7 +329,7 @@ __global__ __launch_bounds__(512) void k_xcf_gemm(const cf* __restrict__ spec_p,
         cf ev[8];
         if constexpr (G::ELDS) {
 #pragma unroll
-          for (int j = 0; j < 8; ++j) ev[j] = es[((vt * KC + kc) * 64 + lane) * 8 + j];
+          for (int j = 0; j < 8; ++j) ev[j] = lane_base(es, vt * KC + kc, lane)[val_at(j)];
         } else {
           load_vals<N>(E, vt, kc, r16, q4, ev);
 #pragma unroll
@@ -625,7 +634,7 @@ __global__ __launch_bounds__(512) void k_xcf_gemm_pt(const cf* __restrict__ spec
     load_vals<N>(Ew, sodd / KC, sodd % KC, r16, q4, vals);
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-      eb[((sodd * PB + sw) * 64 + lane) * 8 + j] = ewok ? cscale(vals[j], kZScale) : cf{0.f, 0.f};
+      lane_base(eb, sodd * PB + sw, lane)[val_at(j)] = ewok ? cscale(vals[j], kZScale) : cf{0.f, 0.f};
   }
   __syncthreads();
 
@@ -665,11 +674,11 @@ __global__ __launch_bounds__(512) void k_xcf_gemm_pt(const cf* __restrict__ spec
       if (stage_now) load_vals<N>(Ew, sstep / KC, sstep % KC, r16, q4, enext);
 #pragma unroll
       for (int pb = 0; pb < PB; ++pb) {
-        const cf* ep = eb + ((buf * PB + pb) * 64 + lane) * 8;
+        const cf* ep = lane_base(static_cast<const cf*>(eb), buf * PB + pb, lane);
         u4v zrh, zrl, zih, zil;
 #pragma unroll
         for (int j = 0; j < 8; j += 2) {
-          const cf z0 = cmulc(ep[j], tcur[j]), z1 = cmulc(ep[j + 1], tcur[j + 1]);
+          const cf z0 = cmulc(ep[val_at(j)], tcur[j]), z1 = cmulc(ep[val_at(j + 1)], tcur[j + 1]);
           unsigned h, lo;
           split_pair<PREC>(z0.x, z1.x, h, lo);
           zrh[j / 2] = h;
@@ -691,7 +700,7 @@ __global__ __launch_bounds__(512) void k_xcf_gemm_pt(const cf* __restrict__ spec
       if (stage_now) {
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-          eb[(((sstep & (NSLOT - 1)) * PB + sw) * 64 + lane) * 8 + j] =
+          lane_base(eb, (sstep & (NSLOT - 1)) * PB + sw, lane)[val_at(j)] =
               ewok ? cscale(enext[j], kZScale) : cf{0.f, 0.f};
       }
 #if EBSD_GEMM_PAIRSYNC
