@@ -219,6 +219,68 @@ struct DFT {
   }
 };
 
+// Length-R DFT for R = 4 Q with Q > 1 (the split of DFT<R>: same twiddles and
+// output order) of inputs some of which are known to be zero: bit j of ZM
+// marks x[j] == 0, x[j] is then not read.  Dropping the additions of exact
+// zeros leaves every output equal to that of DFT<R, DIR> up to the sign of
+// zero results.  At most one input of each first-stage butterfly pair
+// (j, j + 2Q) may be zero.
+template <int R, int DIR, int ZM>
+__device__ __forceinline__ void dft_zero(cf* x) {
+  constexpr int Q = R / 4;
+  static_assert(R % 4 == 0 && Q > 1 && split_factor<R>() == 4, "radix 4 x Q");
+  cf t[R];
+  static_for<0, Q>([&](auto bi) {
+    constexpr int b = decltype(bi)::value;
+    constexpr bool z0 = (ZM >> b) & 1, z1 = (ZM >> (Q + b)) & 1, z2 = (ZM >> (2 * Q + b)) & 1,
+                   z3 = (ZM >> (3 * Q + b)) & 1;
+    static_assert(!(z0 && z2) && !(z1 && z3), "a butterfly pair with two zero inputs");
+    cf a0, a1, b0, d1;
+    if constexpr (z0) {
+      a0 = x[2 * Q + b];
+      a1 = cf{-x[2 * Q + b].x, -x[2 * Q + b].y};
+    } else if constexpr (z2) {
+      a0 = a1 = x[b];
+    } else {
+      a0 = cadd(x[b], x[2 * Q + b]);
+      a1 = csub(x[b], x[2 * Q + b]);
+    }
+    if constexpr (z1) {
+      b0 = x[3 * Q + b];
+      d1 = cf{-x[3 * Q + b].x, -x[3 * Q + b].y};
+    } else if constexpr (z3) {
+      b0 = d1 = x[Q + b];
+    } else {
+      b0 = cadd(x[Q + b], x[3 * Q + b]);
+      d1 = csub(x[Q + b], x[3 * Q + b]);
+    }
+    const cf b1 = cmuli<DIR>(d1);
+    const cf v[4] = {cadd(a0, b0), cadd(a1, b1), csub(a0, b0), csub(a1, b1)};
+    static_for<0, 4>([&](auto ci) {
+      constexpr int c = decltype(ci)::value;
+      t[c * Q + b] = twiddle<(long)b * c, R, DIR>(v[c]);
+    });
+  });
+  static_for<0, 4>([&](auto ci) {
+    constexpr int c = decltype(ci)::value;
+    DFT<Q, DIR>::run(&t[c * Q]);
+    static_for<0, Q>([&](auto di) {
+      constexpr int d = decltype(di)::value;
+      x[c + 4 * d] = t[c * Q + d];
+    });
+  });
+}
+
+// Inputs a of a first radix-R1 pass over u = R2 a + b (any b in [0, R2)) that
+// fall between the band edges B and N - B, i.e. are zero for every b.
+template <int N, int R1, int R2, int B>
+constexpr int band_gap_mask() {
+  int m = 0;
+  for (int a = 0; a < R1; ++a)
+    if (R2 * a > B && R2 * a + R2 - 1 < N - B) m |= 1 << a;
+  return m;
+}
+
 // ---------------------------------------------------------------------------
 // Per-size plan of the two-pass decomposition N = R1 * R2 used for every
 // 2-D transform, and the band half-width B of the filtered spectra (the

@@ -316,10 +316,13 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
                                                           float* __restrict__ scores, int* __restrict__ queue) {
   constexpr int N = 128, R1 = 16, R2 = 8, B = 48, NV = 49;
   constexpr int SPEC = NV * (2 * B + 1);
+  constexpr int GAP = band_gap_mask<N, R1, R2, B>();  // a = 7, 8, 9
+  static_assert(GAP == 0x380, "band gap of the 128 plan");
   constexpr int AV = N + 1;  // A[v][y] row stride (odd: the phase-2 writes spread over banks)
   // X [c][b][v] (R1*R2*NV), A [v][y] (NV*AV), Y [c][b][q] (R1*R2*64) share one buffer
   constexpr int LDSN = (R1 * R2 * 64 > NV * AV) ? R1 * R2 * 64 : NV * AV;
   __shared__ cf lds[LDSN];
+  static_assert((R1 * R2 - 1) * NV + 63 < LDSN, "phase-2 reads of lanes past the band stay in LDS");
   __shared__ float red[8];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -363,17 +366,20 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
     // the sixteen loads are in flight together)
     {
       cf x[R1];
-      // uniform row address + one lane offset: scalar-base loads, no per-row VGPRs
+      // uniform row address + one lane offset: scalar-base loads, no per-row VGPRs;
+      // inputs between the band edges for every wave are neither loaded nor added
       const unsigned voff = (unsigned)(vlane ? lane : NV - 1) * (unsigned)sizeof(cf);
 #pragma unroll
       for (int a = 0; a < R1; ++a) {
+        if ((GAP >> a) & 1) continue;
         const int u = R2 * a + wave;
         const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : 0);
         x[a] = *reinterpret_cast<const cf*>(reinterpret_cast<const char*>(T + kk * NV) + voff);
       }
 #pragma unroll
-      for (int a = 0; a < R1; ++a) x[a] = cmulc(ev[a], x[a]);
-      DFT<R1, 1>::run(x);
+      for (int a = 0; a < R1; ++a)
+        if (!((GAP >> a) & 1)) x[a] = cmulc(ev[a], x[a]);
+      dft_zero<R1, 1, GAP>(x);
 #pragma unroll
       for (int c = 1; c < R1; ++c) x[c] = cmul(x[c], tw[c]);
       if (vlane) {
@@ -388,7 +394,7 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
     for (int j = 0; j < 2; ++j) {
       const int c = wave + 8 * j;
 #pragma unroll
-      for (int b = 0; b < R2; ++b) h[j][b] = vlane ? lds[(c * R2 + b) * NV + lane] : cf{0.f, 0.f};
+      for (int b = 0; b < R2; ++b) h[j][b] = lds[(c * R2 + b) * NV + lane];  // lanes >= NV: in-bounds, never stored
       DFT<R2, 1>::run(h[j]);
     }
     __syncthreads();
@@ -402,24 +408,38 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
     }
     __syncthreads();
     // phase 3: wave b, lane q: packed rows q and q + 64
+    // S(v) = A(q, v) + i A(q + 64, v) for 0 < v <= B, conj(A(q, N - v)) +
+    // i conj(A(q + 64, N - v)) for v >= N - B, (A(q, 0).x, A(q + 64, 0).x)
+    // at v = 0 and 0 in the gap: every row is read (clamped, no branch, so the
+    // reads are in flight together) and the cases are uniform coefficients
+    // c = +-1 or 0 (fma(c, y, x) = x + c y exactly)
     cf s[R1];
-#pragma unroll
-    for (int a = 0; a < R1; ++a) {
-      const int v = R2 * a + wave;
-      if (v == 0) {
-        s[a] = cf{lds[lane].x, lds[lane + 64].x};
-      } else if (v <= B) {
-        const cf p0 = lds[v * AV + lane], p1 = lds[v * AV + lane + 64];
-        s[a] = cf{p0.x - p1.y, p0.y + p1.x};
-      } else if (v >= N - B) {
-        const int w = N - v;
-        const cf p0 = lds[w * AV + lane], p1 = lds[w * AV + lane + 64];
-        s[a] = cf{p0.x + p1.y, p1.x - p0.y};
-      } else {
-        s[a] = cf{0.f, 0.f};
-      }
+    {
+      cf p0[R1], p1[R1];
+      static_for<0, R1>([&](auto ai) {
+        constexpr int a = decltype(ai)::value;
+        if constexpr (!((GAP >> a) & 1)) {
+          const int v = R2 * a + wave;
+          const int w = v <= B ? v : (v >= N - B ? N - v : 0);
+          p0[a] = lds[w * AV + lane];
+          p1[a] = lds[w * AV + lane + 64];
+        }
+      });
+      static_for<0, R1>([&](auto ai) {
+        constexpr int a = decltype(ai)::value;
+        if constexpr (!((GAP >> a) & 1)) {
+          const int v = R2 * a + wave;
+          const float c = v == 0 ? 0.f : (v >= N - B ? -1.f : 1.f);
+          s[a] = cf{__fmaf_rn(-c, p1[a].y, p0[a].x), __fmaf_rn(c, p0[a].y, p1[a].x)};
+          // rows a that are in the band for some waves only (here a = 6)
+          constexpr bool always_in = R2 * a + R2 - 1 <= B || R2 * a >= N - B;
+          if constexpr (!always_in) {
+            if (v > B && v < N - B) s[a] = cf{0.f, 0.f};
+          }
+        }
+      });
     }
-    DFT<R1, 1>::run(s);
+    dft_zero<R1, 1, GAP>(s);  // v = 8 a + b in the gap for a = 7, 8, 9
 #pragma unroll
     for (int c = 1; c < R1; ++c) s[c] = cmul(s[c], tw[c]);
     __syncthreads();
@@ -519,6 +539,9 @@ struct WLay {
   // hold the pattern's phase-1 values in registers across the template loop
   // (at 160 they would spill; there each template re-reads them through L1)
   static constexpr bool ECACHE = N != 160;
+  // first-pass inputs a zero for every wave (u or v = R2 a + b between the
+  // band edges): a = 4 at 64, 5 and 6 at 96, 7 to 9 at 128
+  static constexpr int GAP = band_gap_mask<N, R1, R2, B>();
 };
 
 template <int N, bool WINDOW, bool PERSIST>
@@ -530,6 +553,7 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
   constexpr int R1 = L::R1, R2 = L::R2, B = L::B, NV = L::NV, SPEC = L::SPEC, AV = L::AV;
   constexpr int NQ = L::NQ, QB = L::QB, NQB = L::NQB, JC = L::JC;
   __shared__ cf lds[L::LDSN];
+  static_assert((R1 * R2 - 1) * NV + 63 < L::LDSN, "phase-2 reads of lanes past the band stay in LDS");
   __shared__ float red[R2];
   __shared__ int item;
   const int tid = threadIdx.x;
@@ -571,15 +595,19 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
       {
         cf x[R1];
         if constexpr (L::ECACHE) {
+          // inputs between the band edges for every wave are neither loaded nor added
           const unsigned voff = (unsigned)(vlane ? lane : NV - 1) * (unsigned)sizeof(cf);
 #pragma unroll
           for (int a = 0; a < R1; ++a) {
+            if ((L::GAP >> a) & 1) continue;
             const int u = R2 * a + wave;
             const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : 0);
             x[a] = *reinterpret_cast<const cf*>(reinterpret_cast<const char*>(T + kk * NV) + voff);
           }
 #pragma unroll
-          for (int a = 0; a < R1; ++a) x[a] = cmulc(ev[a], x[a]);
+          for (int a = 0; a < R1; ++a)
+            if (!((L::GAP >> a) & 1)) x[a] = cmulc(ev[a], x[a]);
+          dft_zero<R1, 1, L::GAP>(x);
         } else {
 #pragma unroll
           for (int a = 0; a < R1; ++a) {
@@ -588,8 +616,8 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
             const cf e = (kk >= 0 && vlane) ? E[kk * NV + lane] : cf{0.f, 0.f};
             x[a] = (kk >= 0 && vlane) ? cmulc(e, T[kk * NV + lane]) : cf{0.f, 0.f};
           }
+          DFT<R1, 1>::run(x);
         }
-        DFT<R1, 1>::run(x);
 #pragma unroll
         for (int c = 1; c < R1; ++c) x[c] = cmul(x[c], root_of<N>((wave * c) % N));
         if (vlane) {
@@ -606,7 +634,7 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
           if (c < R1) {
             cf h[R2];
 #pragma unroll
-            for (int b = 0; b < R2; ++b) h[b] = vlane ? lds[(c * R2 + b) * NV + lane] : cf{0.f, 0.f};
+            for (int b = 0; b < R2; ++b) h[b] = lds[(c * R2 + b) * NV + lane];  // lanes >= NV: never stored
             DFT<R2, 1>::run(h);
             if (vlane) {
 #pragma unroll
@@ -621,7 +649,7 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
           const int c = wave + R2 * j;
           if (c < R1) {
 #pragma unroll
-            for (int b = 0; b < R2; ++b) h[j][b] = vlane ? lds[(c * R2 + b) * NV + lane] : cf{0.f, 0.f};
+            for (int b = 0; b < R2; ++b) h[j][b] = lds[(c * R2 + b) * NV + lane];  // lanes >= NV: in-bounds, never stored
             DFT<R2, 1>::run(h[j]);
           }
         }
@@ -664,7 +692,8 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
             sv[a] = cf{0.f, 0.f};
           }
         }
-        DFT<R1, 1>::run(sv);
+        if constexpr (L::ECACHE) dft_zero<R1, 1, L::GAP>(sv);  // the same band gap along v
+        else DFT<R1, 1>::run(sv);
 #pragma unroll
         for (int c = 1; c < R1; ++c) sv[c] = cmul(sv[c], root_of<N>((wave * c) % N));
         if constexpr (!L::SEPA && NQB == 1) __syncthreads();  // Y overwrites A, which other waves may still read
