@@ -297,6 +297,17 @@ __global__ __launch_bounds__(NT) void k_xcf_peak(const cf* __restrict__ spec_p, 
 //   phase 3  wave b, lane q:  radix 16 over v = 8a + b of the packed row pair
 //                             (q, q + 64), twiddle
 //   phase 4  wave c, lane q:  radix 8 over b -> rho(row q and q + 64, x = c + 16 d)
+// Raw buffer view of one spectrum (gfx9 descriptor word 3: 32-bit data
+// format, no stride; reads past the byte count return zero): a load then
+// takes its lane offset in one VGPR and its uniform row offset in an SGPR,
+// with no per-load address arithmetic.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t spectrum_rsrc(const cf* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<cf*>(p), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ cf buffer_cf(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+  return __builtin_bit_cast(cf, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
 template <int N>
 struct RootTable {
   cf w[N];
@@ -366,15 +377,16 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
     // the sixteen loads are in flight together)
     {
       cf x[R1];
-      // uniform row address + one lane offset: scalar-base loads, no per-row VGPRs;
+      // buffer loads: one lane offset, uniform row offsets, no per-row VGPRs;
       // inputs between the band edges for every wave are neither loaded nor added
       const unsigned voff = (unsigned)(vlane ? lane : NV - 1) * (unsigned)sizeof(cf);
+      const __amdgpu_buffer_rsrc_t Tr = spectrum_rsrc(T, SPEC * (int)sizeof(cf));
 #pragma unroll
       for (int a = 0; a < R1; ++a) {
         if ((GAP >> a) & 1) continue;
         const int u = R2 * a + wave;
         const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : 0);
-        x[a] = *reinterpret_cast<const cf*>(reinterpret_cast<const char*>(T + kk * NV) + voff);
+        x[a] = buffer_cf(Tr, voff, kk * NV * (int)sizeof(cf));
       }
 #pragma unroll
       for (int a = 0; a < R1; ++a)
@@ -448,6 +460,8 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
     __syncthreads();
     // phase 4: waves take c = wave and c = wave + 8; outputs x = c + 16 d
     float m = -INFINITY;
+    const float mq0 = abs(signed_shift(lane, N)) <= max_shift ? 0.f : -INFINITY;
+    const float mq1 = abs(signed_shift(lane + 64, N)) <= max_shift ? 0.f : -INFINITY;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int c = wave + 8 * j;
@@ -458,10 +472,10 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
 #pragma unroll
       for (int d = 0; d < R2; ++d) {
         if constexpr (WINDOW) {
+          // the column test is uniform; the rows of this lane enter through
+          // additive 0 / -inf masks (exact)
           const int x = c + R1 * d;
-          const bool okx = abs(signed_shift(x, N)) <= max_shift;
-          if (okx && abs(signed_shift(lane, N)) <= max_shift) m = fmaxf(m, z[d].x);
-          if (okx && abs(signed_shift(lane + 64, N)) <= max_shift) m = fmaxf(m, z[d].y);
+          if (abs(signed_shift(x, N)) <= max_shift) m = fmaxf(m, fmaxf(z[d].x + mq0, z[d].y + mq1));
         } else {
           m = fmaxf(m, fmaxf(z[d].x, z[d].y));
         }
@@ -536,12 +550,14 @@ struct WLay {
   // few spills it costs): two 8-wave blocks per CU at 96 (128 VGPRs), at 64
   // as many as EBSD_SEARCHW_MINW64 asks; at 160 LDS allows one block
   static constexpr int MINW = N == 96 ? 4 : (N == 64 ? EBSD_SEARCHW_MINW64 : 1);
-  // hold the pattern's phase-1 values in registers across the template loop
-  // (at 160 they would spill; there each template re-reads them through L1)
-  static constexpr bool ECACHE = N != 160;
   // first-pass inputs a zero for every wave (u or v = R2 a + b between the
-  // band edges): a = 4 at 64, 5 and 6 at 96, 7 to 9 at 128
+  // band edges): a = 4 at 64, 5 and 6 at 96, 7 to 9 at 128, 4 and 5 at 160;
+  // skipped where the first radix splits as 4 x Q (not at 160, radix 10)
   static constexpr int GAP = band_gap_mask<N, R1, R2, B>();
+  static constexpr bool ZGAP = R1 % 4 == 0 && R1 > 4;
+  // template loads as raw buffer loads (measured: 1.03x at 64, neutral at
+  // 160, 0.93x at 96, where the global-load form schedules better)
+  static constexpr bool BUFLOAD = N != 96;
 };
 
 template <int N, bool WINDOW, bool PERSIST>
@@ -574,50 +590,39 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
   while (g < nblk) {
     const int64_t chunk = g / np, p = g - chunk * np;
     const cf* E = spec_p + p * SPEC;
-    cf ev[L::ECACHE ? R1 : 1];
-    if constexpr (L::ECACHE) {
+    // the pattern's phase-1 values, held in registers across the template loop
+    cf ev[R1];
 #pragma unroll
-      for (int a = 0; a < R1; ++a) {
-        const int u = R2 * a + wave;
-        const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : -1);
-        ev[a] = (kk >= 0 && vlane) ? E[kk * NV + lane] : cf{0.f, 0.f};
-      }
+    for (int a = 0; a < R1; ++a) {
+      const int u = R2 * a + wave;
+      const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : -1);
+      ev[a] = (kk >= 0 && vlane) ? E[kk * NV + lane] : cf{0.f, 0.f};
     }
     const int64_t l0 = chunk * lchunk;
     const int64_t l1 = l0 + lchunk < nl ? l0 + lchunk : nl;
     for (int64_t l = l0; l < l1; ++l) {
       const cf* T = spec_l + l * SPEC;
-      // phase 1: wave b, lane v: radix R1 over u = R2 a + b, twiddle.  With the
-      // pattern values cached (zero outside the band) every lane loads from a
-      // clamped in-band address without a branch, so all R1 loads are in
-      // flight together and the product stays zero where it must; at 160 the
-      // pattern values are re-read per template and out-of-band rows skipped
+      // phase 1: wave b, lane v: radix R1 over u = R2 a + b, twiddle.  The
+      // cached pattern values are zero outside the band, so every lane loads
+      // its template values from a clamped in-band address without a branch
+      // (all R1 loads in flight together) and the products stay zero there
       {
         cf x[R1];
-        if constexpr (L::ECACHE) {
-          // inputs between the band edges for every wave are neither loaded nor added
-          const unsigned voff = (unsigned)(vlane ? lane : NV - 1) * (unsigned)sizeof(cf);
+        const unsigned voff = (unsigned)(vlane ? lane : NV - 1) * (unsigned)sizeof(cf);
+        const __amdgpu_buffer_rsrc_t Tr = spectrum_rsrc(T, SPEC * (int)sizeof(cf));
 #pragma unroll
-          for (int a = 0; a < R1; ++a) {
-            if ((L::GAP >> a) & 1) continue;
-            const int u = R2 * a + wave;
-            const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : 0);
-            x[a] = *reinterpret_cast<const cf*>(reinterpret_cast<const char*>(T + kk * NV) + voff);
-          }
-#pragma unroll
-          for (int a = 0; a < R1; ++a)
-            if (!((L::GAP >> a) & 1)) x[a] = cmulc(ev[a], x[a]);
-          dft_zero<R1, 1, L::GAP>(x);
-        } else {
-#pragma unroll
-          for (int a = 0; a < R1; ++a) {
-            const int u = R2 * a + wave;
-            const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : -1);
-            const cf e = (kk >= 0 && vlane) ? E[kk * NV + lane] : cf{0.f, 0.f};
-            x[a] = (kk >= 0 && vlane) ? cmulc(e, T[kk * NV + lane]) : cf{0.f, 0.f};
-          }
-          DFT<R1, 1>::run(x);
+        for (int a = 0; a < R1; ++a) {
+          if (L::ZGAP && ((L::GAP >> a) & 1)) continue;  // neither loaded nor added
+          const int u = R2 * a + wave;
+          const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : 0);
+          if constexpr (L::BUFLOAD) x[a] = buffer_cf(Tr, voff, kk * NV * (int)sizeof(cf));
+          else x[a] = *reinterpret_cast<const cf*>(reinterpret_cast<const char*>(T + kk * NV) + voff);
         }
+#pragma unroll
+        for (int a = 0; a < R1; ++a)
+          if (!(L::ZGAP && ((L::GAP >> a) & 1))) x[a] = cmulc(ev[a], x[a]);
+        if constexpr (L::ZGAP) dft_zero<R1, 1, L::GAP>(x);
+        else DFT<R1, 1>::run(x);
 #pragma unroll
         for (int c = 1; c < R1; ++c) x[c] = cmul(x[c], root_of<N>((wave * c) % N));
         if (vlane) {
@@ -672,6 +677,8 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
       for (int qb = 0; qb < NQB; ++qb) {
         const int q = qb * QB + lane;
         const bool qlane = lane < QB && q < NQ;
+        const float mq0 = abs(signed_shift(q, N)) <= max_shift ? 0.f : -INFINITY;
+        const float mq1 = abs(signed_shift(q + NQ, N)) <= max_shift ? 0.f : -INFINITY;
         // phase 3: wave b, lane q: radix R1 over v = R2 a + b of the packed rows (q, q + N/2)
         cf sv[R1];
 #pragma unroll
@@ -692,7 +699,7 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
             sv[a] = cf{0.f, 0.f};
           }
         }
-        if constexpr (L::ECACHE) dft_zero<R1, 1, L::GAP>(sv);  // the same band gap along v
+        if constexpr (L::ZGAP) dft_zero<R1, 1, L::GAP>(sv);  // the same band gap along v
         else DFT<R1, 1>::run(sv);
 #pragma unroll
         for (int c = 1; c < R1; ++c) sv[c] = cmul(sv[c], root_of<N>((wave * c) % N));
@@ -715,10 +722,9 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
 #pragma unroll
               for (int d = 0; d < R2; ++d) {
                 if constexpr (WINDOW) {
+                  // uniform column test; row masks additive 0 / -inf (exact)
                   const int x = c + R1 * d;
-                  const bool okx = abs(signed_shift(x, N)) <= max_shift;
-                  if (okx && abs(signed_shift(q, N)) <= max_shift) m = fmaxf(m, z[d].x);
-                  if (okx && abs(signed_shift(q + NQ, N)) <= max_shift) m = fmaxf(m, z[d].y);
+                  if (abs(signed_shift(x, N)) <= max_shift) m = fmaxf(m, fmaxf(z[d].x + mq0, z[d].y + mq1));
                 } else {
                   m = fmaxf(m, fmaxf(z[d].x, z[d].y));
                 }

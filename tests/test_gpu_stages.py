@@ -105,6 +105,27 @@ def test_xcf_window(n):
         assert (s[k][1], s[k][0]) == sr and abs(h[k] - hr) < 5e-6
 
 
+@pytest.mark.parametrize("n,s", [(64, 0), (64, 9), (96, 5), (128, 0), (128, 15), (128, 40), (160, 7)])
+def test_windowed_scores_match_oracle(n, s):
+    # the FFT search restricted to |s_x|, |s_y| <= s (s = 0: the origin only;
+    # s = 40 at 128: both rows of some packed row pairs inside the window)
+    banner("windowed scores n=%d s=%d" % (n, s))
+    t = tm()
+    p, l = 3, 37
+    _, _, pats = _pats(n, p, seed=40 + n + s, offsets=4.0)
+    master = band_master()
+    lq = random_quats(np.random.default_rng(n + s), l)
+    tmpl = t.project_templates(dev(master), dev(lq), n, (0.5, 0.5, 0.6))
+    sp = t.pattern_spectra(dev(pats))
+    sl = t.pattern_spectra(tmpl)
+    sc = host(t.xcf_scores(sp, sl, n, t.params_default(max_shift=s)))
+    bp, bl = t.spectra_to_complex(sp, n), t.spectra_to_complex(sl, n)
+    fl = [t.band_to_full(bl[j], n) for j in range(l)]
+    for i in range(p):
+        ref = oxcf.library_scores(t.band_to_full(bp[i], n), fl, max_shift=s)
+        assert np.max(np.abs(sc[i] - ref)) < 5e-6
+
+
 @pytest.mark.parametrize("n,p,l", [(64, 5, 45), (96, 3, 33), (128, 2, 70), (160, 2, 31)])
 def test_scores_match_oracle(n, p, l):
     # L is not a multiple of the 32-template chunk: ragged tail
