@@ -60,6 +60,9 @@ constexpr int kGemmPatternTile = EBSD_GEMM_PATTERN_TILE;
 #ifndef EBSD_GEMM_PAIRSYNC
 #define EBSD_GEMM_PAIRSYNC 1
 #endif
+#ifndef EBSD_GEMM_SUPER
+#define EBSD_GEMM_SUPER 0  // template blocks per super-tile; 0: 4, or 2 at 256 (L2 per XCD)
+#endif
 
 template <int N, int ST>
 struct GemmLay {
@@ -581,9 +584,9 @@ __device__ __forceinline__ void stage1_tiles2(const u4v& zrh, const u4v& zrl, co
 // closes each pair of steps; with EBSD_GEMM_PAIRSYNC=0 the two-slot form
 // with a barrier per step) and every template value a wave loads serves PB patterns, so each pair
 // costs SPEC / PB template bytes and SPEC / 8 pattern bytes of cache traffic
-// instead of a full spectrum of each.  Blocks are numbered template-block
-// major, so the blocks running at one time on an XCD share their templates
-// in its L2 while the patterns stream.
+// instead of a full spectrum of each.  Blocks are numbered in super-tiles of
+// a few template blocks, so the blocks running at one time on an XCD share
+// their templates in its L2 and each streamed pattern block serves several.
 template <int N, int ST, int PREC, int PB>
 __global__ __launch_bounds__(512) void k_xcf_gemm_pt(const cf* __restrict__ spec_p, int64_t np,
                                                      const cf* __restrict__ spec_l, int64_t nl, int64_t npb,
@@ -602,7 +605,22 @@ __global__ __launch_bounds__(512) void k_xcf_gemm_pt(const cf* __restrict__ spec
   const int64_t per = (nblk + 7) / 8;
   const int64_t g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (g >= nblk) return;
-  const int64_t tb = g / npb, pbk = g - tb * npb;
+  // super-tiles of TS template blocks: consecutive blocks (running at one time
+  // on an XCD) cycle through the TS template blocks of one pattern block, so
+  // each pattern block is read once per super-tile from HBM, not per
+  // template block (the last super-tile may hold fewer template blocks).
+  // TS x 8 template spectra stay in the XCD's L2: 4 x 8 x 38 KB at 128,
+  // 2 x 8 x 150 KB at 256 (measured 1.05x at 128 and 256 over TS = 1)
+  int64_t tb, pbk;
+  {
+    constexpr int TS = EBSD_GEMM_SUPER > 0 ? EBSD_GEMM_SUPER : (N >= 256 ? 2 : 4);
+    const int64_t ntb = (nl + 7) / 8;
+    const int64_t st = g / (TS * npb), tb0 = st * TS;
+    const int64_t ts = ntb - tb0 < TS ? ntb - tb0 : TS;
+    const int64_t r = g - tb0 * npb;
+    pbk = r / ts;
+    tb = tb0 + (r - pbk * ts);
+  }
   const int64_t p0 = pbk * PB;
   const int64_t l = tb * 8 + wave;
   const bool lok = l < nl;
