@@ -29,6 +29,7 @@ def pair_flops(n):
 
 
 PEAK_FP32_VALU = 157.3e12   # MI355X fp32 vector, FLOP/s (published)
+PEAK_MFMA_FP32 = 157.3e12   # dense FP32 matrix (v_mfma_f32_*), published
 PEAK_MFMA_16BIT = 2.5e15    # MI355X dense FP16 / BF16 matrix, FLOP/s (published)
 
 
@@ -593,9 +594,9 @@ def learned_proposal(tm, library, n_train, epochs, n_test, k=32, bsz=256, n=128)
                        "correlation with exhaustive fallback below tau" % (library, n_train, epochs, n_test, k),
            "train_s": t_train, "train_steps": steps, "batch": bsz, "final_loss": final_loss,
            "train_samples_per_s": steps * bsz / t_train,
-           "train_step_roofline": {"bound": "alu", "achieved": train_flops / t_step / 1e12,
-                                   "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
-                                   "frac": train_flops / t_step / PEAK_FP32_VALU,
+           "train_step_roofline": {"bound": "mfma", "achieved": train_flops / t_step / 1e12,
+                                   "peak": PEAK_MFMA_FP32 / 1e12, "unit": "TFLOP/s",
+                                   "frac": train_flops / t_step / PEAK_MFMA_FP32,
                                    "flops_per_sample_forward": cnn_flops_per_sample(library)},
            "forward_patterns_per_s": bsz * 8 / t_fwd,
            "tau": tau,

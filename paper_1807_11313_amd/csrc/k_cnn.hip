@@ -15,18 +15,26 @@ namespace cnn {
 // ---------------------------------------------------------------------------
 // Tiled FP32 GEMM on the matrix cores: C(m, n) = sum_k A(m, k) B(k, n) over k
 // in the block's slice [z * kslice, (z + 1) * kslice) of [0, K).  64 x 64
-// tiles, 16-deep K steps through LDS; wave w owns the 32 x 32 quarter
+// tiles, KS-deep K steps through two LDS stages; wave w owns the 32 x 32 quarter
 // (w & 1, w >> 1) as 2 x 2 tiles of v_mfma_f32_16x16x4f32 (A operand: lane l
 // holds row l % 16, k = l / 16; B: k = l / 16, column l % 16; accumulator:
 // rows 4 (l / 16) + r, column l % 16).  A::KFAST / B::KFAST choose which
 // index runs along consecutive threads when the tile is loaded (the one that
 // is contiguous in memory).
 typedef float f4c __attribute__((ext_vector_type(4)));
+#ifndef EBSD_TGEMM_KS
+#define EBSD_TGEMM_KS 16
+#endif
+constexpr int KS = EBSD_TGEMM_KS;  // K depth of one step
+constexpr int KR = KS / 4;         // operand values per thread and step
 
 template <class A, class Bm, class Out>
 __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N, int K, int kslice) {
-  __shared__ float as[16][64 + 1];
-  __shared__ float bs[16][64 + 1];
+  // two LDS stages: the operand values of the next K step are loaded into
+  // registers while the matrix cores work on the current one, then stored
+  // into the other stage (one barrier per step)
+  __shared__ float as[2][KS][64 + 1];
+  __shared__ float bs[2][KS][64 + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
@@ -38,42 +46,52 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4c{0.f, 0.f, 0.f, 0.f};
   const int r16 = lane & 15, q4 = lane >> 4;
-  for (int k0 = kb; k0 < ke; k0 += 16) {
+  // this thread's KR (m, k) and (k, n) positions in a KS-deep step
+  int am[KR], ak[KR], bn[KR], bk[KR];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int idx = tid + 256 * r;
-      int mm, kk;
-      if constexpr (A::KFAST) {
-        kk = idx & 15;
-        mm = idx >> 4;
-      } else {
-        mm = idx & 63;
-        kk = idx >> 6;
-      }
-      const int m = m0 + mm, k = k0 + kk;
-      as[kk][mm] = (m < M && k < ke) ? a(m, k) : 0.0f;
-      int nn;
-      if constexpr (Bm::KFAST) {
-        kk = idx & 15;
-        nn = idx >> 4;
-      } else {
-        nn = idx & 63;
-        kk = idx >> 6;
-      }
-      const int n = n0 + nn, k2 = k0 + kk;
-      bs[kk][nn] = (n < N && k2 < ke) ? b(k2, n) : 0.0f;
+  for (int r = 0; r < KR; ++r) {
+    const int idx = tid + 256 * r;
+    am[r] = A::KFAST ? idx / KS : idx & 63;
+    ak[r] = A::KFAST ? idx % KS : idx >> 6;
+    bn[r] = Bm::KFAST ? idx / KS : idx & 63;
+    bk[r] = Bm::KFAST ? idx % KS : idx >> 6;
+  }
+  float ra[KR], rb[KR];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+      const int m = m0 + am[r], k = k0 + ak[r];
+      ra[r] = (m < M && k < ke) ? a(m, k) : 0.0f;
+      const int n = n0 + bn[r], k2 = k0 + bk[r];
+      rb[r] = (n < N && k2 < ke) ? b(k2, n) : 0.0f;
     }
-    __syncthreads();
+  };
+  auto stash = [&](int st) {
 #pragma unroll
-    for (int k4 = 0; k4 < 16; k4 += 4) {
-      const float a0 = as[k4 + q4][wm + r16], a1 = as[k4 + q4][wm + 16 + r16];
-      const float b0 = bs[k4 + q4][wn + r16], b1 = bs[k4 + q4][wn + 16 + r16];
+    for (int r = 0; r < KR; ++r) {
+      as[st][ak[r]][am[r]] = ra[r];
+      bs[st][bk[r]][bn[r]] = rb[r];
+    }
+  };
+  fetch(kb);
+  stash(0);
+  __syncthreads();
+  int st = 0;
+  for (int k0 = kb; k0 < ke; k0 += KS) {
+    const bool more = k0 + KS < ke;
+    if (more) fetch(k0 + KS);
+#pragma unroll
+    for (int k4 = 0; k4 < KS; k4 += 4) {
+      const float a0 = as[st][k4 + q4][wm + r16], a1 = as[st][k4 + q4][wm + 16 + r16];
+      const float b0 = bs[st][k4 + q4][wn + r16], b1 = bs[st][k4 + q4][wn + 16 + r16];
       acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
     }
+    if (more) stash(st ^ 1);
     __syncthreads();
+    st ^= 1;
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -217,13 +235,24 @@ struct RowOut {  // C[m * ld + n] = acc (+ bias[n])
   }
 };
 
+// K slice of a split into `splits` parts (a whole number of K steps) and the
+// number of slices z that gemm launches: callers summing the partials use
+// the same z
+static int k_slice(int K, int splits) {
+  splits = splits < 1 ? 1 : splits;
+  const int kslice = (K + splits - 1) / splits;
+  return (kslice + KS - 1) / KS * KS;
+}
+static int k_slices(int K, int splits) {
+  const int kslice = k_slice(K, splits);
+  return (K + kslice - 1) / kslice;
+}
+
 template <class A, class Bm, class Out>
 static hipError_t gemm(A a, Bm b, Out out, int M, int N, int K, int splits, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  splits = splits < 1 ? 1 : splits;
-  int kslice = (K + splits - 1) / splits;
-  kslice = (kslice + 15) & ~15;
-  const int z = (K + kslice - 1) / kslice;
+  const int kslice = k_slice(K, splits);
+  const int z = k_slices(K, splits);
   dim3 grid((N + 63) / 64, (M + 63) / 64, z < 1 ? 1 : z);
   hipLaunchKernelGGL((k_tgemm<A, Bm, Out>), grid, dim3(256), 0, st, a, b, out, M, N, K, kslice);
   return hipGetLastError();
@@ -690,8 +719,7 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
     const int smax = (L + 255) / 256;
     s = s > smax ? smax : (s < 1 ? 1 : s);
     while ((size_t)s * bsz * kFeatures > part_floats && s > 1) s = (s + 1) / 2;
-    const int kslice = ((L + s - 1) / s + 15) & ~15;
-    const int z = (L + kslice - 1) / kslice;
+    const int z = k_slices(L, s);
     e = gemm(RowK{act.dz, L}, BRowN{params + lay.fc_w, kFeatures}, SplitOut{part, (int)bsz, kFeatures}, (int)bsz,
              kFeatures, L, s, st);
     if (e != hipSuccess) return e;
@@ -709,8 +737,7 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
     const int64_t tiles = (int64_t)((co + 63) / 64) * ((N + 63) / 64);
     int s = splits_for(K, tiles);
     while ((size_t)s * co * N > part_floats && s > 1) s = (s + 1) / 2;
-    int kslice = ((K + s - 1) / s + 15) & ~15;
-    const int z = (K + kslice - 1) / kslice;
+    const int z = k_slices(K, s);
     e = gemm(ConvBwdWA{act.g[i], co, lw}, ConvBwdWB{in, ci, lw}, SplitOut{part, co, N}, co, N, K, s, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_split_sum, dim3(nb((int64_t)co * N)), dim3(256), 0, st, part, z, (int64_t)co * N,
