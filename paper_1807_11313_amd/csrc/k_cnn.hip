@@ -258,13 +258,37 @@ static hipError_t gemm(A a, Bm b, Out out, int M, int N, int K, int splits, hipS
   return hipGetLastError();
 }
 
-// part [z][M][N] -> out [M][N] (+= when accumulate)
-__global__ void k_split_sum(const float* __restrict__ part, int z, int64_t mn, float* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= mn) return;
+// part [z][M][N] -> out [M][N]: a block sums 64 consecutive outputs with G
+// groups of 64 threads, group g taking the partials k = g, g + G, ...; the
+// groups' sums are then added in group order (a fixed order, as the split
+// itself is fixed).  G = 16 when the split is long (few outputs, many
+// partials: the first layer's weight gradient), else 1.
+template <int G>
+__global__ __launch_bounds__(64 * G) void k_split_sum(const float* __restrict__ part, int z, int64_t mn,
+                                                      float* __restrict__ out) {
+  __shared__ float acc[G][64];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   float s = 0.0f;
-  for (int k = 0; k < z; ++k) s += part[(size_t)k * mn + i];
-  out[i] = s;
+  if (i < mn)
+    for (int k = g; k < z; k += G) s += part[(size_t)k * mn + i];
+  if constexpr (G == 1) {
+    if (i < mn) out[i] = s;
+  } else {
+    acc[g][lane] = s;
+    __syncthreads();
+    if (g == 0 && i < mn) {
+      float t = acc[0][lane];
+#pragma unroll
+      for (int h = 1; h < G; ++h) t += acc[h][lane];
+      out[i] = t;
+    }
+  }
+}
+static void split_sum(const float* part, int z, int64_t mn, float* out, hipStream_t st) {
+  const unsigned blocks = (unsigned)((mn + 63) / 64);
+  if (z >= 64) hipLaunchKernelGGL(k_split_sum<16>, dim3(blocks), dim3(1024), 0, st, part, z, mn, out);
+  else hipLaunchKernelGGL(k_split_sum<1>, dim3(blocks), dim3(64), 0, st, part, z, mn, out);
 }
 
 // partial sums over (b, pixel) of g[b][c][pixel]: block (c, z) sums images
@@ -723,8 +747,7 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
     e = gemm(RowK{act.dz, L}, BRowN{params + lay.fc_w, kFeatures}, SplitOut{part, (int)bsz, kFeatures}, (int)bsz,
              kFeatures, L, s, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_split_sum, dim3(nb(bsz * kFeatures)), dim3(256), 0, st, part, z, (int64_t)bsz * kFeatures,
-                       act.dp[3]);
+    split_sum(part, z, (int64_t)bsz * kFeatures, act.dp[3], st);
   }
   int w = kInSize >> 3;  // conv4 input side (8)
   for (int i = 3; i >= 0; --i) {
@@ -740,8 +763,7 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
     const int z = k_slices(K, s);
     e = gemm(ConvBwdWA{act.g[i], co, lw}, ConvBwdWB{in, ci, lw}, SplitOut{part, co, N}, co, N, K, s, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_split_sum, dim3(nb((int64_t)co * N)), dim3(256), 0, st, part, z, (int64_t)co * N,
-                       grad + lay.conv_w[i]);
+    split_sum(part, z, (int64_t)co * N, grad + lay.conv_w[i], st);
     {
       const int zs = (int)(bsz < 64 ? bsz : 64);
       double* cpart = reinterpret_cast<double*>(part);  // the weight-gradient partials are summed already
