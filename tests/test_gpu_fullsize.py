@@ -1,8 +1,11 @@
 """The map workloads at their full size (10,000 patterns of 128^2 against
 4,000 library templates searched over all shifts, and the same map at 256^2
-searched by the FP16 hi + lo DFT-GEMM over |s| <= 15 px: the launch
+searched by the FP16 hi + lo DFT-GEMM over |s| <= 15 px; the ragged batch of
+20,000 patterns against 8,000 templates with its stencil; the learned
+proposal trained on 200,000 patterns and run on 50,000: the launch
 configurations the bench times), checked on sampled patterns that the FP64
-oracle indexes and refines one by one from the same inputs.
+oracle indexes and refines one by one from the same inputs (the proposal
+against the exhaustive search).
 
 * Library index: the oracle's, bit-exact outside the near-tie rule
   (tau_tie = 2e-4); inside it the GPU's pick scores within tau_tie of the
@@ -101,3 +104,106 @@ def test_map256_dftgemm_sampled_against_oracle():
     rref = pipeline.refine_orientations(sample, cfg["master"], cfg["pcs"][idx], cfg["lib_q"][best], oprm)
     d = np.rad2deg([rotations.disorientation_q(a, b) for a, b in zip(q_all[idx], rref["q"])])
     assert np.max(d) < 0.05, d
+
+
+def test_ragged_batch_sampled_against_oracle():
+    # the ragged batch at full size (20,000 patterns of 64 / 96 / 128 / 160,
+    # 8,000 templates, 27-point stencil, one graph launch); sampled patterns
+    # of the 64 and 96 classes (whose oracle libraries are the cheapest)
+    from oracle import stencil
+    banner("full-size ragged batch 20,000 x 8,000 + stencil, sampled against the oracle")
+    t = tm()
+    cfg = configs.ragged(device="cuda:0")
+    data, offs, ns = configs.pack_ragged(cfg, device="cuda:0")
+    assert len(ns) == 20000 and len(cfg["lib_q"]) == 8000
+    plan = t.RaggedPlan(ns, offs, len(cfg["lib_q"]), stencil=True)
+    res = plan.run(data, dev(cfg["master"]), cfg["pc"], dev(cfg["lib_q"]), pc_per=dev(cfg["pcs"]))
+    best, sidx = host(res["best_idx"]), host(res["stencil_idx"])
+    q, h, s = host(res["q"]), host(res["peak_h"]), host(res["shift"])
+    plan.close()
+    prm = oracle.Params()
+    rng = np.random.default_rng(13)
+    for n in (64, 96):
+        idx = np.sort(rng.choice(np.nonzero(ns == n)[0], 2, replace=False))
+        pats = np.stack([configs.ragged_pattern(cfg, i) for i in idx]).astype(np.float64)
+        banner("oracle: 8,000 library spectra at %d^2" % n)
+        lib_spec = pipeline.library_spectra(cfg["master"], cfg["lib_q"], n, cfg["pc"], prm)
+        ref = pipeline.index_patterns(pats, cfg["master"], cfg["pc"], cfg["lib_q"], prm, lib_spec=lib_spec,
+                                      return_scores=True)
+        for a, i in enumerate(idx):
+            if ref["gap"][a] > TAU_TIE:
+                assert best[i] == ref["best_idx"][a], (n, i, best[i], ref["best_idx"][a])
+            else:
+                assert ref["scores"][a][best[i]] >= ref["h_int"][a] - TAU_TIE
+        st = stencil.stencil_refine(list(pats), cfg["master"], cfg["pcs"][idx], cfg["lib_q"][best[idx]], prm)
+        for a, i in enumerate(idx):
+            if st["gap"][a] <= TAU_TIE:
+                assert st["h_int"][a][sidx[i]] >= st["h_int"][a].max() - TAU_TIE
+                continue
+            assert sidx[i] == st["idx"][a], (n, i, sidx[i], st["idx"][a])
+            d = np.rad2deg(rotations.misorientation_angle(rotations.quat_to_matrix(q[i]),
+                                                          rotations.quat_to_matrix(st["q"][a])))
+            assert d < 1e-6, d
+            assert abs(h[i] - st["peak_h"][a]) < 1e-4
+            assert np.max(np.abs(s[i] - st["shift"][a])) <= 0.02 + 1e-6
+
+
+def test_learned_proposal_full_size():
+    # the proposal workload at full size: the network trained on the GPU on
+    # 200,000 projected patterns (2 epochs) for 8,000 classes; 50,000 test
+    # patterns at 128^2 searched exhaustively and pruned (top 32 + fallback
+    # below tau = 1st percentile of the exhaustive peak height on 10,000
+    # validation patterns).  The exhaustive search, pinned to the oracle by
+    # the tests above, is the judge.
+    from fixtures import band_master, random_fz_quats, random_quats, simulate_patterns
+    banner("full-size learned proposal: training 200,000 x 2 epochs, 50,000 test patterns")
+    t = tm()
+    n, L, k, bsz, n_train = 128, 8000, 32, 256, 200000
+    lq = dev(random_fz_quats(np.random.default_rng(11), L))
+    master = dev(band_master())
+    pc = (0.5, 0.5, 0.6)
+
+    def patterns(p, seed):
+        rng = np.random.default_rng(seed)
+        q = random_quats(rng, p)
+        off = rng.uniform(-5, 5, size=(p, 2))
+        pcs = np.stack([0.5 + off[:, 0] / n, 0.5 + off[:, 1] / n, np.full(p, 0.6)], 1)
+        return pcs, simulate_patterns(q, n, pcs, ("poisson_gauss", 1000.0, 5.0), seed=seed, device="cuda:0",
+                                      dtype=torch.float32).contiguous()
+
+    net = t.Cnn(L, seed=5)
+    x = torch.empty((bsz, 64, 64), device="cuda:0")
+    y = torch.empty(bsz, dtype=torch.int32, device="cuda:0")
+    loss = torch.empty(1, device="cuda:0")
+    for s in range(2 * n_train // bsz):
+        t.cnn_make_batch(master, pc, lq, n, bsz, (s * bsz) % n_train, 1000 + (s * bsz) // n_train, x=x, labels=y)
+        net.train_step(x, y, 1e-3, loss)
+    print("[gpu]   final training loss %.3f" % float(loss.item()), flush=True)
+    _, val = patterns(10000, 31)
+    tau = float(np.percentile(host(t.index_patterns(val, master, pc, lq)["peak_h"]), 1.0))
+    del val
+    pcs, test = patterns(50000, 32)
+    ex = t.index_patterns(test, master, pc, lq, scores=True)
+    top2 = torch.topk(ex.pop("scores"), 2, dim=1).values
+    gap = host(top2[:, 0] - top2[:, 1])
+    del top2
+    pr = t.index_proposed(test, master, pc, lq, net, top_k=k, fallback_tau=tau)
+    best_ex, best_pr = host(ex["best_idx"]), host(pr["best_idx"])
+    fb = host(pr["fallback"]).astype(bool)
+    clear = gap > TAU_TIE
+    agree = best_ex == best_pr
+    print("[gpu]   agreement %.4f, fallback %.4f, tau %.3f" % (agree.mean(), fb.mean(), tau), flush=True)
+    assert np.all(agree[clear & fb])
+    assert agree[clear].mean() >= 0.95
+    assert np.array_equal(host(pr["peak_h"])[agree], host(ex["peak_h"])[agree])
+    assert np.array_equal(host(pr["shift"])[agree], host(ex["shift"])[agree])
+    assert len(best_pr) * k + fb.sum() * L < 0.3 * len(best_pr) * L
+    # both picks refined the same way
+    pc_per = dev(pcs)
+    q_ex = host(t.refine_orientations(test, master, pc, ex["best_q"], pc_per=pc_per)["q"])
+    q_pr = host(t.refine_orientations(test, master, pc, pr["best_q"], pc_per=pc_per)["q"])
+    sub = np.random.default_rng(5).choice(len(q_ex), 2000, replace=False)
+    d = np.rad2deg([rotations.disorientation_q(a, b) for a, b in zip(q_ex[sub], q_pr[sub])])
+    print("[gpu]   refined pruned vs exhaustive: %.4f within 0.1 deg" % np.mean(d < 0.1), flush=True)
+    assert np.mean(d < 0.1) >= 0.99
+    net.close()
