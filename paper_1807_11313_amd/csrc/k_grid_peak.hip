@@ -66,8 +66,11 @@ __global__ void k_grid_tables(int n, int bnd, int kappa, int m, float2* tab) {
   tab[i] = make_float2((float)c, (float)s);
 }
 
-template <int VJ, int MB>
-__global__ __launch_bounds__(256) void k_grid_peak(int n, int bnd, const cf* __restrict__ spec_p,
+// TB x TB threads: thread (ty, tx) holds rows b = ty + TB i and columns
+// v (or a) = tx + TB j.  TB = 32 (16 waves) where the LDS of one block leaves
+// no room for a second on the CU, so the CU still has 4 waves per SIMD.
+template <int VJ, int MB, int TB>
+__global__ __launch_bounds__(TB * TB) void k_grid_peak(int n, int bnd, const cf* __restrict__ spec_p,
                                                    const cf* __restrict__ spec_l, const int32_t* __restrict__ pi,
                                                    const int32_t* __restrict__ li, const int32_t* __restrict__ centre,
                                                    int kappa, int m, int int_keys, const cf* __restrict__ tab,
@@ -82,8 +85,9 @@ __global__ __launch_bounds__(256) void k_grid_peak(int n, int bnd, const cf* __r
   const cf* F1 = tab;
   const cf* F2 = tab + nk * msz;
   const cf* rn = tab + (nk + nv) * msz;
+  constexpr int NT = TB * TB;
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  const int tx = tid % TB, ty = tid / TB;
   const int64_t k = blockIdx.x;
   const cf* E = spec_p + (pi ? (int64_t)pi[k] : k) * spec;
   const cf* T = spec_l + (li ? (int64_t)li[k] : k) * spec;
@@ -98,7 +102,7 @@ __global__ __launch_bounds__(256) void k_grid_peak(int n, int bnd, const cf* __r
   for (int u0 = 0; u0 < nk; u0 += UC) {
     const int uc = min(UC, nk - u0);
     __syncthreads();
-    for (int t = tid; t < uc * nv; t += 256) {
+    for (int t = tid; t < uc * nv; t += NT) {
       const int kk = u0 + t / nv;
       const int u = kk <= bnd ? kk : kk - nk;
       int r = (u * y0) % n;
@@ -106,18 +110,18 @@ __global__ __launch_bounds__(256) void k_grid_peak(int n, int bnd, const cf* __r
       const int e = u0 * nv + t;
       zc[t] = cmul(cmulc(E[e], T[e]), rn[r]);
     }
-    for (int t = tid; t < uc * msz; t += 256) fc[t] = F1[u0 * msz + t];
+    for (int t = tid; t < uc * msz; t += NT) fc[t] = F1[u0 * msz + t];
     __syncthreads();
     for (int uu = 0; uu < uc; ++uu) {
       cf zv[VJ];
 #pragma unroll
       for (int j = 0; j < VJ; ++j) {
-        const int v = tx + 16 * j;
+        const int v = tx + TB * j;
         zv[j] = v < nv ? zc[uu * nv + v] : cf{0.f, 0.f};
       }
 #pragma unroll
       for (int i = 0; i < MB; ++i) {
-        const int b = ty + 16 * i;
+        const int b = ty + TB * i;
         const cf f = b < msz ? fc[uu * msz + b] : cf{0.f, 0.f};
 #pragma unroll
         for (int j = 0; j < VJ; ++j) {
@@ -130,14 +134,14 @@ __global__ __launch_bounds__(256) void k_grid_peak(int n, int bnd, const cf* __r
   // G'(b, v) = G(b, v) exp(2 pi i v x0 / n) w_v
 #pragma unroll
   for (int j = 0; j < VJ; ++j) {
-    const int v = tx + 16 * j;
+    const int v = tx + TB * j;
     if (v < nv) {
       int r = (v * x0) % n;
       if (r < 0) r += n;
       const cf w = cscale(rn[r], v == 0 ? 1.0f : 2.0f);
 #pragma unroll
       for (int i = 0; i < MB; ++i) {
-        const int b = ty + 16 * i;
+        const int b = ty + TB * i;
         if (b < msz) g[b * nv + v] = cmul(acc[i][j], w);
       }
     }
@@ -151,15 +155,15 @@ __global__ __launch_bounds__(256) void k_grid_peak(int n, int bnd, const cf* __r
   for (int v0 = 0; v0 < nv; v0 += UC) {
     const int vc = min(UC, nv - v0);
     __syncthreads();
-    for (int t = tid; t < vc * msz; t += 256) fc[t] = F2[v0 * msz + t];
+    for (int t = tid; t < vc * msz; t += NT) fc[t] = F2[v0 * msz + t];
     __syncthreads();
     for (int vv = 0; vv < vc; ++vv) {
       cf gv[MB], fv[MB];
 #pragma unroll
       for (int i = 0; i < MB; ++i) {
-        const int b = ty + 16 * i;
+        const int b = ty + TB * i;
         gv[i] = b < msz ? g[b * nv + v0 + vv] : cf{0.f, 0.f};
-        const int a = tx + 16 * i;
+        const int a = tx + TB * i;
         fv[i] = a < msz ? fc[vv * msz + a] : cf{0.f, 0.f};
       }
 #pragma unroll
@@ -173,10 +177,10 @@ __global__ __launch_bounds__(256) void k_grid_peak(int n, int bnd, const cf* __r
   int bi = 0x7fffffff;
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
-    const int b = ty + 16 * i;
+    const int b = ty + TB * i;
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
-      const int a = tx + 16 * j;
+      const int a = tx + TB * j;
       if (b < msz && a < msz) {
         int key = b * msz + a;
         if (int_keys) {
@@ -190,15 +194,15 @@ __global__ __launch_bounds__(256) void k_grid_peak(int n, int bnd, const cf* __r
     }
   }
   wave_argmax(best, bi);
-  __shared__ float rv[4];
-  __shared__ int ri[4];
+  __shared__ float rv[NT / 64];
+  __shared__ int ri[NT / 64];
   if ((tid & 63) == 0) {
     rv[tid >> 6] = best;
     ri[tid >> 6] = bi;
   }
   __syncthreads();
   if (tid == 0) {
-    for (int w = 1; w < 4; ++w) argmax_merge(best, bi, rv[w], ri[w]);
+    for (int w = 1; w < NT / 64; ++w) argmax_merge(best, bi, rv[w], ri[w]);
     int da, db;  // grid offsets of the winner
     if (int_keys) {
       const int limit = n * n;
@@ -234,27 +238,32 @@ hipError_t launch_grid_tables(int n, int kappa, int m, float2* tab, hipStream_t 
   return hipGetLastError();
 }
 
-template <int VJ>
+template <int VJ, int TB>
 static hipError_t grid_vj(int n, int bnd, const float2* spec_p, const float2* spec_l, const int32_t* pi,
                           const int32_t* li, int64_t k, const int32_t* centre, int kappa, int m, int int_keys,
                           const float2* tab, float* h, float* s, int32_t* si, hipStream_t stream) {
   const int msz = 2 * m + 1;
   const size_t shm = grid_lds_bytes(n, m);
-  const int mb = (msz + 15) / 16;
-#define EBSD_GRID(MBV)                                                                                          \
-  do {                                                                                                          \
-    hipFuncSetAttribute((const void*)k_grid_peak<VJ, MBV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); \
-    hipLaunchKernelGGL((k_grid_peak<VJ, MBV>), dim3((unsigned)k), dim3(256), shm, stream, n, bnd,                 \
-                       (const cf*)spec_p, (const cf*)spec_l, pi, li, centre, kappa, m, int_keys,                \
-                       (const cf*)tab, h, s, si);                                                               \
+  const int mb = (msz + TB - 1) / TB;
+#define EBSD_GRID(MBV)                                                                                              \
+  do {                                                                                                              \
+    (void)hipFuncSetAttribute((const void*)k_grid_peak<VJ, MBV, TB>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
+                              (int)shm);                                                                          \
+    hipLaunchKernelGGL((k_grid_peak<VJ, MBV, TB>), dim3((unsigned)k), dim3(TB * TB), shm, stream, n, bnd,             \
+                       (const cf*)spec_p, (const cf*)spec_l, pi, li, centre, kappa, m, int_keys,                    \
+                       (const cf*)tab, h, s, si);                                                                   \
   } while (0)
   if (mb <= 1) EBSD_GRID(1);
   else if (mb <= 2) EBSD_GRID(2);
   else if (mb <= 4) EBSD_GRID(4);
   else if (mb <= 7) EBSD_GRID(7);
-  else if (mb <= 10) EBSD_GRID(10);
-  else if (mb <= 13) EBSD_GRID(13);
-  else return hipErrorInvalidValue;
+  else if constexpr (TB == 16) {  // 32 x 7 rows already cover what 16 x 13 do
+    if (mb <= 10) EBSD_GRID(10);
+    else if (mb <= 13) EBSD_GRID(13);
+    else return hipErrorInvalidValue;
+  } else {
+    return hipErrorInvalidValue;
+  }
 #undef EBSD_GRID
   return hipGetLastError();
 }
@@ -265,7 +274,7 @@ static hipError_t launch_grid(int n, const float2* spec_p, const float2* spec_l,
   if (k <= 0) return hipSuccess;
   const int bnd = band_of(n);
   if (bnd < 0 || grid_lds_bytes(n, m) > 160 * 1024) return hipErrorInvalidValue;
-  const int64_t kmax = (int64_t(1) << 31) / 256;  // blocks x threads of one dispatch below 2^31
+  const int64_t kmax = (int64_t(1) << 31) / 1024;  // blocks x threads of one dispatch below 2^31
   if (k > kmax) {
     const int64_t sc = (int64_t)(bnd + 1) * (2 * bnd + 1);
     for (int64_t s0 = 0; s0 < k; s0 += kmax) {
@@ -277,10 +286,14 @@ static hipError_t launch_grid(int n, const float2* spec_p, const float2* spec_l,
     }
     return hipSuccess;
   }
+  // one block per CU by LDS: 32 x 32 threads, else 16 x 16
+  const bool wide = grid_lds_bytes(n, m) > 80 * 1024;
   if (bnd + 1 <= 64)
-    return grid_vj<4>(n, bnd, spec_p, spec_l, pi, li, k, centre, kappa, m, int_keys, tab, h, s, si, stream);
+    return wide ? grid_vj<2, 32>(n, bnd, spec_p, spec_l, pi, li, k, centre, kappa, m, int_keys, tab, h, s, si, stream)
+                : grid_vj<4, 16>(n, bnd, spec_p, spec_l, pi, li, k, centre, kappa, m, int_keys, tab, h, s, si, stream);
   if (bnd + 1 <= 112)
-    return grid_vj<7>(n, bnd, spec_p, spec_l, pi, li, k, centre, kappa, m, int_keys, tab, h, s, si, stream);
+    return wide ? grid_vj<4, 32>(n, bnd, spec_p, spec_l, pi, li, k, centre, kappa, m, int_keys, tab, h, s, si, stream)
+                : grid_vj<7, 16>(n, bnd, spec_p, spec_l, pi, li, k, centre, kappa, m, int_keys, tab, h, s, si, stream);
   return hipErrorInvalidValue;
 }
 
