@@ -132,11 +132,13 @@ __device__ __forceinline__ void split_pair(float a, float b, unsigned& hi, unsig
     hi = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(a, b));
     lo = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(sub_half_lo(hi, a), sub_half_hi(hi, b)));
   } else {
-    unsigned short ha, la, hb, lb;
-    split2<PREC>(a, ha, la);
-    split2<PREC>(b, hb, lb);
-    hi = (unsigned)ha | ((unsigned)hb << 16);
-    lo = (unsigned)la | ((unsigned)lb << 16);
+    // BF16, round to nearest even: both values by one packed conversion; the
+    // hi halves back in FP32 are the top 16 bits, so x - hi is exact
+    typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    hi = __builtin_bit_cast(unsigned, __builtin_convertvector(f2v{a, b}, bf2));
+    const float ha = __builtin_bit_cast(float, hi << 16), hb = __builtin_bit_cast(float, hi & 0xffff0000u);
+    lo = __builtin_bit_cast(unsigned, __builtin_convertvector(f2v{a - ha, b - hb}, bf2));
   }
 }
 
