@@ -9,6 +9,10 @@ peak is the score, the best template wins and its peak is upsampled.
 ``refine_orientations``: the refinement of section "Orientation and Pattern
 Centre Refinement" from a starting orientation, at each pattern's own
 pattern centre.
+
+``refine_from_match``: the same refinement whose first x/y step reuses the
+search's shift, corrected for the beam-induced PC move (one library for the
+whole map).
 """
 
 import numpy as np
@@ -61,6 +65,26 @@ def refine_orientations(patterns, master, pcs, q_init, prm=None):
     out = dict(q=np.zeros((p, 4)), peak_h=np.zeros(p), shift=np.zeros((p, 2)))
     for i in range(p):
         r, h, s = refine.refine_one(patterns[i], master, rs[i], pcs[i], prm)
+        out["q"][i] = rotations.matrix_to_quat(r)
+        out["peak_h"][i] = h
+        out["shift"][i] = (s[1], s[0])
+    return out
+
+
+def refine_from_match(patterns, master, pcs, pc_nominal, q_init, match_shift, prm=None):
+    """Refinement that starts from the search's own measurement: q_init and
+    match_shift [P, 2] (x, y) px are the search's best_q and shift against
+    the library projected at pc_nominal; pcs [P, 3] are the points' own
+    pattern centres.  Returns dict(q, peak_h, shift (x, y))."""
+    prm = prm or Params()
+    patterns = np.asarray(patterns, dtype=np.float64)
+    p = patterns.shape[0]
+    rs = rotations.quat_to_matrix(q_init)
+    ms = np.asarray(match_shift, dtype=np.float64)
+    out = dict(q=np.zeros((p, 4)), peak_h=np.zeros(p), shift=np.zeros((p, 2)))
+    for i in range(p):
+        r, h, s = refine.refine_one_from_match(patterns[i], master, rs[i], pcs[i], pc_nominal,
+                                               (ms[i, 1], ms[i, 0]), prm)
         out["q"][i] = rotations.matrix_to_quat(r)
         out["peak_h"][i] = h
         out["shift"][i] = (s[1], s[0])

@@ -30,7 +30,7 @@ x/y-updated orientation.
 
 import numpy as np
 
-from . import geometry, rotations, spectra, xcf
+from . import geometry, pcmodel, rotations, spectra, xcf
 
 
 def xy_update(r, shift, pcz, n):
@@ -136,14 +136,20 @@ def measure_shift(pattern, template, prm):
     return xcf.subpixel_peak(se, st, s_int, prm.upsample)
 
 
-def refine_one(pattern, master, r0, pc, prm, trace=None):
+def refine_one(pattern, master, r0, pc, prm, trace=None, first_shift=None):
     """Refine one pattern from orientation matrix r0 (fixed n_iter iterations),
-    then measure the final peak height and shift.  Returns (R, h, (s_y, s_x))."""
+    then measure the final peak height and shift.  Returns (R, h, (s_y, s_x)).
+
+    first_shift (s_y, s_x), if given, replaces the projection and correlation
+    of the first x/y step (the beam-shift-corrected shift of the search)."""
     n = pattern.shape[0]
     r = np.array(r0, dtype=np.float64)
-    for _ in range(prm.n_iter):
-        t = geometry.project(master, r, n, pc)
-        _, s = measure_shift(pattern, t, prm)
+    for it in range(prm.n_iter):
+        if it == 0 and first_shift is not None:
+            s = (float(first_shift[0]), float(first_shift[1]))
+        else:
+            t = geometry.project(master, r, n, pc)
+            _, s = measure_shift(pattern, t, prm)
         r = xy_update(r, s, pc[2], n)
         t = geometry.project(master, r, n, pc)
         g = measure_gamma(pattern, t, prm)
@@ -153,3 +159,14 @@ def refine_one(pattern, master, r0, pc, prm, trace=None):
     t = geometry.project(master, r, n, pc)
     h, s = measure_shift(pattern, t, prm)
     return r, h, s
+
+
+def refine_one_from_match(pattern, master, r0, pc, pc_nominal, match_shift, prm, trace=None):
+    """refine_one whose first x/y step uses the shift the search measured
+    against the library template (projected at pc_nominal), less the
+    translation that the move from pc_nominal to the point's pc causes.
+    match_shift is (s_y, s_x) px."""
+    n = pattern.shape[0]
+    by, bx = pcmodel.beam_shift(pc, pc_nominal, n)
+    s0 = (match_shift[0] - by, match_shift[1] - bx)
+    return refine_one(pattern, master, r0, pc, prm, trace=trace, first_shift=s0)
