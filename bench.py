@@ -102,6 +102,9 @@ def main():
                     help="precision of the timed step's search (0 FP32 FFT, 1 FP16x2, 2 BF16x2, 3 BF16)")
     ap.add_argument("--search-max-shift", type=int, default=-1, help="shift window of the timed step (-1: all)")
     ap.add_argument("--form-steps", type=int, default=3)
+    ap.add_argument("--no-drift", action="store_true",
+                    help="skip the drifting-pattern-centre map (beam-shift-corrected refinement)")
+    ap.add_argument("--drift-steps", type=int, default=3)
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the split-precision search on the same map at 256^2")
     ap.add_argument("--precision-patterns", type=int, default=10000)
@@ -250,6 +253,9 @@ def main():
     # the oracle's sample, on the host, before the 128^2 map is released
     cpu_cfg = {"patterns": cfg["patterns"][:3].cpu(), "lib_q": cfg["lib_q"][:400], "master": cfg["master"],
                "pc": cfg["pc"], "pcs": cfg["pcs"][:2], "true_q": cfg["true_q"][:2]}
+    if not args.no_drift:
+        line["drift"] = drift_map(tm, args.patterns, args.library, args.drift_steps)
+        torch.cuda.empty_cache()
     if not args.no_precision:
         del pats, cfg, out, idx
         torch.cuda.empty_cache()
@@ -316,6 +322,76 @@ def compare_forms(tm, pats, master, cfg, lib_q, pc_per, best_ref, q_ref, steps):
                      "refined_vs_truth_deg_median": float(np.median(vs_true)),
                      "refined_vs_truth_deg_p95": float(np.percentile(vs_true, 95))}
         print("[bench] form %s: %.0f patterns/s" % (name, res[name]["patterns_per_s"]), file=sys.stderr, flush=True)
+    return res
+
+
+def drift_map(tm, patterns, library, steps, sample=1000):
+    """The map with a pattern centre drifting across it (pcx over 0.13 and pcy
+    over 0.08 screen widths, pcz over 0.02), one library at the nominal PC.
+    A step evaluates the affine PC model on the device, runs the exhaustive
+    FP32 search and refines either from the search's beam-shift-corrected
+    shift (ebsd_refine_from_match) or by re-projecting at each point's PC
+    from the start (ebsd_refine_orientations); without any PC correction
+    (every point refined at the nominal PC) the drift reads as rotation."""
+    import numpy as np
+    import torch
+    from fixtures import configs
+    from oracle import rotations
+
+    dev = torch.device("cuda:0")
+    side = int(round(patterns ** 0.5))
+    print("[bench] generating drifting-PC map %dx%d at 128^2, library %d" % (side, side, library),
+          file=sys.stderr, flush=True)
+    cfg = configs.drift_map(rows=side, cols=side, n=128, l=library, device=dev, dtype=torch.float32)
+    pats = cfg["patterns"].contiguous()
+    master = torch.as_tensor(cfg["master"], device=dev).contiguous()
+    lib_q = torch.as_tensor(cfg["lib_q"], device=dev).contiguous()
+    m = cfg["model"]
+    P = pats.shape[0]
+    pick = np.linspace(0, P - 1, min(sample, P)).astype(int)
+
+    def pcs():
+        return tm.pc_map(m["pc0"], m["d_col"], m["d_row"], m["width"], P, m["col0"], m["row0"])
+
+    variants = {
+        "from_match": lambda r, pc: tm.refine_from_match(pats, master, cfg["pc"], r["best_q"], r["shift"], pc_per=pc),
+        "reproject": lambda r, pc: tm.refine_orientations(pats, master, cfg["pc"], r["best_q"], pc_per=pc),
+        "no_pc_correction": lambda r, pc: tm.refine_orientations(pats, master, cfg["pc"], r["best_q"]),
+    }
+    res = {"workload": "drifting PC: %d patterns (%dx%d, 20 grains) at 128x128 fp32, %d-orientation library at the "
+                       "nominal PC, pcx/pcy/pcz drift 0.13/0.08/0.02 screen widths across the map, SNR 5"
+                       % (P, side, side, lib_q.shape[0])}
+    for name, refine in variants.items():
+        def step():
+            pc = pcs()
+            r = tm.index_patterns(pats, master, cfg["pc"], lib_q)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            out = refine(r, pc)
+            e1.record()
+            return out, (e0, e1)
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evs = []
+        for _ in range(steps):
+            out, ev = step()
+            evs.append(ev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        q = out["q"].cpu().numpy()
+        mis = np.rad2deg([rotations.disorientation_q(q[i], cfg["true_q"][i]) for i in pick])
+        res[name] = {"patterns_per_s": P * steps / (t1 - t0),
+                     "refine_ms": float(np.mean([a.elapsed_time(b) for a, b in evs])),
+                     "refined_vs_truth_deg_median": float(np.median(mis)),
+                     "refined_vs_truth_deg_p95": float(np.percentile(mis, 95)),
+                     "within_0.2_deg": float(np.mean(mis < 0.2))}
+        print("[bench] drift %s: %.0f patterns/s, refine %.1f ms, median %.3f deg, within 0.2 deg %.4f"
+              % (name, res[name]["patterns_per_s"], res[name]["refine_ms"], res[name]["refined_vs_truth_deg_median"],
+                 res[name]["within_0.2_deg"]), file=sys.stderr, flush=True)
+    res["accuracy_sample"] = "%d map points vs simulated truth" % len(pick)
     return res
 
 

@@ -11,6 +11,9 @@ map       a 100 x 100 map (10,000 patterns) at 128^2: 20 Voronoi grains with
           mirrors the paper's deformed alpha-iron map (9,130 patterns at
           128^2, section "Deformed alpha-Fe Dataset").
 map256    the same map at 256^2.
+drift     the map with a pattern centre drifting linearly across it (the
+          spans of the paper's wide silicon map), one library at the nominal
+          PC.
 ragged    20,000 patterns with sizes drawn from {64, 96, 128, 160} (25 % each,
           shuffled), otherwise as `map`; library of 8,000.
 
@@ -62,6 +65,33 @@ def map_grid(seed=2, rows=100, cols=100, n=128, l=4000, n_grains=20, device="cpu
     pats = simulate_patterns(true_q, n, pcs, noise, seed=seed + 1000, device=device, dtype=dtype)
     return dict(master=master, patterns=pats, pcs=pcs, offsets=off, true_q=true_q, lib_q=lib_q,
                 n=n, pc=(0.5, 0.5, PCZ), grain=gid)
+
+
+def drift_map(seed=5, rows=100, cols=100, n=128, l=4000, n_grains=20, span=(0.13, 0.08, 0.02), device="cpu",
+              noise=("poisson_gauss", 1000.0, 5.0), dtype=torch.float64):
+    """The map workload with a pattern centre that drifts across the map:
+    pcx spans 0.13 screen widths along a row and pcy 0.08 down a column
+    (the spans of the paper's wide silicon map, 0.39-0.52 and 0.11-0.19),
+    pcz 0.02 down a column, linear in the beam position and centred on the
+    nominal (0.5, 0.5, 0.6) at the map centre.  `model` holds the affine
+    coefficients (pc0, d_col, d_row, col0, row0, width); `pcs` are the true
+    per-point centres the patterns were simulated at."""
+    rng = np.random.default_rng(seed)
+    master = band_master()
+    gid = voronoi_map(rng, rows, cols, n_grains)
+    grain_q = random_quats(rng, n_grains)
+    true_q = perturb_quats(rng, grain_q[gid], 1.0)
+    pc0 = (0.5, 0.5, PCZ)
+    d_col = (span[0] / max(cols - 1, 1), 0.0, 0.0)
+    d_row = (0.0, span[1] / max(rows - 1, 1), span[2] / max(rows - 1, 1))
+    col0, row0 = (cols - 1) / 2.0, (rows - 1) / 2.0
+    rr, cc = np.meshgrid(np.arange(rows, dtype=np.float64), np.arange(cols, dtype=np.float64), indexing="ij")
+    pcs = np.stack([pc0[0] + (cc - col0) * d_col[0], pc0[1] + (rr - row0) * d_row[1],
+                    pc0[2] + (rr - row0) * d_row[2]], axis=-1).reshape(-1, 3)
+    lib_q = random_fz_quats(rng, l)
+    pats = simulate_patterns(true_q, n, pcs, noise, seed=seed + 1000, device=device, dtype=dtype)
+    return dict(master=master, patterns=pats, pcs=pcs, true_q=true_q, lib_q=lib_q, n=n, pc=pc0, grain=gid,
+                model=dict(pc0=pc0, d_col=d_col, d_row=d_row, col0=col0, row0=row0, width=cols))
 
 
 def ragged(seed=4, p=20000, l=8000, sizes=(64, 96, 128, 160), device="cpu"):

@@ -179,6 +179,55 @@ int ebsd_refine_orientations(const ebsd_batch* pats, const ebsd_master* mp, cons
                              const double* q_init, const ebsd_params* prm, double* q_out, float* peak_h,
                              float* shift, void* stream);
 
+/*
+ * Map-wide pattern-centre model (section "Orientation and Pattern Centre
+ * Refinement", Figure 6 B, and the silicon-map demonstrations: the PC drifts
+ * as the beam scans the map; the paper imports its model and states no
+ * form).  Affine in the map position: point k of a row-major map `width`
+ * points wide sits at col = k mod width, row = k / width (integer division)
+ * and has
+ *   pc(k) = pc0 + (col - col0) d_col + (row - row0) d_row,
+ * each a (pcx, pcy, pcz) triple in screen widths.
+ */
+typedef struct {
+  double pc0[3];
+  double d_col[3];
+  double d_row[3];
+  double col0, row0;
+  int64_t width;
+} ebsd_pc_model;
+
+/*
+ * Evaluates the model for points 0 .. P-1 into pc_out (device float64
+ * [P][3], the layout of ebsd_geometry.pc_per).  width >= 1; P = 0 is a
+ * no-op.
+ */
+int ebsd_pc_map(const ebsd_pc_model* model, int64_t P, double* pc_out, void* stream);
+
+/*
+ * Refinement that starts from the search's own measurement (section
+ * "Orientation and Pattern Centre Refinement": one library at one pattern
+ * centre; the shift measured against it is corrected for the beam-induced
+ * PC move before Equation 7 turns it into a rotation).  The first x/y step
+ * takes
+ *   s = match_shift - n (pc_per[p].x - pcx, pc_per[p].y - pcy)
+ * (a PC move by (dx, dy) screen widths translates the pattern by +n (dx, dy)
+ * px) in place of a projection and correlation at the starting
+ * orientation; the z step, the further iterations and the final
+ * measurement are those of ebsd_refine_orientations at each point's own PC.
+ * With n_iter = 0 it is the final measurement alone.
+ *   geo          pcx, pcy, pcz: the PC the library was projected at;
+ *                pc_per: per-point PCs (device [P][3]) or NULL (every point
+ *                at the library's PC: no correction)
+ *   q_init       device float64 [P][4]: the search's best_q
+ *   match_shift  device float32 [P][2] (s_x, s_y) px: the search's shift
+ *                for the same patterns and orientations
+ * Outputs as ebsd_refine_orientations (q_out may alias q_init).
+ */
+int ebsd_refine_from_match(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo,
+                           const double* q_init, const float* match_shift, const ebsd_params* prm, double* q_out,
+                           float* peak_h, float* shift, void* stream);
+
 /* ---- stage entry points (the same kernels, exposed for stage-by-stage checks) ---- */
 
 /*

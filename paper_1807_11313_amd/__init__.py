@@ -16,7 +16,7 @@ import numpy as np
 __all__ = ["lib", "Params", "index_patterns", "refine_orientations", "project_templates",
            "pattern_spectra", "spectrum_floats", "xcf_peak", "xcf_scores", "xcf_subpixel",
            "measure_rotation", "params_default", "version", "RaggedPlan", "Cnn", "cnn_make_batch", "cnn_topk",
-           "index_proposed", "LIB_PATH", "EXPORTS"]
+           "index_proposed", "refine_from_match", "pc_map", "PcModel", "LIB_PATH", "EXPORTS"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libebsd_tm.so")
@@ -29,7 +29,7 @@ EXPORTS = ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_index
            "ebsd_ragged_run", "ebsd_ragged_plan_tiles", "ebsd_ragged_plan_destroy", "ebsd_cnn_param_count",
            "ebsd_cnn_create", "ebsd_cnn_destroy", "ebsd_cnn_get_params", "ebsd_cnn_set_params", "ebsd_cnn_input",
            "ebsd_cnn_forward", "ebsd_cnn_gradients", "ebsd_cnn_train_step", "ebsd_cnn_make_batch", "ebsd_cnn_topk",
-           "ebsd_index_proposed")
+           "ebsd_index_proposed", "ebsd_pc_map", "ebsd_refine_from_match")
 
 RAGGED_STENCIL, RAGGED_EAGER, RAGGED_NO_AUTOTUNE = 1, 2, 4
 
@@ -48,6 +48,11 @@ class Master(ctypes.Structure):
 class Geometry(ctypes.Structure):
     _fields_ = [("pcx", ctypes.c_double), ("pcy", ctypes.c_double), ("pcz", ctypes.c_double),
                 ("pc_per", ctypes.c_void_p)]
+
+
+class PcModel(ctypes.Structure):
+    _fields_ = [("pc0", ctypes.c_double * 3), ("d_col", ctypes.c_double * 3), ("d_row", ctypes.c_double * 3),
+                ("col0", ctypes.c_double), ("row0", ctypes.c_double), ("width", ctypes.c_int64)]
 
 
 class Params(ctypes.Structure):
@@ -85,6 +90,8 @@ def lib():
     L.ebsd_index_patterns.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, i64, dp(Params), vp, vp, vp, vp,
                                       vp, vp]
     L.ebsd_refine_orientations.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, dp(Params), vp, vp, vp, vp]
+    L.ebsd_refine_from_match.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, vp, dp(Params), vp, vp, vp, vp]
+    L.ebsd_pc_map.argtypes = [dp(PcModel), i64, vp, vp]
     L.ebsd_project_templates.argtypes = [dp(Master), vp, i64, i32, dp(Geometry), vp, vp]
     L.ebsd_pattern_spectra.argtypes = [vp, i64, i32, dp(Params), vp, vp, vp]
     L.ebsd_xcf_peak.argtypes = [vp, vp, vp, vp, i64, i32, dp(Params), vp, vp, vp, vp]
@@ -211,6 +218,37 @@ def refine_orientations(patterns, master, pc, q_init, pc_per=None, prm=None):
                                         _params(prm), _ptr(out["q"]), _ptr(out["peak_h"]), _ptr(out["shift"]),
                                         _stream())
     _check(rc, "ebsd_refine_orientations")
+    return out
+
+
+def refine_from_match(patterns, master, pc, q_init, match_shift, pc_per=None, prm=None):
+    """Refinement whose first x/y step reuses the search's shift (match_shift
+    float32 [P, 2] (x, y) px against the library projected at pc), less the
+    beam-induced move to pc_per.  Returns dict(q, peak_h, shift) as CUDA
+    tensors."""
+    import torch
+    p, n = patterns.shape[0], patterns.shape[-1]
+    dev = patterns.device
+    out = dict(q=torch.empty((p, 4), dtype=torch.float64, device=dev),
+               peak_h=torch.empty(p, dtype=torch.float32, device=dev),
+               shift=torch.empty((p, 2), dtype=torch.float32, device=dev))
+    batch = Batch(_ptr(patterns, torch.float32, "patterns").value, p, n)
+    rc = lib().ebsd_refine_from_match(ctypes.byref(batch), ctypes.byref(_master(master)),
+                                      ctypes.byref(_geo(pc, pc_per)), _ptr(q_init, torch.float64, "q_init"),
+                                      _ptr(match_shift, torch.float32, "match_shift"), _params(prm),
+                                      _ptr(out["q"]), _ptr(out["peak_h"]), _ptr(out["shift"]), _stream())
+    _check(rc, "ebsd_refine_from_match")
+    return out
+
+
+def pc_map(pc0, d_col, d_row, width, p, col0=0.0, row0=0.0, device="cuda"):
+    """Per-point pattern centres float64 [p, 3] of the affine map model."""
+    import torch
+    out = torch.empty((p, 3), dtype=torch.float64, device=device)
+    m = PcModel((ctypes.c_double * 3)(*map(float, pc0)), (ctypes.c_double * 3)(*map(float, d_col)),
+                (ctypes.c_double * 3)(*map(float, d_row)), float(col0), float(row0), int(width))
+    rc = lib().ebsd_pc_map(ctypes.byref(m), p, _ptr(out) if p > 0 else None, _stream())
+    _check(rc, "ebsd_pc_map")
     return out
 
 
@@ -488,5 +526,5 @@ def index_proposed(patterns, master, pc, lib_q, cnn, top_k=32, fallback_tau=0.0,
                                      _ptr(lib_q, torch.float64, "lib_q"), lib_q.shape[0], cnn._h, top_k,
                                      float(fallback_tau), _params(prm), _ptr(out["best_idx"]), _ptr(out["best_q"]),
                                      _ptr(out["peak_h"]), _ptr(out["shift"]), _ptr(out["fallback"]), _stream()),
-           "ebsd_index_proposed")
+           "ebsd_index_proposed", "ebsd_pc_map", "ebsd_refine_from_match")
     return out

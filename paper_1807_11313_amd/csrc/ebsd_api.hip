@@ -426,10 +426,16 @@ int ebsd_index_patterns(const ebsd_batch* pats, const ebsd_master* mp, const ebs
   return EBSD_OK;
 }
 
-int ebsd_refine_orientations(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo,
-                             const double* q_init, const ebsd_params* prm, double* q_out, float* peak_h,
-                             float* shift, void* stream) {
-  g_last_error.clear();
+}  // extern "C"
+
+namespace {
+
+// The refinement of both entry points; match_shift (may be NULL) replaces the
+// first iteration's projection and correlation by the search's shift less
+// the beam-induced PC translation.
+int refine_impl(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo, const double* q_init,
+                const float* match_shift, const ebsd_params* prm, double* q_out, float* peak_h, float* shift,
+                void* stream) {
   int rc;
   if (!pats) return fail(EBSD_E_INVALID, "null batch");
   const int n = pats->n;
@@ -477,9 +483,14 @@ int ebsd_refine_orientations(const ebsd_batch* pats, const ebsd_master* mp, cons
              "subpixel");
     return EBSD_OK;
   };
+  const double pc0[2] = {geo->pcx, geo->pcy};
   for (int it = 0; it < p.n_iter; ++it) {
-    if ((rc = measure_shift(h_sub, s_sub))) return rc;
-    EBSD_TRY(launch_update_xy(q_out, s_sub, P, pcp, geo->pcz, n, st), "update_xy");
+    if (it == 0 && match_shift) {
+      EBSD_TRY(launch_update_xy(q_out, match_shift, P, pcp, geo->pcz, n, st, pc0), "update_xy(match)");
+    } else {
+      if ((rc = measure_shift(h_sub, s_sub))) return rc;
+      EBSD_TRY(launch_update_xy(q_out, s_sub, P, pcp, geo->pcz, n, st), "update_xy");
+    }
     EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, q_out, P, pcp, geo->pcx, geo->pcy, geo->pcz, tmpl, st),
              "project");
     EBSD_TRY(launch_logpolar(n, tmpl, P, p.n_rho, p.n_eta, lp_t, st), "logpolar(templates)");
@@ -487,6 +498,50 @@ int ebsd_refine_orientations(const ebsd_batch* pats, const ebsd_master* mp, cons
     EBSD_TRY(launch_update_z(q_out, gam, P, st), "update_z");
   }
   if ((rc = measure_shift(peak_h, shift))) return rc;
+  return EBSD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ebsd_refine_orientations(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo,
+                             const double* q_init, const ebsd_params* prm, double* q_out, float* peak_h,
+                             float* shift, void* stream) {
+  g_last_error.clear();
+  return refine_impl(pats, mp, geo, q_init, nullptr, prm, q_out, peak_h, shift, stream);
+}
+
+int ebsd_refine_from_match(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo,
+                           const double* q_init, const float* match_shift, const ebsd_params* prm, double* q_out,
+                           float* peak_h, float* shift, void* stream) {
+  g_last_error.clear();
+  if (pats && pats->P > 0 && !match_shift) return fail(EBSD_E_INVALID, "null match_shift");
+  return refine_impl(pats, mp, geo, q_init, match_shift, prm, q_out, peak_h, shift, stream);
+}
+
+int ebsd_pc_map(const ebsd_pc_model* model, int64_t P, double* pc_out, void* stream) {
+  g_last_error.clear();
+  if (!model) return fail(EBSD_E_INVALID, "null model");
+  if (P < 0) return fail(EBSD_E_INVALID, "P must be >= 0");
+  if (model->width < 1) return fail(EBSD_E_INVALID, "width must be >= 1");
+  for (int c = 0; c < 3; ++c)
+    if (!std::isfinite(model->pc0[c]) || !std::isfinite(model->d_col[c]) || !std::isfinite(model->d_row[c]))
+      return fail(EBSD_E_INVALID, "model coefficients must be finite");
+  if (!std::isfinite(model->col0) || !std::isfinite(model->row0)) return fail(EBSD_E_INVALID, "col0, row0 must be finite");
+  if (P > 0x7fffffffLL) return fail(EBSD_E_INVALID, "P must fit in int32");
+  if (P == 0) return EBSD_OK;
+  if (!pc_out) return fail(EBSD_E_INVALID, "null pc_out");
+  PcModel m;
+  for (int c = 0; c < 3; ++c) {
+    m.pc0[c] = model->pc0[c];
+    m.d_col[c] = model->d_col[c];
+    m.d_row[c] = model->d_row[c];
+  }
+  m.col0 = model->col0;
+  m.row0 = model->row0;
+  m.width = model->width;
+  EBSD_TRY(launch_pc_map(m, P, pc_out, (hipStream_t)stream), "pc_map");
   return EBSD_OK;
 }
 

@@ -114,9 +114,19 @@ hipError_t launch_eta_peak(const float* lp_e, const float* lp_t, int64_t k, int 
                            int n_eta, int kappa, double* gamma, hipStream_t stream);
 
 // FP64 orientation updates: R <- R (Ry(beta) Rx(alpha))^T from s_sub, and
-// R <- R Rz(gamma)^T.
+// R <- R Rz(gamma)^T.  beam_pc0 (x, y), if given with pc_per, is the PC the
+// shift was measured at: the PC-move translation is subtracted first.
 hipError_t launch_update_xy(double* q, const float* s_sub, int64_t k, const double* pc_per,
-                            double pcz, int n, hipStream_t stream);
+                            double pcz, int n, hipStream_t stream, const double* beam_pc0 = nullptr);
+
+// Affine map-wide pattern-centre model: pc(k) = pc0 + (col - col0) d_col +
+// (row - row0) d_row, col = k mod width, row = k / width.
+struct PcModel {
+  double pc0[3], d_col[3], d_row[3];
+  double col0, row0;
+  int64_t width;
+};
+hipError_t launch_pc_map(const PcModel& m, int64_t k, double* out, hipStream_t stream);
 hipError_t launch_update_z(double* q, const double* gamma, int64_t k, hipStream_t stream);
 
 }  // namespace ebsd

@@ -389,13 +389,22 @@ __global__ __launch_bounds__(256) void k_eta_peak(const float* __restrict__ lp_e
 // FP64 orientation updates (Equation 7 with the atan reading; log-polar z):
 // with c = R d, a crystal rotated by Q in the detector frame has orientation
 // R Q^T, i.e. quaternion q (x) conj(q_Q).
+// With `beam` set, the shift was measured against a template projected at
+// (pcx0, pcy0) and the pattern sits at pc_per[i]: the PC move translates the
+// pattern by +n (dx, dy) px, which is taken off before the angles.
 __global__ void k_update_xy(double* __restrict__ q, const float* __restrict__ s_sub, int64_t kk,
-                            const double* __restrict__ pc_per, double pcz, int n) {
+                            const double* __restrict__ pc_per, double pcz, int n, int beam, double pcx0,
+                            double pcy0) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= kk) return;
   const double dd = (pc_per ? pc_per[3 * i + 2] : pcz) * (double)n;
-  const double beta = atan((double)s_sub[2 * i] / dd);
-  const double alpha = -atan((double)s_sub[2 * i + 1] / dd);
+  double sx = (double)s_sub[2 * i], sy = (double)s_sub[2 * i + 1];
+  if (beam) {
+    sx -= (double)n * (pc_per[3 * i] - pcx0);
+    sy -= (double)n * (pc_per[3 * i + 1] - pcy0);
+  }
+  const double beta = atan(sx / dd);
+  const double alpha = -atan(sy / dd);
   // conj(q_y(beta) q_x(alpha)) = conj(q_x(alpha)) conj(q_y(beta))
   const double cxi[4] = {cos(0.5 * alpha), -sin(0.5 * alpha), 0.0, 0.0};
   const double cyi[4] = {cos(0.5 * beta), 0.0, -sin(0.5 * beta), 0.0};
@@ -492,10 +501,31 @@ hipError_t launch_eta_peak(const float* lp_e, const float* lp_t, int64_t k, int 
 }
 
 hipError_t launch_update_xy(double* q, const float* s_sub, int64_t k, const double* pc_per, double pcz,
-                            int n, hipStream_t stream) {
+                            int n, hipStream_t stream, const double* beam_pc0) {
   if (k <= 0) return hipSuccess;
+  const int beam = beam_pc0 != nullptr && pc_per != nullptr;
   hipLaunchKernelGGL(k_update_xy, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, stream, q, s_sub, k, pc_per,
-                     pcz, n);
+                     pcz, n, beam, beam ? beam_pc0[0] : 0.0, beam ? beam_pc0[1] : 0.0);
+  return hipGetLastError();
+}
+
+// Affine map-wide PC model, one point per thread: separately rounded
+// products and sums (no fused multiply-add), in the order
+// (pc0 + (col - col0) d_col) + (row - row0) d_row.
+__global__ void k_pc_map(PcModel m, int64_t kk, double* __restrict__ out) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= kk) return;
+  const int64_t row = i / m.width;
+  const double a = (double)(i - row * m.width) - m.col0;
+  const double b = (double)row - m.row0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) out[3 * i + c] = (m.pc0[c] + a * m.d_col[c]) + b * m.d_row[c];
+}
+
+hipError_t launch_pc_map(const PcModel& m, int64_t k, double* out, hipStream_t stream) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pc_map, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, stream, m, k, out);
   return hipGetLastError();
 }
 

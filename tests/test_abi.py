@@ -104,3 +104,31 @@ def test_ragged_plan_argument_errors():
     assert create(sizes, offs, prm=pkg.params_default(precision=1, max_shift=5)) == -4
     assert h.value is None
     assert lib.ebsd_ragged_plan_destroy(None) == 0
+
+
+def test_pc_map_and_refine_from_match_argument_errors():
+    pkg, lib = _lib()
+    d3 = ctypes.c_double * 3
+    good = dict(pc0=d3(0.5, 0.5, 0.6), d_col=d3(1e-3, 0, 0), d_row=d3(0, 1e-3, 0), col0=0.0, row0=0.0, width=10)
+
+    def call(p, out=0x1000, **kw):
+        m = pkg.PcModel(**dict(good, **kw))
+        return lib.ebsd_pc_map(ctypes.byref(m), p, ctypes.c_void_p(out) if out else None, None)
+
+    assert call(5, width=0) == -1 and b"width" in lib.ebsd_last_error()
+    assert call(5, out=0) == -1
+    assert call(-1) == -1
+    assert call(5, d_col=d3(float("nan"), 0, 0)) == -1 and b"finite" in lib.ebsd_last_error()
+    assert call(5, row0=float("inf")) == -1
+    assert call(0, out=0) == 0
+    assert lib.ebsd_pc_map(None, 5, ctypes.c_void_p(0x1000), None) == -1
+    batch = pkg.Batch(0x1000, 4, 128)
+    m = pkg.Master(0x2000, 256, 256)
+    g = pkg.Geometry(0.5, 0.5, 0.6, None)
+    rc = lib.ebsd_refine_from_match(ctypes.byref(batch), ctypes.byref(m), ctypes.byref(g), ctypes.c_void_p(0x3000),
+                                    None, None, ctypes.c_void_p(0x4000), ctypes.c_void_p(0x5000),
+                                    ctypes.c_void_p(0x6000), None)
+    assert rc == -1 and b"match_shift" in lib.ebsd_last_error()
+    empty = pkg.Batch(0x1000, 0, 128)
+    assert lib.ebsd_refine_from_match(ctypes.byref(empty), ctypes.byref(m), ctypes.byref(g), None, None, None, None,
+                                      None, None, None) == 0
