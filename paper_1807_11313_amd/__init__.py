@@ -526,5 +526,5 @@ def index_proposed(patterns, master, pc, lib_q, cnn, top_k=32, fallback_tau=0.0,
                                      _ptr(lib_q, torch.float64, "lib_q"), lib_q.shape[0], cnn._h, top_k,
                                      float(fallback_tau), _params(prm), _ptr(out["best_idx"]), _ptr(out["best_q"]),
                                      _ptr(out["peak_h"]), _ptr(out["shift"]), _ptr(out["fallback"]), _stream()),
-           "ebsd_index_proposed", "ebsd_pc_map", "ebsd_refine_from_match")
+           "ebsd_index_proposed")
     return out

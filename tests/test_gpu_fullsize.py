@@ -11,8 +11,10 @@ against the exhaustive search).
   (tau_tie = 2e-4); inside it the GPU's pick scores within tau_tie of the
   oracle's best.
 * Peak height 1e-4, sub-pixel shift 0.02 px (where the picks agree).
-* Refinement from the GPU's picks with per-pattern pattern centres: the
-  oracle's orientation to 0.05 deg.
+* Refinement with per-pattern pattern centres (re-projected from the start,
+  and from the search's shift as the bench times it), from the oracle's own
+  picks and shifts where the picks agree: the oracle's orientation to
+  0.05 deg.
 """
 
 import numpy as np
@@ -39,9 +41,11 @@ def test_map_workload_sampled_against_oracle():
     assert tuple(pats.shape) == (10000, 128, 128) and len(cfg["lib_q"]) == 4000
     master, lq = dev(cfg["master"]), dev(cfg["lib_q"])
     res = t.index_patterns(pats, master, cfg["pc"], lq)
-    rr = t.refine_orientations(pats, master, cfg["pc"], res["best_q"], pc_per=dev(cfg["pcs"]))
+    pc_per = dev(cfg["pcs"])
+    rr = t.refine_orientations(pats, master, cfg["pc"], res["best_q"], pc_per=pc_per)
+    rm = t.refine_from_match(pats, master, cfg["pc"], res["best_q"], res["shift"], pc_per=pc_per)
     best_all = host(res["best_idx"])
-    h_all, s_all, q_all = host(res["peak_h"]), host(res["shift"]), host(rr["q"])
+    h_all, s_all, q_all, qm_all = host(res["peak_h"]), host(res["shift"]), host(rr["q"]), host(rm["q"])
     assert np.all((best_all >= 0) & (best_all < 4000))
 
     idx = np.sort(np.random.default_rng(11).choice(len(best_all), SAMPLE, replace=False))
@@ -61,10 +65,15 @@ def test_map_workload_sampled_against_oracle():
     assert np.max(np.abs(h_all[idx][same] - ref["peak_h"][same])) < 1e-4
     assert np.max(np.abs(s_all[idx][same] - ref["shift"][same])) <= 0.02 + 1e-6
 
-    banner("oracle: refinement of the sampled patterns")
-    rref = pipeline.refine_orientations(sample, cfg["master"], cfg["pcs"][idx], cfg["lib_q"][best], prm)
+    banner("oracle: refinement of the sampled patterns (both forms)")
+    # from the oracle's own picks and shifts; compared where the picks agree
+    rref = pipeline.refine_orientations(sample, cfg["master"], cfg["pcs"][idx], ref["best_q"], prm)
     d = np.rad2deg([rotations.disorientation_q(a, b) for a, b in zip(q_all[idx], rref["q"])])
-    assert np.max(d) < 0.05, d
+    assert np.max(d[same]) < 0.05, d
+    mref = pipeline.refine_from_match(sample, cfg["master"], cfg["pcs"][idx], cfg["pc"], ref["best_q"], ref["shift"],
+                                      prm)
+    d = np.rad2deg([rotations.disorientation_q(a, b) for a, b in zip(qm_all[idx], mref["q"])])
+    assert np.max(d[same]) < 0.05, d
 
 
 def test_map256_dftgemm_sampled_against_oracle():
@@ -79,7 +88,7 @@ def test_map256_dftgemm_sampled_against_oracle():
     master, lq = dev(cfg["master"]), dev(cfg["lib_q"])
     prm = t.params_default(precision=1, max_shift=s)
     res = t.index_patterns(pats, master, cfg["pc"], lq, prm=prm)
-    rr = t.refine_orientations(pats, master, cfg["pc"], res["best_q"], pc_per=dev(cfg["pcs"]), prm=prm)
+    rr = t.refine_from_match(pats, master, cfg["pc"], res["best_q"], res["shift"], pc_per=dev(cfg["pcs"]), prm=prm)
     best_all = host(res["best_idx"])
     h_all, s_all, q_all = host(res["peak_h"]), host(res["shift"]), host(rr["q"])
 
@@ -101,9 +110,12 @@ def test_map256_dftgemm_sampled_against_oracle():
     assert np.max(np.abs(s_all[idx][same] - ref["shift"][same])) <= 0.02 + 1e-6
 
     banner("oracle: refinement of the sampled patterns")
-    rref = pipeline.refine_orientations(sample, cfg["master"], cfg["pcs"][idx], cfg["lib_q"][best], oprm)
+    # the bench's refinement (from the search's shift), from the oracle's own
+    # picks and shifts, compared where the picks agree
+    rref = pipeline.refine_from_match(sample, cfg["master"], cfg["pcs"][idx], cfg["pc"], ref["best_q"], ref["shift"],
+                                      oprm)
     d = np.rad2deg([rotations.disorientation_q(a, b) for a, b in zip(q_all[idx], rref["q"])])
-    assert np.max(d) < 0.05, d
+    assert np.max(d[same]) < 0.05, d
 
 
 def test_ragged_batch_sampled_against_oracle():
