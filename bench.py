@@ -107,6 +107,7 @@ def main():
     ap.add_argument("--no-drift", action="store_true",
                     help="skip the drifting-pattern-centre map (beam-shift-corrected refinement)")
     ap.add_argument("--drift-steps", type=int, default=3)
+    ap.add_argument("--no-capture", action="store_true", help="skip the capture-range (FWHM) sweep")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the split-precision search on the same map at 256^2")
     ap.add_argument("--precision-patterns", type=int, default=10000)
@@ -256,6 +257,8 @@ def main():
     # the oracle's sample, on the host, before the 128^2 map is released
     cpu_cfg = {"patterns": cfg["patterns"][:3].cpu(), "lib_q": cfg["lib_q"][:400], "master": cfg["master"],
                "pc": cfg["pc"], "pcs": cfg["pcs"][:2], "true_q": cfg["true_q"][:2]}
+    if not args.no_capture:
+        line["capture"] = capture_sweep(tm)
     if not args.no_drift:
         line["drift"] = drift_map(tm, args.patterns, args.library, args.drift_steps)
         torch.cuda.empty_cache()
@@ -395,6 +398,52 @@ def drift_map(tm, patterns, library, steps, sample=1000):
               % (name, res[name]["patterns_per_s"], res[name]["refine_ms"], res[name]["refined_vs_truth_deg_median"],
                  res[name]["within_0.2_deg"]), file=sys.stderr, flush=True)
     res["accuracy_sample"] = "%d map points vs simulated truth" % len(pick)
+    return res
+
+
+def capture_sweep(tm, n_ref=8, span=30.0, step=0.5):
+    """Capture range of the correlation (Figures 3 and 4 analogues): the
+    integer peak of a reference pattern against the crystal rotated about
+    the detector x, y and z axes in 0.5 deg steps over +-30 deg, at the PC
+    (0.5, 0.3, 0.6); FWHM per axis averaged over n_ref random reference
+    orientations, per screen size, and at 128^2 per pattern-centre error of
+    the rotated patterns."""
+    import numpy as np
+    import torch
+    from fixtures import band_master, random_quats
+
+    dev = torch.device("cuda:0")
+    pc = (0.5, 0.3, 0.6)
+    master = torch.as_tensor(band_master(), device=dev).contiguous()
+    q_ref = torch.as_tensor(random_quats(np.random.default_rng(77), n_ref), device=dev).contiguous()
+    th_h = np.arange(-span, span + 1e-9, step)
+    th = torch.as_tensor(th_h, device=dev).contiguous()
+
+    def run(n, pc_test):
+        tm.capture_range(master, q_ref, n, pc, pc_test, th)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, w = tm.capture_range(master, q_ref, n, pc, pc_test, th)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        w = w.cpu().numpy()
+        return {"fwhm_deg_mean_xyz": [float(v) for v in w.mean(axis=0)],
+                "fwhm_deg_min_xyz": [float(v) for v in w.min(axis=0)],
+                "rotated_patterns_per_s": n_ref * 3 * len(th_h) / dt}
+
+    res = {"workload": "capture range: %d reference orientations x 3 detector axes x %d angles (%.1f deg steps "
+                       "over +-%.0f deg), PC (0.5, 0.3, 0.6), integer correlation peak" % (n_ref, len(th_h), step, span),
+           "screen": {}, "pc_error_128": {}}
+    for n in (64, 96, 128, 160):
+        res["screen"][str(n)] = run(n, pc)
+    for axis, k in (("x", 0), ("y", 1), ("z", 2)):
+        for d in (0.01, 0.03, 0.05):
+            pt = list(pc)
+            pt[k] += d
+            res["pc_error_128"]["%s+%.2f" % (axis, d)] = run(128, tuple(pt))
+    s = res["screen"]
+    print("[bench] capture FWHM (x, y, z) deg: " + ", ".join(
+        "%s: %s" % (n, "/".join("%.1f" % v for v in s[n]["fwhm_deg_mean_xyz"])) for n in s), file=sys.stderr, flush=True)
     return res
 
 

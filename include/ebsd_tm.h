@@ -228,6 +228,29 @@ int ebsd_refine_from_match(const ebsd_batch* pats, const ebsd_master* mp, const 
                            const double* q_init, const float* match_shift, const ebsd_params* prm, double* q_out,
                            float* peak_h, float* shift, void* stream);
 
+/*
+ * Capture range of the correlation (section "SO(3) Sampling Frequency",
+ * Figures 3 and 4): for each reference orientation r and each detector axis
+ * a = x, y, z, the integer correlation peak of the reference pattern
+ * (projected at geo_ref's PC) against the pattern of the crystal rotated by
+ * theta_k about that axis (orientation R Q^T, projected at geo_test's PC, so
+ * that a PC error can be studied), and the full width at half maximum of
+ * that curve above its floor: the level is halfway between its largest and
+ * smallest samples (the correlation of a shifted, unrelated pattern stays
+ * well above zero); from the largest sample the width runs outwards to the
+ * first sample below the level on each side, interpolated linearly (a side
+ * that never drops reports the end of the sampled range).
+ *   q_ref      device float64 [R][4]
+ *   theta_deg  device float64 [T], ascending, degrees
+ *   geo_ref, geo_test  pattern centres (pc_per ignored)
+ *   h          out: device float32 [R][3][T]
+ *   width      out: device float64 [R][3], degrees
+ * Scratch holds the 3 R T rotated images and spectra.
+ */
+int ebsd_capture_range(const ebsd_master* mp, const double* q_ref, int64_t R, int32_t n,
+                       const ebsd_geometry* geo_ref, const ebsd_geometry* geo_test, const double* theta_deg,
+                       int32_t T, const ebsd_params* prm, float* h, double* width, void* stream);
+
 /* ---- stage entry points (the same kernels, exposed for stage-by-stage checks) ---- */
 
 /*

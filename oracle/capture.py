@@ -11,9 +11,12 @@ Readings (the paper gives no formula for the width):
 * the curve is the integer correlation peak h(theta) (the score the library
   search ranks by) of the reference pattern against the pattern rotated by
   theta, a detector-frame rotation Q, orientation R Q^T;
-* the full width at half maximum is measured at half the curve's largest
-  sample: from that sample, walk outwards on each side to the first sample
-  below the level and interpolate linearly between it and its inner
+* the full width at half maximum is measured above the curve's floor (the
+  correlation of a shifted, unrelated pattern stays well above zero, and
+  the paper motivates the width by the contrast of the match over that
+  baseline): level = (largest + smallest sample) / 2; from the largest
+  sample (the first, on ties) walk outwards on each side to the first
+  sample below the level and interpolate linearly between it and its inner
   neighbour; a side that never drops below the level reports the end of
   the sampled range (the width is then a lower bound).
 """
@@ -48,7 +51,7 @@ def fwhm(thetas_deg, h):
     t = np.asarray(thetas_deg, dtype=np.float64)
     h = np.asarray(h, dtype=np.float64)
     k0 = int(np.argmax(h))
-    level = 0.5 * h[k0]
+    level = 0.5 * (h[k0] + np.min(h))
 
     def edge(step):
         k = k0

@@ -16,7 +16,8 @@ import numpy as np
 __all__ = ["lib", "Params", "index_patterns", "refine_orientations", "project_templates",
            "pattern_spectra", "spectrum_floats", "xcf_peak", "xcf_scores", "xcf_subpixel",
            "measure_rotation", "params_default", "version", "RaggedPlan", "Cnn", "cnn_make_batch", "cnn_topk",
-           "index_proposed", "refine_from_match", "pc_map", "PcModel", "LIB_PATH", "EXPORTS"]
+           "index_proposed", "refine_from_match", "pc_map", "PcModel", "capture_range", "LIB_PATH",
+           "EXPORTS"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libebsd_tm.so")
@@ -29,7 +30,7 @@ EXPORTS = ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_index
            "ebsd_ragged_run", "ebsd_ragged_plan_tiles", "ebsd_ragged_plan_destroy", "ebsd_cnn_param_count",
            "ebsd_cnn_create", "ebsd_cnn_destroy", "ebsd_cnn_get_params", "ebsd_cnn_set_params", "ebsd_cnn_input",
            "ebsd_cnn_forward", "ebsd_cnn_gradients", "ebsd_cnn_train_step", "ebsd_cnn_make_batch", "ebsd_cnn_topk",
-           "ebsd_index_proposed", "ebsd_pc_map", "ebsd_refine_from_match")
+           "ebsd_index_proposed", "ebsd_pc_map", "ebsd_refine_from_match", "ebsd_capture_range")
 
 RAGGED_STENCIL, RAGGED_EAGER, RAGGED_NO_AUTOTUNE = 1, 2, 4
 
@@ -92,6 +93,8 @@ def lib():
     L.ebsd_refine_orientations.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, dp(Params), vp, vp, vp, vp]
     L.ebsd_refine_from_match.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, vp, dp(Params), vp, vp, vp, vp]
     L.ebsd_pc_map.argtypes = [dp(PcModel), i64, vp, vp]
+    L.ebsd_capture_range.argtypes = [dp(Master), vp, i64, i32, dp(Geometry), dp(Geometry), vp, i32, dp(Params), vp,
+                                     vp, vp]
     L.ebsd_project_templates.argtypes = [dp(Master), vp, i64, i32, dp(Geometry), vp, vp]
     L.ebsd_pattern_spectra.argtypes = [vp, i64, i32, dp(Params), vp, vp, vp]
     L.ebsd_xcf_peak.argtypes = [vp, vp, vp, vp, i64, i32, dp(Params), vp, vp, vp, vp]
@@ -250,6 +253,22 @@ def pc_map(pc0, d_col, d_row, width, p, col0=0.0, row0=0.0, device="cuda"):
     rc = lib().ebsd_pc_map(ctypes.byref(m), p, _ptr(out) if p > 0 else None, _stream())
     _check(rc, "ebsd_pc_map")
     return out
+
+
+def capture_range(master, q_ref, n, pc_ref, pc_test, theta_deg, prm=None):
+    """Capture curves h float32 [R, 3, T] (axes x, y, z) and their FWHM
+    float64 [R, 3] (degrees) for reference orientations q_ref [R, 4] and
+    ascending angles theta_deg [T] (CUDA float64)."""
+    import torch
+    r, t = q_ref.shape[0], theta_deg.shape[0]
+    h = torch.empty((r, 3, t), dtype=torch.float32, device=q_ref.device)
+    width = torch.empty((r, 3), dtype=torch.float64, device=q_ref.device)
+    rc = lib().ebsd_capture_range(ctypes.byref(_master(master)), _ptr(q_ref, torch.float64, "q_ref"), r, n,
+                                  ctypes.byref(_geo(pc_ref)), ctypes.byref(_geo(pc_test)),
+                                  _ptr(theta_deg, torch.float64, "theta_deg"), t, _params(prm), _ptr(h), _ptr(width),
+                                  _stream())
+    _check(rc, "ebsd_capture_range")
+    return h, width
 
 
 def project_templates(master, q, n, pc, pc_per=None):

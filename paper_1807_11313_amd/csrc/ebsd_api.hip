@@ -520,6 +520,50 @@ int ebsd_refine_from_match(const ebsd_batch* pats, const ebsd_master* mp, const 
   return refine_impl(pats, mp, geo, q_init, match_shift, prm, q_out, peak_h, shift, stream);
 }
 
+int ebsd_capture_range(const ebsd_master* mp, const double* q_ref, int64_t R, int32_t n,
+                       const ebsd_geometry* geo_ref, const ebsd_geometry* geo_test, const double* theta_deg,
+                       int32_t T, const ebsd_params* prm, float* h, double* width, void* stream) {
+  g_last_error.clear();
+  int rc;
+  ebsd_params p;
+  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p)) || (rc = check_master(mp)) ||
+      (rc = check_geometry(geo_ref)) || (rc = check_geometry(geo_test)))
+    return rc;
+  if (R < 0) return fail(EBSD_E_INVALID, "R must be >= 0");
+  if (T < 1) return fail(EBSD_E_INVALID, "T must be >= 1");
+  if (R * 3 * (int64_t)T > 0x7fffffffLL) return fail(EBSD_E_INVALID, "R x 3 x T must fit in int32");
+  if (R == 0) return EBSD_OK;
+  if (!q_ref || !theta_deg || !h || !width) return fail(EBSD_E_INVALID, "null pointer");
+  if (!fft_supported(n) && !window_peak_supported(n, p.max_shift))
+    return fail(EBSD_E_UNSUPPORTED, "at this size the peak needs a shift window (max_shift >= 0)");
+
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  const int64_t K = R * 3 * (int64_t)T;
+  const int64_t sc = spec_complex(n);
+  const int64_t npix = (int64_t)n * n;
+  const FilterParams fp = filter_of(p, n);
+  EBSD_ALLOC(qt, double, 4 * K, ws);
+  EBSD_ALLOC(ref_of, int32_t, K, ws);
+  EBSD_ALLOC(img_r, float, npix * R, ws);
+  EBSD_ALLOC(img_t, float, npix * K, ws);
+  EBSD_ALLOC(spec_r, float2, sc * R, ws);
+  EBSD_ALLOC(spec_t, float2, sc * K, ws);
+  EBSD_ALLOC(s_int, int32_t, 2 * K, ws);
+  EBSD_TRY(launch_capture_orient(q_ref, R, theta_deg, T, qt, ref_of, st), "capture orientations");
+  EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, q_ref, R, nullptr, geo_ref->pcx, geo_ref->pcy, geo_ref->pcz,
+                          img_r, st),
+           "project(references)");
+  EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, qt, K, nullptr, geo_test->pcx, geo_test->pcy, geo_test->pcz,
+                          img_t, st),
+           "project(rotated)");
+  if ((rc = do_spectra(n, img_r, R, fp, spec_r, nullptr, ws, st))) return rc;
+  if ((rc = do_spectra(n, img_t, K, fp, spec_t, nullptr, ws, st))) return rc;
+  if ((rc = do_peak(n, p, spec_r, spec_t, ref_of, nullptr, K, h, s_int, ws, st))) return rc;
+  EBSD_TRY(launch_fwhm(h, R * 3, theta_deg, T, width, st), "fwhm");
+  return EBSD_OK;
+}
+
 int ebsd_pc_map(const ebsd_pc_model* model, int64_t P, double* pc_out, void* stream) {
   g_last_error.clear();
   if (!model) return fail(EBSD_E_INVALID, "null model");

@@ -127,6 +127,12 @@ struct PcModel {
   int64_t width;
 };
 hipError_t launch_pc_map(const PcModel& m, int64_t k, double* out, hipStream_t stream);
+
+// Capture range: rotated test orientations q[(r*3 + a)*nt + k] = q_ref[r] (x)
+// conj(q_a(theta_k)) with ref_of = r, and the FWHM of nc sampled curves.
+hipError_t launch_capture_orient(const double* q_ref, int64_t nr, const double* theta_deg, int nt, double* q,
+                                 int32_t* ref_of, hipStream_t stream);
+hipError_t launch_fwhm(const float* h, int64_t nc, const double* t, int nt, double* width, hipStream_t stream);
 hipError_t launch_update_z(double* q, const double* gamma, int64_t k, hipStream_t stream);
 
 }  // namespace ebsd

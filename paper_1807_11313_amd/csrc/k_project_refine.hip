@@ -523,6 +523,75 @@ __global__ void k_pc_map(PcModel m, int64_t kk, double* __restrict__ out) {
   for (int c = 0; c < 3; ++c) out[3 * i + c] = (m.pc0[c] + a * m.d_col[c]) + b * m.d_row[c];
 }
 
+// Capture-range test orientations: entry (r, a, k) = q_ref[r] (x) conj(q_a(theta_k))
+// (orientation R Q^T for a detector-frame rotation Q about axis a = x, y, z),
+// stored at ((r * 3 + a) * nt + k); ref_of holds r (the reference's index).
+__global__ void k_capture_orient(const double* __restrict__ q_ref, int64_t nr, const double* __restrict__ theta_deg,
+                                 int nt, double* __restrict__ q, int32_t* __restrict__ ref_of) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nr * 3 * nt) return;
+  const int k = (int)(i % nt);
+  const int a = (int)((i / nt) % 3);
+  const int64_t r = i / (3 * (int64_t)nt);
+  const double h = 0.5 * theta_deg[k] * (3.14159265358979323846 / 180.0);
+  const double sh = sin(h);
+  const double cq[4] = {cos(h), a == 0 ? -sh : 0.0, a == 1 ? -sh : 0.0, a == 2 ? -sh : 0.0};
+  double o[4];
+  qmul(q_ref + 4 * r, cq, o);
+  qstore(q + 4 * i, o);
+  ref_of[i] = (int32_t)r;
+}
+
+// Full width at half maximum of each sampled curve above its floor, one
+// thread per curve: level = (largest + smallest sample) / 2; from the first
+// maximum, walk outwards to the first sample below the level on each side
+// and interpolate linearly; a side that stays above reports the end of the
+// sampled range.
+__global__ void k_fwhm(const float* __restrict__ h, int64_t nc, const double* __restrict__ t, int nt,
+                       double* __restrict__ width) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nc) return;
+  const float* c = h + i * nt;
+  int k0 = 0;
+  float lo = c[0];
+  for (int k = 1; k < nt; ++k) {
+    if (c[k] > c[k0]) k0 = k;
+    lo = fminf(lo, c[k]);
+  }
+  const double level = 0.5 * ((double)c[k0] + (double)lo);
+  double e[2];
+  for (int side = 0; side < 2; ++side) {
+    const int step = side ? 1 : -1;
+    int k = k0;
+    e[side] = t[k0];
+    while (k + step >= 0 && k + step < nt) {
+      const double a = c[k], b = c[k + step];
+      if (b < level) {
+        e[side] = t[k] + (t[k + step] - t[k]) * (a - level) / (a - b);
+        break;
+      }
+      k += step;
+      e[side] = t[k];
+    }
+  }
+  width[i] = e[1] - e[0];
+}
+
+hipError_t launch_capture_orient(const double* q_ref, int64_t nr, const double* theta_deg, int nt, double* q,
+                                 int32_t* ref_of, hipStream_t stream) {
+  const int64_t k = nr * 3 * nt;
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_capture_orient, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, stream, q_ref, nr, theta_deg,
+                     nt, q, ref_of);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwhm(const float* h, int64_t nc, const double* t, int nt, double* width, hipStream_t stream) {
+  if (nc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fwhm, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, stream, h, nc, t, nt, width);
+  return hipGetLastError();
+}
+
 hipError_t launch_pc_map(const PcModel& m, int64_t k, double* out, hipStream_t stream) {
   if (k <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_pc_map, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, stream, m, k, out);

@@ -132,3 +132,24 @@ def test_pc_map_and_refine_from_match_argument_errors():
     empty = pkg.Batch(0x1000, 0, 128)
     assert lib.ebsd_refine_from_match(ctypes.byref(empty), ctypes.byref(m), ctypes.byref(g), None, None, None, None,
                                       None, None, None) == 0
+
+
+def test_capture_range_argument_errors():
+    pkg, lib = _lib()
+    m = pkg.Master(0x2000, 256, 256)
+    g = pkg.Geometry(0.5, 0.3, 0.6, None)
+    bad_g = pkg.Geometry(0.5, 0.3, 0.0, None)
+    vp = ctypes.c_void_p
+
+    def call(R=2, n=64, T=5, geo_t=g, q=0x3000, out=0x4000):
+        return lib.ebsd_capture_range(ctypes.byref(m), vp(q) if q else None, R, n, ctypes.byref(g),
+                                      ctypes.byref(geo_t), vp(0x5000), T, None, vp(out) if out else None,
+                                      vp(0x6000), None)
+
+    assert call(n=100) == -4
+    assert call(T=0) == -1 and b"T must be" in lib.ebsd_last_error()
+    assert call(R=-1) == -1
+    assert call(geo_t=bad_g) == -1 and b"pcz" in lib.ebsd_last_error()
+    assert call(q=0) == -1 and call(out=0) == -1
+    assert call(R=1 << 30, T=4) == -1 and b"int32" in lib.ebsd_last_error()
+    assert call(R=0) == 0

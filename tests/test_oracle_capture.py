@@ -19,12 +19,12 @@ def test_fwhm_of_a_triangle_is_exact(wl, wr):
     assert abs(capture.fwhm(T, h) - 0.5 * (wl + wr)) < 1e-12
 
 
-def test_fwhm_of_a_gaussian():
+def test_fwhm_of_a_gaussian_on_a_floor():
+    # level halfway between the peak (1.0) and the floor (0.2): the textbook
+    # width 2 sqrt(2 ln 2) sigma of the Gaussian above its baseline
     sigma = 3.0
     h = 0.2 + 0.8 * np.exp(-T ** 2 / (2 * sigma ** 2))
-    # level = half of the maximum (1.0), i.e. 0.8 exp(-t^2 / 2 s^2) = 0.3
-    want = 2 * sigma * np.sqrt(2 * np.log(0.8 / 0.3))
-    assert abs(capture.fwhm(T, h) - want) < 0.02
+    assert abs(capture.fwhm(T, h) - 2 * sigma * np.sqrt(2 * np.log(2))) < 0.02
 
 
 def test_fwhm_off_centre_peak_and_open_side():
@@ -32,6 +32,7 @@ def test_fwhm_off_centre_peak_and_open_side():
     assert abs(capture.fwhm(T, h) - 2 * 2.0 * np.sqrt(2 * np.log(2))) < 0.02
     # never below half on the right: the width runs to the sampled end
     h2 = np.where(T < 0, np.exp(-T ** 2 / 8.0), 1.0)
+    assert h2.min() < 1e-40
     assert abs(capture.fwhm(T, h2) - (30.0 + 2.0 * np.sqrt(2 * np.log(2)))) < 0.02
 
 
