@@ -108,6 +108,8 @@ def main():
                     help="skip the drifting-pattern-centre map (beam-shift-corrected refinement)")
     ap.add_argument("--drift-steps", type=int, default=3)
     ap.add_argument("--no-capture", action="store_true", help="skip the capture-range (FWHM) sweep")
+    ap.add_argument("--no-so3", action="store_true",
+                    help="skip the equispaced-library sweep (sizes, nearest-neighbour statistics, map at 7 deg)")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the split-precision search on the same map at 256^2")
     ap.add_argument("--precision-patterns", type=int, default=10000)
@@ -257,6 +259,8 @@ def main():
     # the oracle's sample, on the host, before the 128^2 map is released
     cpu_cfg = {"patterns": cfg["patterns"][:3].cpu(), "lib_q": cfg["lib_q"][:400], "master": cfg["master"],
                "pc": cfg["pc"], "pcs": cfg["pcs"][:2], "true_q": cfg["true_q"][:2]}
+    if not args.no_so3:
+        line["so3"] = so3_sweep(tm, pats, master, cfg, pc_per)
     if not args.no_capture:
         line["capture"] = capture_sweep(tm)
     if not args.no_drift:
@@ -398,6 +402,61 @@ def drift_map(tm, patterns, library, steps, sample=1000):
               % (name, res[name]["patterns_per_s"], res[name]["refine_ms"], res[name]["refined_vs_truth_deg_median"],
                  res[name]["within_0.2_deg"]), file=sys.stderr, flush=True)
     res["accuracy_sample"] = "%d map points vs simulated truth" % len(pick)
+    return res
+
+
+def so3_sweep(tm, pats, master, cfg, pc_per, spacings=(10.0, 7.0, 5.0, 3.0), index_spacing=7.0):
+    """Equispaced fundamental-zone libraries (Figure 2 analogue): size,
+    generation time and nearest-neighbour disorientation statistics per
+    spacing; then the map step with the library at the paper's 7 deg in
+    place of the random one."""
+    import numpy as np
+    import torch
+    from oracle import rotations
+
+    res = {"libraries": {}}
+    for sp in spacings:
+        tm.so3_library(sp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        q = tm.so3_library(sp)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ang, _ = tm.nn_disorientation(q)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        a = ang.cpu().numpy()
+        hist, edges = np.histogram(a, bins=np.arange(0.0, a.max() + 0.2, 0.1))
+        res["libraries"]["%g" % sp] = {
+            "orientations": int(q.shape[0]), "generate_ms": (t1 - t0) * 1e3, "nn_ms": (t2 - t1) * 1e3,
+            "nn_pairs_per_s": q.shape[0] ** 2 / (t2 - t1),
+            "nn_deg_max": float(a.max()), "nn_deg_mean": float(a.mean()), "nn_deg_median": float(np.median(a)),
+            "nn_deg_mode": float(edges[int(np.argmax(hist))] + 0.05),
+            "nn_below_0.9_spacing": float(np.mean(a < 0.9 * sp))}
+        print("[bench] so3 %g deg: %d orientations, nn max %.3f mean %.3f deg" % (sp, q.shape[0], a.max(), a.mean()),
+              file=sys.stderr, flush=True)
+    lib = tm.so3_library(index_spacing)
+    P = pats.shape[0]
+
+    def step():
+        r = tm.index_patterns(pats, master, cfg["pc"], lib)
+        return tm.refine_from_match(pats, master, cfg["pc"], r["best_q"], r["shift"], pc_per=pc_per)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    q = out["q"].cpu().numpy()
+    pick = np.linspace(0, P - 1, 500).astype(int)
+    mis = np.rad2deg([rotations.disorientation_q(q[i], cfg["true_q"][i]) for i in pick])
+    res["map_with_library"] = {"spacing_deg": index_spacing, "library": int(lib.shape[0]),
+                               "patterns_per_s": P / dt, "refined_vs_truth_deg_median": float(np.median(mis)),
+                               "refined_vs_truth_deg_p95": float(np.percentile(mis, 95)),
+                               "within_0.2_deg": float(np.mean(mis < 0.2)), "accuracy_sample": "500 map points"}
+    print("[bench] map with the %g deg library (%d): %.0f patterns/s, median %.3f deg, within 0.2 deg %.3f"
+          % (index_spacing, lib.shape[0], P / dt, np.median(mis), np.mean(mis < 0.2)), file=sys.stderr, flush=True)
     return res
 
 

@@ -251,6 +251,41 @@ int ebsd_capture_range(const ebsd_master* mp, const double* q_ref, int64_t R, in
                        const ebsd_geometry* geo_ref, const ebsd_geometry* geo_test, const double* theta_deg,
                        int32_t T, const ebsd_params* prm, float* h, double* width, void* stream);
 
+/*
+ * Equispaced orientation library (section "SO(3) Spacing", Figure 2): an
+ * S^2 x S^1 sampling of SO(3) reduced to the cubic fundamental zone.  For a
+ * spacing d: m = round(pi / d) polar rings theta_i = pi i / m, ring i with
+ * n_i = max(1, round(2 m sin theta_i)) azimuths phi_j = 2 pi j / n_i; the
+ * circle with n_psi = round(2 pi / d) angles psi_k = 2 pi k / n_psi (rounding
+ * half to even); grid point (theta, phi, psi) is the orientation
+ * Rz(phi) Ry(theta) Rz(psi - phi).  A point is kept if no cubic equivalent
+ * has a larger |w| by more than 1e-12; among equivalents tied within 1e-12
+ * only the one whose canonical quaternion (w >= 0; at w = 0 the first
+ * non-zero component positive) is lexicographically smallest is kept.  The
+ * full grid over SO(3) holds 24 x 618.0 points at 10 deg and 24 x 4956 at
+ * 5 deg (the paper's library sizes, 618 and 4958).
+ *   spacing_deg  in [0.5, 90]
+ *   q_out        device float64 [cap][4], the kept points in grid order
+ *                (w >= 0); only the first cap are written (cap = 0 and
+ *                q_out = NULL query the size)
+ *   count        HOST int64: the number of library orientations
+ * Synchronises `stream` (the count is read back); scratch holds the full
+ * grid (32 B per point, 8 pi^2 / d^3 points).
+ */
+int ebsd_so3_library(double spacing_deg, double* q_out, int64_t cap, int64_t* count, void* stream);
+
+/*
+ * Nearest-neighbour disorientation within a set of orientations (Equation 6
+ * with the 24 proper cubic operators; Figure 2): for each orientation, the
+ * smallest disorientation angle to any other member and that member's
+ * index (ties to the smaller index).
+ *   q       device float64 [L][4] unit quaternions; L = 0 or L >= 2
+ *   nn_deg  out: device float64 [L], degrees
+ *   nn_idx  out: device int32 [L]
+ * All pairs are compared (L^2 work).
+ */
+int ebsd_nn_disorientation(const double* q, int64_t L, double* nn_deg, int32_t* nn_idx, void* stream);
+
 /* ---- stage entry points (the same kernels, exposed for stage-by-stage checks) ---- */
 
 /*

@@ -16,8 +16,8 @@ import numpy as np
 __all__ = ["lib", "Params", "index_patterns", "refine_orientations", "project_templates",
            "pattern_spectra", "spectrum_floats", "xcf_peak", "xcf_scores", "xcf_subpixel",
            "measure_rotation", "params_default", "version", "RaggedPlan", "Cnn", "cnn_make_batch", "cnn_topk",
-           "index_proposed", "refine_from_match", "pc_map", "PcModel", "capture_range", "LIB_PATH",
-           "EXPORTS"]
+           "index_proposed", "refine_from_match", "pc_map", "PcModel", "capture_range", "so3_library",
+           "nn_disorientation", "LIB_PATH", "EXPORTS"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libebsd_tm.so")
@@ -30,7 +30,8 @@ EXPORTS = ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_index
            "ebsd_ragged_run", "ebsd_ragged_plan_tiles", "ebsd_ragged_plan_destroy", "ebsd_cnn_param_count",
            "ebsd_cnn_create", "ebsd_cnn_destroy", "ebsd_cnn_get_params", "ebsd_cnn_set_params", "ebsd_cnn_input",
            "ebsd_cnn_forward", "ebsd_cnn_gradients", "ebsd_cnn_train_step", "ebsd_cnn_make_batch", "ebsd_cnn_topk",
-           "ebsd_index_proposed", "ebsd_pc_map", "ebsd_refine_from_match", "ebsd_capture_range")
+           "ebsd_index_proposed", "ebsd_pc_map", "ebsd_refine_from_match", "ebsd_capture_range",
+           "ebsd_so3_library", "ebsd_nn_disorientation")
 
 RAGGED_STENCIL, RAGGED_EAGER, RAGGED_NO_AUTOTUNE = 1, 2, 4
 
@@ -93,6 +94,8 @@ def lib():
     L.ebsd_refine_orientations.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, dp(Params), vp, vp, vp, vp]
     L.ebsd_refine_from_match.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, vp, dp(Params), vp, vp, vp, vp]
     L.ebsd_pc_map.argtypes = [dp(PcModel), i64, vp, vp]
+    L.ebsd_so3_library.argtypes = [ctypes.c_double, vp, i64, dp(i64), vp]
+    L.ebsd_nn_disorientation.argtypes = [vp, i64, vp, vp, vp]
     L.ebsd_capture_range.argtypes = [dp(Master), vp, i64, i32, dp(Geometry), dp(Geometry), vp, i32, dp(Params), vp,
                                      vp, vp]
     L.ebsd_project_templates.argtypes = [dp(Master), vp, i64, i32, dp(Geometry), vp, vp]
@@ -253,6 +256,30 @@ def pc_map(pc0, d_col, d_row, width, p, col0=0.0, row0=0.0, device="cuda"):
     rc = lib().ebsd_pc_map(ctypes.byref(m), p, _ptr(out) if p > 0 else None, _stream())
     _check(rc, "ebsd_pc_map")
     return out
+
+
+def so3_library(spacing_deg, device="cuda"):
+    """Equispaced fundamental-zone orientation library float64 [L, 4]."""
+    import torch
+    count = ctypes.c_int64(0)
+    _check(lib().ebsd_so3_library(float(spacing_deg), None, 0, ctypes.byref(count), _stream()), "ebsd_so3_library")
+    out = torch.empty((max(count.value, 1), 4), dtype=torch.float64, device=device)
+    n = ctypes.c_int64(0)
+    _check(lib().ebsd_so3_library(float(spacing_deg), _ptr(out), count.value, ctypes.byref(n), _stream()),
+           "ebsd_so3_library")
+    return out[:n.value]
+
+
+def nn_disorientation(q):
+    """Nearest-neighbour cubic disorientation (degrees, float64 [L]) and index
+    (int32 [L]) within q [L, 4]."""
+    import torch
+    n = q.shape[0]
+    ang = torch.empty(n, dtype=torch.float64, device=q.device)
+    idx = torch.empty(n, dtype=torch.int32, device=q.device)
+    _check(lib().ebsd_nn_disorientation(_ptr(q, torch.float64, "q"), n, _ptr(ang), _ptr(idx), _stream()),
+           "ebsd_nn_disorientation")
+    return ang, idx
 
 
 def capture_range(master, q_ref, n, pc_ref, pc_test, theta_deg, prm=None):

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libebsd_tm.so")
 SOURCES = ["ebsd_api.hip", "k_spectra_xcf.hip", "k_project_refine.hip", "k_xcf_gemm.hip", "k_grid_peak.hip",
-           "k_spectra256.hip", "ebsd_ragged.hip", "k_cnn.hip", "ebsd_cnn.hip"]
+           "k_spectra256.hip", "ebsd_ragged.hip", "k_cnn.hip", "ebsd_cnn.hip", "k_so3.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

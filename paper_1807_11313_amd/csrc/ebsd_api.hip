@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
@@ -561,6 +562,48 @@ int ebsd_capture_range(const ebsd_master* mp, const double* q_ref, int64_t R, in
   if ((rc = do_spectra(n, img_t, K, fp, spec_t, nullptr, ws, st))) return rc;
   if ((rc = do_peak(n, p, spec_r, spec_t, ref_of, nullptr, K, h, s_int, ws, st))) return rc;
   EBSD_TRY(launch_fwhm(h, R * 3, theta_deg, T, width, st), "fwhm");
+  return EBSD_OK;
+}
+
+int ebsd_so3_library(double spacing_deg, double* q_out, int64_t cap, int64_t* count, void* stream) {
+  g_last_error.clear();
+  if (!count) return fail(EBSD_E_INVALID, "null count");
+  if (!(spacing_deg >= 0.5 && spacing_deg <= 90.0)) return fail(EBSD_E_INVALID, "spacing must be in [0.5, 90] deg");
+  if (cap < 0) return fail(EBSD_E_INVALID, "cap must be >= 0");
+  if (cap > 0 && !q_out) return fail(EBSD_E_INVALID, "null q_out");
+  // ring and circle counts (round half to even, as the grid is defined)
+  const double d = spacing_deg * (M_PI / 180.0);
+  const int m = std::max(1, (int)std::nearbyint(M_PI / d));
+  const int n_psi = std::max(1, (int)std::nearbyint(2.0 * M_PI / d));
+  std::vector<int64_t> off((size_t)m + 2, 0);
+  for (int i = 0; i <= m; ++i) {
+    const double theta = M_PI * i / m;
+    off[(size_t)i + 1] = off[(size_t)i] + std::max<int64_t>(1, (int64_t)std::nearbyint((2.0 * m) * std::sin(theta)));
+  }
+  const int64_t n_all = off[(size_t)m + 1] * n_psi;
+  hipStream_t st = (hipStream_t)stream;
+  {
+    Scratch ws(st);
+    EBSD_ALLOC(ring_off, int64_t, m + 2, ws);
+    EBSD_ALLOC(q_all, double, 4 * n_all, ws);
+    EBSD_ALLOC(keep, unsigned char, n_all, ws);
+    EBSD_ALLOC(dcount, int64_t, 1, ws);
+    EBSD_TRY(hipMemcpyAsync(ring_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice, st),
+             "ring table");
+    EBSD_TRY(launch_so3_library(ring_off, m, n_psi, n_all, q_all, keep, q_out, cap, dcount, st), "so3 library");
+    EBSD_TRY(hipMemcpyAsync(count, dcount, sizeof(int64_t), hipMemcpyDeviceToHost, st), "count");
+    EBSD_TRY(hipStreamSynchronize(st), "synchronise");
+  }
+  return EBSD_OK;
+}
+
+int ebsd_nn_disorientation(const double* q, int64_t L, double* nn_deg, int32_t* nn_idx, void* stream) {
+  g_last_error.clear();
+  if (L < 0 || L == 1) return fail(EBSD_E_INVALID, "L must be 0 or at least 2");
+  if (L > 0x7fffffffLL) return fail(EBSD_E_INVALID, "L must fit in int32");
+  if (L == 0) return EBSD_OK;
+  if (!q || !nn_deg || !nn_idx) return fail(EBSD_E_INVALID, "null pointer");
+  EBSD_TRY(launch_nn_disorientation(q, L, nn_deg, nn_idx, (hipStream_t)stream), "nn disorientation");
   return EBSD_OK;
 }
 

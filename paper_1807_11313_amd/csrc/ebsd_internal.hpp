@@ -133,6 +133,17 @@ hipError_t launch_pc_map(const PcModel& m, int64_t k, double* out, hipStream_t s
 hipError_t launch_capture_orient(const double* q_ref, int64_t nr, const double* theta_deg, int nt, double* q,
                                  int32_t* ref_of, hipStream_t stream);
 hipError_t launch_fwhm(const float* h, int64_t nc, const double* t, int nt, double* width, hipStream_t stream);
+
+// Equispaced orientation library: the S^2 x S^1 grid (ring_off[m + 2]: first
+// azimuth index of each of the m + 1 polar rings, then the total), reduced
+// to the cubic fundamental zone and compacted in grid order into q_out (at
+// most cap entries); *count (device) receives the full count.
+hipError_t launch_so3_library(const int64_t* ring_off, int m, int n_psi, int64_t n_all, double* q_all,
+                              unsigned char* keep, double* q_out, int64_t cap, int64_t* count, hipStream_t stream);
+// Nearest-neighbour cubic disorientation (degrees) and index of each of n
+// orientations.
+hipError_t launch_nn_disorientation(const double* q, int64_t n, double* nn_deg, int32_t* nn_idx,
+                                    hipStream_t stream);
 hipError_t launch_update_z(double* q, const double* gamma, int64_t k, hipStream_t stream);
 
 }  // namespace ebsd

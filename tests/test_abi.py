@@ -153,3 +153,18 @@ def test_capture_range_argument_errors():
     assert call(q=0) == -1 and call(out=0) == -1
     assert call(R=1 << 30, T=4) == -1 and b"int32" in lib.ebsd_last_error()
     assert call(R=0) == 0
+
+
+def test_so3_library_and_nn_argument_errors():
+    _, lib = _lib()
+    vp = ctypes.c_void_p
+    cnt = ctypes.c_int64(-7)
+    assert lib.ebsd_so3_library(0.1, None, 0, ctypes.byref(cnt), None) == -1 and b"spacing" in lib.ebsd_last_error()
+    assert lib.ebsd_so3_library(float("nan"), None, 0, ctypes.byref(cnt), None) == -1
+    assert lib.ebsd_so3_library(10.0, None, 5, ctypes.byref(cnt), None) == -1 and b"q_out" in lib.ebsd_last_error()
+    assert lib.ebsd_so3_library(10.0, None, -1, ctypes.byref(cnt), None) == -1
+    assert lib.ebsd_so3_library(10.0, None, 0, None, None) == -1
+    assert cnt.value == -7
+    assert lib.ebsd_nn_disorientation(vp(0x1000), 1, vp(0x2000), vp(0x3000), None) == -1
+    assert lib.ebsd_nn_disorientation(vp(0x1000), 5, None, vp(0x3000), None) == -1
+    assert lib.ebsd_nn_disorientation(None, 0, None, None, None) == 0
