@@ -2,10 +2,11 @@
 4,000 library templates searched over all shifts, and the same map at 256^2
 searched by the FP16 hi + lo DFT-GEMM over |s| <= 15 px; the ragged batch of
 20,000 patterns against 8,000 templates with its stencil; the learned
-proposal trained on 200,000 patterns and run on 50,000: the launch
-configurations the bench times), checked on sampled patterns that the FP64
-oracle indexes and refines one by one from the same inputs (the proposal
-against the exhaustive search).
+proposal trained on 200,000 patterns and run on 50,000; the 3 deg
+equispaced library with its nearest neighbours and the capture-range sweep:
+the launch configurations the bench times), checked on sampled patterns
+that the FP64 oracle indexes and refines one by one from the same inputs
+(the proposal against the exhaustive search).
 
 * Library index: the oracle's, bit-exact outside the near-tie rule
   (tau_tie = 2e-4); inside it the GPU's pick scores within tau_tie of the
@@ -219,3 +220,44 @@ def test_learned_proposal_full_size():
     print("[gpu]   refined pruned vs exhaustive: %.4f within 0.1 deg" % np.mean(d < 0.1), flush=True)
     assert np.mean(d < 0.1) >= 0.99
     net.close()
+
+
+def test_so3_library_and_neighbours_at_bench_size():
+    # the bench's finest library (3 deg, 22,946 orientations): the whole
+    # library against the oracle's, and the all-pairs nearest neighbours of
+    # 24 sampled members against the oracle's disorientations to every member
+    from oracle import so3grid
+    banner("so3 library at 3 deg and sampled nearest neighbours")
+    t = tm()
+    q = t.so3_library(3.0)
+    got = host(q)
+    want = so3grid.library(3.0)
+    assert got.shape == want.shape and np.max(np.abs(got - want)) < 1e-12
+    ang, idx = t.nn_disorientation(q)
+    ang, idx = host(ang), host(idx)
+    r = rotations.quat_to_matrix(want)
+    ops = rotations.cubic_operators()
+    for a in np.linspace(0, len(want) - 1, 24).astype(int):
+        d = np.rad2deg(rotations.disorientation(r[a][None], r, ops))
+        d[a] = np.inf
+        assert abs(ang[a] - d.min()) < 1e-9 and abs(d[idx[a]] - d.min()) < 1e-9
+
+
+def test_capture_range_at_bench_size():
+    # the bench's sweep shape (8 references x 3 axes x 121 angles over +-30
+    # deg at 160^2); one full curve per axis against the oracle
+    from fixtures import band_master, random_quats
+    from oracle import capture
+    banner("capture range 8 x 3 x 121 at 160^2, sampled curves")
+    t = tm()
+    master = band_master()
+    q_ref = random_quats(np.random.default_rng(77), 8)
+    th = np.arange(-30.0, 30.0 + 1e-9, 0.5)
+    pc = (0.5, 0.3, 0.6)
+    h, w = t.capture_range(dev(master), dev(q_ref), 160, pc, pc, dev(th))
+    h, w = host(h), host(w)
+    for r, a in ((0, 0), (3, 1), (7, 2)):
+        ref = capture.capture_curve(master, rotations.quat_to_matrix(q_ref[r]), "xyz"[a], th, 160, pc, pc,
+                                    oracle.Params())
+        assert np.max(np.abs(h[r, a] - ref)) < 1e-4
+        assert abs(w[r, a] - capture.fwhm(th, ref)) < 0.02
