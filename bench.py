@@ -48,14 +48,17 @@ def gemm_pair_flops(n, s, precision):
 
 
 def kernel_source_hash(prof):
-    """sha256 prefix of the profiled kernel's definition (from its marker to
-    the closing brace at column 0) and of the headers it includes: the byte
-    counters are used only while these are unchanged."""
+    """sha256 prefix of the profiled kernel's definition and of its launcher
+    (each from its marker to the closing brace at column 0; the launcher
+    sets the template chunk, which sets the traffic) and of the headers it
+    includes: the byte counters are used only while these are unchanged."""
     import hashlib
     src = open(os.path.join(ROOT, prof["source"])).read()
-    i = src.index(prof["kernel_marker"])
-    j = src.index("\n}\n", i) + 3
-    h = hashlib.sha256(src[i:j].encode())
+    h = hashlib.sha256()
+    for marker in [prof["kernel_marker"]] + ([prof["launcher_marker"]] if "launcher_marker" in prof else []):
+        i = src.index(marker)
+        j = src.index("\n}\n", i) + 3
+        h.update(src[i:j].encode())
     for hdr in prof["headers"]:
         h.update(open(os.path.join(ROOT, hdr), "rb").read())
     return h.hexdigest()[:16]

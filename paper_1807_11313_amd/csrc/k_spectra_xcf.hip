@@ -1026,10 +1026,13 @@ hipError_t launch_spectra_gather(int n, const float* imgs, const int64_t* img_of
   return hipGetLastError();
 }
 
+#ifndef EBSD_SEARCH_LCHUNK
+#define EBSD_SEARCH_LCHUNK 32
+#endif
 hipError_t launch_xcf_scores(int n, const float2* spec_p, int64_t p, const float2* spec_l,
                              int64_t l, int max_shift, float* scores, hipStream_t stream) {
   if (p <= 0 || l <= 0) return hipSuccess;
-  const int lchunk = 32;
+  const int lchunk = EBSD_SEARCH_LCHUNK;
   const int64_t nchunk = (l + lchunk - 1) / lchunk;
   // patterns per dispatch so that blocks x threads stays below 2^31
   const int64_t pmax = (kMaxItems / 1024 - 8) / nchunk;
