@@ -253,9 +253,15 @@ static hipError_t grid_vj(int n, int bnd, const float2* spec_p, const float2* sp
                        (const cf*)spec_p, (const cf*)spec_l, pi, li, centre, kappa, m, int_keys,                    \
                        (const cf*)tab, h, s, si);                                                                   \
   } while (0)
+  // rows per thread rounded up as little as possible: every extra row is a
+  // full set of FMAs on zeros (the sub-pixel grid, 151 rows at kappa = 100,
+  // takes 5 on 32 x 32 threads)
   if (mb <= 1) EBSD_GRID(1);
   else if (mb <= 2) EBSD_GRID(2);
+  else if (mb <= 3) EBSD_GRID(3);
   else if (mb <= 4) EBSD_GRID(4);
+  else if (mb <= 5) EBSD_GRID(5);
+  else if (mb <= 6) EBSD_GRID(6);
   else if (mb <= 7) EBSD_GRID(7);
   else if constexpr (TB == 16) {  // 32 x 7 rows already cover what 16 x 13 do
     if (mb <= 10) EBSD_GRID(10);
