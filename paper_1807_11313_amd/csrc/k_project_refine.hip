@@ -64,7 +64,19 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ maste
   float wv[4], wu[4];
   keys4(v - v0f, wv);
   keys4(u - u0f, wu);
-  const int v0 = (int)v0f, u0 = (int)u0f;
+  // phi is in [0, 2 pi] (rounding included), so u0 is in [0, mw]; the clamp
+  // only guards the reads against a non-finite orientation.  Each periodic
+  // azimuth tap index is then in [-1, mw + 2] and one conditional wrap each
+  // way gives the same column as a modulo (mw >= 4)
+  const int v0 = (int)v0f, u0 = min(max((int)u0f, 0), mw);
+  int col[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    int c = u0 + b - 1;
+    c += c < 0 ? mw : 0;
+    c -= c >= mw ? mw : 0;
+    col[b] = c;
+  }
   float acc = 0.0f;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -72,11 +84,7 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ maste
     const float* mrow = master + (int64_t)row * mw;
     float ra = 0.0f;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int col = (u0 + b - 1) % mw;
-      if (col < 0) col += mw;
-      ra = __fmaf_rn(wu[b], mrow[col], ra);
-    }
+    for (int b = 0; b < 4; ++b) ra = __fmaf_rn(wu[b], mrow[col[b]], ra);
     acc = __fmaf_rn(wv[a], ra, acc);
   }
   out[k * (int64_t)n * n + pix] = acc;
