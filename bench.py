@@ -111,6 +111,8 @@ def main():
                     help="skip the drifting-pattern-centre map (beam-shift-corrected refinement)")
     ap.add_argument("--drift-steps", type=int, default=3)
     ap.add_argument("--no-capture", action="store_true", help="skip the capture-range (FWHM) sweep")
+    ap.add_argument("--no-search-kernels", action="store_true",
+                    help="skip timing each size's search kernel alone (4,096 x 4,096 random spectra)")
     ap.add_argument("--no-so3", action="store_true",
                     help="skip the equispaced-library sweep (sizes, nearest-neighbour statistics, map at 7 deg)")
     ap.add_argument("--no-precision", action="store_true",
@@ -262,6 +264,8 @@ def main():
     # the oracle's sample, on the host, before the 128^2 map is released
     cpu_cfg = {"patterns": cfg["patterns"][:3].cpu(), "lib_q": cfg["lib_q"][:400], "master": cfg["master"],
                "pc": cfg["pc"], "pcs": cfg["pcs"][:2], "true_q": cfg["true_q"][:2]}
+    if not args.no_search_kernels:
+        line["search_kernels"] = search_kernels(tm)
     if not args.no_so3:
         line["so3"] = so3_sweep(tm, pats, master, cfg, pc_per)
     if not args.no_capture:
@@ -405,6 +409,38 @@ def drift_map(tm, patterns, library, steps, sample=1000):
               % (name, res[name]["patterns_per_s"], res[name]["refine_ms"], res[name]["refined_vs_truth_deg_median"],
                  res[name]["within_0.2_deg"]), file=sys.stderr, flush=True)
     res["accuracy_sample"] = "%d map points vs simulated truth" % len(pick)
+    return res
+
+
+def search_kernels(tm, sizes=(64, 96, 128, 160), count=4096, reps=2):
+    """The FFT-form search kernel of each size alone: count x count random
+    band spectra, every cyclic shift, HIP-event timing of the kernel
+    (pairs/s and nominal TFLOP/s against the FP32 vector peak)."""
+    import torch
+
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(1)
+    res = {"workload": "%d x %d random band spectra per size, all shifts" % (count, count)}
+    for n in sizes:
+        f = tm.spectrum_floats(n)
+        sp = torch.randn((count, f), generator=g, device="cuda:0") * 1e-2
+        sl = torch.randn((count, f), generator=g, device="cuda:0") * 1e-2
+        tm.xcf_scores(sp, sl, n)
+        torch.cuda.synchronize()
+        tm.timing_read()
+        tm.timing_enable(True)
+        for _ in range(reps):
+            tm.xcf_scores(sp, sl, n)
+        torch.cuda.synchronize()
+        tm.timing_enable(False)
+        ms, c = tm.timing_read()
+        ms /= max(c, 1)
+        pairs = count * count / (ms / 1e3)
+        res[str(n)] = {"ms": ms, "pairs_per_s": pairs, "tflops_nominal": pairs * pair_flops(n) / 1e12,
+                       "frac_of_fp32_vector_peak": pairs * pair_flops(n) / PEAK_FP32_VALU}
+        del sp, sl
+    print("[bench] search kernels alone: " + ", ".join("%s: %.3g pairs/s" % (n, res[str(n)]["pairs_per_s"])
+                                                        for n in sizes), file=sys.stderr, flush=True)
     return res
 
 
