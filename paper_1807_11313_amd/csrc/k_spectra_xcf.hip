@@ -544,7 +544,14 @@ struct WLay {
   static constexpr int AOFF = SEPA ? XN : 0;
   static constexpr int YOFF = SEPA ? 0 : (NQB > 1 ? AN : 0);
   static constexpr int cmx(int a, int b) { return a > b ? a : b; }
-  static constexpr int LDSN = cmx(cmx(XN, AOFF + AN), YOFF + YN);
+  // templates per wave: at 64 the band columns (25) and packed row pairs
+  // (32) of one template fill half a wave, so each 32-lane half takes its
+  // own template, with its own LDS region
+  static constexpr int TPW = N == 64 ? 2 : 1;
+  static constexpr int SUB = 64 / TPW;                  // lanes per template
+  static constexpr int LDSH = cmx(cmx(XN, AOFF + AN), YOFF + YN);
+  static constexpr int LDSN = LDSH * TPW;
+  static_assert(NV <= SUB && QB <= SUB, "a template's columns and row block fit its lanes");
   static constexpr int NT = R2 * 64;
   // waves per SIMD the register allocation must allow (occupancy beats the
   // few spills it costs): two 8-wave blocks per CU at 96 (128 VGPRs), at 64
@@ -568,13 +575,19 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
   using L = WLay<N>;
   constexpr int R1 = L::R1, R2 = L::R2, B = L::B, NV = L::NV, SPEC = L::SPEC, AV = L::AV;
   constexpr int NQ = L::NQ, QB = L::QB, NQB = L::NQB, JC = L::JC;
+  constexpr int TPW = L::TPW, SUB = L::SUB;
   __shared__ cf lds[L::LDSN];
-  static_assert((R1 * R2 - 1) * NV + 63 < L::LDSN, "phase-2 reads of lanes past the band stay in LDS");
-  __shared__ float red[R2];
+  static_assert((R1 * R2 - 1) * NV + SUB - 1 < L::LDSH, "phase-2 reads of lanes past the band stay in LDS");
+  __shared__ float red[R2 * TPW];
   __shared__ int item;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // this lane's template (half of the wave at TPW = 2), lane within it, and
+  // the template's LDS region
+  const int half = TPW == 2 ? lane / SUB : 0;
+  const int sl = TPW == 2 ? lane - half * SUB : lane;
+  cf* const lt = lds + half * L::LDSH;
   int64_t g;
   if constexpr (PERSIST) {
     if (tid == 0) item = atomicAdd(queue, 1);
@@ -585,7 +598,7 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
     g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
   }
   if (g >= nblk) return;
-  const bool vlane = lane < NV;
+  const bool vlane = sl < NV;
 
   while (g < nblk) {
     const int64_t chunk = g / np, p = g - chunk * np;
@@ -596,11 +609,15 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
     for (int a = 0; a < R1; ++a) {
       const int u = R2 * a + wave;
       const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : -1);
-      ev[a] = (kk >= 0 && vlane) ? E[kk * NV + lane] : cf{0.f, 0.f};
+      ev[a] = (kk >= 0 && vlane) ? E[kk * NV + sl] : cf{0.f, 0.f};
     }
     const int64_t l0 = chunk * lchunk;
     const int64_t l1 = l0 + lchunk < nl ? l0 + lchunk : nl;
-    for (int64_t l = l0; l < l1; ++l) {
+    for (int64_t l = l0; l < l1; l += TPW) {
+      // at TPW = 2 the halves take templates l and l + 1; past the end of the
+      // chunk both take l (the second result is not written)
+      const bool two = TPW == 2 && l + 1 < l1;
+      const int th = two ? half : 0;
       const cf* T = spec_l + l * SPEC;
       // phase 1: wave b, lane v: radix R1 over u = R2 a + b, twiddle.  The
       // cached pattern values are zero outside the band, so every lane loads
@@ -608,8 +625,8 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
       // (all R1 loads in flight together) and the products stay zero there
       {
         cf x[R1];
-        const unsigned voff = (unsigned)(vlane ? lane : NV - 1) * (unsigned)sizeof(cf);
-        const __amdgpu_buffer_rsrc_t Tr = spectrum_rsrc(T, SPEC * (int)sizeof(cf));
+        const unsigned voff = (unsigned)(th * SPEC + (vlane ? sl : NV - 1)) * (unsigned)sizeof(cf);
+        const __amdgpu_buffer_rsrc_t Tr = spectrum_rsrc(T, (two ? 2 : 1) * SPEC * (int)sizeof(cf));
 #pragma unroll
         for (int a = 0; a < R1; ++a) {
           if (L::ZGAP && ((L::GAP >> a) & 1)) continue;  // neither loaded nor added
@@ -627,7 +644,7 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
         for (int c = 1; c < R1; ++c) x[c] = cmul(x[c], root_of<N>((wave * c) % N));
         if (vlane) {
 #pragma unroll
-          for (int c = 0; c < R1; ++c) lds[(c * R2 + wave) * NV + lane] = x[c];
+          for (int c = 0; c < R1; ++c) lt[(c * R2 + wave) * NV + sl] = x[c];
         }
       }
       __syncthreads();
@@ -639,11 +656,11 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
           if (c < R1) {
             cf h[R2];
 #pragma unroll
-            for (int b = 0; b < R2; ++b) h[b] = lds[(c * R2 + b) * NV + lane];  // lanes >= NV: never stored
+            for (int b = 0; b < R2; ++b) h[b] = lt[(c * R2 + b) * NV + sl];  // lanes >= NV: never stored
             DFT<R2, 1>::run(h);
             if (vlane) {
 #pragma unroll
-              for (int d = 0; d < R2; ++d) lds[L::AOFF + lane * AV + c + R1 * d] = h[d];
+              for (int d = 0; d < R2; ++d) lt[L::AOFF + sl * AV + c + R1 * d] = h[d];
             }
           }
         }
@@ -654,7 +671,7 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
           const int c = wave + R2 * j;
           if (c < R1) {
 #pragma unroll
-            for (int b = 0; b < R2; ++b) h[j][b] = lds[(c * R2 + b) * NV + lane];  // lanes >= NV: in-bounds, never stored
+            for (int b = 0; b < R2; ++b) h[j][b] = lt[(c * R2 + b) * NV + sl];  // lanes >= NV: in-bounds, never stored
             DFT<R2, 1>::run(h[j]);
           }
         }
@@ -665,18 +682,18 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
             const int c = wave + R2 * j;
             if (c < R1) {
 #pragma unroll
-              for (int d = 0; d < R2; ++d) lds[lane * AV + c + R1 * d] = h[j][d];
+              for (int d = 0; d < R2; ++d) lt[sl * AV + c + R1 * d] = h[j][d];
             }
           }
         }
       }
       __syncthreads();
-      const cf* A = lds + L::AOFF;
+      const cf* A = lt + L::AOFF;
       float m = -INFINITY;
 #pragma unroll
       for (int qb = 0; qb < NQB; ++qb) {
-        const int q = qb * QB + lane;
-        const bool qlane = lane < QB && q < NQ;
+        const int q = qb * QB + sl;
+        const bool qlane = sl < QB && q < NQ;
         const float mq0 = abs(signed_shift(q, N)) <= max_shift ? 0.f : -INFINITY;
         const float mq1 = abs(signed_shift(q + NQ, N)) <= max_shift ? 0.f : -INFINITY;
         // phase 3: wave b, lane q: radix R1 over v = R2 a + b of the packed rows (q, q + N/2)
@@ -704,9 +721,9 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
 #pragma unroll
         for (int c = 1; c < R1; ++c) sv[c] = cmul(sv[c], root_of<N>((wave * c) % N));
         if constexpr (!L::SEPA && NQB == 1) __syncthreads();  // Y overwrites A, which other waves may still read
-        if (lane < QB) {
+        if (sl < QB) {
 #pragma unroll
-          for (int c = 0; c < R1; ++c) lds[L::YOFF + (c * R2 + wave) * QB + lane] = sv[c];
+          for (int c = 0; c < R1; ++c) lt[L::YOFF + (c * R2 + wave) * QB + sl] = sv[c];
         }
         __syncthreads();
         // phase 4: wave takes c = wave + R2 j: radix R2 over b -> x = c + R1 d
@@ -716,7 +733,7 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
           if (c < R1) {
             cf z[R2];
 #pragma unroll
-            for (int b = 0; b < R2; ++b) z[b] = lds[L::YOFF + (c * R2 + b) * QB + (lane < QB ? lane : 0)];
+            for (int b = 0; b < R2; ++b) z[b] = lt[L::YOFF + (c * R2 + b) * QB + (sl < QB ? sl : 0)];
             DFT<R2, 1>::run(z);
             if (qlane) {
 #pragma unroll
@@ -734,14 +751,26 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
         }
         if (qb + 1 < NQB) __syncthreads();
       }
-      m = wave_max(m);
-      if (lane == 0) red[wave] = m;
+      if constexpr (TPW == 2) {
+#pragma unroll
+        for (int off = SUB / 2; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));  // within the half
+        if (sl == 0) red[wave * 2 + half] = m;
+      } else {
+        m = wave_max(m);
+        if (lane == 0) red[wave] = m;
+      }
       __syncthreads();
       if (tid == 0) {
         float r = red[0];
 #pragma unroll
-        for (int w = 1; w < R2; ++w) r = fmaxf(r, red[w]);
+        for (int w = 1; w < R2; ++w) r = fmaxf(r, red[w * TPW]);
         scores[p * nl + l] = r;
+        if (two) {
+          float r1 = red[1];
+#pragma unroll
+          for (int w = 1; w < R2; ++w) r1 = fmaxf(r1, red[w * TPW + 1]);
+          scores[p * nl + l + 1] = r1;
+        }
       }
     }
     if constexpr (!PERSIST) break;
