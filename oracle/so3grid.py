@@ -4,7 +4,7 @@
 Section "SO(3) Spacing" and Figure 2: the library is an S^2 x S^1 sampling of
 SO(3) reduced to the cubic fundamental zone; the sphere is split into
 equidistant polar rings with as many azimuths on each ring as its
-circumference needs, the circle linearly.  Its quality is judged by the
+circumference needs, the circle linearly.  Its quality is measured by the
 disorientation (Equation 6) from each library orientation to its nearest
 neighbour in the library.
 

@@ -167,7 +167,7 @@ def test_learned_proposal_full_size():
     # patterns at 128^2 searched exhaustively and pruned (top 32 + fallback
     # below tau = 1st percentile of the exhaustive peak height on 10,000
     # validation patterns).  The exhaustive search, pinned to the oracle by
-    # the tests above, is the judge.
+    # the tests above, is the reference.
     from fixtures import band_master, random_fz_quats, random_quats, simulate_patterns
     banner("full-size learned proposal: training 200,000 x 2 epochs, 50,000 test patterns")
     t = tm()

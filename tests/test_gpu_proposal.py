@@ -2,7 +2,7 @@
 threshold) against the exhaustive search it replaces, and what the trained
 network gains over the same pruning without training.
 
-The exhaustive FP32 search is the judge: where the exhaustive top-2 gap
+The exhaustive FP32 search is the reference: where the exhaustive top-2 gap
 exceeds tau_tie the pruned search must pick the same template for at least
 95 % of the patterns (and for every pattern that fell back), with the same
 peak height and shift wherever it picks the same template.  The gain is the number of
