@@ -134,7 +134,7 @@ def main():
                     help="also run one elementwise copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the path has no multi-GPU form in this build "
+        print("bench.py runs on one GPU only: the library has no multi-GPU form "
               "(patterns would be split across GPUs with the library replicated)", file=sys.stderr)
         sys.exit(2)
 

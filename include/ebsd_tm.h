@@ -65,7 +65,7 @@ extern "C" {
 #define EBSD_E_INVALID (-1)     /* null pointer, bad size or parameter      */
 #define EBSD_E_NOMEM (-2)       /* device allocation failed                 */
 #define EBSD_E_DEVICE (-3)      /* HIP runtime or launch error              */
-#define EBSD_E_UNSUPPORTED (-4) /* valid request this build does not serve  */
+#define EBSD_E_UNSUPPORTED (-4) /* valid request the library does not serve */
 
 /* Arithmetic of the correlation search (the library ranking):
  *   FP32    FP32 FFT form (every cyclic shift, or a window)

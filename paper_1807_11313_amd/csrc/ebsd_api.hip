@@ -39,7 +39,7 @@ int fail_hip(hipError_t e, const char* where) {
 
 // Scratch allocated in stream order on the caller's stream and released in
 // stream order when the call returns; the device memory pool keeps it for
-// the next call, so repeated calls do not reach the driver.
+// the next call, so repeated calls do not reach the kernel-mode allocator.
 class Scratch {
  public:
   explicit Scratch(hipStream_t s) : stream_(s) {}
