@@ -805,8 +805,9 @@ def learned_proposal(tm, library, n_train, epochs, n_test, k=32, bsz=256, n=128)
     x_test = tm.Cnn.input(test[:bsz * 8])
     _, t_fwd = timed(lambda: net.forward(x_test), reps=5)
     # both picks refined the same way (the library pick is only the start)
-    rf_ex, t_rf = timed(lambda: tm.refine_orientations(test, master, pc, ex["best_q"], pc_per=pc_per), reps=1)
-    rf_pr, _ = timed(lambda: tm.refine_orientations(test, master, pc, pr["best_q"], pc_per=pc_per), reps=1)
+    rf_ex, t_rf = timed(lambda: tm.refine_from_match(test, master, pc, ex["best_q"], ex["shift"], pc_per=pc_per),
+                        reps=1)
+    rf_pr, _ = timed(lambda: tm.refine_from_match(test, master, pc, pr["best_q"], pr["shift"], pc_per=pc_per), reps=1)
     b_ex, b_pr = ex["best_idx"].cpu().numpy(), pr["best_idx"].cpu().numpy()
     fb = pr["fallback"].cpu().numpy().astype(bool)
     q_ex, q_pr = rf_ex["q"].cpu().numpy(), rf_pr["q"].cpu().numpy()
