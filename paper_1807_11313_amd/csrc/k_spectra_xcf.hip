@@ -169,14 +169,6 @@ __device__ __forceinline__ void xcf_core(const cf* __restrict__ E, const cf* __r
   }
 }
 
-struct MaxEpi {
-  float m;
-  int n, s;
-  __device__ __forceinline__ void operator()(int y, int x, float v) {
-    if (s < 0 || (abs(signed_shift(y, n)) <= s && abs(signed_shift(x, n)) <= s)) m = fmaxf(m, v);
-  }
-};
-
 struct ArgmaxEpi {
   float m;
   int i, n, s;
@@ -187,68 +179,6 @@ struct ArgmaxEpi {
       argmax_merge(m, i, v, y * n + x);
   }
 };
-
-template <int NT>
-__device__ __forceinline__ float block_max(float v, float* red, int tid) {
-  v = wave_max(v);
-  if ((tid & 63) == 0) red[tid >> 6] = v;
-  __syncthreads();
-  float r = red[0];
-#pragma unroll
-  for (int w = 1; w < NT / 64; ++w) r = fmaxf(r, red[w]);
-  __syncthreads();
-  return r;
-}
-
-// Scores of every pattern against a chunk of templates.  Blocks are
-// numbered so that consecutive blocks on one XCD (blocks are dealt to the 8
-// XCDs round robin) share a template chunk, which then stays in that XCD's L2.
-//
-// PERSIST: the grid is sized to the resident capacity and every block takes
-// work items (pattern, template chunk) from the device counter *queue (zero
-// at launch) until all nblk items are taken; items are numbered chunk-major
-// as the block numbers are, so concurrently running blocks share a chunk.
-template <int N, int NT, bool PERSIST>
-__global__ __launch_bounds__(NT) void k_xcf_scores(const cf* __restrict__ spec_p, int64_t np,
-                                                   const cf* __restrict__ spec_l, int64_t nl,
-                                                   int lchunk, int64_t nblk, int max_shift,
-                                                   float* __restrict__ scores, int* __restrict__ queue) {
-  using L = Lay<N>;
-  __shared__ cf lds[L::LDS];
-  __shared__ cf tw[N];
-  __shared__ float red[NT / 64];
-  __shared__ int item;
-  const int tid = threadIdx.x;
-  int64_t g;
-  if constexpr (PERSIST) {
-    if (tid == 0) item = atomicAdd(queue, 1);
-    __syncthreads();
-    g = item;
-  } else {
-    const int64_t per = (nblk + 7) / 8;
-    g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  }
-  if (g >= nblk) return;
-  load_roots<N, NT>(tw, tid);
-  __syncthreads();
-  while (g < nblk) {
-    const int64_t chunk = g / np, p = g - chunk * np;
-    const cf* E = spec_p + p * L::SPEC;
-    const int64_t l0 = chunk * lchunk;
-    const int64_t l1 = l0 + lchunk < nl ? l0 + lchunk : nl;
-    for (int64_t l = l0; l < l1; ++l) {
-      MaxEpi epi{-INFINITY, N, max_shift};
-      xcf_core<N, NT>(E, spec_l + l * L::SPEC, lds, tw, tid, epi);
-      const float m = block_max<NT>(epi.m, red, tid);
-      if (tid == 0) scores[p * nl + l] = m;
-    }
-    if constexpr (!PERSIST) break;
-    __syncthreads();
-    if (tid == 0) item = atomicAdd(queue, 1);
-    __syncthreads();
-    g = item;
-  }
-}
 
 template <int N, int NT>
 __global__ __launch_bounds__(NT) void k_xcf_peak(const cf* __restrict__ spec_p, const cf* __restrict__ spec_l,
