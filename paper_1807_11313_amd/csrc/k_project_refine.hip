@@ -191,6 +191,48 @@ __global__ __launch_bounds__(256) void k_logpolar(const float* __restrict__ imgs
   }
 }
 
+// Maximum of the trigonometric interpolant of the normalised eta
+// correlation over D_int + a / kappa, |a| <= ceil(0.75 kappa), from its
+// transform C(q), q in [0, n_eta / 2] (ties to the smallest a); thread 0
+// writes gamma = 2 pi D / n_eta.  A block of 256 threads; rv / ri are
+// 4-entry shared scratch.
+__device__ __forceinline__ void eta_interpolate(const float* cqr, const float* cqi, int n_eta, int d_int,
+                                                int kappa, float* rv, int* ri, double* gamma_out) {
+  const int tid = threadIdx.x;
+  const int m = (3 * kappa + 3) / 4;
+  const int kn = kappa * n_eta;
+  float best = -INFINITY;
+  int besta = 0x7fffffff;
+  for (int a = -m + tid; a <= m; a += 256) {
+    const int ph = kappa * d_int + a;
+    float v = cqr[0];
+    for (int qq = 1; qq < n_eta / 2; ++qq) {
+      int idx = (qq * ph) % kn;
+      if (idx < 0) idx += kn;
+      float sn, cs;
+      sincospif(2.0f * (float)idx / (float)kn, &sn, &cs);
+      v += 2.0f * (cqr[qq] * cs - cqi[qq] * sn);
+    }
+    // Nyquist term cos(pi t) = (-1)^d_int cos(pi a / kappa)
+    const float ny = ((d_int & 1) ? -1.0f : 1.0f) * cospif((float)a / (float)kappa);
+    v += cqr[n_eta / 2] * ny;
+    v /= (float)n_eta;
+    argmax_merge(best, besta, v, a + m);
+  }
+  wave_argmax(best, besta);
+  __syncthreads();
+  if ((tid & 63) == 0) {
+    rv[tid >> 6] = best;
+    ri[tid >> 6] = besta;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 4; ++w) argmax_merge(best, besta, rv[w], ri[w]);
+    const double dsub = (double)d_int + (double)(besta - m) / (double)kappa;
+    *gamma_out = 2.0 * 3.14159265358979323846 * dsub / (double)n_eta;
+  }
+}
+
 // eta correlation c(D) = sum_k w_k sum_m Le[k][m] Lt[k][m - D] (Hann weights
 // over radius), normalised; integer argmax (ties to the smallest D), then the
 // maximum of its trigonometric interpolant over D_int + a / kappa,
@@ -359,38 +401,7 @@ __global__ __launch_bounds__(256) void k_eta_peak(const float* __restrict__ lp_e
     cqi[qq] = ai;
   }
   __syncthreads();
-  const int m = (3 * kappa + 3) / 4;
-  const int kn = kappa * n_eta;
-  float best = -INFINITY;
-  int besta = 0x7fffffff;
-  for (int a = -m + tid; a <= m; a += 256) {
-    const int ph = kappa * d_int + a;
-    float v = cqr[0];
-    for (int qq = 1; qq < n_eta / 2; ++qq) {
-      int idx = (qq * ph) % kn;
-      if (idx < 0) idx += kn;
-      float sn, cs;
-      sincospif(2.0f * (float)idx / (float)kn, &sn, &cs);
-      v += 2.0f * (cqr[qq] * cs - cqi[qq] * sn);
-    }
-    // Nyquist term cos(pi t) = (-1)^d_int cos(pi a / kappa)
-    const float ny = ((d_int & 1) ? -1.0f : 1.0f) * cospif((float)a / (float)kappa);
-    v += cqr[n_eta / 2] * ny;
-    v /= (float)n_eta;
-    argmax_merge(best, besta, v, a + m);
-  }
-  wave_argmax(best, besta);
-  __syncthreads();
-  if ((tid & 63) == 0) {
-    rv[tid >> 6] = best;
-    ri[tid >> 6] = besta;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int w = 1; w < 4; ++w) argmax_merge(best, besta, rv[w], ri[w]);
-    const double dsub = (double)d_int + (double)(besta - m) / (double)kappa;
-    gamma[k] = 2.0 * 3.14159265358979323846 * dsub / (double)n_eta;
-  }
+  eta_interpolate(cqr, cqi, n_eta, d_int, kappa, rv, ri, gamma + k);
 }
 
 // ---------------------------------------------------------------------------
@@ -485,10 +496,177 @@ hipError_t launch_logpolar(int n, const float* imgs, int64_t k, int n_rho, int n
   return hipGetLastError();
 }
 
+// The same eta correlation through row transforms, for n_eta = NE = P1 x P2
+// (P2 threads per radius row, RG rows at a time).  Row k is packed as
+// z = Le[k] + i Lt[k] and transformed once (forward: radix P1 in registers
+// over m = P2 a + j, twiddle, radix P2 over j); with S(q) = Z(q) + conj(Z(-q))
+// and D(q) = Z(q) - conj(Z(-q)), Le's transform times the conjugate of Lt's
+// is i S conj(D) / 4.  The weighted products are summed over rows in a
+// fixed order into A(q), q in [0, NE / 2]; c(D) is the inverse transform of
+// A, and the transform of the normalised c that the interpolation needs is
+// A times the normalisation.  The energies are the direct weighted sums.
+template <int NE>
+__global__ __launch_bounds__(256) void k_eta_fft(const float* __restrict__ lp_e, const float* __restrict__ lp_t,
+                                                 int n_rho, int kappa, double* __restrict__ gamma) {
+  constexpr int P2 = NE >= 512 ? 32 : 16, P1 = NE / P2, RG = 256 / P2, NQ = NE / 2 + 1;
+  constexpr int CPT = (P1 + P2 - 1) / P2, QPT = (NQ + 255) / 256;
+  static_assert(P1 * P2 == NE && RG * P2 == 256, "row layout");
+  extern __shared__ float fsm[];
+  cf* yb = reinterpret_cast<cf*>(fsm);                // [RG][NE]
+  cf* pr = yb + RG * NE;                              // [RG][NQ]
+  cf* rt = pr + RG * NQ;                              // [NE] exp(+2 pi i t / NE)
+  float* cc = reinterpret_cast<float*>(rt + NE);      // [NE]
+  float* cqr = cc + NE;                               // [NQ]
+  float* cqi = cqr + NQ;                              // [NQ]
+  __shared__ float rsum[8];
+  __shared__ float rv[4];
+  __shared__ int ri[4];
+  const int64_t k = blockIdx.x;
+  const int tid = threadIdx.x, j = tid % P2, g = tid / P2;
+  const float* E = lp_e + k * (int64_t)n_rho * NE;
+  const float* T = lp_t + k * (int64_t)n_rho * NE;
+  for (int t = tid; t < NE; t += 256) {
+    float sn, cs;
+    sincospif(2.0f * (float)t / (float)NE, &sn, &cs);
+    rt[t] = cf{cs, sn};
+  }
+  cf acc[QPT];
+#pragma unroll
+  for (int i = 0; i < QPT; ++i) acc[i] = cf{0.f, 0.f};
+  float ee = 0.0f, tt = 0.0f;
+  cf* yg = yb + g * NE;
+  cf* pg = pr + g * NQ;
+  __syncthreads();
+  for (int r0 = 0; r0 < n_rho; r0 += RG) {
+    const int r = r0 + g;
+    const bool rok = r < n_rho;
+    const float sw = sinpif(((float)r + 0.5f) / (float)n_rho);
+    const float w = rok ? sw * sw : 0.0f;
+    cf x[P1];
+    float pe = 0.0f, pt = 0.0f;
+#pragma unroll
+    for (int a = 0; a < P1; ++a) {
+      const int m = P2 * a + j;
+      const float ev = rok ? E[(int64_t)r * NE + m] : 0.0f;
+      const float tv = rok ? T[(int64_t)r * NE + m] : 0.0f;
+      x[a] = cf{ev, tv};
+      pe = __fmaf_rn(ev, ev, pe);
+      pt = __fmaf_rn(tv, tv, pt);
+    }
+    ee = __fmaf_rn(w, pe, ee);
+    tt = __fmaf_rn(w, pt, tt);
+    DFT<P1, -1>::run(x);
+#pragma unroll
+    for (int c = 1; c < P1; ++c) x[c] = cmulc(x[c], rt[(j * c) % NE]);
+#pragma unroll
+    for (int c = 0; c < P1; ++c) yg[c * P2 + j] = x[c];
+    __syncthreads();
+    cf h[CPT][P2];
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const int c = j + P2 * i;
+      if (c < P1) {
+#pragma unroll
+        for (int b = 0; b < P2; ++b) h[i][b] = yg[c * P2 + b];
+        DFT<P2, -1>::run(h[i]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const int c = j + P2 * i;
+      if (c < P1) {
+#pragma unroll
+        for (int d = 0; d < P2; ++d) yg[c + P1 * d] = h[i][d];  // Z(c + P1 d)
+      }
+    }
+    __syncthreads();
+    for (int q = j; q < NQ; q += P2) {
+      const cf zq = yg[q], zm = yg[(NE - q) % NE];
+      const cf sq = cf{zq.x + zm.x, zq.y - zm.y};
+      const cf dq = cf{zq.x - zm.x, zq.y + zm.y};
+      const cf p = cmulc(sq, dq);
+      pg[q] = cf{-0.25f * w * p.y, 0.25f * w * p.x};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+      const int q = tid + 256 * i;
+      if (q < NQ) {
+        cf sum = pr[q];
+        for (int g2 = 1; g2 < RG; ++g2) sum = cadd(sum, pr[g2 * NQ + q]);
+        acc[i] = cadd(acc[i], sum);
+      }
+    }
+    __syncthreads();
+  }
+  // A(q) into pr[0 .. NQ), then c(D) = (1/NE) [A(0) + (-1)^D A(NE/2) + 2 sum_q Re(A(q) e^{2 pi i q D / NE})]
+#pragma unroll
+  for (int i = 0; i < QPT; ++i) {
+    const int q = tid + 256 * i;
+    if (q < NQ) pr[q] = acc[i];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    ee += __shfl_xor(ee, off, 64);
+    tt += __shfl_xor(tt, off, 64);
+  }
+  if ((tid & 63) == 0) {
+    rsum[tid >> 6] = ee;
+    rsum[4 + (tid >> 6)] = tt;
+  }
+  __syncthreads();
+  for (int d = tid; d < NE; d += 256) {
+    float v = 0.0f;
+    for (int q = 1; q < NE / 2; ++q) {
+      const cf e = rt[(q * d) % NE];
+      v = __fmaf_rn(pr[q].x, e.x, __fmaf_rn(-pr[q].y, e.y, v));
+    }
+    cc[d] = (pr[0].x + ((d & 1) ? -pr[NE / 2].x : pr[NE / 2].x) + 2.0f * v) / (float)NE;
+  }
+  __syncthreads();
+  const float norm = sqrtf((rsum[0] + rsum[1] + rsum[2] + rsum[3]) * (rsum[4] + rsum[5] + rsum[6] + rsum[7]));
+  const float inv = norm > 0.0f ? 1.0f / norm : 0.0f;
+  float bv = -INFINITY;
+  int bi = 0x7fffffff;
+  for (int d = tid; d < NE; d += 256) argmax_merge(bv, bi, cc[d] * inv, d);
+  wave_argmax(bv, bi);
+  if ((tid & 63) == 0) {
+    rv[tid >> 6] = bv;
+    ri[tid >> 6] = bi;
+  }
+  __syncthreads();
+  for (int w = 0; w < 4; ++w) argmax_merge(bv, bi, rv[w], ri[w]);
+  const int d_int = bi >= NE / 2 ? bi - NE : bi;
+  for (int q = tid; q < NQ; q += 256) {
+    cqr[q] = pr[q].x * inv;
+    cqi[q] = pr[q].y * inv;
+  }
+  __syncthreads();
+  eta_interpolate(cqr, cqi, NE, d_int, kappa, rv, ri, gamma + k);
+}
+
 hipError_t launch_eta_peak(const float* lp_e, const float* lp_t, int64_t k, int n_rho, int n_eta,
                            int kappa, double* gamma, hipStream_t stream) {
   if (k <= 0) return hipSuccess;
   if (n_eta > 1024 || n_rho < 2 || k > (int64_t(1) << 31) / 256) return hipErrorInvalidValue;
+  // the default grids (n_eta = 2 N) through row transforms
+#define EBSD_ETAF(NE)                                                                                         \
+  do {                                                                                                        \
+    constexpr int P2 = NE >= 512 ? 32 : 16, NQ = NE / 2 + 1;                                                  \
+    const size_t shf = sizeof(cf) * ((size_t)(256 / P2) * (NE + NQ) + NE) + sizeof(float) * (NE + 2 * NQ);    \
+    (void)hipFuncSetAttribute((const void*)k_eta_fft<NE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shf); \
+    hipLaunchKernelGGL(k_eta_fft<NE>, dim3((unsigned)k), dim3(256), shf, stream, lp_e, lp_t, n_rho, kappa, gamma); \
+    return hipGetLastError();                                                                                 \
+  } while (0)
+  switch (n_eta) {
+    case 128: EBSD_ETAF(128);
+    case 192: EBSD_ETAF(192);
+    case 256: EBSD_ETAF(256);
+    case 320: EBSD_ETAF(320);
+    case 512: EBSD_ETAF(512);
+    default: break;
+  }
+#undef EBSD_ETAF
   // register-blocked lags for n_eta = 64 R (R = 2, 3, 4, 5, 8: every size at n_eta = 2 N), else one
   // lag per thread
   const int rb = n_eta % 64 == 0 ? n_eta / 64 : 0;
