@@ -237,94 +237,53 @@ __device__ __forceinline__ void eta_interpolate(const float* cqr, const float* c
 // over radius), normalised; integer argmax (ties to the smallest D), then the
 // maximum of its trigonometric interpolant over D_int + a / kappa,
 // |a| <= ceil(0.75 kappa) (ties to the smallest a); gamma = 2 pi D / n_eta.
-// R > 0 (n_eta = 64 R): lane l of wave g accumulates the lags d = R l + r,
-// r < R, over the radius rows g, g + 4, ...: the m loop runs in blocks of R
-// and the template row, stored twice over (index m - d in [-n_eta, n_eta)),
-// is read in chunks of R consecutive values, each reused for R products, so
-// one LDS read serves R FMAs.  The four waves' sums are then added in wave
-// order.  R = 0: one lag per thread, every value read from LDS (any n_eta).
-template <int R>
+// Direct form, one lag per thread, every value read from LDS: any n_eta (the
+// default grids take the transform form below).
 __global__ __launch_bounds__(256) void k_eta_peak(const float* __restrict__ lp_e,
                                                   const float* __restrict__ lp_t, int n_rho,
                                                   int n_eta, int kappa, double* __restrict__ gamma) {
   extern __shared__ float fsm[];
   constexpr int RC = 8;  // radius rows staged per step
-  constexpr int TW = R > 0 ? 2 : 1;    // template row copies
   float* le = fsm;                     // [RC][n_eta]
-  float* lt = fsm + RC * n_eta;        // [RC][TW n_eta]
-  float* cc = lt + RC * TW * n_eta;    // [n_eta]
+  float* lt = fsm + RC * n_eta;        // [RC][n_eta]
+  float* cc = lt + RC * n_eta;         // [n_eta]
   float* cq = cc + n_eta;              // [2][n_eta / 2 + 1]
   const int64_t k = blockIdx.x;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6;
   const float* E = lp_e + k * (int64_t)n_rho * n_eta;
   const float* T = lp_t + k * (int64_t)n_rho * n_eta;
   constexpr int DMAX = 4;  // n_eta <= 1024
-  float acc[R > 0 ? R : DMAX];
+  float acc[DMAX];
 #pragma unroll
-  for (int j = 0; j < (R > 0 ? R : DMAX); ++j) acc[j] = 0.0f;
+  for (int j = 0; j < DMAX; ++j) acc[j] = 0.0f;
   float ee = 0.0f, tt = 0.0f;
   for (int r0 = 0; r0 < n_rho; r0 += RC) {
     const int rc = min(RC, n_rho - r0);
     __syncthreads();
     for (int t = tid; t < rc * n_eta; t += 256) {
       le[t] = E[r0 * n_eta + t];
-      const float v = T[r0 * n_eta + t];
-      if constexpr (R > 0) {
-        const int row = t / n_eta, j = t - row * n_eta;
-        lt[row * 2 * n_eta + j] = v;          // t[j - n_eta] for j - n_eta in [-n_eta, 0)
-        lt[row * 2 * n_eta + n_eta + j] = v;  // t[j]
-      } else {
-        lt[t] = v;
-      }
+      lt[t] = T[r0 * n_eta + t];
     }
     __syncthreads();
     for (int rr = 0; rr < rc; ++rr) {
       const float s = sinpif(((float)(r0 + rr) + 0.5f) / (float)n_rho);
       const float w = s * s;
       const float* er = le + rr * n_eta;
-      if constexpr (R > 0) {
-        if ((rr & 3) == wv) {
-          const float* tx = lt + rr * 2 * n_eta + n_eta;  // tx[i] = t[i mod n_eta], i in [-n_eta, n_eta)
-          float a[R], ca[R], cb[R];
+      const float* tr = lt + rr * n_eta;
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            a[r] = 0.0f;
-            ca[r] = tx[-R * lane - R + r];  // chunk of block q = 0: t[R (q - l) - R + r]
-          }
-          for (int q = 0; q < 64; ++q) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) cb[r] = tx[R * (q - lane) + r];
-#pragma unroll
-            for (int i = 0; i < R; ++i) {
-              const float e = er[R * q + i];
-              // lag R l + r at m = R q + i reads t[R (q - l) + i - r]
-#pragma unroll
-              for (int r = 0; r < R; ++r) a[r] = __fmaf_rn(e, i - r >= 0 ? cb[i - r] : ca[R + i - r], a[r]);
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) ca[r] = cb[r];
-          }
-#pragma unroll
-          for (int r = 0; r < R; ++r) acc[r] = __fmaf_rn(w, a[r], acc[r]);
-        }
-      } else {
-        const float* tr = lt + rr * n_eta;
-#pragma unroll
-        for (int j = 0; j < DMAX; ++j) {
-          const int d = tid + 256 * j;
-          if (d < n_eta) {
-            float a = 0.0f;
-            // m - d wraps at m = d
-            for (int m = 0; m < d; ++m) a = __fmaf_rn(er[m], tr[m - d + n_eta], a);
-            for (int m = d; m < n_eta; ++m) a = __fmaf_rn(er[m], tr[m - d], a);
-            acc[j] = __fmaf_rn(w, a, acc[j]);
-          }
+      for (int j = 0; j < DMAX; ++j) {
+        const int d = tid + 256 * j;
+        if (d < n_eta) {
+          float a = 0.0f;
+          // m - d wraps at m = d
+          for (int m = 0; m < d; ++m) a = __fmaf_rn(er[m], tr[m - d + n_eta], a);
+          for (int m = d; m < n_eta; ++m) a = __fmaf_rn(er[m], tr[m - d], a);
+          acc[j] = __fmaf_rn(w, a, acc[j]);
         }
       }
       if (tid < n_eta) {
         // per-thread partial energies over this row
-        const float* trow = R > 0 ? lt + rr * 2 * n_eta + n_eta : lt + rr * n_eta;
+        const float* trow = lt + rr * n_eta;
         float pe = 0.0f, pt = 0.0f;
         for (int m = tid; m < n_eta; m += 256) {
           pe = __fmaf_rn(er[m], er[m], pe);
@@ -335,21 +294,11 @@ __global__ __launch_bounds__(256) void k_eta_peak(const float* __restrict__ lp_e
       }
     }
   }
-  // raw correlation into cc (R > 0: the four waves' partial sums in wave order)
-  if constexpr (R > 0) {
-    __syncthreads();
-    float* part = le;  // [4][n_eta] over the staging buffers
+  // raw correlation into cc
 #pragma unroll
-    for (int r = 0; r < R; ++r) part[wv * n_eta + R * lane + r] = acc[r];
-    __syncthreads();
-    for (int d = tid; d < n_eta; d += 256)
-      cc[d] = ((part[d] + part[n_eta + d]) + part[2 * n_eta + d]) + part[3 * n_eta + d];
-  } else {
-#pragma unroll
-    for (int j = 0; j < DMAX; ++j) {
-      const int d = tid + 256 * j;
-      if (d < n_eta) cc[d] = acc[j];
-    }
+  for (int j = 0; j < DMAX; ++j) {
+    const int d = tid + 256 * j;
+    if (d < n_eta) cc[d] = acc[j];
   }
   // energies
   for (int off = 32; off > 0; off >>= 1) {
@@ -667,22 +616,9 @@ hipError_t launch_eta_peak(const float* lp_e, const float* lp_t, int64_t k, int 
     default: break;
   }
 #undef EBSD_ETAF
-  // register-blocked lags for n_eta = 64 R (R = 2, 3, 4, 5, 8: every size at n_eta = 2 N), else one
-  // lag per thread
-  const int rb = n_eta % 64 == 0 ? n_eta / 64 : 0;
-  const int tw = (rb == 2 || rb == 3 || rb == 4 || rb == 5 || rb == 8) ? 2 : 1;
-  const size_t shm = sizeof(float) * ((size_t)(1 + tw) * 8 * n_eta + n_eta + 2 * (n_eta / 2 + 1));
-#define EBSD_ETA(RV) \
-  hipLaunchKernelGGL(k_eta_peak<RV>, dim3((unsigned)k), dim3(256), shm, stream, lp_e, lp_t, n_rho, n_eta, kappa, gamma)
-  switch (tw == 2 ? rb : 0) {
-    case 2: EBSD_ETA(2); break;
-    case 3: EBSD_ETA(3); break;
-    case 4: EBSD_ETA(4); break;
-    case 5: EBSD_ETA(5); break;
-    case 8: EBSD_ETA(8); break;
-    default: EBSD_ETA(0); break;
-  }
-#undef EBSD_ETA
+  const size_t shm = sizeof(float) * ((size_t)2 * 8 * n_eta + n_eta + 2 * (n_eta / 2 + 1));
+  (void)hipFuncSetAttribute((const void*)k_eta_peak, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(k_eta_peak, dim3((unsigned)k), dim3(256), shm, stream, lp_e, lp_t, n_rho, n_eta, kappa, gamma);
   return hipGetLastError();
 }
 

@@ -195,6 +195,39 @@ def test_rotation_measurement_matches_oracle(n):
         assert abs(d_gpu - d_ref) <= 3.0 / kappa + 1e-9
 
 
+@pytest.mark.parametrize("n,n_rho,n_eta", [(128, 64, 384), (128, 44, 512), (96, 50, 192), (64, 20, 320),
+                                           (160, 33, 128), (64, 24, 1024)])
+def test_rotation_measurement_other_grids(n, n_rho, n_eta):
+    # log-polar grids other than the default: the direct eta correlation
+    # (n_eta = 384, and 1,024, its largest) and the transform form with row
+    # counts that leave the last row group partly empty; the same near-tie
+    # rule as above
+    banner("log-polar n=%d grid %d x %d" % (n, n_rho, n_eta))
+    t = tm()
+    master = band_master()
+    rng = np.random.default_rng(70 + n_eta)
+    from oracle import rotations as orot
+    q0 = random_quats(rng, 3)
+    pc = (0.5, 0.5, 0.6)
+    pats, tmpls = [], []
+    for k, deg in enumerate((2.2, -1.1, 3.3)):
+        r0 = orot.quat_to_matrix(q0[k])
+        rt = r0 @ orot.rot_z(np.deg2rad(deg)).T
+        pats.append(simulate_patterns(orot.matrix_to_quat(rt)[None], n, np.array([pc]), ("poisson", 500.0),
+                                      seed=k).numpy()[0])
+        tmpls.append(ogeo.project(master, r0, n, pc).astype(np.float32))
+    pats, tmpls = np.array(pats), np.array(tmpls)
+    g = host(t.measure_rotation(dev(pats), dev(tmpls), t.params_default(n_rho=n_rho, n_eta=n_eta)))
+    prm = OParams(n_rho=n_rho, n_eta=n_eta)
+    kappa = prm.upsample
+    for k in range(3):
+        c = oref.eta_correlation_of(pats[k].astype(np.float64), tmpls[k].astype(np.float64), prm)
+        v_ref, d_ref = oref.eta_peak(c, kappa)
+        d_gpu = g[k] * n_eta / (2 * np.pi)
+        assert oref.eta_value(c, d_gpu)[0] >= v_ref - 2e-6
+        assert abs(d_gpu - d_ref) <= 3.0 / kappa + 1e-9
+
+
 def test_empty_inputs_are_noops():
     t = tm()
     e = torch.empty((0, 64, 64), dtype=torch.float32, device="cuda:0")
