@@ -168,26 +168,46 @@ __global__ __launch_bounds__(256) void k_logpolar(const float* __restrict__ imgs
   const double rmin = 2.0, rmax = 0.5 * n - 2.0;
   const int lane = tid & 63, wave = tid >> 6;
   float* o = out + k * (int64_t)n_rho * n_eta;
+  // the angles' (cos, sin), the same for every radius; each lane keeps its
+  // samples of a row in registers until the row mean is known, so every
+  // output value is written once
+  __shared__ float2 ang[1024];
+  for (int m = tid; m < n_eta; m += 256) {
+    float sn, cs;
+    sincospif(2.0f * (float)m / (float)n_eta, &sn, &cs);
+    ang[m] = make_float2(cs, sn);
+  }
+  __syncthreads();
+  constexpr int MPL = 1024 / 64;  // samples per lane at the largest n_eta
   for (int row = wave; row < n_rho; row += 4) {
     const float r = (float)(rmin * pow(rmax / rmin, (double)row / (double)(n_rho - 1)));
     float sum = 0.0f;
-    for (int m = lane; m < n_eta; m += 64) {
-      float sn, cs;
-      sincospif(2.0f * (float)m / (float)n_eta, &sn, &cs);
-      const float col = c + r * cs, rw = c + r * sn;
-      const float r0f = floorf(rw), c0f = floorf(col);
-      const float fr = rw - r0f, fc = col - c0f;
-      const int r0 = (int)r0f, c0 = (int)c0f;
-      const float* p = img + r0 * n + c0;
-      const float val = (1.0f - fr) * ((1.0f - fc) * p[0] + fc * p[1]) + fr * ((1.0f - fc) * p[n] + fc * p[n + 1]);
-      const float x = (val - fmean) * inv_std;
-      o[row * n_eta + m] = x;
-      sum += x;
+    float xs[MPL];
+#pragma unroll
+    for (int i = 0; i < MPL; ++i) {
+      const int m = lane + 64 * i;
+      if (m < n_eta) {
+        const float cs = ang[m].x, sn = ang[m].y;
+        const float col = c + r * cs, rw = c + r * sn;
+        const float r0f = floorf(rw), c0f = floorf(col);
+        const float fr = rw - r0f, fc = col - c0f;
+        const int r0 = (int)r0f, c0 = (int)c0f;
+        const float* p = img + r0 * n + c0;
+        const float val =
+            (1.0f - fr) * ((1.0f - fc) * p[0] + fc * p[1]) + fr * ((1.0f - fc) * p[n] + fc * p[n + 1]);
+        const float x = (val - fmean) * inv_std;
+        xs[i] = x;
+        sum += x;
+      }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
     const float mu = sum / (float)n_eta;
-    for (int m = lane; m < n_eta; m += 64) o[row * n_eta + m] -= mu;
+#pragma unroll
+    for (int i = 0; i < MPL; ++i) {
+      const int m = lane + 64 * i;
+      if (m < n_eta) o[row * n_eta + m] = xs[i] - mu;
+    }
   }
 }
 
