@@ -532,7 +532,7 @@ int ebsd_capture_range(const ebsd_master* mp, const double* q_ref, int64_t R, in
     return rc;
   if (R < 0) return fail(EBSD_E_INVALID, "R must be >= 0");
   if (T < 1) return fail(EBSD_E_INVALID, "T must be >= 1");
-  if (R * 3 * (int64_t)T > 0x7fffffffLL) return fail(EBSD_E_INVALID, "R x 3 x T must fit in int32");
+  if (R > 0x7fffffffLL / (3 * (int64_t)T)) return fail(EBSD_E_INVALID, "R x 3 x T must fit in int32");
   if (R == 0) return EBSD_OK;
   if (!q_ref || !theta_deg || !h || !width) return fail(EBSD_E_INVALID, "null pointer");
   if (!fft_supported(n) && !window_peak_supported(n, p.max_shift))

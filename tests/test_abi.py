@@ -152,6 +152,7 @@ def test_capture_range_argument_errors():
     assert call(geo_t=bad_g) == -1 and b"pcz" in lib.ebsd_last_error()
     assert call(q=0) == -1 and call(out=0) == -1
     assert call(R=1 << 30, T=4) == -1 and b"int32" in lib.ebsd_last_error()
+    assert call(R=(1 << 62), T=1000) == -1 and b"int32" in lib.ebsd_last_error()
     assert call(R=0) == 0
 
 
