@@ -128,7 +128,9 @@ def test_windowed_scores_match_oracle(n, s):
 
 @pytest.mark.parametrize("n,p,l", [(64, 5, 45), (96, 3, 33), (128, 2, 70), (160, 2, 31)])
 def test_scores_match_oracle(n, p, l):
-    # L is not a multiple of the 32-template chunk: ragged tail
+    # L is not a multiple of the 32-template chunk: ragged tail (at 64, where
+    # each half-wave takes its own template, an odd tail of 13 leaves the
+    # last pair's second half without a template)
     banner("scores n=%d p=%d l=%d" % (n, p, l))
     t = tm()
     _, _, pats = _pats(n, p, seed=30 + n)
