@@ -440,6 +440,12 @@ int ebsd_cnn_gradients(ebsd_cnn cnn, const float* x, const int32_t* labels, int6
 /* One Adam step (beta 0.9, 0.999, eps 1e-8) on the batch's gradient. */
 int ebsd_cnn_train_step(ebsd_cnn cnn, const float* x, const int32_t* labels, int64_t B, float lr, float* loss,
                         void* stream);
+/* One Adam step (Kingma and Ba, Algorithm 1: beta 0.9, 0.999, eps 1e-8,
+ * bias-corrected moments; step count t = 1, 2, ... since creation or the last
+ * ebsd_cnn_set_params) from a caller-supplied gradient grad (device [count],
+ * parameter order), with step size lr > 0.  ebsd_cnn_train_step is
+ * ebsd_cnn_gradients followed by this step. */
+int ebsd_cnn_apply_gradient(ebsd_cnn cnn, const float* grad, float lr, void* stream);
 /* Training data made on the device: sample s in [first, first + B) gets a
  * uniform random orientation and an in-plane pattern-centre offset of up to
  * +-max_offset_px (Philox4x32-10 keyed by seed, counter s), is projected at

@@ -166,3 +166,16 @@ def nearest_library(q, lib_q):
     srl = np.einsum("sij,ljk->slik", ops, rl)
     tr = np.einsum("ij,slij->sl", rq, srl).max(axis=0)
     return int(np.argmax(tr))
+
+
+def adam_step(w, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (Kingma and Ba, ICLR 2015, Algorithm 1) on parameters w
+    with gradient g at step t = 1, 2, ...: biased moment estimates m and v,
+    their bias-corrected forms m / (1 - beta1^t) and v / (1 - beta2^t), and
+    w - lr m_hat / (sqrt(v_hat) + eps).  Returns (w, m, v)."""
+    w, g, m, v = (np.asarray(a, dtype=np.float64) for a in (w, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return w - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

@@ -29,7 +29,8 @@ EXPORTS = ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_index
            "ebsd_measure_rotation", "ebsd_timing_enable", "ebsd_timing_read", "ebsd_ragged_plan_create",
            "ebsd_ragged_run", "ebsd_ragged_plan_tiles", "ebsd_ragged_plan_destroy", "ebsd_cnn_param_count",
            "ebsd_cnn_create", "ebsd_cnn_destroy", "ebsd_cnn_get_params", "ebsd_cnn_set_params", "ebsd_cnn_input",
-           "ebsd_cnn_forward", "ebsd_cnn_gradients", "ebsd_cnn_train_step", "ebsd_cnn_make_batch", "ebsd_cnn_topk",
+           "ebsd_cnn_forward", "ebsd_cnn_gradients", "ebsd_cnn_train_step", "ebsd_cnn_apply_gradient",
+           "ebsd_cnn_make_batch", "ebsd_cnn_topk",
            "ebsd_index_proposed", "ebsd_pc_map", "ebsd_refine_from_match", "ebsd_capture_range",
            "ebsd_so3_library", "ebsd_nn_disorientation")
 
@@ -121,6 +122,7 @@ def lib():
     L.ebsd_cnn_forward.argtypes = [vp, vp, i64, vp, vp]
     L.ebsd_cnn_gradients.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     L.ebsd_cnn_train_step.argtypes = [vp, vp, vp, i64, f32, vp, vp]
+    L.ebsd_cnn_apply_gradient.argtypes = [vp, vp, f32, vp]
     L.ebsd_cnn_make_batch.argtypes = [dp(Master), dp(Geometry), vp, i64, i32, i64, i64, u64, f64, f64, f64, vp, vp,
                                       vp, vp]
     L.ebsd_cnn_topk.argtypes = [vp, i64, i32, i32, vp, vp]
@@ -175,13 +177,31 @@ def _ptr(t, dtype=None, name="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _shape(t, shape, name):
+    """Raises ValueError unless t has the given shape (None = any extent)."""
+    if t is None:
+        return
+    if t.dim() != len(shape) or any(w is not None and g != w for g, w in zip(t.shape, shape)):
+        want = "(" + ", ".join("*" if w is None else str(w) for w in shape) + ")"
+        raise ValueError("%s must have shape %s, got %s" % (name, want, tuple(t.shape)))
+
+
+def _patterns(patterns):
+    """(P, n) of a [P][n][n] pattern stack."""
+    if patterns.dim() != 3 or patterns.shape[1] != patterns.shape[2]:
+        raise ValueError("patterns must be [P][n][n], got %s" % (tuple(patterns.shape),))
+    return patterns.shape[0], patterns.shape[2]
+
+
 def _master(master):
     import torch
+    _shape(master, (None, None), "master")
     return Master(_ptr(master, torch.float32, "master").value, master.shape[0], master.shape[1])
 
 
-def _geo(pc, pc_per=None):
+def _geo(pc, pc_per=None, p=None):
     import torch
+    _shape(pc_per, (p, 3), "pc_per")
     return Geometry(float(pc[0]), float(pc[1]), float(pc[2]),
                     None if pc_per is None else _ptr(pc_per, torch.float64, "pc_per").value)
 
@@ -193,7 +213,9 @@ def _params(prm):
 def index_patterns(patterns, master, pc, lib_q, prm=None, scores=False):
     """Returns dict(best_idx, best_q, peak_h, shift[, scores]) as CUDA tensors."""
     import torch
-    p, n = patterns.shape[0], patterns.shape[-1]
+    p, n = _patterns(patterns)
+    _shape(lib_q, (None, 4), "lib_q")
+    _shape(master, (None, None), "master")
     dev = patterns.device
     out = dict(best_idx=torch.empty(p, dtype=torch.int32, device=dev),
                best_q=torch.empty((p, 4), dtype=torch.float64, device=dev),
@@ -213,14 +235,17 @@ def index_patterns(patterns, master, pc, lib_q, prm=None, scores=False):
 def refine_orientations(patterns, master, pc, q_init, pc_per=None, prm=None):
     """Returns dict(q, peak_h, shift) as CUDA tensors."""
     import torch
-    p, n = patterns.shape[0], patterns.shape[-1]
+    p, n = _patterns(patterns)
+    _shape(q_init, (p, 4), "q_init")
+    _shape(pc_per, (p, 3), "pc_per")
+    _shape(master, (None, None), "master")
     dev = patterns.device
     out = dict(q=torch.empty((p, 4), dtype=torch.float64, device=dev),
                peak_h=torch.empty(p, dtype=torch.float32, device=dev),
                shift=torch.empty((p, 2), dtype=torch.float32, device=dev))
     batch = Batch(_ptr(patterns, torch.float32, "patterns").value, p, n)
     rc = lib().ebsd_refine_orientations(ctypes.byref(batch), ctypes.byref(_master(master)),
-                                        ctypes.byref(_geo(pc, pc_per)), _ptr(q_init, torch.float64, "q_init"),
+                                        ctypes.byref(_geo(pc, pc_per, p)), _ptr(q_init, torch.float64, "q_init"),
                                         _params(prm), _ptr(out["q"]), _ptr(out["peak_h"]), _ptr(out["shift"]),
                                         _stream())
     _check(rc, "ebsd_refine_orientations")
@@ -233,14 +258,18 @@ def refine_from_match(patterns, master, pc, q_init, match_shift, pc_per=None, pr
     beam-induced move to pc_per.  Returns dict(q, peak_h, shift) as CUDA
     tensors."""
     import torch
-    p, n = patterns.shape[0], patterns.shape[-1]
+    p, n = _patterns(patterns)
+    _shape(q_init, (p, 4), "q_init")
+    _shape(pc_per, (p, 3), "pc_per")
+    _shape(master, (None, None), "master")
+    _shape(match_shift, (p, 2), "match_shift")
     dev = patterns.device
     out = dict(q=torch.empty((p, 4), dtype=torch.float64, device=dev),
                peak_h=torch.empty(p, dtype=torch.float32, device=dev),
                shift=torch.empty((p, 2), dtype=torch.float32, device=dev))
     batch = Batch(_ptr(patterns, torch.float32, "patterns").value, p, n)
     rc = lib().ebsd_refine_from_match(ctypes.byref(batch), ctypes.byref(_master(master)),
-                                      ctypes.byref(_geo(pc, pc_per)), _ptr(q_init, torch.float64, "q_init"),
+                                      ctypes.byref(_geo(pc, pc_per, p)), _ptr(q_init, torch.float64, "q_init"),
                                       _ptr(match_shift, torch.float32, "match_shift"), _params(prm),
                                       _ptr(out["q"]), _ptr(out["peak_h"]), _ptr(out["shift"]), _stream())
     _check(rc, "ebsd_refine_from_match")
@@ -274,6 +303,7 @@ def nn_disorientation(q):
     """Nearest-neighbour cubic disorientation (degrees, float64 [L]) and index
     (int32 [L]) within q [L, 4]."""
     import torch
+    _shape(q, (None, 4), "q")
     n = q.shape[0]
     ang = torch.empty(n, dtype=torch.float64, device=q.device)
     idx = torch.empty(n, dtype=torch.int32, device=q.device)
@@ -287,6 +317,8 @@ def capture_range(master, q_ref, n, pc_ref, pc_test, theta_deg, prm=None):
     float64 [R, 3] (degrees) for reference orientations q_ref [R, 4] and
     ascending angles theta_deg [T] (CUDA float64)."""
     import torch
+    _shape(q_ref, (None, 4), "q_ref")
+    _shape(theta_deg, (None,), "theta_deg")
     r, t = q_ref.shape[0], theta_deg.shape[0]
     h = torch.empty((r, 3, t), dtype=torch.float32, device=q_ref.device)
     width = torch.empty((r, 3), dtype=torch.float64, device=q_ref.device)
@@ -300,9 +332,11 @@ def capture_range(master, q_ref, n, pc_ref, pc_test, theta_deg, prm=None):
 
 def project_templates(master, q, n, pc, pc_per=None):
     import torch
+    _shape(q, (None, 4), "q")
+    _shape(pc_per, (q.shape[0], 3), "pc_per")
     out = torch.empty((q.shape[0], n, n), dtype=torch.float32, device=q.device)
     rc = lib().ebsd_project_templates(ctypes.byref(_master(master)), _ptr(q, torch.float64, "q"), q.shape[0], n,
-                                      ctypes.byref(_geo(pc, pc_per)), _ptr(out), _stream())
+                                      ctypes.byref(_geo(pc, pc_per, q.shape[0])), _ptr(out), _stream())
     _check(rc, "ebsd_project_templates")
     return out
 
@@ -310,7 +344,7 @@ def project_templates(master, q, n, pc, pc_per=None):
 def pattern_spectra(imgs, prm=None, energy=False):
     """Unit-energy band spectra [K][B+1][2B+1] complex64 (and FP64 energies)."""
     import torch
-    k, n = imgs.shape[0], imgs.shape[-1]
+    k, n = _patterns(imgs)
     nf = spectrum_floats(n)
     if nf < 0:
         raise ValueError("unsupported size %d" % n)
@@ -322,9 +356,30 @@ def pattern_spectra(imgs, prm=None, energy=False):
     return (spec, en) if energy else spec
 
 
+def _spectra_and_pairs(spec_p, spec_l, pi, li, n):
+    """Checks band spectra [*][floats(n)] and, for index arrays, that every
+    index lies in its stack (a device read: these are test hooks)."""
+    nf = spectrum_floats(n)
+    if nf < 0:
+        raise ValueError("unsupported size %d" % n)
+    _shape(spec_p, (None, nf), "spec_p")
+    _shape(spec_l, (None, nf), "spec_l")
+    if pi is None:
+        if spec_l.shape[0] != spec_p.shape[0]:
+            raise ValueError("without index arrays spec_p and spec_l pair row by row")
+        return spec_p.shape[0]
+    _shape(pi, (None,), "pi")
+    _shape(li, (pi.shape[0],), "li")
+    k = pi.shape[0]
+    if k and (int(pi.min()) < 0 or int(pi.max()) >= spec_p.shape[0] or int(li.min()) < 0
+              or int(li.max()) >= spec_l.shape[0]):
+        raise ValueError("pair index out of range")
+    return k
+
+
 def xcf_peak(spec_p, spec_l, pi, li, n, prm=None, want_map=False):
     import torch
-    k = pi.shape[0] if pi is not None else spec_p.shape[0]
+    k = _spectra_and_pairs(spec_p, spec_l, pi, li, n)
     dev = spec_p.device
     h = torch.empty(k, dtype=torch.float32, device=dev)
     s = torch.empty((k, 2), dtype=torch.int32, device=dev)
@@ -338,6 +393,11 @@ def xcf_peak(spec_p, spec_l, pi, li, n, prm=None, want_map=False):
 
 def xcf_scores(spec_p, spec_l, n, prm=None):
     import torch
+    nf = spectrum_floats(n)
+    if nf < 0:
+        raise ValueError("unsupported size %d" % n)
+    _shape(spec_p, (None, nf), "spec_p")
+    _shape(spec_l, (None, nf), "spec_l")
     p, l = spec_p.shape[0], spec_l.shape[0]
     out = torch.empty((p, l), dtype=torch.float32, device=spec_p.device)
     rc = lib().ebsd_xcf_scores(_ptr(spec_p, torch.float32), p, _ptr(spec_l, torch.float32), l, n, _params(prm),
@@ -348,7 +408,8 @@ def xcf_scores(spec_p, spec_l, n, prm=None):
 
 def xcf_subpixel(spec_p, spec_l, pi, li, s_int, n, prm=None):
     import torch
-    k = s_int.shape[0]
+    k = _spectra_and_pairs(spec_p, spec_l, pi, li, n)
+    _shape(s_int, (k, 2), "s_int")
     h = torch.empty(k, dtype=torch.float32, device=spec_p.device)
     s = torch.empty((k, 2), dtype=torch.float32, device=spec_p.device)
     rc = lib().ebsd_xcf_subpixel(_ptr(spec_p, torch.float32), _ptr(spec_l, torch.float32),
@@ -360,7 +421,8 @@ def xcf_subpixel(spec_p, spec_l, pi, li, s_int, n, prm=None):
 
 def measure_rotation(pats, tmpls, prm=None):
     import torch
-    k, n = pats.shape[0], pats.shape[-1]
+    k, n = _patterns(pats)
+    _shape(tmpls, (k, n, n), "tmpls")
     g = torch.empty(k, dtype=torch.float64, device=pats.device)
     rc = lib().ebsd_measure_rotation(_ptr(pats, torch.float32, "pats"), _ptr(tmpls, torch.float32, "tmpls"), k, n,
                                      _params(prm), _ptr(g), _stream())
@@ -410,6 +472,7 @@ class RaggedPlan:
         if sizes.shape != offsets.shape or sizes.ndim != 1:
             raise ValueError("sizes and offsets must be 1-D arrays of equal length")
         self.P, self.L = int(sizes.shape[0]), int(L)
+        self.min_floats = int(np.max(offsets + sizes.astype(np.int64) ** 2)) if self.P else 0
         flags = (RAGGED_STENCIL if stencil else 0) | (RAGGED_EAGER if eager else 0) | \
             (0 if autotune else RAGGED_NO_AUTOTUNE)
         h = ctypes.c_void_p()
@@ -436,7 +499,14 @@ class RaggedPlan:
         import torch
         if lib_q.shape[0] != self.L:
             raise ValueError("library size differs from the plan's")
-        m, g = _master(master), _geo(pc, pc_per)
+        _shape(lib_q, (self.L, 4), "lib_q")
+        _shape(data, (None,), "data")
+        if data.shape[0] < self.min_floats:
+            raise ValueError("data holds %d floats, the layout needs %d" % (data.shape[0], self.min_floats))
+        for key, shape in (("best_idx", (self.P,)), ("q", (self.P, 4)), ("peak_h", (self.P,)),
+                           ("shift", (self.P, 2)), ("stencil_idx", (self.P,))):
+            _shape(out.get(key), shape, key)
+        m, g = _master(master), _geo(pc, pc_per, self.P)
         _check(lib().ebsd_ragged_run(self._h, _ptr(data, torch.float32, "data"), ctypes.byref(m), ctypes.byref(g),
                                      _ptr(lib_q, torch.float64, "lib_q"), _ptr(out.get("best_idx")),
                                      _ptr(out["q"]), _ptr(out["peak_h"]), _ptr(out["shift"]),
@@ -493,7 +563,7 @@ class Cnn:
     @staticmethod
     def input(patterns):
         import torch
-        p, n = patterns.shape[0], patterns.shape[-1]
+        p, n = _patterns(patterns)
         x = torch.empty((p, 64, 64), dtype=torch.float32, device=patterns.device)
         _check(lib().ebsd_cnn_input(_ptr(patterns, torch.float32, "patterns"), p, n, _ptr(x), _stream()),
                "ebsd_cnn_input")
@@ -501,6 +571,7 @@ class Cnn:
 
     def forward(self, x):
         import torch
+        _shape(x, (None, 64, 64), "x")
         out = torch.empty((x.shape[0], self.n_classes), dtype=torch.float32, device=x.device)
         _check(lib().ebsd_cnn_forward(self._h, _ptr(x, torch.float32, "x"), x.shape[0], _ptr(out), _stream()),
                "ebsd_cnn_forward")
@@ -508,6 +579,8 @@ class Cnn:
 
     def gradients(self, x, labels):
         import torch
+        _shape(x, (None, 64, 64), "x")
+        _shape(labels, (x.shape[0],), "labels")
         g = torch.empty(self.param_count, dtype=torch.float32, device=x.device)
         loss = torch.empty(1, dtype=torch.float32, device=x.device)
         _check(lib().ebsd_cnn_gradients(self._h, _ptr(x, torch.float32, "x"), _ptr(labels, torch.int32, "labels"),
@@ -516,11 +589,21 @@ class Cnn:
 
     def train_step(self, x, labels, lr, loss=None):
         import torch
+        _shape(x, (None, 64, 64), "x")
+        _shape(labels, (x.shape[0],), "labels")
         if loss is None:
             loss = torch.empty(1, dtype=torch.float32, device=x.device)
         _check(lib().ebsd_cnn_train_step(self._h, _ptr(x, torch.float32, "x"), _ptr(labels, torch.int32, "labels"),
                                          x.shape[0], float(lr), _ptr(loss), _stream()), "ebsd_cnn_train_step")
         return loss
+
+    def apply_gradient(self, grad, lr):
+        """One Adam step from a given gradient (float32 [param_count])."""
+        import torch
+        if grad.numel() != self.param_count:
+            raise ValueError("expected %d gradient values" % self.param_count)
+        _check(lib().ebsd_cnn_apply_gradient(self._h, _ptr(grad, torch.float32, "grad"), float(lr), _stream()),
+               "ebsd_cnn_apply_gradient")
 
     def close(self):
         if getattr(self, "_h", None):
@@ -539,6 +622,10 @@ def cnn_make_batch(master, pc, lib_q, n, batch, first, seed, max_offset_px=5.0, 
     import torch
     dev = master.device
     x = x if x is not None else torch.empty((batch, 64, 64), dtype=torch.float32, device=dev)
+    _shape(x, (batch, 64, 64), "x")
+    _shape(labels, (batch,), "labels")
+    _shape(q_true, (batch, 4), "q_true")
+    _shape(lib_q, (None, 4), "lib_q")
     m, g = _master(master), _geo(pc)
     L = lib_q.shape[0] if lib_q is not None else 0
     _check(lib().ebsd_cnn_make_batch(ctypes.byref(m), ctypes.byref(g), _ptr(lib_q, torch.float64, "lib_q"), L, n,
@@ -551,6 +638,7 @@ def cnn_make_batch(master, pc, lib_q, n, batch, first, seed, max_offset_px=5.0, 
 
 def cnn_topk(logits, k):
     import torch
+    _shape(logits, (None, None), "logits")
     idx = torch.empty((logits.shape[0], k), dtype=torch.int32, device=logits.device)
     _check(lib().ebsd_cnn_topk(_ptr(logits, torch.float32, "logits"), logits.shape[0], logits.shape[1], k, _ptr(idx),
                                _stream()), "ebsd_cnn_topk")
@@ -559,7 +647,9 @@ def cnn_topk(logits, k):
 
 def index_proposed(patterns, master, pc, lib_q, cnn, top_k=32, fallback_tau=0.0, prm=None):
     import torch
-    p, n = patterns.shape[0], patterns.shape[-1]
+    p, n = _patterns(patterns)
+    _shape(lib_q, (None, 4), "lib_q")
+    _shape(master, (None, None), "master")
     dev = patterns.device
     out = dict(best_idx=torch.empty(p, dtype=torch.int32, device=dev),
                best_q=torch.empty((p, 4), dtype=torch.float64, device=dev),

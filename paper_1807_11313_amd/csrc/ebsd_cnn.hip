@@ -313,6 +313,17 @@ int ebsd_cnn_train_step(ebsd_cnn c, const float* x, const int32_t* labels, int64
   return EBSD_OK;
 }
 
+int ebsd_cnn_apply_gradient(ebsd_cnn c, const float* grad, float lr, void* stream) {
+  g_last_error.clear();
+  int rc;
+  if ((rc = check_cnn(c))) return rc;
+  if (!(lr > 0.0f)) return fail(EBSD_E_INVALID, "lr must be > 0");
+  if (!grad) return fail(EBSD_E_INVALID, "null pointer");
+  c->step += 1;
+  CN_TRY(cnn::adam(c->params, grad, c->m, c->v, c->lay.total, c->step, lr, (hipStream_t)stream), "adam");
+  return EBSD_OK;
+}
+
 int ebsd_cnn_make_batch(const ebsd_master* mp, const ebsd_geometry* geo, const double* lib_q, int64_t L, int32_t n,
                         int64_t B, int64_t first, uint64_t seed, double max_offset_px, double counts, double snr,
                         float* x, int32_t* labels, double* q_true, void* stream) {

@@ -427,7 +427,7 @@ __device__ __forceinline__ uint4 philox(uint64_t i, uint32_t stream, uint64_t se
   }
   return make_uint4(c0, c1, c2, c3);
 }
-// uniform in (0, 1)
+// uniform in (0, 1]: (53 bits + 1/2) / 2^53 (the top value rounds to 1)
 __device__ __forceinline__ double unit(uint32_t a, uint32_t b) {
   const uint64_t x = ((uint64_t)a << 21) ^ (uint64_t)(b >> 11);  // 53 bits
   return ((double)(x & ((1ull << 53) - 1)) + 0.5) * (1.0 / 9007199254740992.0);

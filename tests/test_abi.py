@@ -169,3 +169,50 @@ def test_so3_library_and_nn_argument_errors():
     assert lib.ebsd_nn_disorientation(vp(0x1000), 1, vp(0x2000), vp(0x3000), None) == -1
     assert lib.ebsd_nn_disorientation(vp(0x1000), 5, None, vp(0x3000), None) == -1
     assert lib.ebsd_nn_disorientation(None, 0, None, None, None) == 0
+
+
+def test_binding_rejects_mismatched_shapes_before_any_call():
+    # Every shape the kernels rely on is checked on the host before a pointer
+    # is taken or the library is called (CPU tensors here: a shape error must
+    # come before the device-tensor check)
+    import numpy as np
+    import torch
+    pkg, _ = _lib()
+    pats = torch.zeros((3, 64, 64))
+    master = torch.zeros((32, 32))
+    lib_q = torch.zeros((5, 4), dtype=torch.float64)
+    q = torch.zeros((3, 4), dtype=torch.float64)
+    ms = torch.zeros((3, 2))
+    pcs = torch.zeros((3, 3), dtype=torch.float64)
+    pc = (0.5, 0.5, 0.6)
+    cases = [
+        lambda: pkg.index_patterns(torch.zeros((3, 64, 63)), master, pc, lib_q),
+        lambda: pkg.index_patterns(torch.zeros((64, 64)), master, pc, lib_q),
+        lambda: pkg.index_patterns(pats, master, pc, torch.zeros((5, 3), dtype=torch.float64)),
+        lambda: pkg.index_patterns(pats, torch.zeros(32), pc, lib_q),
+        lambda: pkg.refine_orientations(pats, master, pc, q[:2]),
+        lambda: pkg.refine_orientations(pats, master, pc, q, pc_per=pcs[:2]),
+        lambda: pkg.refine_orientations(pats, master, pc, q, pc_per=torch.zeros((3, 2), dtype=torch.float64)),
+        lambda: pkg.refine_from_match(pats, master, pc, q, ms[:, :1]),
+        lambda: pkg.refine_from_match(pats, master, pc, q, torch.zeros((4, 2))),
+        lambda: pkg.refine_from_match(pats, master, pc, q, ms, pc_per=pcs[:1]),
+        lambda: pkg.project_templates(master, torch.zeros((3, 3), dtype=torch.float64), 64, pc),
+        lambda: pkg.project_templates(master, q, 64, pc, pc_per=pcs[:2]),
+        lambda: pkg.pattern_spectra(torch.zeros((2, 64, 32))),
+        lambda: pkg.measure_rotation(pats, pats[:2]),
+        lambda: pkg.xcf_scores(torch.zeros((2, 7)), torch.zeros((2, 7)), 64),
+        lambda: pkg.nn_disorientation(torch.zeros((4, 3), dtype=torch.float64)),
+        lambda: pkg.capture_range(master, torch.zeros((2, 3), dtype=torch.float64), 64, pc, pc,
+                                  torch.zeros(5, dtype=torch.float64)),
+    ]
+    for k, f in enumerate(cases):
+        with pytest.raises(ValueError):
+            f()
+    nf = pkg.spectrum_floats(64)
+    sp = torch.zeros((4, nf))
+    with pytest.raises(ValueError):
+        pkg.xcf_subpixel(sp, sp, torch.tensor([0, 4], dtype=torch.int32), torch.tensor([0, 1], dtype=torch.int32),
+                         torch.zeros((2, 2), dtype=torch.int32), 64)
+    with pytest.raises(ValueError):
+        pkg.xcf_peak(sp, sp, torch.tensor([0, 1], dtype=torch.int32), torch.tensor([0], dtype=torch.int32), 64)
+    assert np.all(np.isfinite([nf]))

@@ -20,7 +20,7 @@ from oracle import spectra as ospec
 from oracle import xcf as oxcf
 from oracle.params import Params as OParams
 
-from .gpu_util import banner, dev, host, tm
+from .gpu_util import banner, dev, host, oracle_spectra, oracle_templates, tm
 
 pytestmark = pytest.mark.gpu
 
@@ -57,8 +57,7 @@ def test_window_peak256_matches_oracle():
     banner("window peak n=256")
     t = tm()
     pats = _pats(4, seed=11, offsets=7.0)
-    spec = t.pattern_spectra(dev(pats))
-    band = t.spectra_to_complex(spec, N)
+    spec, _, full = oracle_spectra(pats, N)
     pairs = ((0, 1), (1, 2), (2, 3), (3, 0), (2, 2))
     pi = dev(np.array([a for a, _ in pairs], np.int32))
     li = dev(np.array([b for _, b in pairs], np.int32))
@@ -66,7 +65,7 @@ def test_window_peak256_matches_oracle():
         h, sh = t.xcf_peak(spec, spec, pi, li, N, t.params_default(max_shift=s))
         h, sh = host(h), host(sh)
         for k, (a, b) in enumerate(pairs):
-            ref = oxcf.xcf_map(t.band_to_full(band[a], N), t.band_to_full(band[b], N))
+            ref = oxcf.xcf_map(full[a], full[b])
             hr, sr = oxcf.integer_peak(ref, max_shift=s)
             assert (sh[k][1], sh[k][0]) == sr, (s, k)
             assert abs(h[k] - hr) < 5e-6
@@ -88,17 +87,19 @@ def test_subpixel256_matches_oracle():
     banner("subpixel n=256")
     t = tm()
     pats = _pats(3, seed=21)
-    spec = t.pattern_spectra(dev(pats))
-    band = t.spectra_to_complex(spec, N)
-    pi = dev(np.array([0, 1, 2], np.int32))
-    li = dev(np.array([1, 2, 0], np.int32))
+    spec, _, full = oracle_spectra(pats, N)
+    pairs = ((0, 1), (1, 2), (2, 0))
+    pi = dev(np.array([a for a, _ in pairs], np.int32))
+    li = dev(np.array([b for _, b in pairs], np.int32))
     prm = t.params_default(max_shift=15)
+    s_ref = [oxcf.integer_peak(oxcf.xcf_map(full[a], full[b]), max_shift=15)[1] for a, b in pairs]
+    s_int = dev(np.array([(sx, sy) for sy, sx in s_ref], np.int32))
     h, s = t.xcf_peak(spec, spec, pi, li, N, prm)
-    hs, ss = t.xcf_subpixel(spec, spec, pi, li, s, N, prm)
-    hs, ss, s = host(hs), host(ss), host(s)
-    for k, (a, b) in enumerate(((0, 1), (1, 2), (2, 0))):
-        ea, eb = t.band_to_full(band[a], N), t.band_to_full(band[b], N)
-        hr, sr = oxcf.subpixel_peak(ea, eb, (int(s[k][1]), int(s[k][0])), kappa=100)
+    assert np.array_equal(host(s), host(s_int))
+    hs, ss = t.xcf_subpixel(spec, spec, pi, li, s_int, N, prm)
+    hs, ss = host(hs), host(ss)
+    for k, (a, b) in enumerate(pairs):
+        hr, sr = oxcf.subpixel_peak(full[a], full[b], s_ref[k], kappa=100)
         assert abs(hs[k] - hr) < 1e-5
         assert abs(ss[k][0] - sr[1]) <= 0.02 + 1e-6 and abs(ss[k][1] - sr[0]) <= 0.02 + 1e-6
 
@@ -109,15 +110,13 @@ def test_gemm256_scores_match_oracle(prec):
     t = tm()
     pats = _pats(2, seed=31 + prec)
     lq = random_quats(np.random.default_rng(prec), 35)
-    tmpl = t.project_templates(dev(band_master()), dev(lq), N, (0.5, 0.5, 0.6))
-    sp, sl = t.pattern_spectra(dev(pats)), t.pattern_spectra(tmpl)
-    bp, bl = t.spectra_to_complex(sp, N), t.spectra_to_complex(sl, N)
-    fl = [t.band_to_full(bl[j], N) for j in range(len(lq))]
+    sp, _, fp = oracle_spectra(pats, N)
+    sl, _, fl = oracle_spectra(oracle_templates(band_master(), lq, N, (0.5, 0.5, 0.6)), N)
     for s in (7, 15):
         got = host(t.xcf_scores(sp, sl, N, t.params_default(precision=prec, max_shift=s)))
         err = 0.0
         for i in range(len(pats)):
-            ref = oxcf.library_scores(t.band_to_full(bp[i], N), fl, max_shift=s)
+            ref = oxcf.library_scores(fp[i], fl, max_shift=s)
             err = max(err, float(np.max(np.abs(got[i] - ref))))
         print("[gpu]   n=256 precision=%d S=%d max |dh| = %.3g" % (prec, s, err), flush=True)
         assert err < TOL[prec]

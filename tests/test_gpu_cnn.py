@@ -15,6 +15,7 @@ import torch
 
 from fixtures import band_master, random_fz_quats, random_quats, simulate_patterns
 from oracle import cnn as ocnn
+from oracle import generator as ogen
 
 from .gpu_util import banner, dev, host, tm
 
@@ -41,35 +42,56 @@ def test_network_input_matches_oracle():
         assert np.max(np.abs(x[k] - ocnn.network_input(pats[k]))) < 1e-5
 
 
-def test_batch_generator_labels_and_inputs():
-    banner("cnn batch generator")
+def test_batch_generator_matches_oracle():
+    # The on-device training-data generator against the oracle's, which draws
+    # the same Philox4x32-10 numbers from its own implementation: the
+    # orientations to 1e-12, the labels exactly, the noisy binned inputs to
+    # 1e-3 (unit variance; the FP32 projection differs from the FP64 one by
+    # ~2e-5 of the master's range before the scaling to counts)
+    banner("cnn batch generator vs oracle")
     t = tm()
+    master = band_master()
     lib, x, y, q = _batch(t, 120, 16, seed=3)
     x, y, q = host(x), host(y), host(q)
-    assert np.all(np.isfinite(x))
-    assert np.allclose(x.mean(axis=(1, 2)), 0.0, atol=1e-4) and np.allclose(x.std(axis=(1, 2)), 1.0, atol=1e-3)
-    assert np.allclose(np.linalg.norm(q, axis=1), 1.0, atol=1e-12) and np.all(q[:, 0] >= 0)
-    for j in range(16):
-        assert y[j] == ocnn.nearest_library(q[j], lib)
+    xr, yr, qr = ogen.make_batch(master, (0.5, 0.5, 0.6), lib, 128, 16, 1000, 3)
+    assert np.max(np.abs(q - qr)) < 1e-12
+    assert np.array_equal(y, yr)
+    err = np.max(np.abs(x - xr))
+    print("[gpu]   generator inputs max abs error %.2e" % err, flush=True)
+    assert err < 1e-3
     # the same counters give the same samples
     _, x2, y2, q2 = _batch(t, 120, 16, seed=3)
     assert np.array_equal(host(x2), x) and np.array_equal(host(q2), q)
+
+
+def _seeded_params(rng, n_cls):
+    """He-normal weights and small biases drawn on the host (seeded), so that
+    no oracle input comes from the device."""
+    parts = []
+    for name, s in ocnn.param_shapes(n_cls):
+        fan_in = int(np.prod(s[1:])) if len(s) > 1 else 1
+        scale = np.sqrt(2.0 / fan_in) if name.endswith(".w") else 0.05
+        parts.append(rng.normal(size=int(np.prod(s))) * scale)
+    return np.concatenate(parts).astype(np.float32)
 
 
 def test_forward_and_gradients_match_oracle():
     banner("cnn forward / backward vs oracle")
     t = tm()
     n_cls, bsz = 50, 4
+    rng = np.random.default_rng(5)
     net = t.Cnn(n_cls, seed=7)
-    _, x, y, _ = _batch(t, n_cls, bsz, seed=5)
-    params = host(net.get_params()).astype(np.float64)
-    xs, ys = host(x).astype(np.float64), host(y)
+    params = _seeded_params(rng, n_cls)
+    net.set_params(dev(params))
+    xs = rng.normal(size=(bsz, 64, 64)).astype(np.float32)
+    ys = rng.integers(0, n_cls, size=bsz).astype(np.int32)
+    x, y = dev(xs), dev(ys)
     logits = host(net.forward(x))
-    ref, _ = ocnn.forward(params, xs, n_cls)
+    ref, _ = ocnn.forward(params.astype(np.float64), xs.astype(np.float64), n_cls)
     assert np.max(np.abs(logits - ref)) <= 1e-4 * np.max(np.abs(ref))
     g, loss = net.gradients(x, y)
     g, loss = host(g).astype(np.float64), float(host(loss)[0])
-    lref, gref = ocnn.loss_and_grad(params, xs, ys, n_cls)
+    lref, gref = ocnn.loss_and_grad(params.astype(np.float64), xs.astype(np.float64), ys, n_cls)
     assert abs(loss - lref) <= 1e-5 * abs(lref)
     k = 0
     for name, s in ocnn.param_shapes(n_cls):
@@ -80,6 +102,51 @@ def test_forward_and_gradients_match_oracle():
         assert err < 1e-3, name
         k += m
     net.close()
+
+
+def test_adam_steps_match_oracle():
+    # three Adam steps from seeded gradients spanning eight decades (and a few
+    # exact zeros) against the FP64 oracle: 1e-6 relative to max(|w|, lr)
+    banner("cnn adam vs oracle")
+    t = tm()
+    n_cls = 20
+    rng = np.random.default_rng(12)
+    net = t.Cnn(n_cls, seed=3)
+    w = _seeded_params(rng, n_cls)
+    net.set_params(dev(w))
+    cnt = w.size
+    wr, m, v = w.astype(np.float64), np.zeros(cnt), np.zeros(cnt)
+    lr = 1e-3
+    for step in range(1, 4):
+        g = (rng.normal(size=cnt) * 10.0 ** rng.uniform(-7, 1, size=cnt)).astype(np.float32)
+        g[rng.integers(0, cnt, size=20)] = 0.0
+        net.apply_gradient(dev(g), lr)
+        wr, m, v = ocnn.adam_step(wr, g.astype(np.float64), m, v, step, lr)
+        got = host(net.get_params()).astype(np.float64)
+        err = np.max(np.abs(got - wr) / np.maximum(np.abs(wr), lr))
+        print("[gpu]   adam step %d: max relative error %.2e" % (step, err), flush=True)
+        assert err < 1e-6
+    net.close()
+
+
+def test_train_step_is_gradients_then_adam():
+    # train_step = gradients + one Adam step, bit for bit (same kernels)
+    t = tm()
+    n_cls = 30
+    rng = np.random.default_rng(13)
+    w = dev(_seeded_params(rng, n_cls))
+    a, b = t.Cnn(n_cls, seed=1), t.Cnn(n_cls, seed=2)
+    a.set_params(w)
+    b.set_params(w)
+    x = dev(rng.normal(size=(16, 64, 64)).astype(np.float32))
+    y = dev(rng.integers(0, n_cls, size=16).astype(np.int32))
+    for _ in range(2):
+        a.train_step(x, y, 1e-3)
+        g, _ = b.gradients(x, y)
+        b.apply_gradient(g, 1e-3)
+    assert torch.equal(a.get_params(), b.get_params())
+    a.close()
+    b.close()
 
 
 def test_set_params_round_trip_and_train_step_lowers_loss():

@@ -1,7 +1,7 @@
 """Parity of the split-precision DFT-GEMM search (MFMA) against the FP64 oracle.
 
-The oracle's windowed integer peak (|s_x|, |s_y| <= S) is evaluated on the
-GPU's own band spectra, so the bound measures only the GEMM arithmetic:
+Both sides start from the same float32 band spectra, made by the oracle from
+seeded images, so the bound measures only the GEMM arithmetic:
 FP16 hi + lo: 1e-4 (the FP32 height tolerance); BF16 hi + lo: 1e-3; plain
 BF16 (one product, ~3 significant digits per operand): 3e-2, reported.
 """
@@ -14,7 +14,7 @@ from fixtures import band_master, configs, random_quats, simulate_patterns
 from oracle import pipeline
 from oracle import xcf as oxcf
 
-from .gpu_util import banner, dev, host, tm
+from .gpu_util import banner, dev, host, oracle_spectra, oracle_templates, tm
 
 pytestmark = pytest.mark.gpu
 
@@ -38,15 +38,13 @@ def test_gemm_scores_match_oracle(n, prec):
     t = tm()
     pats, lq = _setup(n, 3, 37, seed=n + 7 * prec)
     master = band_master()
-    tmpl = t.project_templates(dev(master), dev(lq), n, (0.5, 0.5, 0.6))
-    sp, sl = t.pattern_spectra(dev(pats)), t.pattern_spectra(tmpl)
-    bp, bl = t.spectra_to_complex(sp, n), t.spectra_to_complex(sl, n)
-    fl = [t.band_to_full(bl[j], n) for j in range(len(lq))]
+    sp, _, fp = oracle_spectra(pats, n)
+    sl, _, fl = oracle_spectra(oracle_templates(master, lq, n, (0.5, 0.5, 0.6)), n)
     for s in (7, 15, 23):
         got = host(t.xcf_scores(sp, sl, n, t.params_default(precision=prec, max_shift=s)))
         err = 0.0
         for i in range(len(pats)):
-            ref = oxcf.library_scores(t.band_to_full(bp[i], n), fl, max_shift=s)
+            ref = oxcf.library_scores(fp[i], fl, max_shift=s)
             err = max(err, float(np.max(np.abs(got[i] - ref))))
         print("[gpu]   n=%d precision=%d S=%d max |dh| = %.3g" % (n, prec, s, err), flush=True)
         assert err < TOL[prec]
@@ -100,9 +98,8 @@ def test_gemm_scores_match_emulated_split(n, prec):
     banner("gemm vs emulated split n=%d precision=%d" % (n, prec))
     t = tm()
     pats, lq = _setup(n, 2, 20, seed=5 * n + prec)
-    tmpl = t.project_templates(dev(band_master()), dev(lq), n, (0.5, 0.5, 0.6))
-    sp, sl = t.pattern_spectra(dev(pats)), t.pattern_spectra(tmpl)
-    bp, bl = t.spectra_to_complex(sp, n), t.spectra_to_complex(sl, n)
+    sp, bp, _ = oracle_spectra(pats, n)
+    sl, bl, _ = oracle_spectra(oracle_templates(band_master(), lq, n, (0.5, 0.5, 0.6)), n)
     name = {1: "fp16x2", 2: "bf16x2", 3: "bf16"}[prec]
     for s in (7, 15):
         got = host(t.xcf_scores(sp, sl, n, t.params_default(precision=prec, max_shift=s)))

@@ -18,7 +18,7 @@ from oracle import spectra as ospec
 from oracle import xcf as oxcf
 from oracle.params import Params as OParams
 
-from .gpu_util import banner, dev, host, tm
+from .gpu_util import banner, dev, host, oracle_spectra, oracle_templates, tm
 
 pytestmark = pytest.mark.gpu
 
@@ -74,15 +74,13 @@ def test_xcf_map_and_integer_peak(n):
     banner("xcf map n=%d" % n)
     t = tm()
     _, _, pats = _pats(n, 6, seed=10 + n)
-    spec = t.pattern_spectra(dev(pats))
-    band = t.spectra_to_complex(spec, n)
+    spec, _, full = oracle_spectra(pats, n)               # the same float32 spectra on both sides
     pi = dev(np.array([0, 1, 2, 3, 4, 5, 0], np.int32))
     li = dev(np.array([0, 2, 2, 5, 1, 3, 4], np.int32))
     h, s, m = t.xcf_peak(spec, spec, pi, li, n, want_map=True)
     h, s, m = host(h), host(s), host(m)
     for k, (a, b) in enumerate(zip(host(pi), host(li))):
-        ea, eb = t.band_to_full(band[a], n), t.band_to_full(band[b], n)
-        ref = oxcf.xcf_map(ea, eb)                       # oracle transform on the GPU's spectra
+        ref = oxcf.xcf_map(full[a], full[b])
         assert np.max(np.abs(m[k] - ref)) < 5e-6
         hr, sr = oxcf.integer_peak(ref)
         assert (s[k][1], s[k][0]) == sr and abs(h[k] - hr) < 5e-6
@@ -93,14 +91,13 @@ def test_xcf_window(n):
     banner("xcf window n=%d" % n)
     t = tm()
     _, _, pats = _pats(n, 3, seed=20 + n, offsets=6.0)
-    spec = t.pattern_spectra(dev(pats))
-    band = t.spectra_to_complex(spec, n)
+    spec, _, full = oracle_spectra(pats, n)
     pi = dev(np.array([0, 1, 2], np.int32))
     li = dev(np.array([1, 2, 0], np.int32))
     h, s = t.xcf_peak(spec, spec, pi, li, n, t.params_default(max_shift=4))
     h, s = host(h), host(s)
     for k, (a, b) in enumerate(((0, 1), (1, 2), (2, 0))):
-        ref = oxcf.xcf_map(t.band_to_full(band[a], n), t.band_to_full(band[b], n))
+        ref = oxcf.xcf_map(full[a], full[b])
         hr, sr = oxcf.integer_peak(ref, max_shift=4)
         assert (s[k][1], s[k][0]) == sr and abs(h[k] - hr) < 5e-6
 
@@ -115,14 +112,11 @@ def test_windowed_scores_match_oracle(n, s):
     _, _, pats = _pats(n, p, seed=40 + n + s, offsets=4.0)
     master = band_master()
     lq = random_quats(np.random.default_rng(n + s), l)
-    tmpl = t.project_templates(dev(master), dev(lq), n, (0.5, 0.5, 0.6))
-    sp = t.pattern_spectra(dev(pats))
-    sl = t.pattern_spectra(tmpl)
+    sp, _, fp = oracle_spectra(pats, n)
+    sl, _, fl = oracle_spectra(oracle_templates(master, lq, n, (0.5, 0.5, 0.6)), n)
     sc = host(t.xcf_scores(sp, sl, n, t.params_default(max_shift=s)))
-    bp, bl = t.spectra_to_complex(sp, n), t.spectra_to_complex(sl, n)
-    fl = [t.band_to_full(bl[j], n) for j in range(l)]
     for i in range(p):
-        ref = oxcf.library_scores(t.band_to_full(bp[i], n), fl, max_shift=s)
+        ref = oxcf.library_scores(fp[i], fl, max_shift=s)
         assert np.max(np.abs(sc[i] - ref)) < 5e-6
 
 
@@ -136,14 +130,11 @@ def test_scores_match_oracle(n, p, l):
     _, _, pats = _pats(n, p, seed=30 + n)
     master = band_master()
     lq = random_quats(np.random.default_rng(n), l)
-    tmpl = t.project_templates(dev(master), dev(lq), n, (0.5, 0.5, 0.6))
-    sp = t.pattern_spectra(dev(pats))
-    sl = t.pattern_spectra(tmpl)
+    sp, _, fp = oracle_spectra(pats, n)
+    sl, _, fl = oracle_spectra(oracle_templates(master, lq, n, (0.5, 0.5, 0.6)), n)
     sc = host(t.xcf_scores(sp, sl, n))
-    bp, bl = t.spectra_to_complex(sp, n), t.spectra_to_complex(sl, n)
-    fl = [t.band_to_full(bl[j], n) for j in range(l)]
     for i in range(p):
-        ref = oxcf.library_scores(t.band_to_full(bp[i], n), fl)
+        ref = oxcf.library_scores(fp[i], fl)
         assert np.max(np.abs(sc[i] - ref)) < 5e-6
 
 
@@ -152,17 +143,19 @@ def test_subpixel_matches_oracle(n):
     banner("subpixel n=%d" % n)
     t = tm()
     _, _, pats = _pats(n, 4, seed=40 + n)
-    spec = t.pattern_spectra(dev(pats))
-    band = t.spectra_to_complex(spec, n)
-    # pattern k against a sub-pixel shifted copy of itself and against a neighbour
-    pi = dev(np.array([0, 1, 2, 3], np.int32))
-    li = dev(np.array([1, 2, 3, 0], np.int32))
+    spec, _, full = oracle_spectra(pats, n)
+    pairs = ((0, 1), (1, 2), (2, 3), (3, 0))
+    pi = dev(np.array([a for a, _ in pairs], np.int32))
+    li = dev(np.array([b for _, b in pairs], np.int32))
+    # the oracle's integer peaks (x, y) start the upsampling on both sides
+    s_ref = [oxcf.integer_peak(oxcf.xcf_map(full[a], full[b]))[1] for a, b in pairs]
+    s_int = dev(np.array([(sx, sy) for sy, sx in s_ref], np.int32))
     h, s = t.xcf_peak(spec, spec, pi, li, n)
-    hs, ss = t.xcf_subpixel(spec, spec, pi, li, s, n)
-    hs, ss, s = host(hs), host(ss), host(s)
-    for k, (a, b) in enumerate(((0, 1), (1, 2), (2, 3), (3, 0))):
-        ea, eb = t.band_to_full(band[a], n), t.band_to_full(band[b], n)
-        hr, sr = oxcf.subpixel_peak(ea, eb, (int(s[k][1]), int(s[k][0])), kappa=100)
+    assert np.array_equal(host(s), host(s_int))
+    hs, ss = t.xcf_subpixel(spec, spec, pi, li, s_int, n)
+    hs, ss = host(hs), host(ss)
+    for k, (a, b) in enumerate(pairs):
+        hr, sr = oxcf.subpixel_peak(full[a], full[b], s_ref[k], kappa=100)
         assert abs(hs[k] - hr) < 1e-5
         assert abs(ss[k][0] - sr[1]) <= 0.02 + 1e-6 and abs(ss[k][1] - sr[0]) <= 0.02 + 1e-6
 

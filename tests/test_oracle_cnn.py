@@ -106,3 +106,38 @@ def test_network_input_bins_and_normalises():
     assert abs(x.mean()) < 1e-12 and abs(x.std() - 1) < 1e-12
     with pytest.raises(ValueError):
         cnn.network_input(np.zeros((96, 96)))
+
+
+def test_adam_constant_gradient_moves_by_lr():
+    # For a constant gradient the bias corrections are exact: m_hat = g and
+    # v_hat = g^2 at every step, so each step moves every parameter by
+    # lr g / (|g| + eps) (a step without the bias correction moves the first
+    # step by lr (1 - b1) / sqrt(1 - b2) = 3.16 lr instead)
+    rng = np.random.default_rng(10)
+    w0 = rng.normal(size=50)
+    g = rng.normal(size=50) * np.logspace(-6, 2, 50)
+    w, m, v = w0.copy(), np.zeros(50), np.zeros(50)
+    lr = 1e-3
+    for t in range(1, 6):
+        w, m, v = cnn.adam_step(w, g, m, v, t, lr)
+        assert np.allclose(w, w0 - t * lr * g / (np.abs(g) + 1e-8), atol=1e-15, rtol=1e-12)
+    # zero gradient: nothing moves
+    w2, _, _ = cnn.adam_step(w0, np.zeros(50), np.zeros(50), np.zeros(50), 1, lr)
+    assert np.array_equal(w2, w0)
+
+
+def test_adam_alternating_gradient_geometric_series():
+    # g_k = (-1)^(k+1): v_hat = 1 exactly, and m_t = (1 - b1) sum_k b1^(t-k) g_k
+    # is a geometric series, m_t = (1 - b1) (-1)^(t+1) (1 - (-b1)^t) / (1 + b1),
+    # so the step is lr m_t / ((1 - b1^t)(1 + eps)).  Swapped betas or a
+    # moment update with the weights exchanged fail this.
+    b1 = 0.9
+    lr = 0.01
+    w, m, v = np.zeros(1), np.zeros(1), np.zeros(1)
+    for t in range(1, 9):
+        g = np.array([(-1.0) ** (t + 1)])
+        w_new, m, v = cnn.adam_step(w, g, m, v, t, lr)
+        m_t = (1 - b1) * (-1.0) ** (t + 1) * (1 - (-b1) ** t) / (1 + b1)
+        assert abs(m[0] - m_t) < 1e-15
+        assert abs((w - w_new)[0] - lr * m_t / ((1 - b1 ** t) * (1 + 1e-8))) < 1e-15
+        w = w_new
