@@ -394,14 +394,17 @@ __global__ void k_mean_loss(const double* __restrict__ loss_row, int bsz, float*
   *loss = (float)(s / bsz);
 }
 
-// Adam (Kingma and Ba), bias-corrected step sizes precomputed on the host
+// Adam (Kingma and Ba), bias-corrected step sizes precomputed on the host;
+// the weights 1 - b1 and 1 - b2 come rounded from double (1.0f - 0.999f
+// would be 1.3e-5 off 0.001)
 __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, int64_t n, float lr_t, float b1, float b2, float eps_t) {
+                       float* __restrict__ v, int64_t n, float lr_t, float b1, float b2, float omb1, float omb2,
+                       float eps_t) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
-  const float mi = b1 * m[i] + (1.0f - b1) * gi;
-  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  const float mi = b1 * m[i] + omb1 * gi;
+  const float vi = b2 * v[i] + omb2 * (gi * gi);
   m[i] = mi;
   v[i] = vi;
   w[i] -= lr_t * mi / (sqrtf(vi) + eps_t);
@@ -787,7 +790,7 @@ hipError_t adam(float* params, const float* grad, float* m, float* v, int64_t n,
   const float lr_t = (float)(lr * sqrt(c2) / c1);
   const float eps_t = (float)(eps * sqrt(c2));
   hipLaunchKernelGGL(k_adam, dim3(nb(n)), dim3(256), 0, st, params, grad, m, v, n, lr_t, (float)b1, (float)b2,
-                     eps_t);
+                     (float)(1.0 - b1), (float)(1.0 - b2), eps_t);
   return hipGetLastError();
 }
 
