@@ -205,6 +205,28 @@ typedef struct {
 int ebsd_pc_map(const ebsd_pc_model* model, int64_t P, double* pc_out, void* stream);
 
 /*
+ * ebsd_refine_orientations without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * ebsd_refine_orientations (bit for bit); its scratch is one static device
+ * array of 256 MiB per GPU, held from the library's first use on that GPU
+ * until the process ends.  A batch needs per pattern
+ * 4 n^2 + 16 (2B+1)(B+1) + 8 n_rho n_eta + 32 bytes (B = 3n/8), at n = 256
+ * another 198,768 bytes of transform scratch, plus tables of a few KB and
+ * 256-byte alignment of each buffer: at the default parameters at most
+ * about 980 patterns of 128 x 128, or 200 of 256 x 256, per call.
+ * Larger batches return EBSD_E_INVALID (the message states the bytes needed)
+ * before anything is enqueued.  Nothing in the scratch needs to start at
+ * zero: every buffer is written before it is read.  All calls on one GPU
+ * share its array, which keeps the last call's contents: calls that overlap
+ * in time on one GPU (different streams or threads) race and must be
+ * serialised by the caller.
+ */
+int ebsd_refine_orientations_noalloc(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo,
+                                     const double* q_init, const ebsd_params* prm, double* q_out, float* peak_h,
+                                     float* shift, void* stream);
+
+/*
  * Refinement that starts from the search's own measurement (section
  * "Orientation and Pattern Centre Refinement": one library at one pattern
  * centre; the shift measured against it is corrected for the beam-induced

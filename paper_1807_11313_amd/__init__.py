@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(HERE, "libebsd_tm.so")
 
 # Every function the header declares.
 EXPORTS = ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_index_patterns",
-           "ebsd_refine_orientations", "ebsd_project_templates", "ebsd_pattern_spectra",
+           "ebsd_refine_orientations", "ebsd_refine_orientations_noalloc", "ebsd_project_templates", "ebsd_pattern_spectra",
            "ebsd_spectrum_floats", "ebsd_xcf_peak", "ebsd_xcf_scores", "ebsd_xcf_subpixel",
            "ebsd_measure_rotation", "ebsd_timing_enable", "ebsd_timing_read", "ebsd_ragged_plan_create",
            "ebsd_ragged_run", "ebsd_ragged_plan_tiles", "ebsd_ragged_plan_destroy", "ebsd_cnn_param_count",
@@ -93,6 +93,8 @@ def lib():
     L.ebsd_index_patterns.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, i64, dp(Params), vp, vp, vp, vp,
                                       vp, vp]
     L.ebsd_refine_orientations.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, dp(Params), vp, vp, vp, vp]
+    L.ebsd_refine_orientations_noalloc.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, dp(Params), vp, vp, vp,
+                                                   vp]
     L.ebsd_refine_from_match.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, vp, dp(Params), vp, vp, vp, vp]
     L.ebsd_pc_map.argtypes = [dp(PcModel), i64, vp, vp]
     L.ebsd_so3_library.argtypes = [ctypes.c_double, vp, i64, dp(i64), vp]
@@ -232,23 +234,30 @@ def index_patterns(patterns, master, pc, lib_q, prm=None, scores=False):
     return out
 
 
-def refine_orientations(patterns, master, pc, q_init, pc_per=None, prm=None):
-    """Returns dict(q, peak_h, shift) as CUDA tensors."""
+def refine_orientations(patterns, master, pc, q_init, pc_per=None, prm=None, out=None, noalloc=False):
+    """Returns dict(q, peak_h, shift) as CUDA tensors (or fills `out`, a dict
+    of such tensors).  noalloc=True calls ebsd_refine_orientations_noalloc,
+    which allocates no device memory (the binding allocates none either when
+    `out` is given)."""
     import torch
     p, n = _patterns(patterns)
     _shape(q_init, (p, 4), "q_init")
     _shape(pc_per, (p, 3), "pc_per")
     _shape(master, (None, None), "master")
     dev = patterns.device
-    out = dict(q=torch.empty((p, 4), dtype=torch.float64, device=dev),
-               peak_h=torch.empty(p, dtype=torch.float32, device=dev),
-               shift=torch.empty((p, 2), dtype=torch.float32, device=dev))
+    if out is None:
+        out = dict(q=torch.empty((p, 4), dtype=torch.float64, device=dev),
+                   peak_h=torch.empty(p, dtype=torch.float32, device=dev),
+                   shift=torch.empty((p, 2), dtype=torch.float32, device=dev))
+    for key, shape in (("q", (p, 4)), ("peak_h", (p,)), ("shift", (p, 2))):
+        _shape(out[key], shape, key)
     batch = Batch(_ptr(patterns, torch.float32, "patterns").value, p, n)
-    rc = lib().ebsd_refine_orientations(ctypes.byref(batch), ctypes.byref(_master(master)),
-                                        ctypes.byref(_geo(pc, pc_per, p)), _ptr(q_init, torch.float64, "q_init"),
-                                        _params(prm), _ptr(out["q"]), _ptr(out["peak_h"]), _ptr(out["shift"]),
-                                        _stream())
-    _check(rc, "ebsd_refine_orientations")
+    name = "ebsd_refine_orientations_noalloc" if noalloc else "ebsd_refine_orientations"
+    rc = getattr(lib(), name)(ctypes.byref(batch), ctypes.byref(_master(master)), ctypes.byref(_geo(pc, pc_per, p)),
+                              _ptr(q_init, torch.float64, "q_init"), _params(prm),
+                              _ptr(out["q"], torch.float64, "q"), _ptr(out["peak_h"], torch.float32, "peak_h"),
+                              _ptr(out["shift"], torch.float32, "shift"), _stream())
+    _check(rc, name)
     return out
 
 

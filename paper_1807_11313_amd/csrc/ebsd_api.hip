@@ -11,6 +11,7 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -37,28 +38,61 @@ int fail_hip(hipError_t e, const char* where) {
     if (e_ != hipSuccess) return fail_hip(e_, where); \
   } while (0)
 
+// Where an entry point's device scratch comes from.
+class Arena {
+ public:
+  virtual ~Arena() = default;
+  virtual void* raw(size_t bytes, hipError_t* err) = 0;
+  template <class T>
+  T* get(size_t count, hipError_t* err) {
+    return static_cast<T*>(raw((count ? count : 1) * sizeof(T), err));
+  }
+};
+
 // Scratch allocated in stream order on the caller's stream and released in
 // stream order when the call returns; the device memory pool keeps it for
 // the next call, so repeated calls do not reach the kernel-mode allocator.
-class Scratch {
+class Scratch : public Arena {
  public:
   explicit Scratch(hipStream_t s) : stream_(s) {}
-  ~Scratch() {
+  ~Scratch() override {
     for (void* p : ptrs_) (void)hipFreeAsync(p, stream_);
   }
-  template <class T>
-  T* get(size_t count, hipError_t* err) {
+  void* raw(size_t bytes, hipError_t* err) override {
     void* p = nullptr;
-    if (count == 0) count = 1;
-    *err = hipMallocAsync(&p, count * sizeof(T), stream_);
+    *err = hipMallocAsync(&p, bytes, stream_);
     if (*err != hipSuccess) return nullptr;
     ptrs_.push_back(p);
-    return static_cast<T*>(p);
+    return p;
   }
 
  private:
   hipStream_t stream_;
   std::vector<void*> ptrs_;
+};
+
+// Consecutive 256-byte aligned pieces of one caller-given device buffer
+// (base may be null: the arena then only adds up the bytes it would hand
+// out, to size a call before anything is enqueued).
+class FixedArena : public Arena {
+ public:
+  FixedArena(void* base, size_t cap) : base_(static_cast<char*>(base)), cap_(cap) {}
+  void* raw(size_t bytes, hipError_t* err) override {
+    const size_t at = (used_ + 255) & ~size_t(255);
+    if (at + bytes > cap_ || at + bytes < at) {
+      *err = hipErrorOutOfMemory;
+      return nullptr;
+    }
+    used_ = at + bytes;
+    *err = hipSuccess;
+    return base_ ? base_ + at : reinterpret_cast<void*>(at + 256);
+  }
+  size_t used() const { return used_; }
+
+ private:
+  char* base_;
+  size_t cap_;
+  size_t used_ = 0;
 };
 
 #define EBSD_ALLOC(var, T, count, scratch)                                   \
@@ -120,11 +154,15 @@ FilterParams filter_of(const ebsd_params& p, int n) {
 }
 
 // Spectra of K contiguous images: one kernel up to 160, three passes through
-// stream-ordered scratch at 256.
+// scratch at 256 (s256: spectra256_scratch_bytes(k) bytes, or taken from ws
+// when null).
 int do_spectra(int n, const float* imgs, int64_t k, const FilterParams& fp, float2* spec, double* energy,
-               Scratch& ws, hipStream_t st) {
+               Arena& ws, hipStream_t st, void* s256 = nullptr) {
   if (n == 256) {
-    EBSD_ALLOC(s256, unsigned char, spectra256_scratch_bytes(k), ws);
+    if (!s256) {
+      EBSD_ALLOC(buf, unsigned char, spectra256_scratch_bytes(k), ws);
+      s256 = buf;
+    }
     EBSD_TRY(launch_spectra256(imgs, k, fp, spec, energy, s256, st), "spectra256");
     return EBSD_OK;
   }
@@ -133,17 +171,21 @@ int do_spectra(int n, const float* imgs, int64_t k, const FilterParams& fp, floa
 }
 
 // Integer peak of explicit pairs: the full-map FFT form where it exists,
-// otherwise the exact shift-window evaluation (needs max_shift >= 0).
+// otherwise the exact shift-window evaluation (needs max_shift >= 0) with
+// the phase tables tab (built here into ws when null).
 int do_peak(int n, const ebsd_params& p, const float2* sp, const float2* sl, const int32_t* pi, const int32_t* li,
-            int64_t k, float* h, int32_t* s, Scratch& ws, hipStream_t st) {
+            int64_t k, float* h, int32_t* s, Arena& ws, hipStream_t st, const float2* tab = nullptr) {
   if (fft_supported(n)) {
     EBSD_TRY(launch_xcf_peak(n, sp, sl, pi, li, k, p.max_shift, h, s, nullptr, st), "xcf_peak");
     return EBSD_OK;
   }
   if (!window_peak_supported(n, p.max_shift))
     return fail(EBSD_E_UNSUPPORTED, "this size needs a shift window (max_shift >= 0) for the integer peak");
-  EBSD_ALLOC(tab, float2, window_table_size(n, p.max_shift), ws);
-  EBSD_TRY(launch_window_tables(n, p.max_shift, tab, st), "window tables");
+  if (!tab) {
+    EBSD_ALLOC(t, float2, window_table_size(n, p.max_shift), ws);
+    EBSD_TRY(launch_window_tables(n, p.max_shift, t, st), "window tables");
+    tab = t;
+  }
   EBSD_TRY(launch_window_peak(n, sp, sl, pi, li, k, p.max_shift, tab, h, s, st), "window peak");
   return EBSD_OK;
 }
@@ -429,34 +471,36 @@ int ebsd_index_patterns(const ebsd_batch* pats, const ebsd_master* mp, const ebs
 
 }  // extern "C"
 
+// Scratch of the allocation-free refinement: one file-scope device array,
+// which each GPU the library runs on holds until the process ends.  In host
+// code its name is not a device address; the address of each device's copy
+// comes from hipGetSymbolAddress on the first call on that device.
+constexpr size_t kNoAllocBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 namespace {
 
-// The refinement of both entry points; match_shift (may be NULL) replaces the
-// first iteration's projection and correlation by the search's shift less
-// the beam-induced PC translation.
-int refine_impl(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo, const double* q_init,
-                const float* match_shift, const ebsd_params* prm, double* q_out, float* peak_h, float* shift,
-                void* stream) {
-  int rc;
-  if (!pats) return fail(EBSD_E_INVALID, "null batch");
-  const int n = pats->n;
-  ebsd_params p;
-  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p)) || (rc = check_master(mp)) ||
-      (rc = check_geometry(geo)))
-    return rc;
-  const int64_t P = pats->P;
-  if (P < 0) return fail(EBSD_E_INVALID, "P must be >= 0");
-  if (P > 0x7fffffffLL) return fail(EBSD_E_INVALID, "P must fit in int32");
-  if (P == 0) return EBSD_OK;
-  if (!pats->data || !q_init || !q_out || !peak_h || !shift) return fail(EBSD_E_INVALID, "null pointer");
-  if (!fft_supported(n) && !window_peak_supported(n, p.max_shift))
-    return fail(EBSD_E_UNSUPPORTED, "at this size the peak needs a shift window (max_shift >= 0)");
+// Every device buffer of one refinement call, taken from one arena before
+// anything is enqueued.
+struct RefineBufs {
+  float* tmpl;
+  float2* spec_p;
+  float2* spec_t;
+  float* lp_e;
+  float* lp_t;
+  float* h_int;
+  float* h_sub;
+  int32_t* s_int;
+  float* s_sub;
+  double* gam;
+  float2* roots;
+  void* s256;     // spectra scratch at 256 (null below)
+  float2* wtab;   // shift-window phase tables (null where the FFT form runs)
+};
 
-  hipStream_t st = (hipStream_t)stream;
-  Scratch ws(st);
+int alloc_refine(Arena& ws, int n, int64_t P, const ebsd_params& p, RefineBufs* b) {
   const int64_t sc = spec_complex(n);
   const int64_t npix = (int64_t)n * n;
-  const FilterParams fp = filter_of(p, n);
   const int64_t lp = (int64_t)p.n_rho * p.n_eta;
   EBSD_ALLOC(tmpl, float, npix * P, ws);
   EBSD_ALLOC(spec_p, float2, sc * P, ws);
@@ -469,18 +513,63 @@ int refine_impl(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geomet
   EBSD_ALLOC(s_sub, float, 2 * P, ws);
   EBSD_ALLOC(gam, double, P, ws);
   EBSD_ALLOC(roots, float2, subpixel_table_size(n, p.upsample), ws);
+  *b = RefineBufs{tmpl, spec_p, spec_t, lp_e, lp_t, h_int, h_sub, s_int, s_sub, gam, roots, nullptr, nullptr};
+  if (n == 256) {
+    EBSD_ALLOC(s256, unsigned char, spectra256_scratch_bytes(P), ws);
+    b->s256 = s256;
+  }
+  if (!fft_supported(n)) {
+    EBSD_ALLOC(wtab, float2, window_table_size(n, p.max_shift), ws);
+    b->wtab = wtab;
+  }
+  return EBSD_OK;
+}
 
+// Validates the arguments of a refinement call; P = 0 leaves *n = 0.
+int check_refine(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo, const double* q_init,
+                 const ebsd_params* prm, double* q_out, float* peak_h, float* shift, ebsd_params* p, int* n_out) {
+  int rc;
+  *n_out = 0;
+  if (!pats) return fail(EBSD_E_INVALID, "null batch");
+  const int n = pats->n;
+  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, p)) || (rc = check_master(mp)) ||
+      (rc = check_geometry(geo)))
+    return rc;
+  const int64_t P = pats->P;
+  if (P < 0) return fail(EBSD_E_INVALID, "P must be >= 0");
+  if (P > 0x7fffffffLL) return fail(EBSD_E_INVALID, "P must fit in int32");
+  if (P == 0) return EBSD_OK;
+  if (!pats->data || !q_init || !q_out || !peak_h || !shift) return fail(EBSD_E_INVALID, "null pointer");
+  if (!fft_supported(n) && !window_peak_supported(n, p->max_shift))
+    return fail(EBSD_E_UNSUPPORTED, "at this size the peak needs a shift window (max_shift >= 0)");
+  *n_out = n;
+  return EBSD_OK;
+}
+
+// The kernel sequence of the refinement on buffers b; match_shift (may be
+// NULL) replaces the first iteration's projection and correlation by the
+// search's shift less the beam-induced PC translation.
+int refine_run(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo, const double* q_init,
+               const float* match_shift, const ebsd_params& p, const RefineBufs& b, double* q_out, float* peak_h,
+               float* shift, hipStream_t st) {
+  int rc;
+  const int n = pats->n;
+  const int64_t P = pats->P;
+  const FilterParams fp = filter_of(p, n);
+  FixedArena none(nullptr, 0);   // every buffer is in b: nothing more may be taken
   if (q_out != q_init) EBSD_TRY(hipMemcpyAsync(q_out, q_init, sizeof(double) * 4 * P, hipMemcpyDeviceToDevice, st), "copy q");
-  EBSD_TRY(launch_subpixel_tables(n, p.upsample, roots, st), "subpixel tables");
-  if ((rc = do_spectra(n, pats->data, P, fp, spec_p, nullptr, ws, st))) return rc;
-  EBSD_TRY(launch_logpolar(n, pats->data, P, p.n_rho, p.n_eta, lp_e, st), "logpolar(patterns)");
+  EBSD_TRY(launch_subpixel_tables(n, p.upsample, b.roots, st), "subpixel tables");
+  if (b.wtab) EBSD_TRY(launch_window_tables(n, p.max_shift, b.wtab, st), "window tables");
+  if ((rc = do_spectra(n, pats->data, P, fp, b.spec_p, nullptr, none, st, b.s256))) return rc;
+  EBSD_TRY(launch_logpolar(n, pats->data, P, p.n_rho, p.n_eta, b.lp_e, st), "logpolar(patterns)");
   const double* pcp = geo->pc_per;
   auto measure_shift = [&](float* h_out, float* s_out) -> int {
-    EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, q_out, P, pcp, geo->pcx, geo->pcy, geo->pcz, tmpl, st),
+    EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, q_out, P, pcp, geo->pcx, geo->pcy, geo->pcz, b.tmpl, st),
              "project");
-    if (int e = do_spectra(n, tmpl, P, fp, spec_t, nullptr, ws, st)) return e;
-    if (int e = do_peak(n, p, spec_p, spec_t, nullptr, nullptr, P, h_int, s_int, ws, st)) return e;
-    EBSD_TRY(launch_subpixel(n, spec_p, spec_t, nullptr, nullptr, P, s_int, p.upsample, roots, h_out, s_out, st),
+    if (int e = do_spectra(n, b.tmpl, P, fp, b.spec_t, nullptr, none, st, b.s256)) return e;
+    if (int e = do_peak(n, p, b.spec_p, b.spec_t, nullptr, nullptr, P, b.h_int, b.s_int, none, st, b.wtab)) return e;
+    EBSD_TRY(launch_subpixel(n, b.spec_p, b.spec_t, nullptr, nullptr, P, b.s_int, p.upsample, b.roots, h_out, s_out,
+                             st),
              "subpixel");
     return EBSD_OK;
   };
@@ -489,16 +578,50 @@ int refine_impl(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geomet
     if (it == 0 && match_shift) {
       EBSD_TRY(launch_update_xy(q_out, match_shift, P, pcp, geo->pcz, n, st, pc0), "update_xy(match)");
     } else {
-      if ((rc = measure_shift(h_sub, s_sub))) return rc;
-      EBSD_TRY(launch_update_xy(q_out, s_sub, P, pcp, geo->pcz, n, st), "update_xy");
+      if ((rc = measure_shift(b.h_sub, b.s_sub))) return rc;
+      EBSD_TRY(launch_update_xy(q_out, b.s_sub, P, pcp, geo->pcz, n, st), "update_xy");
     }
-    EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, q_out, P, pcp, geo->pcx, geo->pcy, geo->pcz, tmpl, st),
+    EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, q_out, P, pcp, geo->pcx, geo->pcy, geo->pcz, b.tmpl, st),
              "project");
-    EBSD_TRY(launch_logpolar(n, tmpl, P, p.n_rho, p.n_eta, lp_t, st), "logpolar(templates)");
-    EBSD_TRY(launch_eta_peak(lp_e, lp_t, P, p.n_rho, p.n_eta, p.upsample, gam, st), "eta_peak");
-    EBSD_TRY(launch_update_z(q_out, gam, P, st), "update_z");
+    EBSD_TRY(launch_logpolar(n, b.tmpl, P, p.n_rho, p.n_eta, b.lp_t, st), "logpolar(templates)");
+    EBSD_TRY(launch_eta_peak(b.lp_e, b.lp_t, P, p.n_rho, p.n_eta, p.upsample, b.gam, st), "eta_peak");
+    EBSD_TRY(launch_update_z(q_out, b.gam, P, st), "update_z");
   }
   if ((rc = measure_shift(peak_h, shift))) return rc;
+  return EBSD_OK;
+}
+
+// The refinement of both pool-backed entry points.
+int refine_impl(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo, const double* q_init,
+                const float* match_shift, const ebsd_params* prm, double* q_out, float* peak_h, float* shift,
+                void* stream) {
+  int rc, n;
+  ebsd_params p;
+  if ((rc = check_refine(pats, mp, geo, q_init, prm, q_out, peak_h, shift, &p, &n))) return rc;
+  if (n == 0) return EBSD_OK;
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  RefineBufs b;
+  if ((rc = alloc_refine(ws, n, pats->P, p, &b))) return rc;
+  return refine_run(pats, mp, geo, q_init, match_shift, p, b, q_out, peak_h, shift, st);
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(void** out) {
+  int dev = -1;
+  EBSD_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(EBSD_E_UNSUPPORTED, "device ordinal beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    EBSD_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(EBSD_E_DEVICE, "hipGetSymbolAddress(scratch) returned null");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
   return EBSD_OK;
 }
 
@@ -511,6 +634,33 @@ int ebsd_refine_orientations(const ebsd_batch* pats, const ebsd_master* mp, cons
                              float* shift, void* stream) {
   g_last_error.clear();
   return refine_impl(pats, mp, geo, q_init, nullptr, prm, q_out, peak_h, shift, stream);
+}
+
+int ebsd_refine_orientations_noalloc(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo,
+                                     const double* q_init, const ebsd_params* prm, double* q_out, float* peak_h,
+                                     float* shift, void* stream) {
+  g_last_error.clear();
+  int rc, n;
+  ebsd_params p;
+  if ((rc = check_refine(pats, mp, geo, q_init, prm, q_out, peak_h, shift, &p, &n))) return rc;
+  if (n == 0) return EBSD_OK;
+  // size the call first: nothing is enqueued if it does not fit
+  FixedArena sizing(nullptr, kNoAllocBytes);
+  RefineBufs b;
+  if (alloc_refine(sizing, n, pats->P, p, &b) != EBSD_OK) {
+    FixedArena need(nullptr, ~size_t(0));
+    (void)alloc_refine(need, n, pats->P, p, &b);
+    char msg[200];
+    std::snprintf(msg, sizeof(msg),
+                  "batch needs %zu bytes of scratch, above the static %zu (%lld patterns of %d x %d)", need.used(),
+                  kNoAllocBytes, (long long)pats->P, n, n);
+    return fail(EBSD_E_INVALID, msg);
+  }
+  void* base = nullptr;
+  if ((rc = scratch_of_current_device(&base))) return rc;
+  FixedArena arena(base, kNoAllocBytes);
+  if ((rc = alloc_refine(arena, n, pats->P, p, &b))) return rc;
+  return refine_run(pats, mp, geo, q_init, nullptr, p, b, q_out, peak_h, shift, (hipStream_t)stream);
 }
 
 int ebsd_refine_from_match(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometry* geo,

@@ -216,3 +216,30 @@ def test_binding_rejects_mismatched_shapes_before_any_call():
     with pytest.raises(ValueError):
         pkg.xcf_peak(sp, sp, torch.tensor([0, 1], dtype=torch.int32), torch.tensor([0], dtype=torch.int32), 64)
     assert np.all(np.isfinite([nf]))
+
+
+def test_noalloc_refine_rejects_on_the_host():
+    # ebsd_refine_orientations_noalloc sizes the call before anything else:
+    # argument errors and batches beyond its static scratch return
+    # EBSD_E_INVALID (the message stating the bytes needed) without a device
+    # call; an empty batch is a no-op
+    pkg, lib = _lib()
+    m = pkg.Master(0x1000, 256, 256)
+    g = pkg.Geometry(0.5, 0.5, 0.6, None)
+    prm = pkg.params_default()
+
+    def call(batch, q=0x2000, prm=prm):
+        return lib.ebsd_refine_orientations_noalloc(ctypes.byref(batch) if batch is not None else None,
+                                                    ctypes.byref(m), ctypes.byref(g), ctypes.c_void_p(q),
+                                                    ctypes.byref(prm), ctypes.c_void_p(0x3000),
+                                                    ctypes.c_void_p(0x4000), ctypes.c_void_p(0x5000), None)
+
+    assert call(None) == -1
+    assert call(pkg.Batch(0x6000, 4, 100)) == -4
+    assert call(pkg.Batch(0x6000, 4, 64), q=0) == -1
+    assert call(pkg.Batch(0x6000, 4, 256)) == -4             # 256 needs a shift window
+    assert call(pkg.Batch(0x6000, 0, 64)) == 0
+    for n, p in ((64, 4000), (128, 1000), (160, 700), (256, 210)):
+        assert call(pkg.Batch(0x6000, p, n), prm=pkg.params_default(max_shift=12)) == -1
+        msg = lib.ebsd_last_error().decode()
+        assert "static" in msg and "bytes" in msg, msg
