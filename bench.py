@@ -64,34 +64,92 @@ def kernel_source_hash(prof):
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(cfg, n, l_full, p_full):
-    """Times the FP64 oracle on a bounded sample and extrapolates to the full
-    workload: L template projections + spectra, P x L correlations, P
-    refinements."""
-    import numpy as np
-    import oracle
-    from oracle import geometry, pipeline, rotations, spectra, xcf
+def _cpu_threads():
+    """Host threads this process may use (the GPU machine's CPU share is 16)."""
+    try:
+        c = len(os.sched_getaffinity(0))
+    except AttributeError:
+        c = os.cpu_count() or 1
+    return max(1, min(c, 16))
 
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_templates(job):
+    import oracle
+    from oracle import pipeline
+    master, qs, n, pc = job
+    return pipeline.library_spectra(master, qs, n, pc, oracle.Params())
+
+
+def _oracle_pairs(job):
+    import oracle
+    from oracle import spectra, xcf
+    pats, lib_spec = job
     prm = oracle.Params()
-    pats = cfg["patterns"][:3].cpu().numpy().astype(np.float64)
-    lib_q = cfg["lib_q"][:400]
-    t0 = time.perf_counter()
-    lib_spec = pipeline.library_spectra(cfg["master"], lib_q, n, cfg["pc"], prm)
-    t_tmpl = (time.perf_counter() - t0) / len(lib_q)
-    t0 = time.perf_counter()
-    sp = [spectra.unit_spectrum(p, prm) for p in pats]
-    for s in sp:
-        xcf.library_scores(s, lib_spec)
-    t_pair = (time.perf_counter() - t0) / (len(pats) * len(lib_q))
-    t0 = time.perf_counter()
-    pipeline.refine_from_match(pats[:2], cfg["master"], cfg["pcs"][:2], cfg["pc"], cfg["true_q"][:2],
-                               np.zeros((2, 2)), prm)
-    t_ref = (time.perf_counter() - t0) / 2
-    total = l_full * t_tmpl + p_full * l_full * t_pair + p_full * t_ref
-    return {"value": p_full / total, "unit": "patterns/s", "cores": 1, "kind": "oracle",
-            "sample": "3 patterns x 400 templates (projection, spectra, correlation) and 2 refinements of the "
-                      "map workload, per-unit times extrapolated to 10,000 x 4,000",
-            "pairs_per_s": 1.0 / t_pair, "s_per_template": t_tmpl, "s_per_refine": t_ref}
+    for p in pats:
+        xcf.library_scores(spectra.unit_spectrum(p, prm), lib_spec)
+    return len(pats)
+
+
+def _oracle_refine(job):
+    import oracle
+    from oracle import pipeline
+    pats, master, pcs, pc, q0, ms = job
+    pipeline.refine_from_match(pats, master, pcs, pc, q0, ms, oracle.Params())
+    return len(pats)
+
+
+def cpu_baseline(sample, n, l_full, p_full):
+    """The FP64 oracle as it stands, run by a pool of worker processes over
+    all host threads the process may use, on a stratified sample of the map
+    workload: the projection and spectra of every 100th library template,
+    the correlation of 1,000 patterns (every 10th map point) against those
+    templates, and the refinement of 64 map points.  Each phase is timed by
+    the wall clock; the per-unit times are extrapolated to the full workload
+    (L templates, P x L pairs, P refinements)."""
+    import multiprocessing as mp
+    import numpy as np
+
+    workers = _cpu_threads()
+    ctx = mp.get_context("spawn")          # fresh interpreters: nothing of the GPU process is inherited
+    pats, lib_q = sample["patterns"], sample["lib_q"]
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_pairs, [(pats[:1], [])] * workers)           # start-up outside the timings
+        t0 = time.perf_counter()
+        parts = pool.map(_oracle_templates, [(sample["master"], q, n, sample["pc"])
+                                             for q in np.array_split(lib_q, min(workers, len(lib_q)))])
+        t_tmpl = time.perf_counter() - t0
+        lib_spec = [s for part in parts for s in part]
+        t0 = time.perf_counter()
+        pool.map(_oracle_pairs, [(c, lib_spec) for c in np.array_split(pats, workers * 4)])
+        t_pairs = time.perf_counter() - t0
+        r = sample["refine"]
+        jobs = [(r["patterns"][k], sample["master"], r["pcs"][k], sample["pc"], r["q0"][k], r["shift"][k])
+                for k in np.array_split(np.arange(len(r["q0"])), workers)]
+        t0 = time.perf_counter()
+        pool.map(_oracle_refine, jobs)
+        t_ref = time.perf_counter() - t0
+    n_pairs = len(pats) * len(lib_q)
+    total = l_full * t_tmpl / len(lib_q) + p_full * l_full * t_pairs / n_pairs + p_full * t_ref / len(r["q0"])
+    return {"value": p_full / total, "unit": "patterns/s", "cores": workers, "kind": "oracle",
+            "cpu_model": _cpu_model(),
+            "sample": "FP64 oracle in %d worker processes: %d templates (every %dth of the library) projected and "
+                      "transformed, %d patterns (every %dth map point) x those templates correlated, %d map points "
+                      "refined; per-unit wall times extrapolated to %d x %d (extrapolated, not a full run)"
+                      % (workers, len(lib_q), l_full // len(lib_q), len(pats), p_full // len(pats), len(r["q0"]),
+                         p_full, l_full),
+            "pairs_per_s": n_pairs / t_pairs, "s_per_template": t_tmpl / len(lib_q),
+            "s_per_refine": t_ref / len(r["q0"]),
+            "phase_wall_s": {"templates": t_tmpl, "pairs": t_pairs, "refine": t_ref}}
 
 
 def main():
@@ -261,9 +319,16 @@ def main():
     }
     if not args.no_forms:
         line["forms"] = compare_forms(tm, pats, master, cfg, lib_q, pc_per, idx["best_idx"], out["q"], args.form_steps)
-    # the oracle's sample, on the host, before the 128^2 map is released
-    cpu_cfg = {"patterns": cfg["patterns"][:3].cpu(), "lib_q": cfg["lib_q"][:400], "master": cfg["master"],
-               "pc": cfg["pc"], "pcs": cfg["pcs"][:2], "true_q": cfg["true_q"][:2]}
+    # the oracle's stratified sample, on the host, before the 128^2 map is
+    # released: every 10th map point, every 100th template, 64 refinements
+    # started at the simulated truth (the refinement's cost does not depend
+    # on its start)
+    ref_idx = np.linspace(0, P - 1, 64).astype(int)
+    cpu_sample = {"patterns": cfg["patterns"][::max(1, P // 1000)][:1000].cpu().numpy().astype(np.float64),
+                  "lib_q": cfg["lib_q"][::max(1, L // 40)][:40], "master": cfg["master"], "pc": cfg["pc"],
+                  "refine": {"patterns": cfg["patterns"][torch.as_tensor(ref_idx, device=dev)].cpu().numpy()
+                             .astype(np.float64), "pcs": cfg["pcs"][ref_idx], "q0": cfg["true_q"][ref_idx],
+                             "shift": np.zeros((len(ref_idx), 2))}}
     if not args.no_search_kernels:
         line["search_kernels"] = search_kernels(tm)
     if not args.no_so3:
@@ -286,7 +351,7 @@ def main():
                                             args.proposal_test)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(cpu_cfg, n, L, P)
+        line["cpu_baseline"] = cpu_baseline(cpu_sample, n, L, P)
     print(json.dumps(line), flush=True)
 
 
@@ -582,6 +647,9 @@ def precision_256(tm, patterns, library, steps, window=15, sample=3, n_sub=96):
     o_pat = [spectra.unit_spectrum(pats_h[i], oprm) for i in range(len(smp))]
     o_lib = {}
 
+    from oracle import cnn as ocnn
+    o_start = [ocnn.nearest_library(cfg["true_q"][i], cfg["lib_q"]) for i in smp]
+
     def o_spec(j):
         if j not in o_lib:
             img = geometry.project(cfg["master"], rotations.quat_to_matrix(cfg["lib_q"][j]), n, cfg["pc"])
@@ -590,8 +658,9 @@ def precision_256(tm, patterns, library, steps, window=15, sample=3, n_sub=96):
 
     res = {"workload": "map: %d patterns (%dx%d grid, 20 grains) at %dx%d fp32 vs %d-orientation cubic library, "
                        "DFT-GEMM search |s| <= %d px + 2-iteration refinement" % (P, side, side, n, n, L, window),
-           "error_sample": "%d patterns x %d random templates (+ the GPU's pick) against the FP64 oracle"
-                           % (len(smp), len(sub))}
+           "error_sample": "%d patterns x %d random templates against the FP64 oracle; the winner's peak and "
+                           "the refinement where the device's pick is the oracle's start (its nearest library "
+                           "orientation to the truth)" % (len(smp), len(sub))}
     ref_best = None
     for name, prec in (("fp16x2", 1), ("bf16x2", 2), ("bf16", 3)):
         prm = tm.params_default(precision=prec, max_shift=window)
@@ -620,24 +689,29 @@ def precision_256(tm, patterns, library, steps, window=15, sample=3, n_sub=96):
         q = out["q"].cpu().numpy()
         vs_true = np.rad2deg([rotations.disorientation_q(q[i], cfg["true_q"][i]) for i in pts])
 
-        # error against the FP64 oracle on the sample
+        # error against the FP64 oracle on the sample: scores over the random
+        # library subset; the winner's peak and the refinement where the
+        # device picked the oracle's start (its nearest library orientation
+        # to the truth), which the oracle then indexes and refines itself
         sc = tm.index_patterns(pats[smp], master, cfg["pc"], lib_q, prm=prm, scores=True)
         sc_h = sc["scores"].cpu().numpy()
-        d_score = d_h = d_s = 0.0
+        d_score = d_h = d_s = d_q = 0.0
+        n_cmp = 0
         for a in range(len(smp)):
-            cols = sorted(set(sub.tolist()) | {int(best[smp[a]])})
-            ref = xcf.library_scores(o_pat[a], [o_spec(j) for j in cols], max_shift=window)
-            d_score = max(d_score, float(np.max(np.abs(sc_h[a, cols] - ref))))
-            b = int(sc["best_idx"][a])
+            ref = xcf.library_scores(o_pat[a], [o_spec(j) for j in sub], max_shift=window)
+            d_score = max(d_score, float(np.max(np.abs(sc_h[a, sub] - ref))))
+            b = o_start[a]
+            if int(sc["best_idx"][a]) != b:
+                continue
+            n_cmp += 1
             ho, so = xcf.subpixel_peak(o_pat[a], o_spec(b),
                                        xcf.integer_peak(xcf.xcf_map(o_pat[a], o_spec(b)), window)[1], oprm.upsample)
             d_h = max(d_h, abs(float(sc["peak_h"][a]) - ho))
             sg = sc["shift"][a].cpu().numpy()
             d_s = max(d_s, abs(sg[0] - so[1]), abs(sg[1] - so[0]))
-        q0 = idx["best_q"].cpu().numpy()[smp]
-        ms0 = idx["shift"].cpu().numpy()[smp].astype(np.float64)
-        rr = pipeline.refine_from_match(pats_h, cfg["master"], cfg["pcs"][smp], cfg["pc"], q0, ms0, oprm)
-        d_q = max(np.rad2deg(rotations.disorientation_q(q[smp[a]], rr["q"][a])) for a in range(len(smp)))
+            rr = pipeline.refine_from_match(pats_h[a:a + 1], cfg["master"], cfg["pcs"][smp[a]:smp[a] + 1], cfg["pc"],
+                                            cfg["lib_q"][b][None], np.array([[so[1], so[0]]]), oprm)
+            d_q = max(d_q, float(np.rad2deg(rotations.disorientation_q(q[smp[a]], rr["q"][0]))))
         res[name] = {"patterns_per_s": P * steps / (t1 - t0), "xcf_pairs_per_s": P * L / search_s,
                      "search_ms": search_s * 1e3,
                      "roofline": {"bound": "mfma", "kernel": "k_xcf_gemm<256>", "achieved": flops / search_s / 1e12,
@@ -648,7 +722,7 @@ def precision_256(tm, patterns, library, steps, window=15, sample=3, n_sub=96):
                      "refined_vs_truth_deg_median": float(np.median(vs_true)),
                      "refined_vs_truth_deg_p95": float(np.percentile(vs_true, 95)),
                      "vs_oracle": {"max_abs_score": d_score, "max_abs_peak_h": d_h, "max_abs_shift_px": float(d_s),
-                                   "max_refined_misorientation_deg": float(d_q)}}
+                                   "max_refined_misorientation_deg": float(d_q), "picks_compared": n_cmp}}
         print("[bench] 256 %s: %.0f patterns/s, %.3g pairs/s, oracle |dh| %.2g"
               % (name, res[name]["patterns_per_s"], res[name]["xcf_pairs_per_s"], d_score),
               file=sys.stderr, flush=True)
@@ -657,15 +731,19 @@ def precision_256(tm, patterns, library, steps, window=15, sample=3, n_sub=96):
 
 def ragged_batch(tm, patterns, library, steps, sample_per_size=1):
     """Patterns of binnings 64, 96, 128 and 160 (25 % each, shuffled) against
-    one library, followed by the 27-point +-0.5 deg stencil, as one graph
-    launch per step (plan built once, tiles autotuned at plan creation).
-    Reports patterns/s and library pairs/s of the whole step, the chosen
-    tiles, accuracy against the simulated truth, and agreement of the
-    stencil's choice with the FP64 oracle from the same start on a sample."""
+    one library, followed by the 27-point +-0.5 deg stencil and the 2-iteration
+    refinement (its first x/y step from the stencil winner's shift), as one
+    graph launch per step (plan built once, tiles autotuned at plan
+    creation).  Reports patterns/s and library pairs/s of the whole step, the
+    chosen tiles, accuracy against the simulated truth, and, on a sample, the
+    final orientation against the FP64 oracle's stencil and refinement started
+    from the oracle's own nearest library orientation (compared where the
+    device's library pick is that same orientation)."""
     import numpy as np
     import torch
     import oracle
     from fixtures import configs
+    from oracle import cnn as ocnn
     from oracle import rotations, stencil
 
     dev = torch.device("cuda:0")
@@ -679,7 +757,7 @@ def ragged_batch(tm, patterns, library, steps, sample_per_size=1):
     pc_per = torch.as_tensor(cfg["pcs"], device=dev).contiguous()
     P, L = len(ns), len(cfg["lib_q"])
     t0 = time.perf_counter()
-    plan = tm.RaggedPlan(ns, offs, L, stencil=True)
+    plan = tm.RaggedPlan(ns, offs, L, stencil=True, refine=True)
     t_plan = time.perf_counter() - t0
     out = plan.run(data, master, cfg["pc"], lib_q, pc_per=pc_per)       # capture + first run
     torch.cuda.synchronize()
@@ -694,30 +772,41 @@ def ragged_batch(tm, patterns, library, steps, sample_per_size=1):
     pts = np.linspace(0, P - 1, 200).astype(int)
     vs_true = np.rad2deg([rotations.disorientation_q(q[i], cfg["true_q"][i]) for i in pts])
     lib_true = np.rad2deg([rotations.disorientation_q(cfg["lib_q"][best[i]], cfg["true_q"][i]) for i in pts])
-    # the stencil's choice against the oracle's from the same library pick
-    agree, dh, total = 0, 0.0, 0
+    # the oracle's stencil + refinement from its own start on a sample
+    agree, dq, dh, total = 0, 0.0, 0.0, 0
     prm = oracle.Params()
     for n in (64, 96, 128, 160):
-        for i in np.nonzero(ns == n)[0][:sample_per_size]:
-            st = stencil.stencil_refine([configs.ragged_pattern(cfg, i)], cfg["master"], cfg["pcs"][i:i + 1],
-                                        cfg["lib_q"][best[i]][None], prm)
+        found = 0
+        for i in np.nonzero(ns == n)[0][:20]:
+            j = ocnn.nearest_library(cfg["true_q"][i], cfg["lib_q"])
+            if j != best[i]:
+                continue
+            rr = stencil.stencil_then_refine([configs.ragged_pattern(cfg, i)], cfg["master"], cfg["pcs"][i:i + 1],
+                                             cfg["lib_q"][j][None], prm)
             total += 1
-            if st["idx"][0] == sidx[i]:
+            if rr["stencil"]["idx"][0] == sidx[i]:
                 agree += 1
-                dh = max(dh, abs(float(out["peak_h"][i]) - st["peak_h"][0]))
+                dq = max(dq, float(np.rad2deg(rotations.disorientation_q(q[i], rr["q"][0]))))
+                dh = max(dh, abs(float(out["peak_h"][i]) - rr["peak_h"][0]))
+            found += 1
+            if found >= sample_per_size:
+                break
     res = {"workload": "ragged: %d patterns, binnings 64/96/128/160 (25%% each, shuffled), %d-orientation cubic "
-                       "library, exhaustive FFT XCF + 27-point +-0.5 deg stencil, one graph launch per step"
-                       % (P, L),
+                       "library, exhaustive FFT XCF + 27-point +-0.5 deg stencil + 2-iteration refinement, one "
+                       "graph launch per step" % (P, L),
            "patterns_per_s": P / dt, "ms_per_step": dt * 1e3, "library_pairs_per_s_whole_step": P * L / dt,
            "stencil_candidates_per_step": 27 * P, "plan_create_s_incl_autotune": t_plan,
            "tiles": plan.tiles(), "steps": steps,
            "library_pick_vs_truth_deg_median": float(np.median(lib_true)),
-           "stencil_vs_truth_deg_median": float(np.median(vs_true)),
-           "stencil_vs_truth_deg_p95": float(np.percentile(vs_true, 95)),
-           "stencil_vs_oracle": {"agreement": agree / max(total, 1), "sample": total,
-                                 "max_abs_peak_h": dh}}
-    print("[bench] ragged: %.0f patterns/s, %.3g library pairs/s" % (res["patterns_per_s"],
-                                                                      res["library_pairs_per_s_whole_step"]),
+           "refined_vs_truth_deg_median": float(np.median(vs_true)),
+           "refined_vs_truth_deg_p95": float(np.percentile(vs_true, 95)),
+           "refined_within_0.1_deg": float(np.mean(vs_true < 0.1)),
+           "vs_oracle": {"stencil_agreement": agree / max(total, 1), "sample": total,
+                         "max_refined_misorientation_deg": dq, "max_abs_peak_h": dh,
+                         "start": "the oracle's nearest library orientation to the truth, where the device "
+                                  "picked the same one"}}
+    print("[bench] ragged: %.0f patterns/s, %.3g library pairs/s, refined median %.3f deg"
+          % (res["patterns_per_s"], res["library_pairs_per_s_whole_step"], res["refined_vs_truth_deg_median"]),
           file=sys.stderr, flush=True)
     plan.close()
     return res

@@ -384,7 +384,9 @@ int ebsd_timing_read(double* total_ms, int64_t* launches);
  * the persistent search kernel for every size present (the number of
  * templates each work item correlates and the persistent grid), keeping the
  * fastest (EBSD_RAGGED_NO_AUTOTUNE keeps 16 templates and the resident
- * capacity).
+ * capacity).  The chosen tiles are kept for the life of the process, keyed by
+ * the device architecture, compute-unit count, size and shift window, and
+ * reused by later plans.
  *
  * ebsd_ragged_run indexes the batch against the library (method of
  * ebsd_index_patterns, each pattern against templates projected at its own
@@ -396,7 +398,13 @@ int ebsd_timing_read(double* total_ms, int64_t* launches);
  * [P][3] device, or the nominal one), keeps the candidate with the largest
  * integer correlation peak (ties: smaller number) and upsamples its peak;
  * this grid search is the coarse alternative to the refinement that the
- * paper's closing discussion mentions.
+ * paper's closing discussion mentions.  With EBSD_RAGGED_REFINE the
+ * orientation is then refined as by ebsd_refine_orientations (n_iter x / y
+ * and z steps at each pattern's own pattern centre, section "Orientation
+ * and Pattern Centre Refinement"), the first x / y step taken from the shift
+ * already measured: the stencil winner's, or without the stencil the
+ * library pick's less the PC-move translation (as ebsd_refine_from_match);
+ * peak_h and shift are then the final measurement's.
  * Outputs in pattern order (device): best_idx [P] library index (may be
  * NULL), q_out [P][4] final orientation, peak_h [P], shift [P][2] (x, y) of
  * the final template, stencil_idx [P] chosen candidate number (-1 without
@@ -409,6 +417,7 @@ typedef struct ebsd_ragged_plan_s* ebsd_ragged_plan;
 #define EBSD_RAGGED_STENCIL 1
 #define EBSD_RAGGED_EAGER 2
 #define EBSD_RAGGED_NO_AUTOTUNE 4
+#define EBSD_RAGGED_REFINE 8
 
 int ebsd_ragged_plan_create(const int32_t* n_per, const int64_t* offset, int64_t P, int64_t L,
                             const ebsd_params* prm, double stencil_step_deg, int32_t flags,
@@ -419,8 +428,9 @@ int ebsd_ragged_run(ebsd_ragged_plan plan, const float* data, const ebsd_master*
 /* Chosen tiles: for each size present, tiles[4 k ..] = (n, patterns,
  * templates per work item, persistent grid blocks); *count sizes (<= 4). */
 int ebsd_ragged_plan_tiles(ebsd_ragged_plan plan, int32_t* tiles, int32_t* count);
-/* Waits for the device (replays may still run on callers' streams), then
- * frees the plan. */
+/* Waits for the plan's last run (on the caller's stream it was given) and
+ * its own streams, then frees the plan; other work on the device is not
+ * waited for. */
 int ebsd_ragged_plan_destroy(ebsd_ragged_plan plan);
 
 /*

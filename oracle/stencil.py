@@ -18,7 +18,7 @@ winner's peak is upsampled as in the search.
 
 import numpy as np
 
-from . import geometry, rotations, spectra, xcf
+from . import geometry, refine, rotations, spectra, xcf
 from .params import Params
 
 STEP_DEG = 0.5
@@ -70,4 +70,26 @@ def stencil_refine(patterns, master, pcs, q_init, prm=None, step_deg=STEP_DEG):
         out["gap"][i] = gap
         out["peak_h"][i] = h_sub
         out["shift"][i] = (s_sub[1], s_sub[0])
+    return out
+
+
+def stencil_then_refine(patterns, master, pcs, q_init, prm=None, step_deg=STEP_DEG):
+    """The stencil around q_init, then the refinement of section "Orientation
+    and Pattern Centre Refinement" from the stencil's pick at each pattern's
+    own pattern centre; its first x / y step takes the shift the stencil
+    already measured for its winner (projected at that same pattern centre),
+    in place of a projection and correlation at the starting orientation.
+    Returns dict(stencil (the stencil_refine result), q, peak_h, shift (x, y))."""
+    prm = prm or Params()
+    st = stencil_refine(patterns, master, pcs, q_init, prm, step_deg)
+    p = len(patterns)
+    out = dict(stencil=st, q=np.zeros((p, 4)), peak_h=np.zeros(p), shift=np.zeros((p, 2)))
+    rs = rotations.quat_to_matrix(st["q"])
+    for i in range(p):
+        img = np.asarray(patterns[i], dtype=np.float64)
+        first = (st["shift"][i][1], st["shift"][i][0])
+        r, h, s = refine.refine_one(img, master, rs[i], pcs[i], prm, first_shift=first)
+        out["q"][i] = rotations.matrix_to_quat(r)
+        out["peak_h"][i] = h
+        out["shift"][i] = (s[1], s[0])
     return out

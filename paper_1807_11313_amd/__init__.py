@@ -34,7 +34,7 @@ EXPORTS = ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_index
            "ebsd_index_proposed", "ebsd_pc_map", "ebsd_refine_from_match", "ebsd_capture_range",
            "ebsd_so3_library", "ebsd_nn_disorientation")
 
-RAGGED_STENCIL, RAGGED_EAGER, RAGGED_NO_AUTOTUNE = 1, 2, 4
+RAGGED_STENCIL, RAGGED_EAGER, RAGGED_NO_AUTOTUNE, RAGGED_REFINE = 1, 2, 4, 8
 
 EBSD_OK = 0
 ERRORS = {-1: "EBSD_E_INVALID", -2: "EBSD_E_NOMEM", -3: "EBSD_E_DEVICE", -4: "EBSD_E_UNSUPPORTED"}
@@ -475,7 +475,8 @@ class RaggedPlan:
     sizes[p] at element offset offsets[p] of one packed float32 buffer
     (host arrays), a library of L orientations and the parameters."""
 
-    def __init__(self, sizes, offsets, L, prm=None, stencil=True, step_deg=0.5, eager=False, autotune=True):
+    def __init__(self, sizes, offsets, L, prm=None, stencil=True, step_deg=0.5, eager=False, autotune=True,
+                 refine=False):
         sizes = np.ascontiguousarray(sizes, dtype=np.int32)
         offsets = np.ascontiguousarray(offsets, dtype=np.int64)
         if sizes.shape != offsets.shape or sizes.ndim != 1:
@@ -483,7 +484,7 @@ class RaggedPlan:
         self.P, self.L = int(sizes.shape[0]), int(L)
         self.min_floats = int(np.max(offsets + sizes.astype(np.int64) ** 2)) if self.P else 0
         flags = (RAGGED_STENCIL if stencil else 0) | (RAGGED_EAGER if eager else 0) | \
-            (0 if autotune else RAGGED_NO_AUTOTUNE)
+            (0 if autotune else RAGGED_NO_AUTOTUNE) | (RAGGED_REFINE if refine else 0)
         h = ctypes.c_void_p()
         _check(lib().ebsd_ragged_plan_create(sizes.ctypes.data_as(ctypes.c_void_p),
                                              offsets.ctypes.data_as(ctypes.c_void_p), self.P, self.L,

@@ -13,8 +13,11 @@
 // class are chosen by timing candidates on the device when the plan is built.
 // The winner's integer and sub-pixel peaks, the stencil (27 candidates per
 // pattern, projected at the pattern's own pattern centre, scored by the
-// integer peak, best by score with ties to the smaller candidate number) and
-// the scatter back to pattern order follow on the capture stream.
+// integer peak, best by score with ties to the smaller candidate number), the
+// refinement (x / y shift steps and log-polar z steps at each pattern's own
+// pattern centre, the first x / y step taken from the stencil's or the
+// search's own shift) and the scatter back to pattern order follow on the
+// capture stream.
 #include "api_util.hpp"
 #include "ebsd_common.hpp"
 
@@ -23,6 +26,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
 #include <vector>
 
 using namespace ebsd;
@@ -41,6 +48,19 @@ constexpr int kNumClasses = 4;
 constexpr int kClassN[kNumClasses] = {160, 128, 96, 64};
 constexpr int kStencil = 27;
 constexpr size_t kStencilBudget = size_t(4) << 30;  // bytes of candidate images + spectra per chunk
+constexpr size_t kRefineBudget = size_t(4) << 30;   // bytes of refinement buffers per chunk
+
+// Pattern images k = 0 .. cc - 1 at element offsets img_off[k] of the packed
+// buffer, copied contiguous (the log-polar resampling reads whole images).
+// One block per image.
+__global__ void k_gather_imgs(const float* __restrict__ data, const int64_t* __restrict__ img_off, int64_t cc,
+                              int npix, float* __restrict__ out) {
+  const int64_t k = blockIdx.x;
+  if (k >= cc) return;
+  const float* src = data + img_off[k];
+  float* dst = out + k * (int64_t)npix;
+  for (int i = threadIdx.x; i < npix; i += 256) dst[i] = src[i];
+}
 
 __global__ void k_fill_i32(int* __restrict__ p, int n, int v) {
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -162,7 +182,9 @@ struct ClassPlan {
   int n = 0;
   int64_t count = 0, row0 = 0;
   int lchunk = 16, grid = 0;
-  int64_t chunk = 0;  // stencil patterns per chunk
+  int64_t chunk = 0;   // stencil patterns per chunk
+  int64_t rchunk = 0;  // refinement patterns per chunk
+  ebsd_params prm{};   // the parameters resolved at this size (log-polar grid)
   float2* lib_spec = nullptr;
   float2* pat_spec = nullptr;
   float2* sub_tab = nullptr;
@@ -208,9 +230,22 @@ struct ebsd_ragged_plan_s {
   int32_t* pick_k = nullptr;
   int32_t* pick_pat = nullptr;
   int32_t* s_best = nullptr;
+  // refinement buffers (one chunk)
+  float* r_img = nullptr;
+  float* r_tmpl = nullptr;
+  float2* r_spec = nullptr;
+  float* r_lpe = nullptr;
+  float* r_lpt = nullptr;
+  float* r_hint = nullptr;
+  int32_t* r_sint = nullptr;
+  float* r_hsub = nullptr;
+  float* r_ssub = nullptr;
+  double* r_gam = nullptr;
   int* queues = nullptr;
   hipStream_t cap = nullptr;
   hipEvent_t fork = nullptr;
+  hipEvent_t ran = nullptr;    // recorded on the caller's stream after each run
+  bool ran_recorded = false;
   hipGraphExec_t exec = nullptr;
   std::vector<uintptr_t> key;
 };
@@ -220,9 +255,19 @@ namespace {
 int plan_layout(ebsd_ragged_plan_s* pl, Arena& a) {
   const int64_t P = pl->P, L = pl->L;
   size_t img_floats = 0, cand = 0, cand_spec = 0;
+  size_t r_pix = 0, r_spec = 0, r_lp = 0, r_rows = 0;
   for (auto& c : pl->cls) {
     if (!c.count) continue;
     const int64_t sc = spec_complex(c.n);
+    if (pl->flags & EBSD_RAGGED_REFINE) {
+      const size_t lp = (size_t)c.prm.n_rho * c.prm.n_eta;
+      const size_t per = (size_t)c.n * c.n * 8 + (size_t)sc * 8 + lp * 8 + 40;
+      c.rchunk = std::max<int64_t>(1, std::min<int64_t>(c.count, (int64_t)(kRefineBudget / per)));
+      r_pix = std::max(r_pix, (size_t)(c.rchunk * c.n * c.n));
+      r_spec = std::max(r_spec, (size_t)(c.rchunk * sc));
+      r_lp = std::max(r_lp, (size_t)c.rchunk * lp);
+      r_rows = std::max(r_rows, (size_t)c.rchunk);
+    }
     c.lib_spec = a.take<float2>((size_t)(L * sc));
     c.pat_spec = a.take<float2>((size_t)(c.count * sc));
     c.sub_tab = a.take<float2>((size_t)subpixel_table_size(c.n, pl->prm.upsample));
@@ -257,13 +302,38 @@ int plan_layout(ebsd_ragged_plan_s* pl, Arena& a) {
   pl->pick_k = a.take<int32_t>(pc);
   pl->pick_pat = a.take<int32_t>(pc);
   pl->s_best = a.take<int32_t>(2 * pc);
+  pl->r_img = a.take<float>(r_pix);
+  pl->r_tmpl = a.take<float>(r_pix);
+  pl->r_spec = a.take<float2>(r_spec);
+  pl->r_lpe = a.take<float>(r_lp);
+  pl->r_lpt = a.take<float>(r_lp);
+  pl->r_hint = a.take<float>(r_rows);
+  pl->r_sint = a.take<int32_t>(2 * r_rows);
+  pl->r_hsub = a.take<float>(r_rows);
+  pl->r_ssub = a.take<float>(2 * r_rows);
+  pl->r_gam = a.take<double>(r_rows);
   pl->queues = a.take<int>(kNumClasses);
   for (int i = 0; i < kNumClasses; ++i) pl->cls[i].queue = pl->queues ? pl->queues + i : nullptr;
   return EBSD_OK;
 }
 
+// Tiles chosen by timing, kept for the life of the process: keyed by the
+// device's architecture and compute-unit count, the size, the shift window
+// and the FP32 FFT form (the only form of the ragged searches).
+using TuneKey = std::tuple<std::string, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+
+TuneKey tune_key(const ebsd_ragged_plan_s* pl, const ClassPlan& c) {
+  hipDeviceProp_t prop;
+  std::string arch = "?";
+  if (hipGetDeviceProperties(&prop, pl->device) == hipSuccess) arch = prop.gcnArchName;
+  return TuneKey(arch, pl->cus, c.n, pl->prm.max_shift);
+}
+
 // Times the persistent search of one class for candidate template chunks and
-// grids on synthetic spectra of the class's size; keeps the fastest.
+// grids on synthetic spectra of the class's size; keeps the fastest (once per
+// process for each key).
 int autotune_class(ebsd_ragged_plan_s* pl, ClassPlan& c) {
   int occ = 0;
   RG_TRY(xcf_persistent_occupancy(c.n, pl->prm.max_shift, &occ), "occupancy");
@@ -271,6 +341,16 @@ int autotune_class(ebsd_ragged_plan_s* pl, ClassPlan& c) {
   c.lchunk = 16;
   c.grid = occ * pl->cus;
   if (pl->flags & EBSD_RAGGED_NO_AUTOTUNE) return EBSD_OK;
+  const TuneKey key = tune_key(pl, c);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      c.lchunk = it->second.first;
+      c.grid = it->second.second;
+      return EBSD_OK;
+    }
+  }
   const int64_t ps = std::min<int64_t>(c.count, 1024), ls = std::min<int64_t>(pl->L, 512);
   const int64_t sc = spec_complex(c.n);
   float2 *sp = nullptr, *sl = nullptr;
@@ -322,6 +402,10 @@ int autotune_class(ebsd_ragged_plan_s* pl, ClassPlan& c) {
     }
   } while (0);
   cleanup();
+  if (rc == EBSD_OK) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache[key] = std::make_pair(c.lchunk, c.grid);
+  }
   return rc;
 }
 
@@ -400,6 +484,62 @@ int enqueue(ebsd_ragged_plan_s* pl, const float* data, const ebsd_master* mp, co
     }
   }
   const bool sten = (pl->flags & EBSD_RAGGED_STENCIL) != 0;
+  if (pl->flags & EBSD_RAGGED_REFINE) {
+    // x / y steps from the correlation shift, z steps from the log-polar eta
+    // correlation, at each pattern's own pattern centre; the first x / y step
+    // takes the shift already measured: the stencil winner's (projected at
+    // the pattern's PC) or the library pick's (projected at the nominal PC,
+    // so the PC-move translation is subtracted first)
+    const double pc0[2] = {geo->pcx, geo->pcy};
+    for (auto& c : pl->cls) {
+      if (!c.count) continue;
+      const ebsd_params& cp = c.prm;
+      const FilterParams fp = filter_of(cp, c.n);
+      const int64_t sc = spec_complex(c.n);
+      const int npix = c.n * c.n;
+      for (int64_t i0 = 0; i0 < c.count; i0 += c.rchunk) {
+        const int64_t cc = std::min<int64_t>(c.rchunk, c.count - i0);
+        const int64_t r0 = c.row0 + i0;
+        double* q = pl->q_row + 4 * r0;
+        const double* pcp = pl->pc_row + 3 * r0;
+        const float2* sp = c.pat_spec + sc * i0;
+        hipLaunchKernelGGL(k_gather_imgs, dim3((unsigned)cc), dim3(256), 0, st, data, c.img_off + i0, cc, npix,
+                           pl->r_img);
+        RG_TRY(hipGetLastError(), "refine gather");
+        RG_TRY(launch_logpolar(c.n, pl->r_img, cc, cp.n_rho, cp.n_eta, pl->r_lpe, st), "refine logpolar(patterns)");
+        auto measure = [&](float* hh, float* ss) -> int {
+          RG_TRY(launch_project(c.n, mp->data, mp->H, mp->W, q, cc, pcp, geo->pcx, geo->pcy, geo->pcz, pl->r_tmpl,
+                                st),
+                 "refine project");
+          RG_TRY(launch_spectra(c.n, pl->r_tmpl, npix, cc, fp, pl->r_spec, nullptr, st), "refine spectra");
+          RG_TRY(launch_xcf_peak(c.n, sp, pl->r_spec, nullptr, nullptr, cc, cp.max_shift, pl->r_hint, pl->r_sint,
+                                 nullptr, st),
+                 "refine peak");
+          RG_TRY(launch_subpixel(c.n, sp, pl->r_spec, nullptr, nullptr, cc, pl->r_sint, cp.upsample, c.sub_tab, hh,
+                                 ss, st),
+                 "refine subpixel");
+          return EBSD_OK;
+        };
+        for (int it = 0; it < cp.n_iter; ++it) {
+          if (it == 0) {
+            RG_TRY(launch_update_xy(q, pl->s_row + 2 * r0, cc, pcp, geo->pcz, c.n, st, sten ? nullptr : pc0),
+                   "refine update_xy(first)");
+          } else {
+            if (int rc = measure(pl->r_hsub, pl->r_ssub)) return rc;
+            RG_TRY(launch_update_xy(q, pl->r_ssub, cc, pcp, geo->pcz, c.n, st), "refine update_xy");
+          }
+          RG_TRY(launch_project(c.n, mp->data, mp->H, mp->W, q, cc, pcp, geo->pcx, geo->pcy, geo->pcz, pl->r_tmpl,
+                                st),
+                 "refine project");
+          RG_TRY(launch_logpolar(c.n, pl->r_tmpl, cc, cp.n_rho, cp.n_eta, pl->r_lpt, st), "refine logpolar");
+          RG_TRY(launch_eta_peak(pl->r_lpe, pl->r_lpt, cc, cp.n_rho, cp.n_eta, cp.upsample, pl->r_gam, st),
+                 "refine eta");
+          RG_TRY(launch_update_z(q, pl->r_gam, cc, st), "refine update_z");
+        }
+        if (int rc = measure(pl->h_row + r0, pl->s_row + 2 * r0)) return rc;
+      }
+    }
+  }
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(P)), dim3(256), 0, st, pl->row_pat, P, pl->best_row, pl->q_row,
                      pl->h_row, pl->s_row, sten ? pl->sidx_row : nullptr, best_idx, q_out, peak_h, shift,
                      stencil_idx);
@@ -415,6 +555,7 @@ void plan_free(ebsd_ragged_plan_s* pl) {
     if (c.done) (void)hipEventDestroy(c.done);
   }
   if (pl->fork) (void)hipEventDestroy(pl->fork);
+  if (pl->ran) (void)hipEventDestroy(pl->ran);
   if (pl->cap) (void)hipStreamDestroy(pl->cap);
   if (pl->mem) (void)hipFree(pl->mem);
   delete pl;
@@ -433,7 +574,7 @@ int ebsd_ragged_plan_create(const int32_t* n_per, const int64_t* offset, int64_t
   if (P < 1 || L < 1) return fail(EBSD_E_INVALID, "P and L must be >= 1");
   if (P > 0x7fffffffLL || L > 0x7fffffffLL) return fail(EBSD_E_INVALID, "P and L must fit in int32");
   if (!n_per || !offset) return fail(EBSD_E_INVALID, "null size or offset array");
-  if (flags & ~(EBSD_RAGGED_STENCIL | EBSD_RAGGED_EAGER | EBSD_RAGGED_NO_AUTOTUNE))
+  if (flags & ~(EBSD_RAGGED_STENCIL | EBSD_RAGGED_EAGER | EBSD_RAGGED_NO_AUTOTUNE | EBSD_RAGGED_REFINE))
     return fail(EBSD_E_INVALID, "unknown flags");
   if (!(stencil_step_deg > 0.0) || stencil_step_deg > 10.0)
     return fail(EBSD_E_INVALID, "stencil step must be in (0, 10] degrees");
@@ -472,7 +613,7 @@ int ebsd_ragged_plan_create(const int32_t* n_per, const int64_t* offset, int64_t
     return fail(EBSD_E_UNSUPPORTED, "ragged pattern sizes must be 64, 96, 128 or 160");
   }
   for (auto& c : pl->cls) {
-    if (c.count && (rc = resolve_params(prm, c.n, &p))) {
+    if (c.count && (rc = resolve_params(prm, c.n, &c.prm))) {
       delete pl;
       return rc;
     }
@@ -495,7 +636,9 @@ int ebsd_ragged_plan_create(const int32_t* n_per, const int64_t* offset, int64_t
   a.base = (char*)pl->mem;
   a.off = 0;
   plan_layout(pl, a);
-  if ((e = hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking)) || (e = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming))) {
+  if ((e = hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking)) ||
+      (e = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming)) ||
+      (e = hipEventCreateWithFlags(&pl->ran, hipEventDisableTiming))) {
     plan_free(pl);
     return fail_hip(e, "ragged plan streams");
   }
@@ -537,8 +680,11 @@ int ebsd_ragged_plan_create(const int32_t* n_per, const int64_t* offset, int64_t
 
 int ebsd_ragged_plan_destroy(ebsd_ragged_plan plan) {
   if (!plan) return EBSD_OK;
-  // replays run on callers' streams: wait for every one before freeing
-  (void)hipDeviceSynchronize();
+  // runs go to callers' streams: wait for the last one (each run records
+  // plan->ran after its work on its stream, and a plan serves one run at a
+  // time), then for the plan's own streams
+  if (plan->ran_recorded) (void)hipEventSynchronize(plan->ran);
+  if (plan->cap) (void)hipStreamSynchronize(plan->cap);
   plan_free(plan);
   return EBSD_OK;
 }
@@ -572,8 +718,12 @@ int ebsd_ragged_run(ebsd_ragged_plan plan, const float* data, const ebsd_master*
   if ((e = hipGetDevice(&dev))) return fail_hip(e, "hipGetDevice");
   if (dev != plan->device) return fail(EBSD_E_INVALID, "the plan was built on another device");
   hipStream_t st = (hipStream_t)stream;
-  if (plan->flags & EBSD_RAGGED_EAGER)
-    return enqueue(plan, data, mp, geo, lib_q, best_idx, q_out, peak_h, shift, stencil_idx, st);
+  if (plan->flags & EBSD_RAGGED_EAGER) {
+    if ((rc = enqueue(plan, data, mp, geo, lib_q, best_idx, q_out, peak_h, shift, stencil_idx, st))) return rc;
+    RG_TRY(hipEventRecord(plan->ran, st), "ragged record");
+    plan->ran_recorded = true;
+    return EBSD_OK;
+  }
   double pcs[3] = {geo->pcx, geo->pcy, geo->pcz};
   uintptr_t pcbits[3];
   std::memcpy(pcbits, pcs, sizeof(pcs));
@@ -606,6 +756,8 @@ int ebsd_ragged_run(ebsd_ragged_plan plan, const float* data, const ebsd_master*
     plan->key = key;
   }
   RG_TRY(hipGraphLaunch(plan->exec, st), "graph launch");
+  RG_TRY(hipEventRecord(plan->ran, st), "ragged record");
+  plan->ran_recorded = true;
   return EBSD_OK;
 }
 

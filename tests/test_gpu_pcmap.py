@@ -54,7 +54,7 @@ def _refine_case(t, cfg, n, pc_per=True, prm=None):
     return rr, ref, q0
 
 
-@pytest.mark.parametrize("n", [64, 128])
+@pytest.mark.parametrize("n", [64, 96, 128, 160])
 def test_refine_from_match_matches_oracle(n):
     banner("refine_from_match n=%d" % n)
     t = tm()

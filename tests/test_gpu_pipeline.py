@@ -67,7 +67,7 @@ def test_index_tiny_config():
     _check_index(res, ref, ref["scores"])
 
 
-@pytest.mark.parametrize("n", [64, 128])
+@pytest.mark.parametrize("n", [64, 96, 128, 160])
 def test_refine_matches_oracle(n):
     banner("refine n=%d" % n)
     t = tm()

@@ -12,6 +12,11 @@ stencil, against the FP64 oracle and against the single-size path.
   of ebsd_index_patterns on that class alone, bit for bit.
 * Every replay of the captured graph, with unrelated eager work and
   synchronisations between replays, equals the eager enqueue bit for bit.
+* With the refinement in the graph: the final orientation within 0.05 deg of
+  the oracle's (stencil then refinement, or the refinement from the search's
+  shift without the stencil), peak height 1e-4, shift 0.02 px.
+Every oracle computation starts from the oracle's own library pick; patterns
+whose device pick differs from it (near ties only) are not compared further.
 """
 
 import numpy as np
@@ -35,6 +40,12 @@ def _workload(p=12, l=40, seed=5, sizes=(64, 96, 128, 160)):
     return cfg, data, offs, ns
 
 
+def _oracle_index(cfg, ns, n, prm):
+    idx = np.nonzero(ns == n)[0]
+    pats = np.stack([configs.ragged_pattern(cfg, i) for i in idx])
+    return idx, pats, pipeline.index_patterns(pats, cfg["master"], cfg["pc"], cfg["lib_q"], prm)
+
+
 def _run(t, plan, cfg, data, pcs=True):
     return plan.run(data, dev(cfg["master"]), cfg["pc"], dev(cfg["lib_q"]),
                     pc_per=dev(cfg["pcs"]) if pcs else None)
@@ -51,16 +62,16 @@ def test_ragged_index_and_stencil_match_oracle():
     q, h, s = host(res["q"]), host(res["peak_h"]), host(res["shift"])
     prm = oracle.Params()
     for n in (64, 96, 128, 160):
-        idx = np.nonzero(ns == n)[0]
-        pats = np.stack([configs.ragged_pattern(cfg, i) for i in idx])
-        ref = pipeline.index_patterns(pats, cfg["master"], cfg["pc"], cfg["lib_q"], prm)
+        idx, pats, ref = _oracle_index(cfg, ns, n, prm)
         for a, i in enumerate(idx):
             if ref["gap"][a] > TAU_TIE:
                 assert best[i] == ref["best_idx"][a], (n, i)
-        # the stencil from the GPU's library pick
-        q0 = cfg["lib_q"][best[idx]]
+        # the stencil from the oracle's own library pick
+        q0 = cfg["lib_q"][ref["best_idx"]]
         st = stencil.stencil_refine(list(pats), cfg["master"], cfg["pcs"][idx], q0, prm)
         for a, i in enumerate(idx):
+            if best[i] != ref["best_idx"][a]:
+                continue
             if st["gap"][a] <= TAU_TIE:
                 assert st["h_int"][a][sidx[i]] >= st["h_int"][a].max() - TAU_TIE
                 continue
@@ -92,14 +103,15 @@ def test_ragged_search_equals_single_size_path():
     plan.close()
 
 
-def test_graph_replays_equal_eager_enqueue():
-    banner("ragged graph replays")
+@pytest.mark.parametrize("refine", [False, True])
+def test_graph_replays_equal_eager_enqueue(refine):
+    banner("ragged graph replays refine=%d" % refine)
     t = tm()
     cfg, data, offs, ns = _workload(p=16, l=50, seed=7)
-    eager = t.RaggedPlan(ns, offs, len(cfg["lib_q"]), stencil=True, eager=True, autotune=False)
+    eager = t.RaggedPlan(ns, offs, len(cfg["lib_q"]), stencil=True, eager=True, autotune=False, refine=refine)
     ref = _run(t, eager, cfg, data)
     torch.cuda.synchronize()
-    plan = t.RaggedPlan(ns, offs, len(cfg["lib_q"]), stencil=True)
+    plan = t.RaggedPlan(ns, offs, len(cfg["lib_q"]), stencil=True, refine=refine)
     out = None
     junk = torch.ones(1 << 20, device="cuda:0")
     for rep in range(4):
@@ -146,4 +158,41 @@ def test_ragged_shift_window_equals_single_size_path():
         ref = t.index_patterns(pats, dev(cfg["master"]), cfg["pc"], dev(cfg["lib_q"]), prm=prm)
         assert np.array_equal(best[idx], host(ref["best_idx"]))
         assert np.array_equal(h[idx], host(ref["peak_h"]))
+    plan.close()
+
+
+@pytest.mark.parametrize("with_stencil", [True, False])
+def test_ragged_refinement_matches_oracle(with_stencil):
+    # the refinement inside the graph: after the stencil, its first x / y
+    # step from the stencil winner's shift; without it, from the library
+    # pick's shift less the PC-move translation
+    banner("ragged refinement vs oracle, stencil=%d" % with_stencil)
+    t = tm()
+    cfg, data, offs, ns = _workload(p=12, l=40, seed=15)
+    plan = t.RaggedPlan(ns, offs, len(cfg["lib_q"]), stencil=with_stencil, refine=True)
+    res = _run(t, plan, cfg, data)
+    best, q, h, s = host(res["best_idx"]), host(res["q"]), host(res["peak_h"]), host(res["shift"])
+    sidx = host(res["stencil_idx"])
+    prm = oracle.Params()
+    compared = 0
+    for n in (64, 96, 128, 160):
+        idx, pats, ref = _oracle_index(cfg, ns, n, prm)
+        q0 = cfg["lib_q"][ref["best_idx"]]
+        if with_stencil:
+            rr = stencil.stencil_then_refine(list(pats), cfg["master"], cfg["pcs"][idx], q0, prm)
+        else:
+            rr = pipeline.refine_from_match(pats, cfg["master"], cfg["pcs"][idx], cfg["pc"], q0, ref["shift"], prm)
+        for a, i in enumerate(idx):
+            if best[i] != ref["best_idx"][a]:
+                continue
+            if with_stencil and sidx[i] != rr["stencil"]["idx"][a]:
+                assert rr["stencil"]["gap"][a] <= TAU_TIE
+                continue
+            d = np.rad2deg(rotations.disorientation_q(q[i], rr["q"][a]))
+            assert d < 0.05, (n, i, d)
+            assert abs(h[i] - rr["peak_h"][a]) < 1e-4, (n, i)
+            assert np.max(np.abs(s[i] - rr["shift"][a])) <= 0.02 + 1e-6, (n, i)
+            compared += 1
+    print("[gpu]   compared %d of %d patterns" % (compared, len(ns)), flush=True)
+    assert compared >= len(ns) - 2
     plan.close()

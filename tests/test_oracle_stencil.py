@@ -84,3 +84,34 @@ def test_stencil_accepts_ragged_sizes():
             geo.project(master, rs[1] @ stencil.stencil_rotation(0, 0, -STEP).T, 96, pcs[1])]
     res = stencil.stencil_refine(pats, master, pcs, q0, Params())
     assert list(res["idx"]) == [9 * 2 + 3 + 1, 9 + 3 + 0]
+
+
+def test_stencil_then_refine_fixed_point_and_convergence():
+    # The pattern is the gridded master's projection at (R_true, PC_i).
+    # Started at R_true Rx(0.5 deg)^T, the stencil's candidate (a = -0.5 deg)
+    # is R_true itself (Rx(-a) Rx(a) = I): identical images, shift exactly 0,
+    # and the refinement cannot move it.  Started 1.4 deg away about a random
+    # axis, the stencil then the refinement land within 0.02 deg.  A first
+    # step that used the shift with the wrong axis order or sign would move
+    # the fixed point or stall the convergence.
+    master = band_master()
+    rng = np.random.default_rng(17)
+    n = 96
+    q_true = random_quats(rng, 2)
+    pcs = np.array([[0.5 + 2 / n, 0.5 - 3 / n, 0.6], [0.5 - 1 / n, 0.5 + 4 / n, 0.62]])
+    pats = [geo.project(master, rot.quat_to_matrix(q_true[i]), n, pcs[i]) for i in range(2)]
+    r_true = rot.quat_to_matrix(q_true)
+    q0 = np.stack([rot.matrix_to_quat(r_true[i] @ rot.rot_x(STEP).T) for i in range(2)])
+    out = stencil.stencil_then_refine(pats, master, pcs, q0, Params())
+    for i in range(2):
+        assert out["stencil"]["idx"][i] == 4                      # (a, b, c) = (-d, 0, 0)
+        assert np.rad2deg(rot.disorientation_q(out["q"][i], q_true[i])) < 1e-9
+        assert abs(out["peak_h"][i] - 1) < 1e-12 and np.allclose(out["shift"][i], 0, atol=1e-12)
+    q1 = np.stack([rot.matrix_to_quat(r_true[i] @ rot.axis_angle_matrix(rng.normal(size=3), np.deg2rad(1.4)))
+                   for i in range(2)])
+    out = stencil.stencil_then_refine(pats, master, pcs, q1, Params())
+    for i in range(2):
+        d_st = np.rad2deg(rot.disorientation_q(out["stencil"]["q"][i], q_true[i]))
+        d = np.rad2deg(rot.disorientation_q(out["q"][i], q_true[i]))
+        assert d < 0.02 and d < d_st
+        assert out["peak_h"][i] > 0.99
