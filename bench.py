@@ -177,6 +177,7 @@ def main():
                     help="skip the split-precision search on the same map at 256^2")
     ap.add_argument("--precision-patterns", type=int, default=10000)
     ap.add_argument("--precision-steps", type=int, default=2)
+    ap.add_argument("--precision-fp32-steps", type=int, default=1)
     ap.add_argument("--no-ragged", action="store_true",
                     help="skip the ragged batch (binnings 64-160, 27-point stencil, one graph launch)")
     ap.add_argument("--ragged-patterns", type=int, default=20000)
@@ -341,7 +342,8 @@ def main():
     if not args.no_precision:
         del pats, cfg, out, idx
         torch.cuda.empty_cache()
-        line["precision256"] = precision_256(tm, args.precision_patterns, args.library, args.precision_steps)
+        line["precision256"] = precision_256(tm, args.precision_patterns, args.library, args.precision_steps,
+                                             fp32_steps=args.precision_fp32_steps)
     if not args.no_ragged:
         torch.cuda.empty_cache()
         line["ragged"] = ragged_batch(tm, args.ragged_patterns, args.ragged_library, args.ragged_steps)
@@ -610,15 +612,17 @@ def capture_sweep(tm, n_ref=8, span=30.0, step=0.5):
     return res
 
 
-def precision_256(tm, patterns, library, steps, window=15, sample=3, n_sub=96):
-    """The map at 256 x 256 with the search as split-precision DFT-GEMMs on
-    MFMA (the FFT form is not built at this size), +-15 px window, followed
-    by the same refinement.  Per precision: patterns/s, pairs/s and the MFMA
-    roofline of the search kernel, agreement of the best template with the
-    FP16 hi + lo form, accuracy against the simulated truth, and the error
-    against the FP64 oracle on a sample of patterns: scores over a random
-    subset of the library plus the GPU's pick, the winner's sub-pixel peak
-    height and shift, and the refined orientation from the same start."""
+def precision_256(tm, patterns, library, steps, window=15, sample=3, n_sub=96, fp32_steps=1):
+    """The map at 256 x 256 with the search over a +-15 px window, followed by
+    the same refinement: first in FP32 (the exact windowed DFT on the vector
+    ALUs; the FFT form is not built at this size), then as split-precision
+    DFT-GEMMs on MFMA.  Per precision: patterns/s, pairs/s and the roofline of
+    the search kernel, agreement of the best template with the FP32 search,
+    accuracy against the simulated truth, and the error against the FP64
+    oracle on a sample of patterns: scores over a random subset of the
+    library, and where the device picked the oracle's start (its nearest
+    library orientation to the truth) the winner's sub-pixel peak height and
+    shift and the refined orientation."""
     import numpy as np
     import torch
     import oracle
@@ -662,8 +666,9 @@ def precision_256(tm, patterns, library, steps, window=15, sample=3, n_sub=96):
                            "the refinement where the device's pick is the oracle's start (its nearest library "
                            "orientation to the truth)" % (len(smp), len(sub))}
     ref_best = None
-    for name, prec in (("fp16x2", 1), ("bf16x2", 2), ("bf16", 3)):
+    for name, prec in (("fp32", 0), ("fp16x2", 1), ("bf16x2", 2), ("bf16", 3)):
         prm = tm.params_default(precision=prec, max_shift=window)
+        n_steps = fp32_steps if prec == 0 else steps
 
         def step():
             r = tm.index_patterns(pats, master, cfg["pc"], lib_q, prm=prm)
@@ -675,14 +680,14 @@ def precision_256(tm, patterns, library, steps, window=15, sample=3, n_sub=96):
         tm.timing_read()
         tm.timing_enable(True)
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for _ in range(n_steps):
             out, idx = step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         tm.timing_enable(False)
         ms, cnt = tm.timing_read()
         search_s = ms / 1e3 / max(cnt, 1)
-        flops = P * L * gemm_pair_flops(n, window, prec)
+        flops = P * L * gemm_pair_flops(n, window, 3 if prec == 0 else prec)
         best = idx["best_idx"].cpu().numpy()
         if ref_best is None:
             ref_best = best
@@ -712,13 +717,17 @@ def precision_256(tm, patterns, library, steps, window=15, sample=3, n_sub=96):
             rr = pipeline.refine_from_match(pats_h[a:a + 1], cfg["master"], cfg["pcs"][smp[a]:smp[a] + 1], cfg["pc"],
                                             cfg["lib_q"][b][None], np.array([[so[1], so[0]]]), oprm)
             d_q = max(d_q, float(np.rad2deg(rotations.disorientation_q(q[smp[a]], rr["q"][0]))))
-        res[name] = {"patterns_per_s": P * steps / (t1 - t0), "xcf_pairs_per_s": P * L / search_s,
-                     "search_ms": search_s * 1e3,
-                     "roofline": {"bound": "mfma", "kernel": "k_xcf_gemm<256>", "achieved": flops / search_s / 1e12,
-                                  "peak": PEAK_MFMA_16BIT / 1e12, "unit": "TFLOP/s",
-                                  "frac": flops / search_s / PEAK_MFMA_16BIT,
-                                  "flops_per_pair": gemm_pair_flops(n, window, prec)},
-                     "best_index_agreement_with_fp16x2": float(np.mean(best == ref_best)),
+        if prec == 0:
+            roof = {"bound": "alu", "kernel": "k_grid_peak (library mode)", "achieved": flops / search_s / 1e12,
+                    "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s", "frac": flops / search_s / PEAK_FP32_VALU,
+                    "flops_per_pair": gemm_pair_flops(n, window, 3)}
+        else:
+            roof = {"bound": "mfma", "kernel": "k_xcf_gemm<256>", "achieved": flops / search_s / 1e12,
+                    "peak": PEAK_MFMA_16BIT / 1e12, "unit": "TFLOP/s", "frac": flops / search_s / PEAK_MFMA_16BIT,
+                    "flops_per_pair": gemm_pair_flops(n, window, prec)}
+        res[name] = {"patterns_per_s": P * n_steps / (t1 - t0), "xcf_pairs_per_s": P * L / search_s,
+                     "search_ms": search_s * 1e3, "roofline": roof,
+                     "best_index_agreement_with_fp32": float(np.mean(best == ref_best)),
                      "refined_vs_truth_deg_median": float(np.median(vs_true)),
                      "refined_vs_truth_deg_p95": float(np.percentile(vs_true, 95)),
                      "vs_oracle": {"max_abs_score": d_score, "max_abs_peak_h": d_h, "max_abs_shift_px": float(d_s),

@@ -49,8 +49,9 @@
  *
  * Supported pattern sizes: n in {64, 96, 128, 160, 256}.  At n = 256 the
  * FFT form of the search and the full correlation map are not built: the
- * search runs in the DFT-GEMM form and every integer peak needs a shift
- * window (max_shift >= 0); other calls return EBSD_E_UNSUPPORTED.
+ * search runs in the DFT-GEMM or the exact FP32 DFT form and every integer
+ * peak needs a shift window (max_shift >= 0); other calls return
+ * EBSD_E_UNSUPPORTED.
  */
 #ifndef EBSD_TM_H
 #define EBSD_TM_H
@@ -68,7 +69,8 @@ extern "C" {
 #define EBSD_E_UNSUPPORTED (-4) /* valid request the library does not serve */
 
 /* Arithmetic of the correlation search (the library ranking):
- *   FP32    FP32 FFT form (every cyclic shift, or a window)
+ *   FP32    FP32 FFT form (every cyclic shift, or a window), or the exact
+ *           FP32 DFT form over a window
  *   FP16X2  DFT-GEMMs on MFMA, operands split into FP16 hi + lo halves,
  *           products hi*hi + hi*lo + lo*hi accumulated in FP32
  *   BF16X2  the same with BF16 halves
@@ -80,13 +82,19 @@ extern "C" {
 #define EBSD_PREC_BF16X2 2
 #define EBSD_PREC_BF16 3
 
-/* Form of the search: AUTO picks FFT for FP32 and DFTGEMM otherwise.
+/* Form of the search: AUTO picks FFT for FP32 (DFT at n = 256, where the
+ * FFT form is not built, when max_shift >= 0) and DFTGEMM otherwise.
  * DFTGEMM evaluates only the shift window |s_x|, |s_y| <= max_shift
  * (max_shift >= 0 required; the window's 2 max_shift + 1 shifts are padded
- * to a multiple of 16 and must fit the on-chip constant operands). */
+ * to a multiple of 16 and must fit the on-chip constant operands).
+ * DFT is the same windowed evaluation in FP32 on the vector ALUs, exactly
+ * the two products of the band-limited correlation (Equations 3 and 6a at
+ * the window's shifts, no split): the FP32 reference of the split forms,
+ * at every supported size (max_shift >= 0, 2 max_shift + 1 <= 208). */
 #define EBSD_FORM_AUTO 0
 #define EBSD_FORM_FFT 1
 #define EBSD_FORM_DFTGEMM 2
+#define EBSD_FORM_DFT 3
 
 /* A batch of P square patterns of side n, pattern p at data + p n n. */
 typedef struct {

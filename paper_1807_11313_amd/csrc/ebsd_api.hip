@@ -130,11 +130,21 @@ int resolve_params(const ebsd_params* in, int n, ebsd_params* out) {
     return fail(EBSD_E_INVALID, "n_eta must be even and in [4, 1024]");
   if (out->precision < EBSD_PREC_FP32 || out->precision > EBSD_PREC_BF16)
     return fail(EBSD_E_UNSUPPORTED, "unknown precision");
-  if (out->form < EBSD_FORM_AUTO || out->form > EBSD_FORM_DFTGEMM) return fail(EBSD_E_UNSUPPORTED, "unknown form");
+  if (out->form < EBSD_FORM_AUTO || out->form > EBSD_FORM_DFT) return fail(EBSD_E_UNSUPPORTED, "unknown form");
   if (out->max_shift < -1) return fail(EBSD_E_INVALID, "max_shift must be >= -1");
-  if (out->form == EBSD_FORM_AUTO) out->form = out->precision == EBSD_PREC_FP32 ? EBSD_FORM_FFT : EBSD_FORM_DFTGEMM;
+  if (out->form == EBSD_FORM_AUTO) {
+    if (out->precision != EBSD_PREC_FP32) out->form = EBSD_FORM_DFTGEMM;
+    else if (size_supported(n) && !fft_supported(n) && out->max_shift >= 0) out->form = EBSD_FORM_DFT;
+    else out->form = EBSD_FORM_FFT;
+  }
   if (out->form == EBSD_FORM_FFT && out->precision != EBSD_PREC_FP32)
     return fail(EBSD_E_UNSUPPORTED, "the FFT form runs in FP32 only");
+  if (out->form == EBSD_FORM_DFT) {
+    if (out->precision != EBSD_PREC_FP32) return fail(EBSD_E_UNSUPPORTED, "the exact DFT form runs in FP32 only");
+    if (out->max_shift < 0) return fail(EBSD_E_INVALID, "the exact DFT form needs a shift window (max_shift >= 0)");
+    if (size_supported(n) && !window_peak_supported(n, out->max_shift))
+      return fail(EBSD_E_UNSUPPORTED, "shift window too large for the exact DFT form at this size");
+  }
   if (out->form == EBSD_FORM_DFTGEMM) {
     if (out->precision == EBSD_PREC_FP32) return fail(EBSD_E_UNSUPPORTED, "the DFT-GEMM form runs in 16-bit halves");
     if (out->max_shift < 0) return fail(EBSD_E_INVALID, "the DFT-GEMM form needs a shift window (max_shift >= 0)");
@@ -217,16 +227,37 @@ int check_geometry(const ebsd_geometry* geo) {
 bool g_timing = false;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
 
-// The search in the requested form: FFT (FP32) or split-precision DFT-GEMM.
+// Constant operands of the search form: the split DFT-GEMM fragments, or the
+// phase tables of the exact FP32 DFT form (built here); none for the FFT form.
+struct SearchConsts {
+  unsigned short* frag = nullptr;
+  float2* wtab = nullptr;
+};
+
+int search_consts(int n, const ebsd_params& p, Arena& ws, hipStream_t st, SearchConsts* c) {
+  if (p.form == EBSD_FORM_DFTGEMM) {
+    EBSD_ALLOC(f, unsigned short, gemm_frag_bytes(n, p.max_shift) / 2, ws);
+    c->frag = f;
+  } else if (p.form == EBSD_FORM_DFT) {
+    EBSD_ALLOC(t, float2, window_table_size(n, p.max_shift), ws);
+    EBSD_TRY(launch_window_tables(n, p.max_shift, t, st), "window tables");
+    c->wtab = t;
+  }
+  return EBSD_OK;
+}
+
+// The search in the requested form: FFT (FP32), split-precision DFT-GEMM, or
+// the exact FP32 DFT over the shift window.
 hipError_t launch_search(int n, const ebsd_params& prm, const float2* sp, int64_t p, const float2* sl, int64_t l,
-                         unsigned short* frag, float* out, hipStream_t st) {
+                         const SearchConsts& c, float* out, hipStream_t st) {
   if (prm.form == EBSD_FORM_DFTGEMM)
-    return launch_xcf_gemm(n, prm.precision - 1, sp, p, sl, l, prm.max_shift, frag, out, st);
+    return launch_xcf_gemm(n, prm.precision - 1, sp, p, sl, l, prm.max_shift, c.frag, out, st);
+  if (prm.form == EBSD_FORM_DFT) return launch_window_scores(n, sp, p, sl, l, prm.max_shift, c.wtab, out, st);
   return launch_xcf_scores(n, sp, p, sl, l, prm.max_shift, out, st);
 }
 
 hipError_t timed_scores(int n, const ebsd_params& prm, const float2* sp, int64_t p, const float2* sl, int64_t l,
-                        unsigned short* frag, float* out, hipStream_t st) {
+                        const SearchConsts& frag, float* out, hipStream_t st) {
   if (!g_timing) return launch_search(n, prm, sp, p, sl, l, frag, out, st);
   hipEvent_t a, b;
   hipError_t e;
@@ -360,12 +391,9 @@ int ebsd_xcf_scores(const float* spec_p, int64_t P, const float* spec_l, int64_t
     return fail(EBSD_E_UNSUPPORTED, "the FFT search is not built at this size; use the DFT-GEMM form");
   hipStream_t st = (hipStream_t)stream;
   Scratch ws(st);
-  unsigned short* frag = nullptr;
-  if (p.form == EBSD_FORM_DFTGEMM) {
-    EBSD_ALLOC(f, unsigned short, gemm_frag_bytes(n, p.max_shift) / 2, ws);
-    frag = f;
-  }
-  EBSD_TRY(timed_scores(n, p, (const float2*)spec_p, P, (const float2*)spec_l, L, frag, scores, st), "xcf_scores");
+  SearchConsts consts;
+  if ((rc = search_consts(n, p, ws, st, &consts))) return rc;
+  EBSD_TRY(timed_scores(n, p, (const float2*)spec_p, P, (const float2*)spec_l, L, consts, scores, st), "xcf_scores");
   return EBSD_OK;
 }
 
@@ -454,12 +482,9 @@ int ebsd_index_patterns(const ebsd_batch* pats, const ebsd_master* mp, const ebs
            "project");
   if (int e = do_spectra(n, tmpl, L, fp, spec_l, nullptr, ws, st)) return e;
   if (int e = do_spectra(n, pats->data, P, fp, spec_p, nullptr, ws, st)) return e;
-  unsigned short* frag = nullptr;
-  if (p.form == EBSD_FORM_DFTGEMM) {
-    EBSD_ALLOC(f, unsigned short, gemm_frag_bytes(n, p.max_shift) / 2, ws);
-    frag = f;
-  }
-  EBSD_TRY(timed_scores(n, p, spec_p, P, spec_l, L, frag, sc_out, st), "xcf_scores");
+  SearchConsts consts;
+  if ((rc = search_consts(n, p, ws, st, &consts))) return rc;
+  EBSD_TRY(timed_scores(n, p, spec_p, P, spec_l, L, consts, sc_out, st), "xcf_scores");
   EBSD_TRY(launch_library_argmax(sc_out, P, L, best_idx, h_int, st), "library_argmax");
   if (int e = do_peak(n, p, spec_p, spec_l, nullptr, best_idx, P, h_tmp, s_int, ws, st)) return e;
   EBSD_TRY(launch_subpixel_tables(n, p.upsample, roots, st), "subpixel tables");

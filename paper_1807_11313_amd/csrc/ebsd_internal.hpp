@@ -35,6 +35,10 @@ hipError_t launch_window_tables(int n, int max_shift, float2* tab, hipStream_t s
 hipError_t launch_window_peak(int n, const float2* spec_p, const float2* spec_l, const int32_t* pi,
                               const int32_t* li, int64_t k, int max_shift, const float2* tab, float* h_int,
                               int32_t* s_int, hipStream_t stream);
+// The same exact FP32 evaluation as a library search: scores[p][l] = the
+// window's largest value for every pattern x template.
+hipError_t launch_window_scores(int n, const float2* spec_p, int64_t p, const float2* spec_l, int64_t l,
+                                int max_shift, const float2* tab, float* scores, hipStream_t stream);
 
 // Contrast-normalise, window, forward 2-D DFT, band-pass, FP64 energy and
 // unit-energy scaling of K n x n images (image k at imgs + k * img_stride).

@@ -11,7 +11,11 @@
 //   rho(b, a) = Re sum_v G'(b, v) F2(v, a),  F2(v, a) = exp(2 pi i v (a - m) / (kappa n))
 // Both stages are products with pattern-independent phase matrices (built in
 // FP64 once per call); Z' and F1 / F2 are streamed through LDS in 16-row
-// chunks, G stays in LDS.  The largest real value wins; ties go to the
+// chunks, G stays in LDS.  One block evaluates one pair: explicit pairs
+// (pi[k], li[k]), or, as the exact FP32 library search over a shift window,
+// every pair of P patterns x L templates (block k0 + blockIdx.x is pattern
+// (k0 + blockIdx.x) / L, template ... % L; its score goes to h_out at that
+// same row-major index).  The largest real value wins; ties go to the
 // smallest (b, a) for the sub-pixel grid, and to the smallest unsigned
 // row-major shift index ((s_y mod n) n + (s_x mod n)) for the integer window.
 #include "ebsd_common.hpp"
@@ -75,7 +79,7 @@ __global__ __launch_bounds__(TB * TB) void k_grid_peak(int n, int bnd, const cf*
                                                    const int32_t* __restrict__ li, const int32_t* __restrict__ centre,
                                                    int kappa, int m, int int_keys, const cf* __restrict__ tab,
                                                    float* __restrict__ h_out, float* __restrict__ s_out,
-                                                   int32_t* __restrict__ s_int_out) {
+                                                   int32_t* __restrict__ s_int_out, int64_t k0, int64_t lib_l) {
   extern __shared__ cf sm[];
   const int nv = bnd + 1, nk = 2 * bnd + 1, spec = nv * nk;
   const int msz = 2 * m + 1;
@@ -88,9 +92,11 @@ __global__ __launch_bounds__(TB * TB) void k_grid_peak(int n, int bnd, const cf*
   constexpr int NT = TB * TB;
   const int tid = threadIdx.x;
   const int tx = tid % TB, ty = tid / TB;
-  const int64_t k = blockIdx.x;
-  const cf* E = spec_p + (pi ? (int64_t)pi[k] : k) * spec;
-  const cf* T = spec_l + (li ? (int64_t)li[k] : k) * spec;
+  const int64_t k = k0 + blockIdx.x;
+  const int64_t kp = lib_l > 0 ? k / lib_l : (pi ? (int64_t)pi[k] : k);
+  const int64_t kl = lib_l > 0 ? k - (k / lib_l) * lib_l : (li ? (int64_t)li[k] : k);
+  const cf* E = spec_p + kp * spec;
+  const cf* T = spec_l + kl * spec;
   const int x0 = centre ? centre[2 * k] : 0, y0 = centre ? centre[2 * k + 1] : 0;
 
   // stage 1: thread (ty, tx) accumulates G(b = ty + 16 i, v = tx + 16 j)
@@ -241,7 +247,8 @@ hipError_t launch_grid_tables(int n, int kappa, int m, float2* tab, hipStream_t 
 template <int VJ, int TB>
 static hipError_t grid_vj(int n, int bnd, const float2* spec_p, const float2* spec_l, const int32_t* pi,
                           const int32_t* li, int64_t k, const int32_t* centre, int kappa, int m, int int_keys,
-                          const float2* tab, float* h, float* s, int32_t* si, hipStream_t stream) {
+                          const float2* tab, float* h, float* s, int32_t* si, hipStream_t stream, int64_t k0 = 0,
+                          int64_t lib_l = 0) {
   const int msz = 2 * m + 1;
   const size_t shm = grid_lds_bytes(n, m);
   const int mb = (msz + TB - 1) / TB;
@@ -251,7 +258,7 @@ static hipError_t grid_vj(int n, int bnd, const float2* spec_p, const float2* sp
                               (int)shm);                                                                          \
     hipLaunchKernelGGL((k_grid_peak<VJ, MBV, TB>), dim3((unsigned)k), dim3(TB * TB), shm, stream, n, bnd,             \
                        (const cf*)spec_p, (const cf*)spec_l, pi, li, centre, kappa, m, int_keys,                    \
-                       (const cf*)tab, h, s, si);                                                                   \
+                       (const cf*)tab, h, s, si, k0, lib_l);                                                        \
   } while (0)
   // rows per thread rounded up as little as possible: every extra row is a
   // full set of FMAs on zeros (the sub-pixel grid, 151 rows at kappa = 100,
@@ -328,6 +335,33 @@ hipError_t launch_window_peak(int n, const float2* spec_p, const float2* spec_l,
                               const int32_t* li, int64_t k, int max_shift, const float2* tab, float* h_int,
                               int32_t* s_int, hipStream_t stream) {
   return launch_grid(n, spec_p, spec_l, pi, li, k, nullptr, 1, max_shift, 1, tab, h_int, nullptr, s_int, stream);
+}
+
+hipError_t launch_window_scores(int n, const float2* spec_p, int64_t p, const float2* spec_l, int64_t l,
+                                int max_shift, const float2* tab, float* scores, hipStream_t stream) {
+  if (p <= 0 || l <= 0) return hipSuccess;
+  const int bnd = band_of(n);
+  if (bnd < 0 || !window_peak_supported(n, max_shift)) return hipErrorInvalidValue;
+  if (bnd + 1 > 112) return hipErrorInvalidValue;
+  const int64_t total = p * l;
+  const int64_t kmax = (int64_t(1) << 31) / 1024;  // blocks x threads of one dispatch below 2^31
+  const bool wide = grid_lds_bytes(n, max_shift) > 80 * 1024;
+  for (int64_t k0 = 0; k0 < total; k0 += kmax) {
+    const int64_t kc = total - k0 < kmax ? total - k0 : kmax;
+    hipError_t e;
+    if (bnd + 1 <= 64)
+      e = wide ? grid_vj<2, 32>(n, bnd, spec_p, spec_l, nullptr, nullptr, kc, nullptr, 1, max_shift, 1, tab, scores,
+                                nullptr, nullptr, stream, k0, l)
+               : grid_vj<4, 16>(n, bnd, spec_p, spec_l, nullptr, nullptr, kc, nullptr, 1, max_shift, 1, tab, scores,
+                                nullptr, nullptr, stream, k0, l);
+    else
+      e = wide ? grid_vj<4, 32>(n, bnd, spec_p, spec_l, nullptr, nullptr, kc, nullptr, 1, max_shift, 1, tab, scores,
+                                nullptr, nullptr, stream, k0, l)
+               : grid_vj<7, 16>(n, bnd, spec_p, spec_l, nullptr, nullptr, kc, nullptr, 1, max_shift, 1, tab, scores,
+                                nullptr, nullptr, stream, k0, l);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace ebsd

@@ -25,7 +25,7 @@ from .gpu_util import banner, dev, host, oracle_spectra, oracle_templates, tm
 pytestmark = pytest.mark.gpu
 
 N = 256
-TOL = {1: 1e-4, 2: 1e-3, 3: 3e-2}
+TOL = {0: 5e-6, 1: 1e-4, 2: 1e-3, 3: 3e-2}
 
 
 def _pats(k, seed, offsets=5.0):
@@ -80,7 +80,11 @@ def test_size256_limits():
     with pytest.raises(pkg.EbsdError):            # every cyclic shift needs the map
         t.xcf_peak(spec, spec, None, None, N)
     with pytest.raises(pkg.EbsdError):            # the FFT search is not built at 256
-        t.xcf_scores(spec, spec, N, t.params_default(max_shift=3))
+        t.xcf_scores(spec, spec, N, t.params_default(max_shift=3, form=1))
+    with pytest.raises(pkg.EbsdError):            # the exact DFT form needs a window
+        t.xcf_scores(spec, spec, N, t.params_default(form=3))
+    with pytest.raises(pkg.EbsdError):            # and runs in FP32 only
+        t.xcf_scores(spec, spec, N, t.params_default(form=3, precision=1, max_shift=3))
 
 
 def test_subpixel256_matches_oracle():
@@ -104,8 +108,10 @@ def test_subpixel256_matches_oracle():
         assert abs(ss[k][0] - sr[1]) <= 0.02 + 1e-6 and abs(ss[k][1] - sr[0]) <= 0.02 + 1e-6
 
 
-@pytest.mark.parametrize("prec", [1, 2, 3])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_gemm256_scores_match_oracle(prec):
+    # precision 0: the exact FP32 DFT form (AUTO at 256 with a window), the
+    # reference the split forms are reported against
     banner("gemm scores n=256 precision=%d" % prec)
     t = tm()
     pats = _pats(2, seed=31 + prec)
@@ -122,7 +128,7 @@ def test_gemm256_scores_match_oracle(prec):
         assert err < TOL[prec]
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_index_and_refine256_match_oracle(prec):
     banner("index + refine n=256 precision=%d" % prec)
     t = tm()

@@ -109,3 +109,25 @@ def test_gemm_scores_match_emulated_split(n, prec):
             err = max(err, float(np.max(np.abs(got[i] - emu))))
         print("[gpu]   n=%d %s S=%d max |gpu - emulated| = %.3g" % (n, name, s, err), flush=True)
         assert err < 3e-6
+
+
+@pytest.mark.parametrize("n", [64, 96, 128, 160])
+def test_exact_dft_form_matches_oracle_and_fft_form(n):
+    # the exact FP32 DFT form (form 3) against the oracle at the FP32 bound,
+    # and against the FFT form's windowed scores on the same spectra
+    banner("exact DFT form n=%d" % n)
+    t = tm()
+    pats, lq = _setup(n, 3, 29, seed=11 * n)
+    sp, _, fp = oracle_spectra(pats, n)
+    sl, _, fl = oracle_spectra(oracle_templates(band_master(), lq, n, (0.5, 0.5, 0.6)), n)
+    for s in (0, 7, 15):
+        got = host(t.xcf_scores(sp, sl, n, t.params_default(form=3, max_shift=s)))
+        fft = host(t.xcf_scores(sp, sl, n, t.params_default(form=1, max_shift=s)))
+        err = 0.0
+        for i in range(len(pats)):
+            ref = oxcf.library_scores(fp[i], fl, max_shift=s)
+            err = max(err, float(np.max(np.abs(got[i] - ref))))
+        print("[gpu]   n=%d S=%d max |dh| = %.3g, vs FFT form %.3g" % (n, s, err, np.max(np.abs(got - fft))),
+              flush=True)
+        assert err < 5e-6
+        assert np.max(np.abs(got - fft)) < 5e-6
