@@ -96,6 +96,15 @@ extern "C" {
 #define EBSD_FORM_DFTGEMM 2
 #define EBSD_FORM_DFT 3
 
+/* Storage of the caller's pattern images (ebsd_params.input): FP32, or BF16
+ * (the bit pattern of bfloat16 values, 2 bytes per pixel, passed through the
+ * same float pointer) widened to FP32 as each pixel is loaded.  BF16 images
+ * are read by ebsd_pattern_spectra, ebsd_index_patterns, the refinements and
+ * ebsd_index_proposed at n <= 160; every other call, and n = 256, returns
+ * EBSD_E_UNSUPPORTED for them. */
+#define EBSD_INPUT_F32 0
+#define EBSD_INPUT_BF16 1
+
 /* A batch of P square patterns of side n, pattern p at data + p n n. */
 typedef struct {
   const float* data;
@@ -128,6 +137,8 @@ typedef struct {
  *   n_rho, n_eta  0, 0: log-polar grid n/2 radii x 2n angles
  *   precision     EBSD_PREC_FP32 (see above)
  *   form          EBSD_FORM_AUTO
+ *   input         EBSD_INPUT_F32 (pattern image storage; a caller whose
+ *                 struct_size ends before this field gets FP32)
  */
 typedef struct {
   uint32_t struct_size; /* sizeof(ebsd_params) */
@@ -139,6 +150,7 @@ typedef struct {
   int32_t n_rho, n_eta;
   int32_t precision;
   int32_t form;
+  int32_t input;
 } ebsd_params;
 
 /* Fills *p with the defaults above. */

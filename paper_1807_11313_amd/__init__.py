@@ -63,7 +63,8 @@ class Params(ctypes.Structure):
                 ("sigma_hp", ctypes.c_double), ("sigma_lp_frac", ctypes.c_double),
                 ("rho_max_frac", ctypes.c_double), ("max_shift", ctypes.c_int32),
                 ("upsample", ctypes.c_int32), ("n_iter", ctypes.c_int32), ("n_rho", ctypes.c_int32),
-                ("n_eta", ctypes.c_int32), ("precision", ctypes.c_int32), ("form", ctypes.c_int32)]
+                ("n_eta", ctypes.c_int32), ("precision", ctypes.c_int32), ("form", ctypes.c_int32),
+                ("input", ctypes.c_int32)]
 
 
 class EbsdError(RuntimeError):
@@ -212,6 +213,25 @@ def _params(prm):
     return ctypes.byref(prm) if prm is not None else None
 
 
+INPUT_F32, INPUT_BF16 = 0, 1
+
+
+def _images(patterns, prm, name="patterns"):
+    """Pointer to float32 or bfloat16 pattern images and the parameter block
+    that states their storage (a copy of prm, or the defaults, with input set
+    for bfloat16)."""
+    import torch
+    if patterns.dtype == torch.bfloat16:
+        q = Params()
+        if prm is None:
+            lib().ebsd_params_default(ctypes.byref(q))
+        else:
+            ctypes.memmove(ctypes.byref(q), ctypes.byref(prm), ctypes.sizeof(Params))
+        q.input = INPUT_BF16
+        return _ptr(patterns, torch.bfloat16, name), q
+    return _ptr(patterns, torch.float32, name), prm
+
+
 def index_patterns(patterns, master, pc, lib_q, prm=None, scores=False):
     """Returns dict(best_idx, best_q, peak_h, shift[, scores]) as CUDA tensors."""
     import torch
@@ -225,7 +245,8 @@ def index_patterns(patterns, master, pc, lib_q, prm=None, scores=False):
                shift=torch.empty((p, 2), dtype=torch.float32, device=dev))
     if scores:
         out["scores"] = torch.empty((p, lib_q.shape[0]), dtype=torch.float32, device=dev)
-    batch = Batch(_ptr(patterns, torch.float32, "patterns").value, p, n)
+    data, prm = _images(patterns, prm)
+    batch = Batch(data.value, p, n)
     rc = lib().ebsd_index_patterns(ctypes.byref(batch), ctypes.byref(_master(master)), ctypes.byref(_geo(pc)),
                                    _ptr(lib_q, torch.float64, "lib_q"), lib_q.shape[0], _params(prm),
                                    _ptr(out["best_idx"]), _ptr(out["best_q"]), _ptr(out["peak_h"]),
@@ -251,7 +272,8 @@ def refine_orientations(patterns, master, pc, q_init, pc_per=None, prm=None, out
                    shift=torch.empty((p, 2), dtype=torch.float32, device=dev))
     for key, shape in (("q", (p, 4)), ("peak_h", (p,)), ("shift", (p, 2))):
         _shape(out[key], shape, key)
-    batch = Batch(_ptr(patterns, torch.float32, "patterns").value, p, n)
+    data, prm = _images(patterns, prm)
+    batch = Batch(data.value, p, n)
     name = "ebsd_refine_orientations_noalloc" if noalloc else "ebsd_refine_orientations"
     rc = getattr(lib(), name)(ctypes.byref(batch), ctypes.byref(_master(master)), ctypes.byref(_geo(pc, pc_per, p)),
                               _ptr(q_init, torch.float64, "q_init"), _params(prm),
@@ -276,7 +298,8 @@ def refine_from_match(patterns, master, pc, q_init, match_shift, pc_per=None, pr
     out = dict(q=torch.empty((p, 4), dtype=torch.float64, device=dev),
                peak_h=torch.empty(p, dtype=torch.float32, device=dev),
                shift=torch.empty((p, 2), dtype=torch.float32, device=dev))
-    batch = Batch(_ptr(patterns, torch.float32, "patterns").value, p, n)
+    data, prm = _images(patterns, prm)
+    batch = Batch(data.value, p, n)
     rc = lib().ebsd_refine_from_match(ctypes.byref(batch), ctypes.byref(_master(master)),
                                       ctypes.byref(_geo(pc, pc_per, p)), _ptr(q_init, torch.float64, "q_init"),
                                       _ptr(match_shift, torch.float32, "match_shift"), _params(prm),
@@ -359,8 +382,8 @@ def pattern_spectra(imgs, prm=None, energy=False):
         raise ValueError("unsupported size %d" % n)
     spec = torch.empty((k, nf), dtype=torch.float32, device=imgs.device)
     en = torch.empty(k, dtype=torch.float64, device=imgs.device) if energy else None
-    rc = lib().ebsd_pattern_spectra(_ptr(imgs, torch.float32, "imgs"), k, n, _params(prm), _ptr(spec), _ptr(en),
-                                    _stream())
+    data, prm = _images(imgs, prm, "imgs")
+    rc = lib().ebsd_pattern_spectra(data, k, n, _params(prm), _ptr(spec), _ptr(en), _stream())
     _check(rc, "ebsd_pattern_spectra")
     return (spec, en) if energy else spec
 
@@ -666,7 +689,8 @@ def index_proposed(patterns, master, pc, lib_q, cnn, top_k=32, fallback_tau=0.0,
                peak_h=torch.empty(p, dtype=torch.float32, device=dev),
                shift=torch.empty((p, 2), dtype=torch.float32, device=dev),
                fallback=torch.empty(p, dtype=torch.int32, device=dev))
-    b = Batch(_ptr(patterns, torch.float32, "patterns").value, p, n)
+    data, prm = _images(patterns, prm)
+    b = Batch(data.value, p, n)
     m, g = _master(master), _geo(pc)
     _check(lib().ebsd_index_proposed(ctypes.byref(b), ctypes.byref(m), ctypes.byref(g),
                                      _ptr(lib_q, torch.float64, "lib_q"), lib_q.shape[0], cnn._h, top_k,

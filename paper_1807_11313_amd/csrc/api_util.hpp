@@ -18,6 +18,7 @@ FilterParams filter_of(const ebsd_params& p, int n);
 int check_master(const ebsd_master* mp);
 int check_geometry(const ebsd_geometry* geo);
 int64_t spec_complex(int n);
+int f32_images_only(const ebsd_params& p);
 
 }  // namespace api
 }  // namespace ebsd

@@ -53,6 +53,8 @@ hipError_t sample_setup(int64_t first, int64_t bsz, uint64_t seed, double pcx, d
                         double max_off_frac, double* q, double* pc, hipStream_t st);
 hipError_t noise_bin(const float* clean, int n, int64_t bsz, int64_t first, uint64_t seed, float counts, float snr,
                      int noisy, float* x, hipStream_t st);
+hipError_t noise_bin(const __bf16* clean, int n, int64_t bsz, int64_t first, uint64_t seed, float counts,
+                     float snr, int noisy, float* x, hipStream_t st);
 hipError_t nearest_library(const double* q, int64_t bsz, const double* lib, int l, int32_t* label,
                            hipStream_t st);
 hipError_t topk(const float* z, int64_t rows, int l, int k, int32_t* idx, hipStream_t st);

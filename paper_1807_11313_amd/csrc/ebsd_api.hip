@@ -132,6 +132,10 @@ int resolve_params(const ebsd_params* in, int n, ebsd_params* out) {
     return fail(EBSD_E_UNSUPPORTED, "unknown precision");
   if (out->form < EBSD_FORM_AUTO || out->form > EBSD_FORM_DFT) return fail(EBSD_E_UNSUPPORTED, "unknown form");
   if (out->max_shift < -1) return fail(EBSD_E_INVALID, "max_shift must be >= -1");
+  if (out->input != EBSD_INPUT_F32 && out->input != EBSD_INPUT_BF16)
+    return fail(EBSD_E_UNSUPPORTED, "unknown pattern input type");
+  if (out->input == EBSD_INPUT_BF16 && n > 160)
+    return fail(EBSD_E_UNSUPPORTED, "BF16 pattern images are read at n <= 160 only");
   if (out->form == EBSD_FORM_AUTO) {
     if (out->precision != EBSD_PREC_FP32) out->form = EBSD_FORM_DFTGEMM;
     else if (size_supported(n) && !fft_supported(n) && out->max_shift >= 0) out->form = EBSD_FORM_DFT;
@@ -198,6 +202,30 @@ int do_peak(int n, const ebsd_params& p, const float2* sp, const float2* sl, con
   }
   EBSD_TRY(launch_window_peak(n, sp, sl, pi, li, k, p.max_shift, tab, h, s, st), "window peak");
   return EBSD_OK;
+}
+
+// Calls that never read the caller's pattern images reject a BF16 input flag.
+int f32_images_only(const ebsd_params& p) {
+  if (p.input != EBSD_INPUT_F32) return fail(EBSD_E_UNSUPPORTED, "this call reads FP32 images only");
+  return EBSD_OK;
+}
+
+// Spectra and log-polar images of the caller's patterns (FP32, or BF16 as
+// p.input says).
+int pattern_spectra(int n, const ebsd_params& p, const float* imgs, int64_t k, const FilterParams& fp, float2* spec,
+                    double* energy, Arena& ws, hipStream_t st, void* s256 = nullptr) {
+  if (p.input == EBSD_INPUT_BF16) {
+    EBSD_TRY(launch_spectra(n, reinterpret_cast<const __bf16*>(imgs), (int64_t)n * n, k, fp, spec, energy, st),
+             "spectra(bf16)");
+    return EBSD_OK;
+  }
+  return do_spectra(n, imgs, k, fp, spec, energy, ws, st, s256);
+}
+
+hipError_t pattern_logpolar(int n, const ebsd_params& p, const float* imgs, int64_t k, float* out, hipStream_t st) {
+  if (p.input == EBSD_INPUT_BF16)
+    return launch_logpolar(n, reinterpret_cast<const __bf16*>(imgs), k, p.n_rho, p.n_eta, out, st);
+  return launch_logpolar(n, imgs, k, p.n_rho, p.n_eta, out, st);
 }
 
 int64_t spec_complex(int n) {
@@ -353,7 +381,7 @@ int ebsd_pattern_spectra(const float* imgs, int64_t K, int32_t n, const ebsd_par
   if (!imgs || !spec) return fail(EBSD_E_INVALID, "null pointer");
   hipStream_t st = (hipStream_t)stream;
   Scratch ws(st);
-  return do_spectra(n, imgs, K, filter_of(p, n), (float2*)spec, energy, ws, st);
+  return pattern_spectra(n, p, imgs, K, filter_of(p, n), (float2*)spec, energy, ws, st);
 }
 
 int ebsd_xcf_peak(const float* spec_p, const float* spec_l, const int32_t* pi, const int32_t* li, int64_t K,
@@ -361,7 +389,7 @@ int ebsd_xcf_peak(const float* spec_p, const float* spec_l, const int32_t* pi, c
   g_last_error.clear();
   int rc;
   ebsd_params p;
-  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p))) return rc;
+  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p)) || (rc = f32_images_only(p))) return rc;
   if (K < 0) return fail(EBSD_E_INVALID, "K must be >= 0");
   if (K == 0) return EBSD_OK;
   if (!spec_p || !spec_l || !h_int || !s_int) return fail(EBSD_E_INVALID, "null pointer");
@@ -383,7 +411,7 @@ int ebsd_xcf_scores(const float* spec_p, int64_t P, const float* spec_l, int64_t
   g_last_error.clear();
   int rc;
   ebsd_params p;
-  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p))) return rc;
+  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p)) || (rc = f32_images_only(p))) return rc;
   if (P < 0 || L < 0) return fail(EBSD_E_INVALID, "P and L must be >= 0");
   if (P == 0 || L == 0) return EBSD_OK;
   if (!spec_p || !spec_l || !scores) return fail(EBSD_E_INVALID, "null pointer");
@@ -403,7 +431,7 @@ int ebsd_xcf_subpixel(const float* spec_p, const float* spec_l, const int32_t* p
   g_last_error.clear();
   int rc;
   ebsd_params p;
-  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p))) return rc;
+  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p)) || (rc = f32_images_only(p))) return rc;
   if (K < 0) return fail(EBSD_E_INVALID, "K must be >= 0");
   if (K == 0) return EBSD_OK;
   if (!spec_p || !spec_l || !s_int || !h_sub || !s_sub) return fail(EBSD_E_INVALID, "null pointer");
@@ -422,7 +450,7 @@ int ebsd_measure_rotation(const float* pats, const float* tmpls, int64_t K, int3
   g_last_error.clear();
   int rc;
   ebsd_params p;
-  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p))) return rc;
+  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p)) || (rc = f32_images_only(p))) return rc;
   if (K < 0) return fail(EBSD_E_INVALID, "K must be >= 0");
   if (K == 0) return EBSD_OK;
   if (!pats || !tmpls || !gamma) return fail(EBSD_E_INVALID, "null pointer");
@@ -481,7 +509,7 @@ int ebsd_index_patterns(const ebsd_batch* pats, const ebsd_master* mp, const ebs
   EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, lib_q, L, nullptr, geo->pcx, geo->pcy, geo->pcz, tmpl, st),
            "project");
   if (int e = do_spectra(n, tmpl, L, fp, spec_l, nullptr, ws, st)) return e;
-  if (int e = do_spectra(n, pats->data, P, fp, spec_p, nullptr, ws, st)) return e;
+  if (int e = pattern_spectra(n, p, pats->data, P, fp, spec_p, nullptr, ws, st)) return e;
   SearchConsts consts;
   if ((rc = search_consts(n, p, ws, st, &consts))) return rc;
   EBSD_TRY(timed_scores(n, p, spec_p, P, spec_l, L, consts, sc_out, st), "xcf_scores");
@@ -585,8 +613,8 @@ int refine_run(const ebsd_batch* pats, const ebsd_master* mp, const ebsd_geometr
   if (q_out != q_init) EBSD_TRY(hipMemcpyAsync(q_out, q_init, sizeof(double) * 4 * P, hipMemcpyDeviceToDevice, st), "copy q");
   EBSD_TRY(launch_subpixel_tables(n, p.upsample, b.roots, st), "subpixel tables");
   if (b.wtab) EBSD_TRY(launch_window_tables(n, p.max_shift, b.wtab, st), "window tables");
-  if ((rc = do_spectra(n, pats->data, P, fp, b.spec_p, nullptr, none, st, b.s256))) return rc;
-  EBSD_TRY(launch_logpolar(n, pats->data, P, p.n_rho, p.n_eta, b.lp_e, st), "logpolar(patterns)");
+  if ((rc = pattern_spectra(n, p, pats->data, P, fp, b.spec_p, nullptr, none, st, b.s256))) return rc;
+  EBSD_TRY(pattern_logpolar(n, p, pats->data, P, b.lp_e, st), "logpolar(patterns)");
   const double* pcp = geo->pc_per;
   auto measure_shift = [&](float* h_out, float* s_out) -> int {
     EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, q_out, P, pcp, geo->pcx, geo->pcy, geo->pcz, b.tmpl, st),
@@ -703,7 +731,7 @@ int ebsd_capture_range(const ebsd_master* mp, const double* q_ref, int64_t R, in
   int rc;
   ebsd_params p;
   if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p)) || (rc = check_master(mp)) ||
-      (rc = check_geometry(geo_ref)) || (rc = check_geometry(geo_test)))
+      (rc = check_geometry(geo_ref)) || (rc = check_geometry(geo_test)) || (rc = f32_images_only(p)))
     return rc;
   if (R < 0) return fail(EBSD_E_INVALID, "R must be >= 0");
   if (T < 1) return fail(EBSD_E_INVALID, "T must be >= 1");

@@ -428,7 +428,10 @@ int ebsd_index_proposed(const ebsd_batch* pats, const ebsd_master* mp, const ebs
   auto run = [&]() -> int {
     int r;
     // network: top-k library orientations per pattern
-    CN_TRY(cnn::noise_bin(pats->data, n, P, 0, 0, 0.0f, 1.0f, 0, x, st), "cnn input");
+    const bool bf16 = p.input == EBSD_INPUT_BF16;
+    const __bf16* pats_bf16 = reinterpret_cast<const __bf16*>(pats->data);
+    if (bf16) CN_TRY(cnn::noise_bin(pats_bf16, n, P, 0, 0, 0.0f, 1.0f, 0, x, st), "cnn input");
+    else CN_TRY(cnn::noise_bin(pats->data, n, P, 0, 0, 0.0f, 1.0f, 0, x, st), "cnn input");
     for (int64_t s = 0; s < P; s += kChunk) {
       const int64_t b = std::min(kChunk, P - s);
       if ((r = forward_chunks(c, x + s * cnn::kInSize * cnn::kInSize, b, logits, st))) return r;
@@ -438,7 +441,8 @@ int ebsd_index_proposed(const ebsd_batch* pats, const ebsd_master* mp, const ebs
     CN_TRY(launch_project(n, mp->data, mp->H, mp->W, lib_q, L, nullptr, geo->pcx, geo->pcy, geo->pcz, tmpl, st),
            "project");
     CN_TRY(launch_spectra(n, tmpl, npix, L, fp, spec_l, nullptr, st), "spectra(templates)");
-    CN_TRY(launch_spectra(n, pats->data, npix, P, fp, spec_p, nullptr, st), "spectra(patterns)");
+    if (bf16) CN_TRY(launch_spectra(n, pats_bf16, npix, P, fp, spec_p, nullptr, st), "spectra(patterns)");
+    else CN_TRY(launch_spectra(n, pats->data, npix, P, fp, spec_p, nullptr, st), "spectra(patterns)");
     // correlation on the candidates only
     hipLaunchKernelGGL(k_pairs, dim3(nb(PK)), dim3(256), 0, st, cand, P, top_k, pi);
     CN_TRY(launch_xcf_peak(n, spec_p, spec_l, pi, cand, PK, p.max_shift, hk, sk, nullptr, st), "xcf(candidates)");

@@ -19,6 +19,10 @@ struct cf {
   float x, y;
 };
 
+// A pattern pixel widened to FP32 (patterns may be stored as FP32 or BF16).
+__device__ __forceinline__ float ld_px(float v) { return v; }
+__device__ __forceinline__ float ld_px(__bf16 v) { return (float)v; }
+
 __device__ __forceinline__ cf cmake(float a, float b) { return cf{a, b}; }
 __device__ __forceinline__ cf cadd(cf a, cf b) { return cf{a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ cf csub(cf a, cf b) { return cf{a.x - b.x, a.y - b.y}; }

@@ -46,6 +46,10 @@ hipError_t launch_window_scores(int n, const float2* spec_p, int64_t p, const fl
 hipError_t launch_spectra(int n, const float* imgs, int64_t img_stride, int64_t k,
                           const FilterParams& fp, float2* spec, double* energy,
                           hipStream_t stream);
+// The same from BF16 pixels (each widened to FP32 on load; n <= 160).
+hipError_t launch_spectra(int n, const __bf16* imgs, int64_t img_stride, int64_t k,
+                          const FilterParams& fp, float2* spec, double* energy,
+                          hipStream_t stream);
 
 // Spectra of K images at element offsets img_off[k] of imgs.
 hipError_t launch_spectra_gather(int n, const float* imgs, const int64_t* img_off, int64_t k,
@@ -110,6 +114,8 @@ hipError_t launch_gather_q(const double* lib_q, const int32_t* best, int64_t p, 
 
 // Log-polar resampling of contrast-normalised images, rows mean-removed.
 hipError_t launch_logpolar(int n, const float* imgs, int64_t k, int n_rho, int n_eta,
+                           float* out, hipStream_t stream);
+hipError_t launch_logpolar(int n, const __bf16* imgs, int64_t k, int n_rho, int n_eta,
                            float* out, hipStream_t stream);
 
 // eta correlation of pattern / template log-polar images, peak refined by

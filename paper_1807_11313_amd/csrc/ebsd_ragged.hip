@@ -580,7 +580,7 @@ int ebsd_ragged_plan_create(const int32_t* n_per, const int64_t* offset, int64_t
     return fail(EBSD_E_INVALID, "stencil step must be in (0, 10] degrees");
   ebsd_params p;
   int rc;
-  if ((rc = resolve_params(prm, 128, &p))) return rc;
+  if ((rc = resolve_params(prm, 128, &p)) || (rc = f32_images_only(p))) return rc;
   if (p.form != EBSD_FORM_FFT) return fail(EBSD_E_UNSUPPORTED, "ragged batches run the FP32 FFT form");
   auto* pl = new ebsd_ragged_plan_s();
   pl->P = P;

@@ -479,17 +479,18 @@ __global__ void k_sample_setup(int64_t first, int64_t bsz, uint64_t seed, double
 // its normal approximation, plus Gaussian read noise fixing the pattern's
 // SNR), f x f block-mean binning to 64 x 64 (f = n / 64) and
 // (x - mean) / std.  One block per pattern.
-__global__ __launch_bounds__(256) void k_noise_bin(const float* __restrict__ clean, int n, int64_t first,
+template <class T>
+__global__ __launch_bounds__(256) void k_noise_bin(const T* __restrict__ clean, int n, int64_t first,
                                                    uint64_t seed, float counts, float snr, int noisy,
                                                    float* __restrict__ x) {
   __shared__ float bin[64 * 64];
   __shared__ double red[8];
   const int64_t j = blockIdx.x;
   const int tid = threadIdx.x;
-  const float* img = clean + (size_t)j * n * n;
+  const T* img = clean + (size_t)j * n * n;
   double s1 = 0.0, s2 = 0.0;
   for (int i = tid; i < n * n; i += 256) {
-    const double v = img[i];
+    const double v = ld_px(img[i]);
     s1 += v;
     s2 += v * v;
   }
@@ -520,7 +521,7 @@ __global__ __launch_bounds__(256) void k_noise_bin(const float* __restrict__ cle
     for (int dy = 0; dy < f; ++dy)
       for (int dx = 0; dx < f; ++dx) {
         const int pix = (by * f + dy) * n + bx * f + dx;
-        float v = img[pix] * scale;
+        float v = ld_px(img[pix]) * scale;
         if (noisy) {
           const float2 z = normal2(philox((s << 20) ^ (uint64_t)pix, 4u, seed));
           v += sqrtf(fmaxf(v, 0.0f)) * z.x + sg * z.y;
@@ -801,13 +802,24 @@ hipError_t sample_setup(int64_t first, int64_t bsz, uint64_t seed, double pcx, d
   return hipGetLastError();
 }
 
-hipError_t noise_bin(const float* clean, int n, int64_t bsz, int64_t first, uint64_t seed, float counts, float snr,
-                     int noisy, float* x, hipStream_t st) {
+template <class T>
+static hipError_t noise_bin_t(const T* clean, int n, int64_t bsz, int64_t first, uint64_t seed, float counts,
+                              float snr, int noisy, float* x, hipStream_t st) {
   if (bsz > (int64_t(1) << 31) / 256) return hipErrorInvalidValue;  // one dispatch below 2^31 items
   if (n % kInSize != 0 || n < kInSize) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_noise_bin, dim3((unsigned)bsz), dim3(256), 0, st, clean, n, first, seed, counts, snr, noisy,
-                     x);
+  hipLaunchKernelGGL(k_noise_bin<T>, dim3((unsigned)bsz), dim3(256), 0, st, clean, n, first, seed, counts, snr,
+                     noisy, x);
   return hipGetLastError();
+}
+
+hipError_t noise_bin(const float* clean, int n, int64_t bsz, int64_t first, uint64_t seed, float counts, float snr,
+                     int noisy, float* x, hipStream_t st) {
+  return noise_bin_t(clean, n, bsz, first, seed, counts, snr, noisy, x, st);
+}
+
+hipError_t noise_bin(const __bf16* clean, int n, int64_t bsz, int64_t first, uint64_t seed, float counts,
+                     float snr, int noisy, float* x, hipStream_t st) {
+  return noise_bin_t(clean, n, bsz, first, seed, counts, snr, noisy, x, st);
 }
 
 hipError_t nearest_library(const double* q, int64_t bsz, const double* lib, int l, int32_t* label,

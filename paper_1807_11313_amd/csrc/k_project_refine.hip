@@ -142,14 +142,15 @@ __global__ void k_gather_q(const double* __restrict__ lib_q, const int32_t* __re
 // centre ((n-1)/2, (n-1)/2), n_rho radii log-spaced in [2, n/2 - 2] px, n_eta
 // angles eta_m = 2 pi m / n_eta measured from +column toward +row, bilinear
 // samples of the contrast-normalised image, each radius row mean-removed.
-__global__ __launch_bounds__(256) void k_logpolar(const float* __restrict__ imgs, int n, int n_rho,
+template <class T>
+__global__ __launch_bounds__(256) void k_logpolar(const T* __restrict__ imgs, int n, int n_rho,
                                                   int n_eta, float* __restrict__ out) {
   const int64_t k = blockIdx.x;
   const int tid = threadIdx.x;
-  const float* img = imgs + k * (int64_t)n * n;
+  const T* img = imgs + k * (int64_t)n * n;
   double s1 = 0.0, s2 = 0.0;
   for (int i = tid; i < n * n; i += 256) {
-    const double v = img[i];
+    const double v = ld_px(img[i]);
     s1 += v;
     s2 += v * v;
   }
@@ -192,9 +193,9 @@ __global__ __launch_bounds__(256) void k_logpolar(const float* __restrict__ imgs
         const float r0f = floorf(rw), c0f = floorf(col);
         const float fr = rw - r0f, fc = col - c0f;
         const int r0 = (int)r0f, c0 = (int)c0f;
-        const float* p = img + r0 * n + c0;
-        const float val =
-            (1.0f - fr) * ((1.0f - fc) * p[0] + fc * p[1]) + fr * ((1.0f - fc) * p[n] + fc * p[n + 1]);
+        const T* p = img + r0 * n + c0;
+        const float val = (1.0f - fr) * ((1.0f - fc) * ld_px(p[0]) + fc * ld_px(p[1])) +
+                          fr * ((1.0f - fc) * ld_px(p[n]) + fc * ld_px(p[n + 1]));
         const float x = (val - fmean) * inv_std;
         xs[i] = x;
         sum += x;
@@ -461,7 +462,15 @@ hipError_t launch_logpolar(int n, const float* imgs, int64_t k, int n_rho, int n
                            hipStream_t stream) {
   if (k <= 0) return hipSuccess;
   if (k > (int64_t(1) << 31) / 256) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_logpolar, dim3((unsigned)k), dim3(256), 0, stream, imgs, n, n_rho, n_eta, out);
+  hipLaunchKernelGGL(k_logpolar<float>, dim3((unsigned)k), dim3(256), 0, stream, imgs, n, n_rho, n_eta, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_logpolar(int n, const __bf16* imgs, int64_t k, int n_rho, int n_eta, float* out,
+                           hipStream_t stream) {
+  if (k <= 0) return hipSuccess;
+  if (k > (int64_t(1) << 31) / 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_logpolar<__bf16>, dim3((unsigned)k), dim3(256), 0, stream, imgs, n, n_rho, n_eta, out);
   return hipGetLastError();
 }
 

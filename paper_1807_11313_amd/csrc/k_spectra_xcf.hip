@@ -712,9 +712,9 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
 }
 
 // ---------------------------------------------------------------------------
-// Forward spectra of K images.
-template <int N, int NT>
-__global__ __launch_bounds__(NT) void k_spectra(const float* __restrict__ imgs, int64_t img_stride,
+// Forward spectra of K images (pixels of type T: float or __bf16).
+template <int N, int NT, class T>
+__global__ __launch_bounds__(NT) void k_spectra(const T* __restrict__ imgs, int64_t img_stride,
                                                 const int64_t* __restrict__ img_off, FilterParams fp,
                                                 cf* __restrict__ spec, double* __restrict__ energy) {
   using L = Lay<N>;
@@ -725,7 +725,7 @@ __global__ __launch_bounds__(NT) void k_spectra(const float* __restrict__ imgs, 
   __shared__ double red[2 * (NT / 64)];
   const int tid = threadIdx.x;
   const int64_t k = blockIdx.x;
-  const float* img = imgs + (img_off ? img_off[k] : k * img_stride);
+  const T* img = imgs + (img_off ? img_off[k] : k * img_stride);
   load_roots<N, NT>(tw, tid);
   for (int i = tid; i < N; i += NT) {
     const float s = sinpif(((float)i + 0.5f) / (float)N);
@@ -735,7 +735,7 @@ __global__ __launch_bounds__(NT) void k_spectra(const float* __restrict__ imgs, 
   // mean and standard deviation in FP64
   double s1 = 0.0, s2 = 0.0;
   for (int i = tid; i < N * N; i += NT) {
-    const double v = (double)img[i];
+    const double v = (double)ld_px(img[i]);
     s1 += v;
     s2 += v * v;
   }
@@ -766,8 +766,8 @@ __global__ __launch_bounds__(NT) void k_spectra(const float* __restrict__ imgs, 
 #pragma unroll
     for (int a = 0; a < R1; ++a) {
       const int col = R2 * a + b;
-      const float v0 = (img[q * N + col] - fmean) * wq0 * win[col];
-      const float v1 = (img[(q + N / 2) * N + col] - fmean) * wq1 * win[col];
+      const float v0 = (ld_px(img[q * N + col]) - fmean) * wq0 * win[col];
+      const float v1 = (ld_px(img[(q + N / 2) * N + col]) - fmean) * wq1 * win[col];
       x[a] = cf{v0, v1};
     }
     DFT<R1, -1>::run(x);
@@ -942,26 +942,38 @@ static constexpr int nt_spec() { return N <= 96 ? 256 : 512; }
 // launcher below keeps its 1-D grids under 2^31 by splitting the items.
 constexpr int64_t kMaxItems = int64_t(1) << 31;
 
-hipError_t launch_spectra(int n, const float* imgs, int64_t img_stride, int64_t k,
-                          const FilterParams& fp, float2* spec, double* energy,
-                          hipStream_t stream) {
+template <class T>
+static hipError_t spectra_t(int n, const T* imgs, int64_t img_stride, int64_t k, const FilterParams& fp,
+                            float2* spec, double* energy, hipStream_t stream) {
   if (k <= 0) return hipSuccess;
   const int64_t kmax = kMaxItems / 512;
   if (k > kmax) {
     const int64_t sc = (int64_t)(band_of(n) + 1) * (2 * band_of(n) + 1);
     for (int64_t s = 0; s < k; s += kmax) {
-      const hipError_t e = launch_spectra(n, imgs + s * img_stride, img_stride, k - s < kmax ? k - s : kmax, fp,
-                                          spec + s * sc, energy ? energy + s : nullptr, stream);
+      const hipError_t e = spectra_t(n, imgs + s * img_stride, img_stride, k - s < kmax ? k - s : kmax, fp,
+                                     spec + s * sc, energy ? energy + s : nullptr, stream);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   }
   EBSD_DISPATCH(n, {
     constexpr int NT = nt_spec<NN>();
-    hipLaunchKernelGGL((k_spectra<NN, NT>), dim3((unsigned)k), dim3(NT), 0, stream, imgs, img_stride,
+    hipLaunchKernelGGL((k_spectra<NN, NT, T>), dim3((unsigned)k), dim3(NT), 0, stream, imgs, img_stride,
                        (const int64_t*)nullptr, fp, (cf*)spec, energy);
   });
   return hipGetLastError();
+}
+
+hipError_t launch_spectra(int n, const float* imgs, int64_t img_stride, int64_t k,
+                          const FilterParams& fp, float2* spec, double* energy,
+                          hipStream_t stream) {
+  return spectra_t(n, imgs, img_stride, k, fp, spec, energy, stream);
+}
+
+hipError_t launch_spectra(int n, const __bf16* imgs, int64_t img_stride, int64_t k,
+                          const FilterParams& fp, float2* spec, double* energy,
+                          hipStream_t stream) {
+  return spectra_t(n, imgs, img_stride, k, fp, spec, energy, stream);
 }
 
 hipError_t launch_spectra_gather(int n, const float* imgs, const int64_t* img_off, int64_t k,
@@ -979,8 +991,8 @@ hipError_t launch_spectra_gather(int n, const float* imgs, const int64_t* img_of
   }
   EBSD_DISPATCH(n, {
     constexpr int NT = nt_spec<NN>();
-    hipLaunchKernelGGL((k_spectra<NN, NT>), dim3((unsigned)k), dim3(NT), 0, stream, imgs, (int64_t)0, img_off,
-                       fp, (cf*)spec, energy);
+    hipLaunchKernelGGL((k_spectra<NN, NT, float>), dim3((unsigned)k), dim3(NT), 0, stream, imgs, (int64_t)0,
+                       img_off, fp, (cf*)spec, energy);
   });
   return hipGetLastError();
 }

@@ -65,3 +65,19 @@ def oracle_templates(master, q, n, pc):
     from oracle import geometry as ogeo
     from oracle import rotations as orot
     return np.stack([ogeo.project(master, r, n, pc) for r in orot.quat_to_matrix(np.asarray(q))])
+
+
+def fallback_tau(t, val, q_true, pcs, master, pc, lq, percentile=1.0, max_error_deg=1.0):
+    """The proposal's fallback threshold: the given percentile of the
+    exhaustive search's integer peak height (the score the pruned search
+    compares with it) among the correctly indexed validation patterns, those
+    whose refined orientation lies within max_error_deg of the truth.
+    Returns (tau, fraction correctly indexed)."""
+    from oracle import rotations
+    ex = t.index_patterns(val, master, pc, lq, scores=True)
+    h_int = host(ex.pop("scores").max(dim=1).values)
+    rf = t.refine_from_match(val, master, pc, ex["best_q"], ex["shift"], pc_per=dev(pcs))
+    q = host(rf["q"])
+    err = np.rad2deg([rotations.disorientation_q(q[i], q_true[i]) for i in range(len(q))])
+    ok = err < max_error_deg
+    return float(np.percentile(h_int[ok], percentile)), float(ok.mean())

@@ -243,3 +243,22 @@ def test_noalloc_refine_rejects_on_the_host():
         assert call(pkg.Batch(0x6000, p, n), prm=pkg.params_default(max_shift=12)) == -1
         msg = lib.ebsd_last_error().decode()
         assert "static" in msg and "bytes" in msg, msg
+
+
+def test_bf16_input_flag_is_validated():
+    # the pattern storage flag: unknown values, BF16 at 256 and BF16 given to
+    # calls that read no images are rejected before anything is enqueued
+    pkg, lib = _lib()
+    ok = pkg.Batch(0x6000, 4, 64)
+    assert pkg.params_default().input == 0
+    assert _index(pkg, lib, ok, pkg.params_default(input=2)) == -4
+    assert _index(pkg, lib, pkg.Batch(0x6000, 4, 256), pkg.params_default(input=1, max_shift=5)) == -4
+    prm = pkg.params_default(input=1)
+    rc = lib.ebsd_xcf_scores(ctypes.c_void_p(0x1000), 2, ctypes.c_void_p(0x2000), 2, 64, ctypes.byref(prm),
+                             ctypes.c_void_p(0x3000), None)
+    assert rc == -4 and b"FP32 images" in lib.ebsd_last_error()
+    # an older caller's parameter block (ending before `input`) reads as FP32
+    short = pkg.params_default()
+    short.struct_size = ctypes.sizeof(pkg.Params) - 4
+    short.input = 7
+    assert _index(pkg, lib, pkg.Batch(0x6000, 0, 64), short) == 0

@@ -26,7 +26,7 @@ import oracle
 from fixtures import configs
 from oracle import pipeline, rotations
 
-from .gpu_util import banner, dev, host, tm
+from .gpu_util import banner, dev, fallback_tau, host, tm
 
 pytestmark = pytest.mark.gpu
 
@@ -165,8 +165,8 @@ def test_learned_proposal_full_size():
     # the proposal workload at full size: the network trained on the GPU on
     # 200,000 projected patterns (2 epochs) for 8,000 classes; 50,000 test
     # patterns at 128^2 searched exhaustively and pruned (top 32 + fallback
-    # below tau = 1st percentile of the exhaustive peak height on 10,000
-    # validation patterns).  The exhaustive search, pinned to the oracle by
+    # below tau = 1st percentile of the exhaustive integer peak height among
+    # the correctly indexed of 10,000 validation patterns).  The exhaustive search, pinned to the oracle by
     # the tests above, is the reference.
     from fixtures import band_master, random_fz_quats, random_quats, simulate_patterns
     banner("full-size learned proposal: training 200,000 x 2 epochs, 50,000 test patterns")
@@ -176,13 +176,14 @@ def test_learned_proposal_full_size():
     master = dev(band_master())
     pc = (0.5, 0.5, 0.6)
 
-    def patterns(p, seed):
+    def patterns(p, seed, truth=False):
         rng = np.random.default_rng(seed)
         q = random_quats(rng, p)
         off = rng.uniform(-5, 5, size=(p, 2))
         pcs = np.stack([0.5 + off[:, 0] / n, 0.5 + off[:, 1] / n, np.full(p, 0.6)], 1)
-        return pcs, simulate_patterns(q, n, pcs, ("poisson_gauss", 1000.0, 5.0), seed=seed, device="cuda:0",
-                                      dtype=torch.float32).contiguous()
+        pats = simulate_patterns(q, n, pcs, ("poisson_gauss", 1000.0, 5.0), seed=seed, device="cuda:0",
+                                 dtype=torch.float32).contiguous()
+        return (q, pcs, pats) if truth else (pcs, pats)
 
     net = t.Cnn(L, seed=5)
     x = torch.empty((bsz, 64, 64), device="cuda:0")
@@ -192,8 +193,9 @@ def test_learned_proposal_full_size():
         t.cnn_make_batch(master, pc, lq, n, bsz, (s * bsz) % n_train, 1000 + (s * bsz) // n_train, x=x, labels=y)
         net.train_step(x, y, 1e-3, loss)
     print("[gpu]   final training loss %.3f" % float(loss.item()), flush=True)
-    _, val = patterns(10000, 31)
-    tau = float(np.percentile(host(t.index_patterns(val, master, pc, lq)["peak_h"]), 1.0))
+    q_val, pcs_val, val = patterns(10000, 31, truth=True)
+    tau, ok = fallback_tau(t, val, q_val, pcs_val, master, pc, lq)
+    print("[gpu]   validation: %.4f correctly indexed" % ok, flush=True)
     del val
     pcs, test = patterns(50000, 32)
     ex = t.index_patterns(test, master, pc, lq, scores=True)

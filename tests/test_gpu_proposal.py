@@ -16,19 +16,20 @@ import torch
 
 from fixtures import band_master, random_fz_quats, random_quats, simulate_patterns
 
-from .gpu_util import banner, dev, host, tm
+from .gpu_util import banner, dev, fallback_tau, host, tm
 
 pytestmark = pytest.mark.gpu
 
 TAU_TIE = 2e-4
 
 
-def _patterns(p, seed, n=128):
+def _patterns(p, seed, n=128, truth=False):
     rng = np.random.default_rng(seed)
     q = random_quats(rng, p)
     off = rng.uniform(-5, 5, size=(p, 2))
     pcs = np.stack([0.5 + off[:, 0] / n, 0.5 + off[:, 1] / n, np.full(p, 0.6)], 1)
-    return simulate_patterns(q, n, pcs, ("poisson_gauss", 1000.0, 5.0), seed=seed)
+    pats = simulate_patterns(q, n, pcs, ("poisson_gauss", 1000.0, 5.0), seed=seed)
+    return (q, pcs, pats) if truth else pats
 
 
 def _train(t, master, lq, steps, seed=3, bsz=256, n=128):
@@ -53,10 +54,12 @@ def test_pruned_search_matches_exhaustive_and_gains_over_untrained():
     net, loss = _train(t, master, lq, 300)
     print("[gpu]   final training loss %.3f" % loss, flush=True)
 
-    # threshold: 1st percentile of the exhaustive peak height on a validation set
-    val = dev(_patterns(128, seed=20))
-    ex_val = t.index_patterns(val, master, pc, lq)
-    tau = float(np.percentile(host(ex_val["peak_h"]), 1.0))
+    # threshold: 1st percentile of the exhaustive integer peak height among
+    # the correctly indexed patterns of a validation set
+    q_val, pcs_val, val = _patterns(128, seed=20, truth=True)
+    tau, ok = fallback_tau(t, dev(val), q_val, pcs_val, master, pc, lq)
+    print("[gpu]   validation: %.3f correctly indexed" % ok, flush=True)
+    assert ok > 0.9
 
     test = dev(_patterns(200, seed=21))
     ex = t.index_patterns(test, master, pc, lq, scores=True)
