@@ -997,13 +997,17 @@ hipError_t launch_spectra_gather(int n, const float* imgs, const int64_t* img_of
   return hipGetLastError();
 }
 
-#ifndef EBSD_SEARCH_LCHUNK
-#define EBSD_SEARCH_LCHUNK 32
-#endif
+// Templates per block of the search.  At 128 a chunk of 64 (2.4 MB of band
+// spectra) stays in one XCD's 4 MB L2 while the blocks running there stream
+// their patterns, and halves the pattern re-reads of a 32-template chunk at
+// the same time (measured); 128 or more templates no longer fit and raise
+// the traffic again.  The other sizes keep 32.
+static int search_lchunk(int n) { return n == 128 ? 64 : 32; }
+
 hipError_t launch_xcf_scores(int n, const float2* spec_p, int64_t p, const float2* spec_l,
                              int64_t l, int max_shift, float* scores, hipStream_t stream) {
   if (p <= 0 || l <= 0) return hipSuccess;
-  const int lchunk = EBSD_SEARCH_LCHUNK;
+  const int lchunk = search_lchunk(n);
   const int64_t nchunk = (l + lchunk - 1) / lchunk;
   // patterns per dispatch so that blocks x threads stays below 2^31
   const int64_t pmax = (kMaxItems / 1024 - 8) / nchunk;
