@@ -59,7 +59,6 @@ hipError_t launch_spectra_gather(int n, const float* imgs, const int64_t* img_of
 // (pattern, chunk of lchunk templates) items from the device counter *queue,
 // which must be zero when the kernel starts.  Block size and the resident
 // blocks per CU of the kernel that serves size n.
-int xcf_block_threads(int n);
 hipError_t xcf_persistent_occupancy(int n, int max_shift, int* blocks_per_cu);
 hipError_t launch_xcf_scores_persistent(int n, const float2* spec_p, int64_t p, const float2* spec_l, int64_t l,
                                         int max_shift, float* scores, int lchunk, int grid, int* queue,

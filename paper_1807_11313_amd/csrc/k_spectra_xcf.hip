@@ -712,6 +712,266 @@ __global__ __launch_bounds__(WLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresw(cons
 }
 
 // ---------------------------------------------------------------------------
+// The same search with every pass's work items spread over all threads of
+// the block (96 and 160).  In the wave-uniform kernel above a wave owns one
+// radix position and its lanes run along the band columns (37 at 96) or the
+// packed row pairs (48 at 96, 40 per block at 160), and the second passes run
+// R1 positions on R2 waves, so a third of the lanes and waves idle.  Here
+// each pass is a list of (radix position, column or row) items, item t on
+// thread t (a second round where there are more items than threads), so the
+// same work takes fewer wave instructions.  A thread's items keep the same
+// (position, column) for every template: its pattern values, template row
+// offsets and row-pass input rows are set up once; twiddles come from a
+// [b][c] table in LDS at a per-thread base.  The arithmetic on every value,
+// including the exact zeros of the band gap, is that of the kernel above,
+// so the scores are the same.
+//
+// A (the column-pass output) has a region of its own, apart from the one X
+// and Y (the first and third passes' outputs) take in turn, so no pass waits
+// for reads of the buffer it writes: 4 barriers per template where shared
+// buffers need 6.  At 96 that is 65.6 KB, two 8-wave blocks per CU, whose
+// barriers interleave (measured: two templates per 16-wave block, one block
+// per CU, run 0.85x for the same work, though their items spread more evenly
+// over the SIMDs); at 160 X and A already had separate regions.
+template <int N>
+struct FLay {
+  using W = WLay<N>;
+  static constexpr int NT = W::NT;
+  static constexpr int cmx(int a, int b) { return a > b ? a : b; }
+  static constexpr int XOFF = 0;                        // X, then Y (measured: 1.03x at 160 over A first)
+  static constexpr int AOFF = cmx(W::XN, W::YN);
+  static constexpr int LDSH = cmx(XOFF + cmx(W::XN, W::YN), AOFF + W::AN);
+  static_assert(AOFF + W::AN <= XOFF || XOFF + cmx(W::XN, W::YN) <= AOFF, "A apart from X and Y");
+};
+
+// Where the band indices lo .. hi (one radix input over all its lanes) lie
+// for a band of half-width B at size N.
+constexpr int kPos = 0, kNeg = 1, kGap = 2, kStraddle = 3;
+template <int N, int B>
+constexpr int band_class_nb(int lo, int hi) {
+  return hi <= B ? kPos : (lo >= N - B ? kNeg : ((lo > B && hi < N - B) ? kGap : kStraddle));
+}
+
+template <int N, bool WINDOW, bool PERSIST>
+__global__ __launch_bounds__(FLay<N>::NT, WLay<N>::MINW) void k_xcf_scoresf(const cf* __restrict__ spec_p, int64_t np,
+                                                             const cf* __restrict__ spec_l, int64_t nl,
+                                                             int lchunk, int64_t nblk, int max_shift,
+                                                             float* __restrict__ scores, int* __restrict__ queue) {
+  using L = WLay<N>;
+  using F = FLay<N>;
+  constexpr int R1 = L::R1, R2 = L::R2, B = L::B, NV = L::NV, SPEC = L::SPEC, AV = L::AV;
+  constexpr int NQ = L::NQ, QB = L::QB, NQB = L::NQB, NT = F::NT;
+  constexpr int T1 = R2 * NV, T2 = R1 * NV, T3 = R2 * QB, T4 = R1 * QB;
+  static_assert(T1 <= NT && T2 <= NT && T3 <= NT, "one round of items in passes 1-3");
+  constexpr int R4 = (T4 + NT - 1) / NT;  // rounds of the last pass
+  constexpr auto band_class = [](int lo, int hi) { return band_class_nb<N, WLay<N>::B>(lo, hi); };
+  __shared__ cf lds[F::LDSH];
+  __shared__ cf twt[R2 * R1];  // twt[b R1 + c] = w_N^(b c), b c < N
+  __shared__ float red[NT / 64];
+  __shared__ int item;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  for (int i = tid; i < R2 * R1; i += NT) twt[i] = root_of<N>((i / R1) * (i % R1));
+
+  // pass-1 item: (b1, v1).  Input a (row u = R2 a + b1) lies for every b1
+  // on the positive side of the band (row kk = u), on its negative side
+  // (kk = u - N + 2B + 1), in its gap, or straddles an edge (per-lane row;
+  // gap rows read row 0 and are multiplied by a cached zero)
+  const bool act1 = tid < T1;
+  const int b1 = act1 ? tid / NV : 0, v1 = act1 ? tid - b1 * NV : 0;
+  const unsigned base1 = (unsigned)(b1 * NV + v1) * (unsigned)sizeof(cf), col1 = (unsigned)v1 * sizeof(cf);
+  unsigned off1[R1];
+#pragma unroll
+  for (int a = 0; a < R1; ++a) {
+    const int u = R2 * a + b1;
+    const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : 0);
+    off1[a] = band_class(R2 * a, R2 * a + R2 - 1) == kStraddle ? (unsigned)(kk * NV + v1) * (unsigned)sizeof(cf) : 0u;
+  }
+  cf* const X = lds + F::XOFF;
+  cf* const Y = lds + F::XOFF;
+  cf* const A = lds + F::AOFF;
+  // pass-2 item: (c2, v2)
+  const bool act2 = tid < T2;
+  const int c2 = act2 ? tid / NV : 0, v2 = act2 ? tid - c2 * NV : 0;
+  // pass-3 item: (b3, q3 of the row block); for input a the band column
+  // v = R2 a + b3 enters as A(v) (1 <= v <= B, k = +1), as the conjugate of
+  // A(N - v) (v >= N - B, k = -1), through its real part only (v = 0, k = 0)
+  // or not at all (the band gap, m = 0)
+  const bool act3 = tid < T3;
+  const int b3 = act3 ? tid / QB : 0, q3 = act3 ? tid - b3 * QB : 0;
+  const int base3p = b3 * AV + q3, base3n = q3 - b3 * AV;  // A(R2 a + b3, q3) and A(N - R2 a - b3, q3) less the constant row
+  int at3[R1];  // element index of A(row, q3) for the inputs that straddle a band edge
+  float k3[R1], m3[R1];
+#pragma unroll
+  for (int a = 0; a < R1; ++a) {
+    const int v = R2 * a + b3;
+    const bool pos = v <= B, neg = v >= N - B;
+    at3[a] = (pos ? v : (neg ? N - v : 0)) * AV + q3;
+    k3[a] = (pos && v > 0) ? 1.0f : (neg ? -1.0f : 0.0f);
+    m3[a] = (pos || neg) ? 1.0f : 0.0f;
+  }
+
+  int64_t g;
+  if constexpr (PERSIST) {
+    if (tid == 0) item = atomicAdd(queue, 1);
+    __syncthreads();
+    g = item;
+  } else {
+    const int64_t per = (nblk + 7) / 8;
+    g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    __syncthreads();  // the twiddle table
+  }
+  if (g >= nblk) return;
+
+  while (g < nblk) {
+    const int64_t chunk = g / np, p = g - chunk * np;
+    const cf* E = spec_p + p * SPEC;
+    cf ev[R1];
+#pragma unroll
+    for (int a = 0; a < R1; ++a) {
+      const int u = R2 * a + b1;
+      const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : -1);
+      ev[a] = (kk >= 0 && act1) ? E[kk * NV + v1] : cf{0.f, 0.f};
+    }
+    const int64_t l0 = chunk * lchunk;
+    const int64_t l1 = l0 + lchunk < nl ? l0 + lchunk : nl;
+    // pass-1 inputs of template T.  At 96 they are issued one template ahead
+    // (before the last pass 4 of the template before), so that their latency
+    // overlaps that pass and the barrier after it (measured 1.05x); at 160
+    // the 20 registers they hold meanwhile make the kernel spill (0.93x)
+    constexpr bool PREFETCH = N == 96;
+    cf xn[R1];
+    const auto load1 = [&](const cf* T) {
+      const __amdgpu_buffer_rsrc_t Tr = spectrum_rsrc(T, SPEC * (int)sizeof(cf));
+      static_for<0, R1>([&](auto ai) {
+        constexpr int a = decltype(ai)::value;
+        constexpr int cls = band_class(R2 * a, R2 * a + R2 - 1);
+        if constexpr (L::ZGAP && ((L::GAP >> a) & 1)) return;  // neither loaded nor added
+        unsigned vo;
+        int so;
+        if constexpr (cls == kPos) { vo = base1; so = R2 * a * NV * (int)sizeof(cf); }
+        else if constexpr (cls == kNeg) { vo = base1; so = (R2 * a - N + 2 * B + 1) * NV * (int)sizeof(cf); }
+        else if constexpr (cls == kGap) { vo = col1; so = 0; }
+        else { vo = off1[a]; so = 0; }
+        static_assert(cls != kNeg || R2 * a - N + 2 * B + 1 >= 0, "non-negative row offset");
+        if constexpr (L::BUFLOAD) xn[a] = buffer_cf(Tr, vo, so);
+        else xn[a] = *reinterpret_cast<const cf*>(reinterpret_cast<const char*>(T) + vo + so);
+      });
+    };
+    if (PREFETCH && act1) load1(spec_l + l0 * SPEC);
+    for (int64_t l = l0; l < l1; ++l) {
+      // pass 1: item (b1, v1): radix R1 over u = R2 a + b1, twiddle
+      if (act1) {
+        if constexpr (!PREFETCH) load1(spec_l + l * SPEC);
+        cf x[R1];
+#pragma unroll
+        for (int a = 0; a < R1; ++a)
+          if (!(L::ZGAP && ((L::GAP >> a) & 1))) x[a] = cmulc(ev[a], xn[a]);
+        if constexpr (L::ZGAP) dft_zero<R1, 1, L::GAP>(x);
+        else DFT<R1, 1>::run(x);
+        const cf* tw = twt + b1 * R1;
+#pragma unroll
+        for (int c = 1; c < R1; ++c) x[c] = cmul(x[c], tw[c]);
+#pragma unroll
+        for (int c = 0; c < R1; ++c) X[(c * R2 + b1) * NV + v1] = x[c];
+      }
+      __syncthreads();
+      // pass 2: item (c2, v2): radix R2 over b -> A(y = c2 + R1 d, v2)
+      if (act2) {
+        cf h[R2];
+#pragma unroll
+        for (int b = 0; b < R2; ++b) h[b] = X[(c2 * R2 + b) * NV + v2];
+        DFT<R2, 1>::run(h);
+#pragma unroll
+        for (int d = 0; d < R2; ++d) A[v2 * AV + c2 + R1 * d] = h[d];
+      }
+      __syncthreads();
+      float m = -INFINITY;
+#pragma unroll
+      for (int qb = 0; qb < NQB; ++qb) {
+        // pass 3: item (b3, q): radix R1 over v = R2 a + b3 of the packed rows (q, q + N/2)
+        if (act3) {
+          cf sv[R1];
+          static_for<0, R1>([&](auto ai) {
+            constexpr int a = decltype(ai)::value;
+            // the columns v = R2 a + b3 of input a over all b3 (column 0, the
+            // DC term, takes its real parts only: the coefficient form)
+            constexpr int cls = a == 0 ? kStraddle : band_class(R2 * a, R2 * a + R2 - 1);
+            if constexpr ((L::ZGAP && ((L::GAP >> a) & 1)) || cls == kGap) {
+              sv[a] = cf{0.f, 0.f};
+            } else if constexpr (cls == kPos) {
+              const cf* pa = A + base3p + R2 * a * AV + qb * QB;
+              const cf p0 = pa[0], p1 = pa[NQ];
+              sv[a] = cf{p0.x - p1.y, p0.y + p1.x};
+            } else if constexpr (cls == kNeg) {
+              const cf* pa = A + base3n + (N - R2 * a) * AV + qb * QB;
+              const cf p0 = pa[0], p1 = pa[NQ];
+              sv[a] = cf{p0.x + p1.y, p1.x - p0.y};
+            } else {
+              const cf* pa = A + at3[a] + qb * QB;
+              const cf p0 = pa[0], p1 = pa[NQ];
+              sv[a] = cf{__fmaf_rn(-k3[a], p1.y, m3[a] * p0.x), __fmaf_rn(k3[a], p0.y, m3[a] * p1.x)};
+            }
+          });
+          if constexpr (L::ZGAP) dft_zero<R1, 1, L::GAP>(sv);
+          else DFT<R1, 1>::run(sv);
+          const cf* tw = twt + b3 * R1;
+#pragma unroll
+          for (int c = 1; c < R1; ++c) sv[c] = cmul(sv[c], tw[c]);
+#pragma unroll
+          for (int c = 0; c < R1; ++c) Y[(c * R2 + b3) * QB + q3] = sv[c];
+        }
+        __syncthreads();
+        if (PREFETCH && qb + 1 == NQB && act1 && l + 1 < l1) load1(spec_l + (l + 1) * SPEC);
+        // pass 4: item (c4, q4): radix R2 over b -> x = c4 + R1 d
+#pragma unroll
+        for (int r = 0; r < R4; ++r) {
+          const int t = tid + r * NT;
+          if (t < T4) {
+            const int c4 = t / QB, q4 = t - c4 * QB;
+            const int qq = qb * QB + q4;
+            cf z[R2];
+#pragma unroll
+            for (int b = 0; b < R2; ++b) z[b] = Y[(c4 * R2 + b) * QB + q4];
+            DFT<R2, 1>::run(z);
+            if (qq < NQ) {
+              if constexpr (WINDOW) {
+                const float mq0 = abs(signed_shift(qq, N)) <= max_shift ? 0.f : -INFINITY;
+                const float mq1 = abs(signed_shift(qq + NQ, N)) <= max_shift ? 0.f : -INFINITY;
+#pragma unroll
+                for (int d = 0; d < R2; ++d) {
+                  const int x = c4 + R1 * d;
+                  const float mx = abs(signed_shift(x, N)) <= max_shift ? 0.f : -INFINITY;
+                  m = fmaxf(m, fmaxf(z[d].x + mq0, z[d].y + mq1) + mx);
+                }
+              } else {
+#pragma unroll
+                for (int d = 0; d < R2; ++d) m = fmaxf(m, fmaxf(z[d].x, z[d].y));
+              }
+            }
+          }
+        }
+        if (qb + 1 < NQB) __syncthreads();  // the next row block's pass 3 overwrites Y
+      }
+      m = wave_max(m);
+      if (lane == 0) red[tid >> 6] = m;
+      __syncthreads();
+      if (tid == 0) {
+        float r = red[0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) r = fmaxf(r, red[w]);
+        scores[p * nl + l] = r;
+      }
+    }
+    if constexpr (!PERSIST) break;
+    __syncthreads();
+    if (tid == 0) item = atomicAdd(queue, 1);
+    __syncthreads();
+    g = item;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Forward spectra of K images (pixels of type T: float or __bf16).
 template <int N, int NT, class T>
 __global__ __launch_bounds__(NT) void k_spectra(const T* __restrict__ imgs, int64_t img_stride,
@@ -997,6 +1257,16 @@ hipError_t launch_spectra_gather(int n, const float* imgs, const int64_t* img_of
   return hipGetLastError();
 }
 
+// 96 and 160 run the search with its work items spread over the whole block
+// (k_xcf_scoresf, scores bit-identical to the wave-uniform kernel's;
+// measured 1.30x and 1.15x over every shift, 1.29x and 1.02x with a +-7
+// window).  64 keeps two templates per wave, 128 its own kernel.
+#ifndef EBSD_SEARCH_FLAT
+#define EBSD_SEARCH_FLAT 1
+#endif
+template <int N, bool WINDOW>
+constexpr bool search_flat() { return EBSD_SEARCH_FLAT && (N == 96 || N == 160); }
+
 // Templates per block of the search.  At 128 a chunk of 64 (2.4 MB of band
 // spectra) stays in one XCD's 4 MB L2 while the blocks running there stream
 // their patterns, and halves the pattern re-reads of a 32-template chunk at
@@ -1034,24 +1304,24 @@ hipError_t launch_xcf_scores(int n, const float2* spec_p, int64_t p, const float
   }
   EBSD_DISPATCH(n, {
     constexpr int NT = WLay<NN>::NT;
-    if (max_shift < 0)
-      hipLaunchKernelGGL((k_xcf_scoresw<NN, false, false>), dim3((unsigned)grid), dim3(NT), 0, stream,
-                         (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, nullptr);
-    else
-      hipLaunchKernelGGL((k_xcf_scoresw<NN, true, false>), dim3((unsigned)grid), dim3(NT), 0, stream,
-                         (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, nullptr);
+    constexpr int NTF = FLay<NN>::NT;
+    if (max_shift < 0) {
+      if constexpr (search_flat<NN, false>())
+        hipLaunchKernelGGL((k_xcf_scoresf<NN, false, false>), dim3((unsigned)grid), dim3(NTF), 0, stream,
+                           (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, nullptr);
+      else
+        hipLaunchKernelGGL((k_xcf_scoresw<NN, false, false>), dim3((unsigned)grid), dim3(NT), 0, stream,
+                           (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, nullptr);
+    } else {
+      if constexpr (search_flat<NN, true>())
+        hipLaunchKernelGGL((k_xcf_scoresf<NN, true, false>), dim3((unsigned)grid), dim3(NTF), 0, stream,
+                           (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, nullptr);
+      else
+        hipLaunchKernelGGL((k_xcf_scoresw<NN, true, false>), dim3((unsigned)grid), dim3(NT), 0, stream,
+                           (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, nullptr);
+    }
   });
   return hipGetLastError();
-}
-
-int xcf_block_threads(int n) {
-  switch (n) {
-    case 64: return WLay<64>::NT;
-    case 96: return WLay<96>::NT;
-    case 128: return 512;
-    case 160: return WLay<160>::NT;
-    default: return 0;
-  }
 }
 
 hipError_t xcf_persistent_occupancy(int n, int max_shift, int* blocks_per_cu) {
@@ -1063,9 +1333,17 @@ hipError_t xcf_persistent_occupancy(int n, int max_shift, int* blocks_per_cu) {
   }
   EBSD_DISPATCH(n, {
     constexpr int NT = WLay<NN>::NT;
-    return max_shift < 0
-               ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_xcf_scoresw<NN, false, true>, NT, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_xcf_scoresw<NN, true, true>, NT, 0);
+    if (max_shift < 0) {
+      if constexpr (search_flat<NN, false>())
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_xcf_scoresf<NN, false, true>, FLay<NN>::NT, 0);
+      else
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_xcf_scoresw<NN, false, true>, NT, 0);
+    } else {
+      if constexpr (search_flat<NN, true>())
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_xcf_scoresf<NN, true, true>, FLay<NN>::NT, 0);
+      else
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_xcf_scoresw<NN, true, true>, NT, 0);
+    }
   });
   return hipSuccess;
 }
@@ -1089,12 +1367,22 @@ hipError_t launch_xcf_scores_persistent(int n, const float2* spec_p, int64_t p, 
   }
   EBSD_DISPATCH(n, {
     constexpr int NT = WLay<NN>::NT;
-    if (max_shift < 0)
-      hipLaunchKernelGGL((k_xcf_scoresw<NN, false, true>), dim3((unsigned)grid), dim3(NT), 0, stream,
-                         (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, queue);
-    else
-      hipLaunchKernelGGL((k_xcf_scoresw<NN, true, true>), dim3((unsigned)grid), dim3(NT), 0, stream,
-                         (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, queue);
+    constexpr int NTF = FLay<NN>::NT;
+    if (max_shift < 0) {
+      if constexpr (search_flat<NN, false>())
+        hipLaunchKernelGGL((k_xcf_scoresf<NN, false, true>), dim3((unsigned)grid), dim3(NTF), 0, stream,
+                           (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, queue);
+      else
+        hipLaunchKernelGGL((k_xcf_scoresw<NN, false, true>), dim3((unsigned)grid), dim3(NT), 0, stream,
+                           (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, queue);
+    } else {
+      if constexpr (search_flat<NN, true>())
+        hipLaunchKernelGGL((k_xcf_scoresf<NN, true, true>), dim3((unsigned)grid), dim3(NTF), 0, stream,
+                           (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, queue);
+      else
+        hipLaunchKernelGGL((k_xcf_scoresw<NN, true, true>), dim3((unsigned)grid), dim3(NT), 0, stream,
+                           (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, queue);
+    }
   });
   return hipGetLastError();
 }
