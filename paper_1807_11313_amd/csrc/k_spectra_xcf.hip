@@ -304,31 +304,39 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
     const cf* T = spec_l + l * SPEC;
     // phase 1 (ev is zero outside the band, so every lane loads from a
     // clamped in-band address without a branch and the product stays zero:
-    // the sixteen loads are in flight together)
-    {
+    // the loads are in flight together).  Wave 0 (b = 0) has unit twiddles
+    // and compile-time rows; for the other waves input a = 6 (u = 48 + b) is
+    // past the band edge too, so it is neither loaded nor added
+    const auto phase1 = [&](auto w0c) {
+      constexpr bool W0 = decltype(w0c)::value;
+      constexpr int G1 = W0 ? GAP : (GAP | 0x40);
+      const int b = W0 ? 0 : wave;
       cf x[R1];
-      // buffer loads: one lane offset, uniform row offsets, no per-row VGPRs;
-      // inputs between the band edges for every wave are neither loaded nor added
+      // buffer loads: one lane offset, uniform row offsets, no per-row VGPRs
       const unsigned voff = (unsigned)(vlane ? lane : NV - 1) * (unsigned)sizeof(cf);
       const __amdgpu_buffer_rsrc_t Tr = spectrum_rsrc(T, SPEC * (int)sizeof(cf));
 #pragma unroll
       for (int a = 0; a < R1; ++a) {
-        if ((GAP >> a) & 1) continue;
-        const int u = R2 * a + wave;
+        if ((G1 >> a) & 1) continue;
+        const int u = R2 * a + b;
         const int kk = u <= B ? u : (u >= N - B ? u - N + 2 * B + 1 : 0);
         x[a] = buffer_cf(Tr, voff, kk * NV * (int)sizeof(cf));
       }
 #pragma unroll
       for (int a = 0; a < R1; ++a)
-        if (!((GAP >> a) & 1)) x[a] = cmulc(ev[a], x[a]);
-      dft_zero<R1, 1, GAP>(x);
+        if (!((G1 >> a) & 1)) x[a] = cmulc(ev[a], x[a]);
+      dft_zero<R1, 1, G1>(x);
+      if constexpr (!W0) {
 #pragma unroll
-      for (int c = 1; c < R1; ++c) x[c] = cmul(x[c], tw[c]);
+        for (int c = 1; c < R1; ++c) x[c] = cmul(x[c], tw[c]);
+      }
       if (vlane) {
 #pragma unroll
-        for (int c = 0; c < R1; ++c) lds[(c * R2 + wave) * NV + lane] = x[c];
+        for (int c = 0; c < R1; ++c) lds[(c * R2 + b) * NV + lane] = x[c];
       }
-    }
+    };
+    if (wave == 0) phase1(std::true_type{});
+    else phase1(std::false_type{});
     __syncthreads();
     // phase 2: waves take c = wave and c = wave + 8
     cf h[2][R2];
@@ -355,13 +363,18 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
     // at v = 0 and 0 in the gap: every row is read (clamped, no branch, so the
     // reads are in flight together) and the cases are uniform coefficients
     // c = +-1 or 0 (fma(c, y, x) = x + c y exactly)
+    // (as in phase 1, wave 0 has unit twiddles and compile-time rows, and
+    // for the other waves v = 48 + b is past the band edge)
     cf s[R1];
-    {
+    const auto phase3 = [&](auto w0c) {
+      constexpr bool W0 = decltype(w0c)::value;
+      constexpr int G3 = W0 ? GAP : (GAP | 0x40);
+      const int b = W0 ? 0 : wave;
       cf p0[R1], p1[R1];
       static_for<0, R1>([&](auto ai) {
         constexpr int a = decltype(ai)::value;
-        if constexpr (!((GAP >> a) & 1)) {
-          const int v = R2 * a + wave;
+        if constexpr (!((G3 >> a) & 1)) {
+          const int v = R2 * a + b;
           const int w = v <= B ? v : (v >= N - B ? N - v : 0);
           p0[a] = lds[w * AV + lane];
           p1[a] = lds[w * AV + lane + 64];
@@ -369,21 +382,20 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
       });
       static_for<0, R1>([&](auto ai) {
         constexpr int a = decltype(ai)::value;
-        if constexpr (!((GAP >> a) & 1)) {
-          const int v = R2 * a + wave;
+        if constexpr (!((G3 >> a) & 1)) {
+          const int v = R2 * a + b;
           const float c = v == 0 ? 0.f : (v >= N - B ? -1.f : 1.f);
           s[a] = cf{__fmaf_rn(-c, p1[a].y, p0[a].x), __fmaf_rn(c, p0[a].y, p1[a].x)};
-          // rows a that are in the band for some waves only (here a = 6)
-          constexpr bool always_in = R2 * a + R2 - 1 <= B || R2 * a >= N - B;
-          if constexpr (!always_in) {
-            if (v > B && v < N - B) s[a] = cf{0.f, 0.f};
-          }
         }
       });
-    }
-    dft_zero<R1, 1, GAP>(s);  // v = 8 a + b in the gap for a = 7, 8, 9
+      dft_zero<R1, 1, G3>(s);  // v = 8 a + b in the gap for a = 7, 8, 9 (and 6 for b > 0)
+      if constexpr (!W0) {
 #pragma unroll
-    for (int c = 1; c < R1; ++c) s[c] = cmul(s[c], tw[c]);
+        for (int c = 1; c < R1; ++c) s[c] = cmul(s[c], tw[c]);
+      }
+    };
+    if (wave == 0) phase3(std::true_type{});
+    else phase3(std::false_type{});
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < R1; ++c) lds[(c * R2 + wave) * 64 + lane] = s[c];
@@ -405,9 +417,9 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
           // the column test is uniform; the rows of this lane enter through
           // additive 0 / -inf masks (exact)
           const int x = c + R1 * d;
-          if (abs(signed_shift(x, N)) <= max_shift) m = fmaxf(m, fmaxf(z[d].x + mq0, z[d].y + mq1));
+          if (abs(signed_shift(x, N)) <= max_shift) m = fmaxf(fmaxf(m, z[d].x + mq0), z[d].y + mq1);
         } else {
-          m = fmaxf(m, fmaxf(z[d].x, z[d].y));
+          m = fmaxf(fmaxf(m, z[d].x), z[d].y);  // one three-input maximum per output pair
         }
       }
     }
