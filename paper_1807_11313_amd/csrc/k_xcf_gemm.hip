@@ -677,7 +677,11 @@ __global__ __launch_bounds__(512) void k_xcf_gemm_pt(const cf* __restrict__ spec
         ar[pb][s] = f4{0.f, 0.f, 0.f, 0.f};
         ai[pb][s] = f4{0.f, 0.f, 0.f, 0.f};
       }
-#pragma unroll 1
+    // two steps per iteration for the split forms at 256 (the next step's
+    // template values then need no register copies: 1.3-1.5 %); one for plain
+    // BF16 and for four patterns per block, where two steps' registers spill
+    constexpr int KU = TWO && PB <= 3 ? 2 : 1;
+#pragma unroll KU
     for (int kc = 0; kc < KC; ++kc) {
       const int step = vt * KC + kc, buf = step & (NSLOT - 1);
       const bool more = step + 1 < NSTEP;
