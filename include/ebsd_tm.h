@@ -367,6 +367,18 @@ int ebsd_xcf_peak(const float* spec_p, const float* spec_l, const int32_t* pi, c
 int ebsd_xcf_scores(const float* spec_p, int64_t P, const float* spec_l, int64_t L, int32_t n,
                     const ebsd_params* prm, float* scores, void* stream);
 
+/*
+ * Scores of each pattern against its own K candidate templates (the pruned
+ * search of the learned proposal): scores float32 [P][K], scores[p][j] =
+ * h_int of pattern p against template cand[p][j] (cand int32 [P][K], device;
+ * an index outside [0, L) is clamped to the nearest template).  The values
+ * equal those ebsd_xcf_scores gives the same pairs (same kernel).  FP32 FFT
+ * form at n = 128 only (EBSD_E_UNSUPPORTED otherwise); K <= L.
+ */
+int ebsd_xcf_scores_cand(const float* spec_p, int64_t P, const float* spec_l, int64_t L,
+                         const int32_t* cand, int32_t K, int32_t n, const ebsd_params* prm,
+                         float* scores, void* stream);
+
 /* Upsampled peak around s_int for K pairs: h_sub float32 [K], s_sub float32 [K][2] (x, y). */
 int ebsd_xcf_subpixel(const float* spec_p, const float* spec_l, const int32_t* pi, const int32_t* li,
                       int64_t K, int32_t n, const int32_t* s_int, const ebsd_params* prm, float* h_sub,

@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 __all__ = ["lib", "Params", "index_patterns", "refine_orientations", "project_templates",
-           "pattern_spectra", "spectrum_floats", "xcf_peak", "xcf_scores", "xcf_subpixel",
+           "pattern_spectra", "spectrum_floats", "xcf_peak", "xcf_scores", "xcf_scores_cand", "xcf_subpixel",
            "measure_rotation", "params_default", "version", "RaggedPlan", "Cnn", "cnn_make_batch", "cnn_topk",
            "index_proposed", "refine_from_match", "pc_map", "PcModel", "capture_range", "so3_library",
            "nn_disorientation", "LIB_PATH", "EXPORTS"]
@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(HERE, "libebsd_tm.so")
 # Every function the header declares.
 EXPORTS = ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_index_patterns",
            "ebsd_refine_orientations", "ebsd_refine_orientations_noalloc", "ebsd_project_templates", "ebsd_pattern_spectra",
-           "ebsd_spectrum_floats", "ebsd_xcf_peak", "ebsd_xcf_scores", "ebsd_xcf_subpixel",
+           "ebsd_spectrum_floats", "ebsd_xcf_peak", "ebsd_xcf_scores", "ebsd_xcf_scores_cand", "ebsd_xcf_subpixel",
            "ebsd_measure_rotation", "ebsd_timing_enable", "ebsd_timing_read", "ebsd_ragged_plan_create",
            "ebsd_ragged_run", "ebsd_ragged_plan_tiles", "ebsd_ragged_plan_destroy", "ebsd_cnn_param_count",
            "ebsd_cnn_create", "ebsd_cnn_destroy", "ebsd_cnn_get_params", "ebsd_cnn_set_params", "ebsd_cnn_input",
@@ -106,6 +106,7 @@ def lib():
     L.ebsd_pattern_spectra.argtypes = [vp, i64, i32, dp(Params), vp, vp, vp]
     L.ebsd_xcf_peak.argtypes = [vp, vp, vp, vp, i64, i32, dp(Params), vp, vp, vp, vp]
     L.ebsd_xcf_scores.argtypes = [vp, i64, vp, i64, i32, dp(Params), vp, vp]
+    L.ebsd_xcf_scores_cand.argtypes = [vp, i64, vp, i64, vp, i32, i32, dp(Params), vp, vp]
     L.ebsd_xcf_subpixel.argtypes = [vp, vp, vp, vp, i64, i32, vp, dp(Params), vp, vp, vp]
     L.ebsd_measure_rotation.argtypes = [vp, vp, i64, i32, dp(Params), vp, vp]
     L.ebsd_timing_enable.argtypes = [ctypes.c_int]
@@ -435,6 +436,24 @@ def xcf_scores(spec_p, spec_l, n, prm=None):
     rc = lib().ebsd_xcf_scores(_ptr(spec_p, torch.float32), p, _ptr(spec_l, torch.float32), l, n, _params(prm),
                                _ptr(out), _stream())
     _check(rc, "ebsd_xcf_scores")
+    return out
+
+
+def xcf_scores_cand(spec_p, spec_l, cand, n, prm=None):
+    """scores[p][j] of pattern p against template cand[p][j] (n = 128)."""
+    import torch
+    nf = spectrum_floats(n)
+    if nf < 0:
+        raise ValueError("unsupported size %d" % n)
+    _shape(spec_p, (None, nf), "spec_p")
+    _shape(spec_l, (None, nf), "spec_l")
+    p, l = spec_p.shape[0], spec_l.shape[0]
+    _shape(cand, (p, None), "cand")
+    k = cand.shape[1]
+    out = torch.empty((p, k), dtype=torch.float32, device=spec_p.device)
+    rc = lib().ebsd_xcf_scores_cand(_ptr(spec_p, torch.float32), p, _ptr(spec_l, torch.float32), l,
+                                    _ptr(cand, torch.int32, "cand"), k, n, _params(prm), _ptr(out), _stream())
+    _check(rc, "ebsd_xcf_scores_cand")
     return out
 
 

@@ -425,6 +425,25 @@ int ebsd_xcf_scores(const float* spec_p, int64_t P, const float* spec_l, int64_t
   return EBSD_OK;
 }
 
+int ebsd_xcf_scores_cand(const float* spec_p, int64_t P, const float* spec_l, int64_t L, const int32_t* cand,
+                         int32_t K, int32_t n, const ebsd_params* prm, float* scores, void* stream) {
+  g_last_error.clear();
+  int rc;
+  ebsd_params p;
+  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p)) || (rc = f32_images_only(p))) return rc;
+  if (P < 0 || L < 0 || K < 0) return fail(EBSD_E_INVALID, "P, L and K must be >= 0");
+  if (K > L) return fail(EBSD_E_INVALID, "K must not exceed L");
+  if (P == 0 || K == 0) return EBSD_OK;
+  if (!spec_p || !spec_l || !cand || !scores) return fail(EBSD_E_INVALID, "null pointer");
+  if (n != 128 || p.form == EBSD_FORM_DFTGEMM || p.form == EBSD_FORM_DFT || p.precision != EBSD_PREC_FP32)
+    return fail(EBSD_E_UNSUPPORTED, "candidate-list scores are built for the FP32 FFT search at n = 128");
+  hipStream_t st = (hipStream_t)stream;
+  EBSD_TRY(launch_xcf_scores_cand(n, (const float2*)spec_p, P, (const float2*)spec_l, L, cand, K, p.max_shift, scores,
+                                  st),
+           "xcf_scores_cand");
+  return EBSD_OK;
+}
+
 int ebsd_xcf_subpixel(const float* spec_p, const float* spec_l, const int32_t* pi, const int32_t* li, int64_t K,
                       int32_t n, const int32_t* s_int, const ebsd_params* prm, float* h_sub, float* s_sub,
                       void* stream) {

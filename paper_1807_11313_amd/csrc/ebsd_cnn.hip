@@ -444,8 +444,14 @@ int ebsd_index_proposed(const ebsd_batch* pats, const ebsd_master* mp, const ebs
     if (bf16) CN_TRY(launch_spectra(n, pats_bf16, npix, P, fp, spec_p, nullptr, st), "spectra(patterns)");
     else CN_TRY(launch_spectra(n, pats->data, npix, P, fp, spec_p, nullptr, st), "spectra(patterns)");
     // correlation on the candidates only
-    hipLaunchKernelGGL(k_pairs, dim3(nb(PK)), dim3(256), 0, st, cand, P, top_k, pi);
-    CN_TRY(launch_xcf_peak(n, spec_p, spec_l, pi, cand, PK, p.max_shift, hk, sk, nullptr, st), "xcf(candidates)");
+    // (at 128 by the library search kernel over each pattern's candidate list,
+    // the scores the exhaustive search gives the same pairs; elsewhere pair by pair)
+    if (n == 128) {
+      CN_TRY(launch_xcf_scores_cand(n, spec_p, P, spec_l, L, cand, top_k, p.max_shift, hk, st), "xcf(candidates)");
+    } else {
+      hipLaunchKernelGGL(k_pairs, dim3(nb(PK)), dim3(256), 0, st, cand, P, top_k, pi);
+      CN_TRY(launch_xcf_peak(n, spec_p, spec_l, pi, cand, PK, p.max_shift, hk, sk, nullptr, st), "xcf(candidates)");
+    }
     hipLaunchKernelGGL(k_pick_candidate, dim3(nb(P)), dim3(256), 0, st, hk, cand, P, top_k, fallback_tau, best_idx,
                        h_best, flag);
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, st, flag, P, list, count);

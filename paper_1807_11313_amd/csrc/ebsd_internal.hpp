@@ -67,6 +67,11 @@ hipError_t launch_xcf_scores_persistent(int n, const float2* spec_p, int64_t p, 
 // Integer-peak scores h[p][l] = max_s rho(p, l; s) for every pattern x template.
 hipError_t launch_xcf_scores(int n, const float2* spec_p, int64_t p, const float2* spec_l,
                              int64_t l, int max_shift, float* scores, hipStream_t stream);
+// The same for each pattern's own k candidates among l templates: scores[p][j]
+// for template cand[p][j], clamped to [0, l) (n = 128; hipErrorInvalidValue for
+// other sizes).
+hipError_t launch_xcf_scores_cand(int n, const float2* spec_p, int64_t p, const float2* spec_l, int64_t l,
+                                  const int32_t* cand, int k, int max_shift, float* scores, hipStream_t stream);
 
 // Integer peak (value, signed shift) for K explicit pairs (pi[k], li[k]),
 // and optionally the full correlation map [K][n][n] (row = s_y mod n).

@@ -250,11 +250,16 @@ struct RootTable {
 };
 __constant__ RootTable<128> c_roots128 = RootTable<128>();
 
-template <bool WINDOW, bool PERSIST>
+// CAND: template l of pattern p is spec_l[cand[p nl + l]] (a list of nl
+// candidates per pattern, as the learned proposal makes; indices clamped to
+// [0, lib_n)) instead of spec_l[l]
+template <bool WINDOW, bool PERSIST, bool CAND = false>
 __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__ spec_p, int64_t np,
                                                           const cf* __restrict__ spec_l, int64_t nl,
                                                           int lchunk, int64_t nblk, int max_shift,
-                                                          float* __restrict__ scores, int* __restrict__ queue) {
+                                                          float* __restrict__ scores, int* __restrict__ queue,
+                                                          const int32_t* __restrict__ cand = nullptr,
+                                                          int64_t lib_n = 0) {
   constexpr int N = 128, R1 = 16, R2 = 8, B = 48, NV = 49;
   constexpr int SPEC = NV * (2 * B + 1);
   constexpr int GAP = band_gap_mask<N, R1, R2, B>();  // a = 7, 8, 9
@@ -301,7 +306,12 @@ __global__ __launch_bounds__(512, 4) void k_xcf_scores128(const cf* __restrict__
   const int64_t l0 = chunk * lchunk;
   const int64_t l1 = l0 + lchunk < nl ? l0 + lchunk : nl;
   for (int64_t l = l0; l < l1; ++l) {
-    const cf* T = spec_l + l * SPEC;
+    int64_t tl = l;
+    if constexpr (CAND) {
+      tl = cand[p * nl + l];
+      tl = tl < 0 ? 0 : (tl >= lib_n ? lib_n - 1 : tl);
+    }
+    const cf* T = spec_l + tl * SPEC;
     // phase 1 (ev is zero outside the band, so every lane loads from a
     // clamped in-band address without a branch and the product stays zero:
     // the loads are in flight together).  Wave 0 (b = 0) has unit twiddles
@@ -1333,6 +1343,41 @@ hipError_t launch_xcf_scores(int n, const float2* spec_p, int64_t p, const float
                            (const cf*)spec_p, p, (const cf*)spec_l, l, lchunk, nblk, max_shift, scores, nullptr);
     }
   });
+  return hipGetLastError();
+}
+
+// Scores of each pattern against its own list of k candidate templates
+// (scores[p k + j] for template cand[p k + j]), by the library search kernel
+// (128 only; other sizes return hipErrorInvalidValue and the caller takes
+// the single-pair kernel).
+hipError_t launch_xcf_scores_cand(int n, const float2* spec_p, int64_t p, const float2* spec_l, int64_t l,
+                                  const int32_t* cand, int k, int max_shift, float* scores, hipStream_t stream) {
+  if (p <= 0 || k <= 0) return hipSuccess;
+  if (l <= 0) return hipErrorInvalidValue;
+  if (n != 128) return hipErrorInvalidValue;
+  const int lchunk = search_lchunk(n);
+  const int64_t nchunk = (k + lchunk - 1) / lchunk;
+  const int64_t pmax = (kMaxItems / 1024 - 8) / nchunk;
+  if (pmax < 1) return hipErrorInvalidValue;
+  if (p > pmax) {
+    const int64_t sc = (int64_t)(band_of(n) + 1) * (2 * band_of(n) + 1);
+    for (int64_t s = 0; s < p; s += pmax) {
+      const hipError_t e = launch_xcf_scores_cand(n, spec_p + s * sc, p - s < pmax ? p - s : pmax, spec_l, l,
+                                                  cand + s * k, k, max_shift, scores + s * k, stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  const int64_t nblk = p * nchunk;
+  const int64_t grid = ((nblk + 7) / 8) * 8;
+  if (max_shift < 0)
+    hipLaunchKernelGGL((k_xcf_scores128<false, false, true>), dim3((unsigned)grid), dim3(512), 0, stream,
+                       (const cf*)spec_p, p, (const cf*)spec_l, (int64_t)k, lchunk, nblk, max_shift, scores, nullptr,
+                       cand, l);
+  else
+    hipLaunchKernelGGL((k_xcf_scores128<true, false, true>), dim3((unsigned)grid), dim3(512), 0, stream,
+                       (const cf*)spec_p, p, (const cf*)spec_l, (int64_t)k, lchunk, nblk, max_shift, scores, nullptr,
+                       cand, l);
   return hipGetLastError();
 }
 

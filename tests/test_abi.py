@@ -262,3 +262,22 @@ def test_bf16_input_flag_is_validated():
     short.struct_size = ctypes.sizeof(pkg.Params) - 4
     short.input = 7
     assert _index(pkg, lib, pkg.Batch(0x6000, 0, 64), short) == 0
+
+
+def test_candidate_scores_arguments_are_checked_on_the_host():
+    # ebsd_xcf_scores_cand rejects bad arguments before anything is enqueued
+    pkg, lib = _lib()
+    prm = pkg.params_default()
+    vp = ctypes.c_void_p
+
+    def call(n=128, p=2, l=4, k=2, cand=0x3000, prm=prm):
+        return lib.ebsd_xcf_scores_cand(vp(0x1000), p, vp(0x2000), l, vp(cand) if cand else None, k, n,
+                                        ctypes.byref(prm), vp(0x4000), None)
+
+    assert call(k=5) == -1                        # K above L
+    assert call(p=-1) == -1
+    assert call(cand=0) == -1                     # null candidate list
+    assert call(n=64) == -4                       # built at 128 only
+    assert call(n=100) == -4                      # unsupported size
+    assert call(prm=pkg.params_default(precision=1, max_shift=15)) == -4
+    assert call(p=0) == 0 and call(k=0) == 0      # nothing to do

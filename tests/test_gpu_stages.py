@@ -120,6 +120,46 @@ def test_windowed_scores_match_oracle(n, s):
         assert np.max(np.abs(sc[i] - ref)) < 5e-6
 
 
+@pytest.mark.parametrize("s", [-1, 0, 7])
+def test_candidate_scores_equal_library_scores(s):
+    # each pattern's own candidate list (repeats, out-of-order, K above the
+    # 64-template chunk, plus out-of-range indices that clamp to the ends):
+    # the same kernel as the library search, so the same bits
+    banner("candidate scores s=%d" % s)
+    t = tm()
+    n, p, l, k = 128, 5, 90, 70
+    _, _, pats = _pats(n, p, seed=70 + s, offsets=4.0)
+    lq = random_quats(np.random.default_rng(71), l)
+    sp, _, fp = oracle_spectra(pats, n)
+    sl, _, _ = oracle_spectra(oracle_templates(band_master(), lq, n, (0.5, 0.5, 0.6)), n)
+    rng = np.random.default_rng(72)
+    cand = rng.integers(0, l, size=(p, k)).astype(np.int32)
+    cand[0, :3] = [-5, l, l + 100]
+    prm = t.params_default(max_shift=s)
+    full = host(t.xcf_scores(sp, sl, n, prm))
+    got = host(t.xcf_scores_cand(sp, sl, dev(cand), n, prm))
+    idx = np.clip(cand, 0, l - 1)
+    assert np.array_equal(got, np.take_along_axis(full, idx, axis=1))
+    ref = oxcf.library_scores(fp[1], oracle_spectra(oracle_templates(band_master(), lq[idx[1]], n, (0.5, 0.5, 0.6)),
+                                                    n)[2], max_shift=s)
+    assert np.max(np.abs(got[1] - ref)) < 5e-6
+
+
+def test_candidate_scores_argument_errors():
+    t = tm()
+    import paper_1807_11313_amd as pkg
+    f64 = t.spectrum_floats(64)
+    sp = torch.zeros((2, f64), device="cuda:0")
+    with pytest.raises(pkg.EbsdError):          # built at 128 only
+        t.xcf_scores_cand(sp, sp, dev(np.zeros((2, 2), np.int32)), 64)
+    f = t.spectrum_floats(128)
+    sp = torch.zeros((2, f), device="cuda:0")
+    with pytest.raises(pkg.EbsdError):          # K above L
+        t.xcf_scores_cand(sp, sp, dev(np.zeros((2, 3), np.int32)), 128)
+    with pytest.raises(ValueError):             # one candidate row per pattern
+        t.xcf_scores_cand(sp, sp, dev(np.zeros((3, 2), np.int32)), 128)
+
+
 @pytest.mark.parametrize("n,p,l", [(64, 5, 45), (96, 3, 33), (128, 2, 70), (160, 2, 31)])
 def test_scores_match_oracle(n, p, l):
     # L is not a multiple of the 32-template chunk: ragged tail (at 64, where
