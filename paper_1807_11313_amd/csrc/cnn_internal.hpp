@@ -37,8 +37,10 @@ struct Acts {
 };
 
 hipError_t init_params(float* params, const Layout& lay, uint64_t seed, hipStream_t st);
+// keep_relu: also write the full ReLU maps act.r (training); otherwise each
+// convolution writes only its pooled map act.p (inference, same values)
 hipError_t forward(const float* params, const Layout& lay, const float* x, int64_t bsz, const Acts& act,
-                   hipStream_t st);
+                   hipStream_t st, bool keep_relu = true);
 // Gradient of the mean cross-entropy into grad (all of it overwritten);
 // part: split-K scratch of part_floats floats; loss_row: [bsz] doubles.
 hipError_t backward(const float* params, const Layout& lay, const float* x, const int32_t* labels, int64_t bsz,

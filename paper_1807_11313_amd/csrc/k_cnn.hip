@@ -28,6 +28,14 @@ typedef float f4c __attribute__((ext_vector_type(4)));
 constexpr int KS = EBSD_TGEMM_KS;  // K depth of one step
 constexpr int KR = KS / 4;         // operand values per thread and step
 
+// output maps that take a lane's four consecutive rows at once (QUAD)
+template <class T, class = void>
+struct OutQuad : std::false_type {};
+template <class T>
+struct OutQuad<T, std::void_t<decltype(T::QUAD)>> : std::bool_constant<T::QUAD> {};
+template <class Out>
+constexpr bool out_quad() { return OutQuad<Out>::value; }
+
 template <class A, class Bm, class Out>
 __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N, int K, int kslice) {
   // two LDS stages: the operand values of the next K step are loaded into
@@ -93,15 +101,26 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
     __syncthreads();
     st ^= 1;
   }
+  if constexpr (out_quad<Out>()) {
+    // the four accumulator rows of a lane (m = 4 g .. 4 g + 3) go out together
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + 16 * i + 4 * q4 + r, n = n0 + wn + 16 * j + r16;
-        if (m < M && n < N) out(m, n, acc[i][j][r], blockIdx.z);
+      for (int j = 0; j < 2; ++j) {
+        const int m = m0 + wm + 16 * i + 4 * q4, n = n0 + wn + 16 * j + r16;
+        if (m < M && n < N) out.quad(m, n, acc[i][j]);
       }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm + 16 * i + 4 * q4 + r, n = n0 + wn + 16 * j + r16;
+          if (m < M && n < N) out(m, n, acc[i][j][r], blockIdx.z);
+        }
+  }
 }
 
 // --- operand maps ---------------------------------------------------------
@@ -120,6 +139,41 @@ struct ConvFwdA {
     if ((unsigned)yy >= (unsigned)w || (unsigned)xx >= (unsigned)w) return 0.0f;
     return in[(((size_t)bb * ci + c) << (2 * lw)) + (yy << lw) + xx];
   }
+};
+// The same convolution with the output pixels ordered by 2 x 2 pooling
+// quad: m = ((b, Y, X), q), pixel (y, x) = (2 Y + q / 2, 2 X + q % 2), so the
+// four accumulator rows of a lane are one quad (every (m, n) value is the one
+// ConvFwdA gives its pixel: same operands, same K order)
+struct ConvFwdQuadA {
+  static constexpr bool KFAST = false;
+  const float* in;
+  int ci, lw;
+  __device__ float operator()(int m, int k) const {
+    const int w = 1 << lw, lo = lw - 1;
+    const int q = m & 3, xq = (m >> 2) & ((1 << lo) - 1), yq = (m >> (2 + lo)) & ((1 << lo) - 1);
+    const int bb = m >> (2 * lw);
+    const int x = 2 * xq + (q & 1), y = 2 * yq + (q >> 1);
+    const int c = k / 9, r = k - 9 * c;
+    const int yy = y + r / 3 - 1, xx = x + r % 3 - 1;
+    if ((unsigned)yy >= (unsigned)w || (unsigned)xx >= (unsigned)w) return 0.0f;
+    return in[(((size_t)bb * ci + c) << (2 * lw)) + (yy << lw) + xx];
+  }
+};
+// pooled[b][n][Y][X] = max over the quad of max(acc + bias[n], 0), which is
+// max(max over the quad of acc + bias[n], 0): adding the bias and clamping
+// are monotone, so the value equals the unfused ReLU then max-pool exactly
+struct ConvReluPoolOut {
+  static constexpr bool QUAD = true;
+  float* out;
+  const float* bias;
+  int co, lw;  // lw: log2 of the pooled side
+  __device__ void quad(int m, int n, const f4c& v) const {
+    const int hw = 1 << (2 * lw);
+    const int bb = (m >> 2) >> (2 * lw), p = (m >> 2) & (hw - 1);
+    const float mx = fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3]));
+    out[((size_t)bb * co + n) * hw + p] = fmaxf(mx + bias[n], 0.0f);
+  }
+  __device__ void operator()(int, int, float, int) const {}
 };
 // B(k, n) = w[n][k] (weights [co][ci * 9])
 struct WeightT {
@@ -697,18 +751,26 @@ hipError_t init_params(float* params, const Layout& lay, uint64_t seed, hipStrea
 
 // forward; act holds r_i, p_i (i = 0..3) and the logits
 hipError_t forward(const float* params, const Layout& lay, const float* x, int64_t bsz, const Acts& act,
-                   hipStream_t st) {
+                   hipStream_t st, bool keep_relu) {
   const float* a = x;
   int ci = 1, w = kInSize;
   hipError_t e;
   for (int i = 0; i < 4; ++i) {
     const int co = kChannels[i], lw = ilog2(w);
     const int M = (int)(bsz * w * w), K = ci * 9;
-    e = gemm(ConvFwdA{a, ci, lw}, WeightT{params + lay.conv_w[i], K},
-             ConvReluOut{act.r[i], params + lay.conv_b[i], co, lw}, M, co, K, 1, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pool_fwd, dim3(nb(bsz * co * (w / 2) * (w / 2))), dim3(256), 0, st, act.r[i],
-                       (int64_t)(bsz * co), lw - 1, act.p[i]);
+    if (keep_relu) {
+      // training keeps the full ReLU maps for the backward pass
+      e = gemm(ConvFwdA{a, ci, lw}, WeightT{params + lay.conv_w[i], K},
+               ConvReluOut{act.r[i], params + lay.conv_b[i], co, lw}, M, co, K, 1, st);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_pool_fwd, dim3(nb(bsz * co * (w / 2) * (w / 2))), dim3(256), 0, st, act.r[i],
+                         (int64_t)(bsz * co), lw - 1, act.p[i]);
+    } else {
+      // inference pools in the product's epilogue: only the pooled maps are written
+      e = gemm(ConvFwdQuadA{a, ci, lw}, WeightT{params + lay.conv_w[i], K},
+               ConvReluPoolOut{act.p[i], params + lay.conv_b[i], co, lw - 1}, M, co, K, 1, st);
+      if (e != hipSuccess) return e;
+    }
     a = act.p[i];
     ci = co;
     w /= 2;
