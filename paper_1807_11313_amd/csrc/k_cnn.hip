@@ -35,6 +35,12 @@ template <class T>
 struct OutQuad<T, std::void_t<decltype(T::QUAD)>> : std::bool_constant<T::QUAD> {};
 template <class Out>
 constexpr bool out_quad() { return OutQuad<Out>::value; }
+// A operand maps with a whole-step fetch (STEP): the KR values k0 + kw + 4 r
+// of one row m (the row-major A tile gives a thread one row and k = w + 4 r)
+template <class T, class = void>
+struct AStep : std::false_type {};
+template <class T>
+struct AStep<T, std::void_t<decltype(T::STEP)>> : std::bool_constant<T::STEP> {};
 
 template <class A, class Bm, class Out>
 __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N, int K, int kslice) {
@@ -66,10 +72,26 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
   }
   float ra[KR], rb[KR];
   auto fetch = [&](int k0) {
+    bool done = false;
+    if constexpr (AStep<A>::value && !A::KFAST) {
+      // am[r] = lane and ak[r] = w + 4 r for every r
+      if (a.stepwise() && k0 + KS <= ke) {
+        const int m = m0 + am[0];
+        if (m < M) {
+          a.step(m, k0, ak[0], ra);
+        } else {
+#pragma unroll
+          for (int r = 0; r < KR; ++r) ra[r] = 0.0f;
+        }
+        done = true;
+      }
+    }
 #pragma unroll
     for (int r = 0; r < KR; ++r) {
-      const int m = m0 + am[r], k = k0 + ak[r];
-      ra[r] = (m < M && k < ke) ? a(m, k) : 0.0f;
+      if (!done) {
+        const int m = m0 + am[r], k = k0 + ak[r];
+        ra[r] = (m < M && k < ke) ? a(m, k) : 0.0f;
+      }
       const int n = n0 + bn[r], k2 = k0 + bk[r];
       rb[r] = (n < N && k2 < ke) ? b(k2, n) : 0.0f;
     }
@@ -126,37 +148,61 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
 // --- operand maps ---------------------------------------------------------
 // Images are NCHW with H = W = 1 << lw.
 
-// forward convolution, A(m = (b, y, x), k = (c, r)): input pixel under tap r
+// Forward convolution, A(m, k) = the input pixel under tap t of channel c,
+// with K ordered tap-major: k = t ci + c, t = 3 (dy + 1) + (dx + 1) (the
+// weights are read in their stored [co][ci][3][3] order through WeightTap).
+// Output pixels m = (b, y, x) row-major, or with QUAD ordered by 2 x 2
+// pooling quad, m = ((b, Y, X), q), pixel (2 Y + q / 2, 2 X + q % 2), so that
+// the four accumulator rows of a lane are one quad.  Offsets are 32-bit
+// (inputs below 2^31 elements).  For ci >= 16 a thread's KR values of a
+// 16-deep step (k = k0 + kw + 4 r) share one tap: one bounds test, and the
+// channels are 4 planes apart.
+template <bool QUAD>
 struct ConvFwdA {
   static constexpr bool KFAST = false;
+  static constexpr bool STEP = true;
   const float* in;
-  int ci, lw;
+  int ci, lci, lw;  // lci = log2 ci
+  __device__ void pix(int m, int& bb, int& y, int& x) const {
+    if constexpr (QUAD) {
+      const int lo = lw - 1, q = m & 3;
+      x = 2 * ((m >> 2) & ((1 << lo) - 1)) + (q & 1);
+      y = 2 * ((m >> (2 + lo)) & ((1 << lo) - 1)) + (q >> 1);
+    } else {
+      x = m & ((1 << lw) - 1);
+      y = (m >> lw) & ((1 << lw) - 1);
+    }
+    bb = m >> (2 * lw);
+  }
   __device__ float operator()(int m, int k) const {
-    const int w = 1 << lw;
-    const int x = m & (w - 1), y = (m >> lw) & (w - 1), bb = m >> (2 * lw);
-    const int c = k / 9, r = k - 9 * c;
-    const int yy = y + r / 3 - 1, xx = x + r % 3 - 1;
+    int bb, y, x;
+    pix(m, bb, y, x);
+    const int t = k >> lci, c = k & ((1 << lci) - 1);
+    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1, w = 1 << lw;
     if ((unsigned)yy >= (unsigned)w || (unsigned)xx >= (unsigned)w) return 0.0f;
-    return in[(((size_t)bb * ci + c) << (2 * lw)) + (yy << lw) + xx];
+    return in[(unsigned)(((((bb << lci) + c) << lw) + yy) << lw) + (unsigned)xx];
+  }
+  __device__ bool stepwise() const { return lci >= 4; }
+  __device__ void step(int m, int k0, int kw, float* v) const {
+    int bb, y, x;
+    pix(m, bb, y, x);
+    const int t = k0 >> lci, c = (k0 & ((1 << lci) - 1)) + kw;
+    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1, w = 1 << lw;
+    const bool inside = (unsigned)yy < (unsigned)w && (unsigned)xx < (unsigned)w;
+    const unsigned base = (unsigned)(((((bb << lci) + c) << lw) + yy) << lw) + (unsigned)xx;
+    const unsigned plane4 = 4u << (2 * lw);
+#pragma unroll
+    for (int r = 0; r < KR; ++r) v[r] = inside ? in[base + r * plane4] : 0.0f;
   }
 };
-// The same convolution with the output pixels ordered by 2 x 2 pooling
-// quad: m = ((b, Y, X), q), pixel (y, x) = (2 Y + q / 2, 2 X + q % 2), so the
-// four accumulator rows of a lane are one quad (every (m, n) value is the one
-// ConvFwdA gives its pixel: same operands, same K order)
-struct ConvFwdQuadA {
-  static constexpr bool KFAST = false;
-  const float* in;
-  int ci, lw;
-  __device__ float operator()(int m, int k) const {
-    const int w = 1 << lw, lo = lw - 1;
-    const int q = m & 3, xq = (m >> 2) & ((1 << lo) - 1), yq = (m >> (2 + lo)) & ((1 << lo) - 1);
-    const int bb = m >> (2 * lw);
-    const int x = 2 * xq + (q & 1), y = 2 * yq + (q >> 1);
-    const int c = k / 9, r = k - 9 * c;
-    const int yy = y + r / 3 - 1, xx = x + r % 3 - 1;
-    if ((unsigned)yy >= (unsigned)w || (unsigned)xx >= (unsigned)w) return 0.0f;
-    return in[(((size_t)bb * ci + c) << (2 * lw)) + (yy << lw) + xx];
+// B(k, n) = weight of output channel n, input channel k % ci, tap k / ci
+// (weights [co][ci][3][3]), for the tap-major K of ConvFwdA
+struct WeightTap {
+  static constexpr bool KFAST = true;
+  const float* w;
+  int k_len, lci;
+  __device__ float operator()(int k, int n) const {
+    return w[(unsigned)(n * k_len) + (unsigned)((k & ((1 << lci) - 1)) * 9 + (k >> lci))];
   }
 };
 // pooled[b][n][Y][X] = max over the quad of max(acc + bias[n], 0), which is
@@ -758,16 +804,17 @@ hipError_t forward(const float* params, const Layout& lay, const float* x, int64
   for (int i = 0; i < 4; ++i) {
     const int co = kChannels[i], lw = ilog2(w);
     const int M = (int)(bsz * w * w), K = ci * 9;
+    const int lci = ilog2(ci);
     if (keep_relu) {
       // training keeps the full ReLU maps for the backward pass
-      e = gemm(ConvFwdA{a, ci, lw}, WeightT{params + lay.conv_w[i], K},
+      e = gemm(ConvFwdA<false>{a, ci, lci, lw}, WeightTap{params + lay.conv_w[i], K, lci},
                ConvReluOut{act.r[i], params + lay.conv_b[i], co, lw}, M, co, K, 1, st);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k_pool_fwd, dim3(nb(bsz * co * (w / 2) * (w / 2))), dim3(256), 0, st, act.r[i],
                          (int64_t)(bsz * co), lw - 1, act.p[i]);
     } else {
       // inference pools in the product's epilogue: only the pooled maps are written
-      e = gemm(ConvFwdQuadA{a, ci, lw}, WeightT{params + lay.conv_w[i], K},
+      e = gemm(ConvFwdA<true>{a, ci, lci, lw}, WeightTap{params + lay.conv_w[i], K, lci},
                ConvReluPoolOut{act.p[i], params + lay.conv_b[i], co, lw - 1}, M, co, K, 1, st);
       if (e != hipSuccess) return e;
     }
