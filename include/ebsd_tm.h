@@ -183,6 +183,33 @@ int ebsd_index_patterns(const ebsd_batch* pats, const ebsd_master* mp, const ebs
                         double* best_q, float* peak_h, float* shift, float* scores, void* stream);
 
 /*
+ * Library plan: the paper generates its library once and matches every
+ * pattern of a map against it (sections "Method Overview" and "Orientation
+ * and Pattern Centre Refinement", one library at the nominal pattern
+ * centre).  ebsd_plan_create projects the L templates at geo's nominal
+ * pattern centre and keeps their filtered band spectra, with a copy of
+ * lib_q, in device memory the plan owns (L x 38 KB at n = 128); the
+ * parameters are fixed with it.  It first checks on the device that every
+ * lib_q row is a unit quaternion (| |q| - 1 | <= 1e-6; EBSD_E_INVALID
+ * otherwise, nothing kept) and therefore waits for `stream` once.  The
+ * spectra are ready in stream order: calls on the same stream may follow at
+ * once, calls on another stream after it has been synchronised.
+ *
+ * ebsd_index_patterns_plan is ebsd_index_patterns against the plan's library
+ * (pats->n must equal the plan's n; outputs as there, best_q from the plan's
+ * copy of lib_q).  The results equal those of ebsd_index_patterns with the
+ * same library and parameters.  A plan may serve calls on several streams;
+ * destroy it only after every such call has finished (synchronise those
+ * streams first).
+ */
+typedef struct ebsd_plan_s* ebsd_plan;
+int ebsd_plan_create(const ebsd_master* mp, const ebsd_geometry* geo, const double* lib_q, int64_t L, int32_t n,
+                     const ebsd_params* prm, ebsd_plan* plan, void* stream);
+int ebsd_index_patterns_plan(ebsd_plan plan, const ebsd_batch* pats, int32_t* best_idx, double* best_q,
+                             float* peak_h, float* shift, float* scores, void* stream);
+int ebsd_plan_destroy(ebsd_plan plan);
+
+/*
  * Refine starting orientations (section "Orientation and Pattern Centre
  * Refinement"): n_iter times { project the template at (R, PC_p); measure
  * the upsampled shift s; R <- R (Ry(beta) Rx(alpha))^T with beta =

@@ -17,7 +17,7 @@ __all__ = ["lib", "Params", "index_patterns", "refine_orientations", "project_te
            "pattern_spectra", "spectrum_floats", "xcf_peak", "xcf_scores", "xcf_scores_cand", "xcf_subpixel",
            "measure_rotation", "params_default", "version", "RaggedPlan", "Cnn", "cnn_make_batch", "cnn_topk",
            "index_proposed", "refine_from_match", "pc_map", "PcModel", "capture_range", "so3_library",
-           "nn_disorientation", "LIB_PATH", "EXPORTS"]
+           "nn_disorientation", "LibraryPlan", "LIB_PATH", "EXPORTS"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libebsd_tm.so")
@@ -32,7 +32,8 @@ EXPORTS = ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_index
            "ebsd_cnn_forward", "ebsd_cnn_gradients", "ebsd_cnn_train_step", "ebsd_cnn_apply_gradient",
            "ebsd_cnn_make_batch", "ebsd_cnn_topk",
            "ebsd_index_proposed", "ebsd_pc_map", "ebsd_refine_from_match", "ebsd_capture_range",
-           "ebsd_so3_library", "ebsd_nn_disorientation")
+           "ebsd_so3_library", "ebsd_nn_disorientation", "ebsd_plan_create", "ebsd_index_patterns_plan",
+           "ebsd_plan_destroy")
 
 RAGGED_STENCIL, RAGGED_EAGER, RAGGED_NO_AUTOTUNE, RAGGED_REFINE = 1, 2, 4, 8
 
@@ -94,6 +95,9 @@ def lib():
     L.ebsd_index_patterns.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, i64, dp(Params), vp, vp, vp, vp,
                                       vp, vp]
     L.ebsd_refine_orientations.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, dp(Params), vp, vp, vp, vp]
+    L.ebsd_plan_create.argtypes = [dp(Master), dp(Geometry), vp, i64, i32, dp(Params), dp(vp), vp]
+    L.ebsd_index_patterns_plan.argtypes = [vp, dp(Batch), vp, vp, vp, vp, vp, vp]
+    L.ebsd_plan_destroy.argtypes = [vp]
     L.ebsd_refine_orientations_noalloc.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, dp(Params), vp, vp, vp,
                                                    vp]
     L.ebsd_refine_from_match.argtypes = [dp(Batch), dp(Master), dp(Geometry), vp, vp, dp(Params), vp, vp, vp, vp]
@@ -254,6 +258,64 @@ def index_patterns(patterns, master, pc, lib_q, prm=None, scores=False):
                                    _ptr(out["shift"]), _ptr(out.get("scores")), _stream())
     _check(rc, "ebsd_index_patterns")
     return out
+
+
+class LibraryPlan:
+    """A library whose template spectra are computed once (ebsd_plan_create):
+    index(patterns) then searches it like index_patterns."""
+
+    def __init__(self, master, pc, lib_q, n, prm=None, input_bf16=False):
+        import torch
+        _shape(lib_q, (None, 4), "lib_q")
+        _shape(master, (None, None), "master")
+        self.n, self.L = int(n), int(lib_q.shape[0])
+        self.input_bf16 = bool(input_bf16)
+        q = Params()
+        if prm is None:
+            lib().ebsd_params_default(ctypes.byref(q))
+        else:
+            ctypes.memmove(ctypes.byref(q), ctypes.byref(prm), ctypes.sizeof(Params))
+        if self.input_bf16:
+            q.input = INPUT_BF16
+        h = ctypes.c_void_p()
+        _check(lib().ebsd_plan_create(ctypes.byref(_master(master)), ctypes.byref(_geo(pc)),
+                                      _ptr(lib_q, torch.float64, "lib_q"), self.L, self.n, ctypes.byref(q),
+                                      ctypes.byref(h), _stream()), "ebsd_plan_create")
+        self._h = h
+
+    def index(self, patterns, scores=False):
+        import torch
+        p, n = _patterns(patterns)
+        if n != self.n:
+            raise ValueError("patterns are %d x %d, the plan is for %d" % (n, n, self.n))
+        if (patterns.dtype == torch.bfloat16) != self.input_bf16:
+            raise ValueError("pattern storage differs from the plan's")
+        dev = patterns.device
+        out = dict(best_idx=torch.empty(p, dtype=torch.int32, device=dev),
+                   best_q=torch.empty((p, 4), dtype=torch.float64, device=dev),
+                   peak_h=torch.empty(p, dtype=torch.float32, device=dev),
+                   shift=torch.empty((p, 2), dtype=torch.float32, device=dev))
+        if scores:
+            out["scores"] = torch.empty((p, self.L), dtype=torch.float32, device=dev)
+        dtype = torch.bfloat16 if self.input_bf16 else torch.float32
+        batch = Batch(_ptr(patterns, dtype, "patterns").value, p, n)
+        _check(lib().ebsd_index_patterns_plan(self._h, ctypes.byref(batch), _ptr(out["best_idx"]),
+                                              _ptr(out["best_q"]), _ptr(out["peak_h"]), _ptr(out["shift"]),
+                                              _ptr(out.get("scores")), _stream()), "ebsd_index_patterns_plan")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            import torch
+            torch.cuda.current_stream().synchronize()  # the plan's calls must have finished
+            lib().ebsd_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def refine_orientations(patterns, master, pc, q_init, pc_per=None, prm=None, out=None, noalloc=False):

@@ -298,6 +298,58 @@ hipError_t timed_scores(int n, const ebsd_params& prm, const float2* sp, int64_t
   return hipSuccess;
 }
 
+// Steps A2-A8 of ebsd_index_patterns against library spectra already in
+// spec_l (L templates, orientations lib_q): pattern spectra, search, library
+// argmax, the winner's integer and sub-pixel peaks.
+int index_against(int n, const ebsd_params& p, const float* pats, int64_t P, const float2* spec_l,
+                  const double* lib_q, int64_t L, int32_t* best_idx, double* best_q, float* peak_h, float* shift,
+                  float* scores, Arena& ws, hipStream_t st) {
+  int rc;
+  const int64_t sc = spec_complex(n);
+  const FilterParams fp = filter_of(p, n);
+  EBSD_ALLOC(spec_p, float2, sc * P, ws);
+  float* sc_out = scores;
+  if (!sc_out) {
+    EBSD_ALLOC(tmp_scores, float, P * L, ws);
+    sc_out = tmp_scores;
+  }
+  EBSD_ALLOC(h_int, float, P, ws);
+  EBSD_ALLOC(s_int, int32_t, 2 * P, ws);
+  EBSD_ALLOC(h_tmp, float, P, ws);
+  EBSD_ALLOC(roots, float2, subpixel_table_size(n, p.upsample), ws);
+  if (int e = pattern_spectra(n, p, pats, P, fp, spec_p, nullptr, ws, st)) return e;
+  SearchConsts consts;
+  if ((rc = search_consts(n, p, ws, st, &consts))) return rc;
+  EBSD_TRY(timed_scores(n, p, spec_p, P, spec_l, L, consts, sc_out, st), "xcf_scores");
+  EBSD_TRY(launch_library_argmax(sc_out, P, L, best_idx, h_int, st), "library_argmax");
+  if (int e = do_peak(n, p, spec_p, spec_l, nullptr, best_idx, P, h_tmp, s_int, ws, st)) return e;
+  EBSD_TRY(launch_subpixel_tables(n, p.upsample, roots, st), "subpixel tables");
+  EBSD_TRY(launch_subpixel(n, spec_p, spec_l, nullptr, best_idx, P, s_int, p.upsample, roots, peak_h, shift, st),
+           "subpixel");
+  if (best_q) EBSD_TRY(launch_gather_q(lib_q, best_idx, P, best_q, st), "gather_q");
+  return EBSD_OK;
+}
+
+// Arguments of a library search at size n common to the direct call and the plan.
+int check_search(int n, const ebsd_params& p) {
+  if (p.form == EBSD_FORM_FFT && !fft_supported(n))
+    return fail(EBSD_E_UNSUPPORTED, "the FFT search is not built at this size; use the DFT-GEMM form");
+  if (!fft_supported(n) && !window_peak_supported(n, p.max_shift))
+    return fail(EBSD_E_UNSUPPORTED, "at this size the peak needs a shift window (max_shift >= 0)");
+  return EBSD_OK;
+}
+
+// Largest | |q| - 1 | over L quaternions, as the bits of a non-negative float
+// (NaN counts as infinite), into *worst (zeroed by the caller).
+__global__ void k_unit_check(const double* __restrict__ q, int64_t L, unsigned* __restrict__ worst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= L) return;
+  const double a = q[4 * i], b = q[4 * i + 1], c = q[4 * i + 2], d = q[4 * i + 3];
+  float dev = (float)fabs(sqrt(a * a + b * b + c * c + d * d) - 1.0);
+  if (!(dev <= 3.0e38f)) dev = INFINITY;
+  atomicMax(worst, __float_as_uint(dev));
+}
+
 }  // namespace api
 }  // namespace ebsd
 
@@ -502,10 +554,7 @@ int ebsd_index_patterns(const ebsd_batch* pats, const ebsd_master* mp, const ebs
   if (!lib_q) return fail(EBSD_E_INVALID, "null library");
   if (P == 0) return EBSD_OK;
   if (!pats->data || !best_idx || !peak_h || !shift) return fail(EBSD_E_INVALID, "null pointer");
-  if (p.form == EBSD_FORM_FFT && !fft_supported(n))
-    return fail(EBSD_E_UNSUPPORTED, "the FFT search is not built at this size; use the DFT-GEMM form");
-  if (!fft_supported(n) && !window_peak_supported(n, p.max_shift))
-    return fail(EBSD_E_UNSUPPORTED, "at this size the peak needs a shift window (max_shift >= 0)");
+  if ((rc = check_search(n, p))) return rc;
 
   hipStream_t st = (hipStream_t)stream;
   Scratch ws(st);
@@ -514,30 +563,97 @@ int ebsd_index_patterns(const ebsd_batch* pats, const ebsd_master* mp, const ebs
   const FilterParams fp = filter_of(p, n);
   EBSD_ALLOC(tmpl, float, npix * L, ws);
   EBSD_ALLOC(spec_l, float2, sc * L, ws);
-  EBSD_ALLOC(spec_p, float2, sc * P, ws);
-  float* sc_out = scores;
-  if (!sc_out) {
-    EBSD_ALLOC(tmp_scores, float, P * L, ws);
-    sc_out = tmp_scores;
-  }
-  EBSD_ALLOC(h_int, float, P, ws);
-  EBSD_ALLOC(s_int, int32_t, 2 * P, ws);
-  EBSD_ALLOC(h_tmp, float, P, ws);
-  EBSD_ALLOC(roots, float2, subpixel_table_size(n, p.upsample), ws);
-
   EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, lib_q, L, nullptr, geo->pcx, geo->pcy, geo->pcz, tmpl, st),
            "project");
   if (int e = do_spectra(n, tmpl, L, fp, spec_l, nullptr, ws, st)) return e;
-  if (int e = pattern_spectra(n, p, pats->data, P, fp, spec_p, nullptr, ws, st)) return e;
-  SearchConsts consts;
-  if ((rc = search_consts(n, p, ws, st, &consts))) return rc;
-  EBSD_TRY(timed_scores(n, p, spec_p, P, spec_l, L, consts, sc_out, st), "xcf_scores");
-  EBSD_TRY(launch_library_argmax(sc_out, P, L, best_idx, h_int, st), "library_argmax");
-  if (int e = do_peak(n, p, spec_p, spec_l, nullptr, best_idx, P, h_tmp, s_int, ws, st)) return e;
-  EBSD_TRY(launch_subpixel_tables(n, p.upsample, roots, st), "subpixel tables");
-  EBSD_TRY(launch_subpixel(n, spec_p, spec_l, nullptr, best_idx, P, s_int, p.upsample, roots, peak_h, shift, st),
-           "subpixel");
-  if (best_q) EBSD_TRY(launch_gather_q(lib_q, best_idx, P, best_q, st), "gather_q");
+  return index_against(n, p, pats->data, P, spec_l, lib_q, L, best_idx, best_q, peak_h, shift, scores, ws, st);
+}
+
+
+// ---------------------------------------------------------------------------
+// Library plans: the templates' band spectra computed once and reused.
+struct ebsd_plan_s {
+  int n;
+  ebsd_params p;
+  int64_t L;
+  float2* spec_l;
+  double* lib_q;
+};
+
+int ebsd_plan_create(const ebsd_master* mp, const ebsd_geometry* geo, const double* lib_q, int64_t L, int32_t n,
+                     const ebsd_params* prm, ebsd_plan* out, void* stream) {
+  g_last_error.clear();
+  int rc;
+  if (!out) return fail(EBSD_E_INVALID, "null output");
+  *out = nullptr;
+  ebsd_params p;
+  if ((rc = check_size(n)) || (rc = resolve_params(prm, n, &p)) || (rc = check_master(mp)) ||
+      (rc = check_geometry(geo)) || (rc = check_search(n, p)))
+    return rc;
+  if (L < 1 || L > 0x7fffffffLL) return fail(EBSD_E_INVALID, "L must be in [1, 2^31)");
+  if (!lib_q) return fail(EBSD_E_INVALID, "null library");
+  hipStream_t st = (hipStream_t)stream;
+  // every library orientation must be a unit quaternion (checked on the
+  // device, then read back: plan creation waits for the stream)
+  {
+    Scratch ws(st);
+    EBSD_ALLOC(worst, unsigned, 1, ws);
+    EBSD_TRY(hipMemsetAsync(worst, 0, sizeof(unsigned), st), "unit check");
+    hipLaunchKernelGGL(k_unit_check, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, st, lib_q, L, worst);
+    EBSD_TRY(hipGetLastError(), "unit check");
+    unsigned bits = 0;
+    EBSD_TRY(hipMemcpyAsync(&bits, worst, sizeof(unsigned), hipMemcpyDeviceToHost, st), "unit check");
+    EBSD_TRY(hipStreamSynchronize(st), "unit check");
+    float dev;
+    memcpy(&dev, &bits, sizeof(float));
+    if (!(dev <= 1e-6f)) return fail(EBSD_E_INVALID, "library orientations must be unit quaternions");
+  }
+  auto* pl = new (std::nothrow) ebsd_plan_s{n, p, L, nullptr, nullptr};
+  if (!pl) return fail(EBSD_E_NOMEM, "plan allocation failed");
+  const int64_t sc = spec_complex(n);
+  if (hipMalloc(&pl->spec_l, sizeof(float2) * sc * L) != hipSuccess ||
+      hipMalloc(&pl->lib_q, sizeof(double) * 4 * L) != hipSuccess) {
+    ebsd_plan_destroy(pl);
+    return fail(EBSD_E_NOMEM, "plan device allocation failed");
+  }
+  rc = [&]() -> int {
+    Scratch ws(st);
+    EBSD_TRY(hipMemcpyAsync(pl->lib_q, lib_q, sizeof(double) * 4 * L, hipMemcpyDeviceToDevice, st), "plan copy");
+    EBSD_ALLOC(tmpl, float, (int64_t)n * n * L, ws);
+    EBSD_TRY(launch_project(n, mp->data, mp->H, mp->W, lib_q, L, nullptr, geo->pcx, geo->pcy, geo->pcz, tmpl, st),
+             "project");
+    return do_spectra(n, tmpl, L, filter_of(p, n), pl->spec_l, nullptr, ws, st);
+  }();
+  if (rc) {
+    (void)hipStreamSynchronize(st);
+    ebsd_plan_destroy(pl);
+    return rc;
+  }
+  *out = pl;
+  return EBSD_OK;
+}
+
+int ebsd_index_patterns_plan(ebsd_plan plan, const ebsd_batch* pats, int32_t* best_idx, double* best_q,
+                             float* peak_h, float* shift, float* scores, void* stream) {
+  g_last_error.clear();
+  if (!plan) return fail(EBSD_E_INVALID, "null plan");
+  if (!pats) return fail(EBSD_E_INVALID, "null batch");
+  if (pats->n != plan->n) return fail(EBSD_E_INVALID, "pattern size differs from the plan's");
+  const int64_t P = pats->P;
+  if (P < 0 || P > 0x7fffffffLL) return fail(EBSD_E_INVALID, "P must be in [0, 2^31)");
+  if (P == 0) return EBSD_OK;
+  if (!pats->data || !best_idx || !peak_h || !shift) return fail(EBSD_E_INVALID, "null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  return index_against(plan->n, plan->p, pats->data, P, plan->spec_l, plan->lib_q, plan->L, best_idx, best_q,
+                       peak_h, shift, scores, ws, st);
+}
+
+int ebsd_plan_destroy(ebsd_plan plan) {
+  if (!plan) return EBSD_OK;
+  if (plan->spec_l) (void)hipFree(plan->spec_l);
+  if (plan->lib_q) (void)hipFree(plan->lib_q);
+  delete plan;
   return EBSD_OK;
 }
 

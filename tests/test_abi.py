@@ -281,3 +281,28 @@ def test_candidate_scores_arguments_are_checked_on_the_host():
     assert call(n=100) == -4                      # unsupported size
     assert call(prm=pkg.params_default(precision=1, max_shift=15)) == -4
     assert call(p=0) == 0 and call(k=0) == 0      # nothing to do
+
+
+def test_plan_arguments_are_checked_on_the_host():
+    # ebsd_plan_create / ebsd_index_patterns_plan reject bad arguments before
+    # any device work; destroying a null plan is a no-op
+    pkg, lib = _lib()
+    vp = ctypes.c_void_p
+    m = pkg.Master(0x1000, 256, 256)
+    g = pkg.Geometry(0.5, 0.5, 0.6, None)
+    h = vp()
+
+    def create(n=128, L=10, q=0x2000, prm=None, out=True, master=m):
+        return lib.ebsd_plan_create(ctypes.byref(master), ctypes.byref(g), vp(q) if q else None, L, n,
+                                    ctypes.byref(prm or pkg.params_default()), ctypes.byref(h) if out else None,
+                                    None)
+
+    assert create(out=False) == -1
+    assert create(L=0) == -1
+    assert create(q=0) == -1
+    assert create(n=100) == -4
+    assert create(n=256) == -4                              # 256 needs a shift window
+    assert create(master=pkg.Master(0x1000, 0, 256)) == -1
+    b = pkg.Batch(0x3000, 4, 128)
+    assert lib.ebsd_index_patterns_plan(None, ctypes.byref(b), vp(1), None, vp(2), vp(3), None, None) == -1
+    assert lib.ebsd_plan_destroy(None) == 0
