@@ -14,19 +14,20 @@ namespace cnn {
 
 // ---------------------------------------------------------------------------
 // Tiled FP32 GEMM on the matrix cores: C(m, n) = sum_k A(m, k) B(k, n) over k
-// in the block's slice [z * kslice, (z + 1) * kslice) of [0, K).  64 x 64
-// tiles, KS-deep K steps through two LDS stages; wave w owns the 32 x 32 quarter
-// (w & 1, w >> 1) as 2 x 2 tiles of v_mfma_f32_16x16x4f32 (A operand: lane l
-// holds row l % 16, k = l / 16; B: k = l / 16, column l % 16; accumulator:
-// rows 4 (l / 16) + r, column l % 16).  A::KFAST / B::KFAST choose which
-// index runs along consecutive threads when the tile is loaded (the one that
-// is contiguous in memory).
+// in the block's slice [z * kslice, (z + 1) * kslice) of [0, K).  TM x TN
+// tiles (TM 64 or 128, TN 32, 64 or 128), KS-deep K steps through two LDS
+// stages; wave w owns the (TM / 2) x (TN / 2) quarter (w & 1, w >> 1) as
+// 16 x 16 tiles of v_mfma_f32_16x16x4f32 (A operand: lane l holds row l % 16,
+// k = l / 16; B: k = l / 16, column l % 16; accumulator: rows 4 (l / 16) + r,
+// column l % 16).  A::KFAST / B::KFAST choose which index runs along
+// consecutive threads when the tile is loaded (the one that is contiguous in
+// memory).  Larger tiles give each LDS operand read and each barrier more
+// products: the launcher takes 128 rows and as many columns as N fills.
 typedef float f4c __attribute__((ext_vector_type(4)));
 #ifndef EBSD_TGEMM_KS
 #define EBSD_TGEMM_KS 16
 #endif
 constexpr int KS = EBSD_TGEMM_KS;  // K depth of one step
-constexpr int KR = KS / 4;         // operand values per thread and step
 
 // output maps that take a lane's four consecutive rows at once (QUAD)
 template <class T, class = void>
@@ -35,73 +36,83 @@ template <class T>
 struct OutQuad<T, std::void_t<decltype(T::QUAD)>> : std::bool_constant<T::QUAD> {};
 template <class Out>
 constexpr bool out_quad() { return OutQuad<Out>::value; }
-// A operand maps with a whole-step fetch (STEP): the KR values k0 + kw + 4 r
-// of one row m (the row-major A tile gives a thread one row and k = w + 4 r)
+// A operand maps with a whole-step fetch (STEP): the values k0 + kw + ks r of
+// one row m (with KFAST false a thread holds one row of the A tile and
+// k = kw + ks r, ks = 256 / TM)
 template <class T, class = void>
 struct AStep : std::false_type {};
 template <class T>
 struct AStep<T, std::void_t<decltype(T::STEP)>> : std::bool_constant<T::STEP> {};
 
-template <class A, class Bm, class Out>
+template <int TM, int TN, class A, class Bm, class Out>
 __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N, int K, int kslice) {
+  static_assert((TM == 64 || TM == 128) && (TN == 32 || TN == 64 || TN == 128), "tile");
+  constexpr int KRA = TM * KS / 256, KRB = TN * KS / 256;  // operand values per thread and step
+  constexpr int TI = TM / 32, TJ = TN / 32;                 // 16 x 16 tiles per wave
   // two LDS stages: the operand values of the next K step are loaded into
   // registers while the matrix cores work on the current one, then stored
   // into the other stage (one barrier per step)
-  __shared__ float as[2][KS][64 + 1];
-  __shared__ float bs[2][KS][64 + 1];
+  __shared__ float as[2][KS][TM + 1];
+  __shared__ float bs[2][KS][TN + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wm = (w & 1) * (TM / 2), wn = (w >> 1) * (TN / 2);
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
   const int kb = blockIdx.z * kslice;
   const int ke = min(K, kb + kslice);
-  f4c acc[2][2];
+  f4c acc[TI][TJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f4c{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < TJ; ++j) acc[i][j] = f4c{0.f, 0.f, 0.f, 0.f};
   const int r16 = lane & 15, q4 = lane >> 4;
-  // this thread's KR (m, k) and (k, n) positions in a KS-deep step
-  int am[KR], ak[KR], bn[KR], bk[KR];
+  // this thread's (m, k) and (k, n) positions in a KS-deep step
+  int am[KRA], ak[KRA], bn[KRB], bk[KRB];
 #pragma unroll
-  for (int r = 0; r < KR; ++r) {
+  for (int r = 0; r < KRA; ++r) {
     const int idx = tid + 256 * r;
-    am[r] = A::KFAST ? idx / KS : idx & 63;
-    ak[r] = A::KFAST ? idx % KS : idx >> 6;
-    bn[r] = Bm::KFAST ? idx / KS : idx & 63;
-    bk[r] = Bm::KFAST ? idx % KS : idx >> 6;
+    am[r] = A::KFAST ? idx / KS : idx % TM;
+    ak[r] = A::KFAST ? idx % KS : idx / TM;
   }
-  float ra[KR], rb[KR];
+#pragma unroll
+  for (int r = 0; r < KRB; ++r) {
+    const int idx = tid + 256 * r;
+    bn[r] = Bm::KFAST ? idx / KS : idx % TN;
+    bk[r] = Bm::KFAST ? idx % KS : idx / TN;
+  }
+  float ra[KRA], rb[KRB];
   auto fetch = [&](int k0) {
     bool done = false;
     if constexpr (AStep<A>::value && !A::KFAST) {
-      // am[r] = lane and ak[r] = w + 4 r for every r
+      // am[r] = tid % TM and ak[r] = tid / TM + (256 / TM) r for every r
       if (a.stepwise() && k0 + KS <= ke) {
         const int m = m0 + am[0];
         if (m < M) {
-          a.step(m, k0, ak[0], ra);
+          a.template step<KRA>(m, k0, ak[0], 256 / TM, ra);
         } else {
 #pragma unroll
-          for (int r = 0; r < KR; ++r) ra[r] = 0.0f;
+          for (int r = 0; r < KRA; ++r) ra[r] = 0.0f;
         }
         done = true;
       }
     }
+    if (!done) {
 #pragma unroll
-    for (int r = 0; r < KR; ++r) {
-      if (!done) {
+      for (int r = 0; r < KRA; ++r) {
         const int m = m0 + am[r], k = k0 + ak[r];
         ra[r] = (m < M && k < ke) ? a(m, k) : 0.0f;
       }
+    }
+#pragma unroll
+    for (int r = 0; r < KRB; ++r) {
       const int n = n0 + bn[r], k2 = k0 + bk[r];
       rb[r] = (n < N && k2 < ke) ? b(k2, n) : 0.0f;
     }
   };
   auto stash = [&](int st) {
 #pragma unroll
-    for (int r = 0; r < KR; ++r) {
-      as[st][ak[r]][am[r]] = ra[r];
-      bs[st][bk[r]][bn[r]] = rb[r];
-    }
+    for (int r = 0; r < KRA; ++r) as[st][ak[r]][am[r]] = ra[r];
+#pragma unroll
+    for (int r = 0; r < KRB; ++r) bs[st][bk[r]][bn[r]] = rb[r];
   };
   fetch(kb);
   stash(0);
@@ -112,12 +123,15 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
     if (more) fetch(k0 + KS);
 #pragma unroll
     for (int k4 = 0; k4 < KS; k4 += 4) {
-      const float a0 = as[st][k4 + q4][wm + r16], a1 = as[st][k4 + q4][wm + 16 + r16];
-      const float b0 = bs[st][k4 + q4][wn + r16], b1 = bs[st][k4 + q4][wn + 16 + r16];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      float av[TI], bv[TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) av[i] = as[st][k4 + q4][wm + 16 * i + r16];
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) bv[j] = bs[st][k4 + q4][wn + 16 * j + r16];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     if (more) stash(st ^ 1);
     __syncthreads();
@@ -126,17 +140,17 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
   if constexpr (out_quad<Out>()) {
     // the four accumulator rows of a lane (m = 4 g .. 4 g + 3) go out together
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < TJ; ++j) {
         const int m = m0 + wm + 16 * i + 4 * q4, n = n0 + wn + 16 * j + r16;
         if (m < M && n < N) out.quad(m, n, acc[i][j]);
       }
   } else {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < TJ; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int m = m0 + wm + 16 * i + 4 * q4 + r, n = n0 + wn + 16 * j + r16;
@@ -154,9 +168,9 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
 // Output pixels m = (b, y, x) row-major, or with QUAD ordered by 2 x 2
 // pooling quad, m = ((b, Y, X), q), pixel (2 Y + q / 2, 2 X + q % 2), so that
 // the four accumulator rows of a lane are one quad.  Offsets are 32-bit
-// (inputs below 2^31 elements).  For ci >= 16 a thread's KR values of a
-// 16-deep step (k = k0 + kw + 4 r) share one tap: one bounds test, and the
-// channels are 4 planes apart.
+// (inputs below 2^31 elements).  For ci >= 16 the values a thread loads in
+// one 16-deep step (k = k0 + kw + ks r, r < 16 / ks) share one tap: one
+// bounds test, and the channels are ks planes apart.
 template <bool QUAD>
 struct ConvFwdA {
   static constexpr bool KFAST = false;
@@ -183,16 +197,17 @@ struct ConvFwdA {
     return in[(unsigned)(((((bb << lci) + c) << lw) + yy) << lw) + (unsigned)xx];
   }
   __device__ bool stepwise() const { return lci >= 4; }
-  __device__ void step(int m, int k0, int kw, float* v) const {
+  template <int CNT>
+  __device__ void step(int m, int k0, int kw, int ks, float* v) const {
     int bb, y, x;
     pix(m, bb, y, x);
     const int t = k0 >> lci, c = (k0 & ((1 << lci) - 1)) + kw;
     const int yy = y + t / 3 - 1, xx = x + t % 3 - 1, w = 1 << lw;
     const bool inside = (unsigned)yy < (unsigned)w && (unsigned)xx < (unsigned)w;
     const unsigned base = (unsigned)(((((bb << lci) + c) << lw) + yy) << lw) + (unsigned)xx;
-    const unsigned plane4 = 4u << (2 * lw);
+    const unsigned plane = (unsigned)ks << (2 * lw);
 #pragma unroll
-    for (int r = 0; r < KR; ++r) v[r] = inside ? in[base + r * plane4] : 0.0f;
+    for (int r = 0; r < CNT; ++r) v[r] = inside ? in[base + r * plane] : 0.0f;
   }
 };
 // B(k, n) = weight of output channel n, input channel k % ci, tap k / ci
@@ -240,28 +255,45 @@ struct ConvReluOut {
   }
 };
 
-// data gradient, A(m = (b, y, x), k = (o, r)) = g[b][o][y - dy + 1][x - dx + 1]
+// data gradient, A(m = (b, y, x), k) = g[b][o][y - dy + 1][x - dx + 1] with
+// K tap-major as in the forward convolution: k = t co + o, t = 3 (dy + 1) +
+// (dx + 1).  32-bit offsets (gradients below 2^31 elements); for co >= 16 a
+// thread's values of one 16-deep step share one tap (one bounds test).
 struct ConvBwdDataA {
   static constexpr bool KFAST = false;
+  static constexpr bool STEP = true;
   const float* g;
-  int co, lw;
+  int lco, lw;  // lco = log2 co
   __device__ float operator()(int m, int k) const {
     const int w = 1 << lw;
     const int x = m & (w - 1), y = (m >> lw) & (w - 1), bb = m >> (2 * lw);
-    const int o = k / 9, r = k - 9 * o;
-    const int yy = y - r / 3 + 1, xx = x - r % 3 + 1;
+    const int t = k >> lco, o = k & ((1 << lco) - 1);
+    const int yy = y - t / 3 + 1, xx = x - t % 3 + 1;
     if ((unsigned)yy >= (unsigned)w || (unsigned)xx >= (unsigned)w) return 0.0f;
-    return g[(((size_t)bb * co + o) << (2 * lw)) + (yy << lw) + xx];
+    return g[(unsigned)(((((bb << lco) + o) << lw) + yy) << lw) + (unsigned)xx];
+  }
+  __device__ bool stepwise() const { return lco >= 4; }
+  template <int CNT>
+  __device__ void step(int m, int k0, int kw, int ks, float* v) const {
+    const int w = 1 << lw;
+    const int x = m & (w - 1), y = (m >> lw) & (w - 1), bb = m >> (2 * lw);
+    const int t = k0 >> lco, o = (k0 & ((1 << lco) - 1)) + kw;
+    const int yy = y - t / 3 + 1, xx = x - t % 3 + 1;
+    const bool inside = (unsigned)yy < (unsigned)w && (unsigned)xx < (unsigned)w;
+    const unsigned base = (unsigned)(((((bb << lco) + o) << lw) + yy) << lw) + (unsigned)xx;
+    const unsigned plane = (unsigned)ks << (2 * lw);
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) v[r] = inside ? g[base + r * plane] : 0.0f;
   }
 };
-// B(k = (o, r), n = c) = w[o][c][r]
+// B(k = t co + o, n = c) = w[o][c][t]
 struct WeightBwdData {
   static constexpr bool KFAST = false;
   const float* w;
-  int ci;
+  int ci, lco;
   __device__ float operator()(int k, int n) const {
-    const int o = k / 9, r = k - 9 * o;
-    return w[((size_t)o * ci + n) * 9 + r];
+    const int t = k >> lco, o = k & ((1 << lco) - 1);
+    return w[(unsigned)((o * ci + n) * 9 + t)];
   }
 };
 // out[b][n][y][x] = acc
@@ -349,12 +381,28 @@ static int k_slices(int K, int splits) {
 }
 
 template <class A, class Bm, class Out>
-static hipError_t gemm(A a, Bm b, Out out, int M, int N, int K, int splits, hipStream_t st) {
+static hipError_t gemm(A a, Bm b, Out out, int M, int N, int K, int splits, hipStream_t st, bool wide = false) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int kslice = k_slice(K, splits);
-  const int z = k_slices(K, splits);
-  dim3 grid((N + 63) / 64, (M + 63) / 64, z < 1 ? 1 : z);
-  hipLaunchKernelGGL((k_tgemm<A, Bm, Out>), grid, dim3(256), 0, st, a, b, out, M, N, K, kslice);
+  const int z = k_slices(K, splits) < 1 ? 1 : k_slices(K, splits);
+  // wide: 128-row tiles and as many columns (up to 128) as N fills, taken
+  // only while that grid still gives every compute unit two blocks (small
+  // batches keep the 64 x 64 tiles, which make four times as many blocks)
+  const int tn = N <= 32 ? 32 : N <= 64 ? 64 : 128;
+  if (wide && (int64_t)((N + tn - 1) / tn) * ((M + 127) / 128) * z < 512) wide = false;
+  if (wide && N <= 32) {
+    hipLaunchKernelGGL((k_tgemm<128, 32, A, Bm, Out>), dim3((N + 31) / 32, (M + 127) / 128, z), dim3(256), 0, st,
+                       a, b, out, M, N, K, kslice);
+  } else if (wide && N <= 64) {
+    hipLaunchKernelGGL((k_tgemm<128, 64, A, Bm, Out>), dim3((N + 63) / 64, (M + 127) / 128, z), dim3(256), 0, st,
+                       a, b, out, M, N, K, kslice);
+  } else if (wide) {
+    hipLaunchKernelGGL((k_tgemm<128, 128, A, Bm, Out>), dim3((N + 127) / 128, (M + 127) / 128, z), dim3(256), 0,
+                       st, a, b, out, M, N, K, kslice);
+  } else {
+    hipLaunchKernelGGL((k_tgemm<64, 64, A, Bm, Out>), dim3((N + 63) / 64, (M + 63) / 64, z), dim3(256), 0, st, a, b,
+                       out, M, N, K, kslice);
+  }
   return hipGetLastError();
 }
 
@@ -808,14 +856,14 @@ hipError_t forward(const float* params, const Layout& lay, const float* x, int64
     if (keep_relu) {
       // training keeps the full ReLU maps for the backward pass
       e = gemm(ConvFwdA<false>{a, ci, lci, lw}, WeightTap{params + lay.conv_w[i], K, lci},
-               ConvReluOut{act.r[i], params + lay.conv_b[i], co, lw}, M, co, K, 1, st);
+               ConvReluOut{act.r[i], params + lay.conv_b[i], co, lw}, M, co, K, 1, st, true);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k_pool_fwd, dim3(nb(bsz * co * (w / 2) * (w / 2))), dim3(256), 0, st, act.r[i],
                          (int64_t)(bsz * co), lw - 1, act.p[i]);
     } else {
       // inference pools in the product's epilogue: only the pooled maps are written
       e = gemm(ConvFwdA<true>{a, ci, lci, lw}, WeightTap{params + lay.conv_w[i], K, lci},
-               ConvReluPoolOut{act.p[i], params + lay.conv_b[i], co, lw - 1}, M, co, K, 1, st);
+               ConvReluPoolOut{act.p[i], params + lay.conv_b[i], co, lw - 1}, M, co, K, 1, st, true);
       if (e != hipSuccess) return e;
     }
     a = act.p[i];
@@ -823,7 +871,7 @@ hipError_t forward(const float* params, const Layout& lay, const float* x, int64
     w /= 2;
   }
   return gemm(RowK{a, kFeatures}, WeightT{params + lay.fc_w, kFeatures},
-              RowOut{act.logits, params + lay.fc_b, lay.classes}, (int)bsz, lay.classes, kFeatures, 1, st);
+              RowOut{act.logits, params + lay.fc_b, lay.classes}, (int)bsz, lay.classes, kFeatures, 1, st, true);
 }
 
 static int splits_for(int64_t k_len, int64_t tiles) {
@@ -845,7 +893,7 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
   hipLaunchKernelGGL(k_mean_loss, dim3(1), dim3(64), 0, st, loss_row, (int)bsz, loss);
   // fc: dW = dz^T f, db = column sums of dz, df = dz W
   e = gemm(ColK{act.dz, L}, BRowN{act.p[3], kFeatures}, RowOut{grad + lay.fc_w, nullptr, kFeatures}, L, kFeatures,
-           (int)bsz, 1, st);
+           (int)bsz, 1, st, true);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_col_sum, dim3(nb(L)), dim3(256), 0, st, act.dz, (int)bsz, L, grad + lay.fc_b);
   {
@@ -884,8 +932,8 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
       hipLaunchKernelGGL(k_channel_sum, dim3(nb(co)), dim3(256), 0, st, cpart, co, zs, grad + lay.conv_b[i]);
     }
     if (i > 0) {
-      e = gemm(ConvBwdDataA{act.g[i], co, lw}, WeightBwdData{params + lay.conv_w[i], ci},
-               NchwOut{act.dp[i - 1], ci, lw}, (int)(bsz * w * w), ci, co * 9, 1, st);
+      e = gemm(ConvBwdDataA{act.g[i], ilog2(co), lw}, WeightBwdData{params + lay.conv_w[i], ci, ilog2(co)},
+               NchwOut{act.dp[i - 1], ci, lw}, (int)(bsz * w * w), ci, co * 9, 1, st, true);
       if (e != hipSuccess) return e;
     }
     w *= 2;
