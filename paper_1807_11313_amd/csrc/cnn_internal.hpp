@@ -28,7 +28,7 @@ Layout layout_of(int n_classes);
 // pool, g[i] gradient at conv i's output (through ReLU), dp[i] gradient at
 // p[i]; logits and their gradient dz.
 struct Acts {
-  float* r[4];
+  uint8_t* arg[4];  // per pooled output: the quad position its gradient goes to (4: none)
   float* p[4];
   float* g[4];
   float* dp[4];
@@ -37,10 +37,10 @@ struct Acts {
 };
 
 hipError_t init_params(float* params, const Layout& lay, uint64_t seed, hipStream_t st);
-// keep_relu: also write the full ReLU maps act.r (training); otherwise each
-// convolution writes only its pooled map act.p (inference, same values)
+// Each convolution writes its pooled map act.p; train: also the gradient
+// positions act.arg that the backward pass needs
 hipError_t forward(const float* params, const Layout& lay, const float* x, int64_t bsz, const Acts& act,
-                   hipStream_t st, bool keep_relu = true);
+                   hipStream_t st, bool train = true);
 // Gradient of the mean cross-entropy into grad (all of it overwritten);
 // part: split-K scratch of part_floats floats; loss_row: [bsz] doubles.
 hipError_t backward(const float* params, const Layout& lay, const float* x, const int32_t* labels, int64_t bsz,

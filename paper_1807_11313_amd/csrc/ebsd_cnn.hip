@@ -138,33 +138,42 @@ int ensure_ws(ebsd_cnn_s* c, int64_t bsz, hipStream_t st) {
   if (c->ws) (void)hipFree(c->ws);
   c->ws = nullptr;
   c->ws_batch = 0;
+  // offsets in floats, each region rounded up to 64 floats
   size_t off = 0;
-  std::vector<std::pair<float**, size_t>> plan;
+  auto take = [&off](size_t floats) {
+    const size_t o = off;
+    off += (floats + 63) & ~size_t(63);
+    return o;
+  };
+  size_t o_arg[4], o_g[4], o_p[4], o_dp[4];
   int w = cnn::kInSize;
   for (int i = 0; i < 4; ++i) {
     const size_t full = (size_t)bsz * cnn::kChannels[i] * w * w;
     const size_t half = full / 4;
-    plan.push_back({&c->act.r[i], full});
-    plan.push_back({&c->act.g[i], full});
-    plan.push_back({&c->act.p[i], half});
-    plan.push_back({&c->act.dp[i], half});
+    o_arg[i] = take((half + 3) / 4);  // one byte per pooled output
+    o_g[i] = take(full);
+    o_p[i] = take(half);
+    o_dp[i] = take(half);
     w /= 2;
   }
-  plan.push_back({&c->act.logits, (size_t)bsz * c->lay.classes});
-  plan.push_back({&c->act.dz, (size_t)bsz * c->lay.classes});
-  plan.push_back({&c->part, kPartFloats});
-  for (auto& e : plan) off += (e.second + 63) & ~size_t(63);
+  const size_t o_logits = take((size_t)bsz * c->lay.classes);
+  const size_t o_dz = take((size_t)bsz * c->lay.classes);
+  const size_t o_part = take(kPartFloats);
   const size_t loss_bytes = sizeof(double) * (size_t)bsz;
   if (hipMalloc(&c->ws, off * sizeof(float) + loss_bytes) != hipSuccess)
     return fail(EBSD_E_NOMEM, "cnn workspace allocation failed");
   float* base = (float*)c->ws;
-  size_t pos = 0;
-  for (auto& e : plan) {
-    *e.first = base + pos;
-    pos += (e.second + 63) & ~size_t(63);
+  for (int i = 0; i < 4; ++i) {
+    c->act.arg[i] = reinterpret_cast<uint8_t*>(base + o_arg[i]);
+    c->act.g[i] = base + o_g[i];
+    c->act.p[i] = base + o_p[i];
+    c->act.dp[i] = base + o_dp[i];
   }
+  c->act.logits = base + o_logits;
+  c->act.dz = base + o_dz;
+  c->part = base + o_part;
   c->part_floats = kPartFloats;
-  c->loss_row = (double*)(base + pos);
+  c->loss_row = (double*)(base + off);
   c->ws_batch = bsz;
   return EBSD_OK;
 }

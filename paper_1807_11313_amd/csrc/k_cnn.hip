@@ -165,27 +165,21 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
 // Forward convolution, A(m, k) = the input pixel under tap t of channel c,
 // with K ordered tap-major: k = t ci + c, t = 3 (dy + 1) + (dx + 1) (the
 // weights are read in their stored [co][ci][3][3] order through WeightTap).
-// Output pixels m = (b, y, x) row-major, or with QUAD ordered by 2 x 2
-// pooling quad, m = ((b, Y, X), q), pixel (2 Y + q / 2, 2 X + q % 2), so that
-// the four accumulator rows of a lane are one quad.  Offsets are 32-bit
-// (inputs below 2^31 elements).  For ci >= 16 the values a thread loads in
-// one 16-deep step (k = k0 + kw + ks r, r < 16 / ks) share one tap: one
-// bounds test, and the channels are ks planes apart.
-template <bool QUAD>
+// Output pixels are ordered by 2 x 2 pooling quad, m = ((b, Y, X), q), pixel
+// (2 Y + q / 2, 2 X + q % 2), so that the four accumulator rows of a lane
+// are one quad.  Offsets are 32-bit (inputs below 2^31 elements).  For
+// ci >= 16 the values a thread loads in one 16-deep step (k = k0 + kw + ks r,
+// r < 16 / ks) share one tap: one bounds test, and the channels are ks
+// planes apart.
 struct ConvFwdA {
   static constexpr bool KFAST = false;
   static constexpr bool STEP = true;
   const float* in;
   int ci, lci, lw;  // lci = log2 ci
   __device__ void pix(int m, int& bb, int& y, int& x) const {
-    if constexpr (QUAD) {
-      const int lo = lw - 1, q = m & 3;
-      x = 2 * ((m >> 2) & ((1 << lo) - 1)) + (q & 1);
-      y = 2 * ((m >> (2 + lo)) & ((1 << lo) - 1)) + (q >> 1);
-    } else {
-      x = m & ((1 << lw) - 1);
-      y = (m >> lw) & ((1 << lw) - 1);
-    }
+    const int lo = lw - 1, q = m & 3;
+    x = 2 * ((m >> 2) & ((1 << lo) - 1)) + (q & 1);
+    y = 2 * ((m >> (2 + lo)) & ((1 << lo) - 1)) + (q >> 1);
     bb = m >> (2 * lw);
   }
   __device__ float operator()(int m, int k) const {
@@ -222,17 +216,30 @@ struct WeightTap {
 };
 // pooled[b][n][Y][X] = max over the quad of max(acc + bias[n], 0), which is
 // max(max over the quad of acc + bias[n], 0): adding the bias and clamping
-// are monotone, so the value equals the unfused ReLU then max-pool exactly
+// are monotone, so the value equals the unfused ReLU then max-pool exactly.
+// With arg (training), arg[b][n][Y][X] = the quad position the pooled
+// gradient flows back to: the first position q (order (0, 0), (0, 1),
+// (1, 0), (1, 1)) whose ReLU output equals the pooled value, if that value is
+// positive, else 4 (ReLU cut: no gradient).
 struct ConvReluPoolOut {
   static constexpr bool QUAD = true;
   float* out;
   const float* bias;
   int co, lw;  // lw: log2 of the pooled side
+  uint8_t* arg;
   __device__ void quad(int m, int n, const f4c& v) const {
     const int hw = 1 << (2 * lw);
     const int bb = (m >> 2) >> (2 * lw), p = (m >> 2) & (hw - 1);
+    const float b = bias[n];
     const float mx = fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3]));
-    out[((size_t)bb * co + n) * hw + p] = fmaxf(mx + bias[n], 0.0f);
+    const float pv = fmaxf(mx + b, 0.0f);
+    const unsigned o = (unsigned)((bb * co + n) << (2 * lw)) + (unsigned)p;
+    out[o] = pv;
+    if (arg) {
+      // v[q] + b == pv > 0 is max(v[q] + b, 0) == pv with a positive value
+      const int q = !(pv > 0.0f) ? 4 : v[0] + b == pv ? 0 : v[1] + b == pv ? 1 : v[2] + b == pv ? 2 : 3;
+      arg[o] = (uint8_t)q;
+    }
   }
   __device__ void operator()(int, int, float, int) const {}
 };
@@ -242,17 +249,6 @@ struct WeightT {
   const float* w;
   int k_len;
   __device__ float operator()(int k, int n) const { return w[(size_t)n * k_len + k]; }
-};
-// out[b][n][y][x] = max(acc + bias[n], 0)
-struct ConvReluOut {
-  float* out;
-  const float* bias;
-  int co, lw;
-  __device__ void operator()(int m, int n, float v, int) const {
-    const int hw = 1 << (2 * lw);
-    const int bb = m >> (2 * lw), p = m & (hw - 1);
-    out[((size_t)bb * co + n) * hw + p] = fmaxf(v + bias[n], 0.0f);
-  }
 };
 
 // data gradient, A(m = (b, y, x), k) = g[b][o][y - dy + 1][x - dx + 1] with
@@ -474,36 +470,20 @@ __global__ void k_col_sum(const float* __restrict__ a, int rows, int cols, float
   out[j] = s;
 }
 
-// 2 x 2 max pool of [planes][2h][2w] -> [planes][h][w]
-__global__ void k_pool_fwd(const float* __restrict__ in, int64_t planes, int lw_out, float* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int wo = 1 << lw_out;
-  if (i >= planes * wo * wo) return;
-  const int64_t pl = i >> (2 * lw_out);
-  const int y = (int)((i >> lw_out) & (wo - 1)), x = (int)(i & (wo - 1));
-  const float* p = in + (pl << (2 * lw_out + 2)) + (size_t)(2 * y) * (2 * wo) + 2 * x;
-  out[i] = fmaxf(fmaxf(p[0], p[1]), fmaxf(p[2 * wo], p[2 * wo + 1]));
-}
-
-// gradient through the pool (first maximal input) and the ReLU (r > 0)
-__global__ void k_pool_bwd(const float* __restrict__ r, const float* __restrict__ pooled,
-                           const float* __restrict__ dpool, int64_t planes, int lw_out, float* __restrict__ g) {
+// gradient through the ReLU and the 2 x 2 max pool: the pooled gradient goes to the
+// quad position arg recorded by the forward pass (4: to none of them)
+__global__ void k_unpool_bwd(const uint8_t* __restrict__ arg, const float* __restrict__ dpool, int64_t planes,
+                             int lw_out, float* __restrict__ g) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int wo = 1 << lw_out;
   if (i >= planes * wo * wo) return;
   const int64_t pl = i >> (2 * lw_out);
   const int y = (int)((i >> lw_out) & (wo - 1)), x = (int)(i & (wo - 1));
   const size_t base = (pl << (2 * lw_out + 2)) + (size_t)(2 * y) * (2 * wo) + 2 * x;
-  const size_t off[4] = {0, 1, (size_t)(2 * wo), (size_t)(2 * wo + 1)};
-  const float m = pooled[i], d = dpool[i];
-  bool done = false;
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const float v = r[base + off[t]];
-    const bool hit = !done && v == m;
-    done = done || hit;
-    g[base + off[t]] = (hit && v > 0.0f) ? d : 0.0f;
-  }
+  const int q = arg[i];
+  const float d = dpool[i];
+  *reinterpret_cast<float2*>(g + base) = float2{q == 0 ? d : 0.0f, q == 1 ? d : 0.0f};
+  *reinterpret_cast<float2*>(g + base + 2 * wo) = float2{q == 2 ? d : 0.0f, q == 3 ? d : 0.0f};
 }
 
 // softmax cross-entropy per row: loss_row[b], dz = (softmax - onehot) / B
@@ -843,9 +823,9 @@ hipError_t init_params(float* params, const Layout& lay, uint64_t seed, hipStrea
   return hipGetLastError();
 }
 
-// forward; act holds r_i, p_i (i = 0..3) and the logits
+// forward; act holds p_i (i = 0..3), in training arg_i, and the logits
 hipError_t forward(const float* params, const Layout& lay, const float* x, int64_t bsz, const Acts& act,
-                   hipStream_t st, bool keep_relu) {
+                   hipStream_t st, bool train) {
   const float* a = x;
   int ci = 1, w = kInSize;
   hipError_t e;
@@ -853,19 +833,12 @@ hipError_t forward(const float* params, const Layout& lay, const float* x, int64
     const int co = kChannels[i], lw = ilog2(w);
     const int M = (int)(bsz * w * w), K = ci * 9;
     const int lci = ilog2(ci);
-    if (keep_relu) {
-      // training keeps the full ReLU maps for the backward pass
-      e = gemm(ConvFwdA<false>{a, ci, lci, lw}, WeightTap{params + lay.conv_w[i], K, lci},
-               ConvReluOut{act.r[i], params + lay.conv_b[i], co, lw}, M, co, K, 1, st, true);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k_pool_fwd, dim3(nb(bsz * co * (w / 2) * (w / 2))), dim3(256), 0, st, act.r[i],
-                         (int64_t)(bsz * co), lw - 1, act.p[i]);
-    } else {
-      // inference pools in the product's epilogue: only the pooled maps are written
-      e = gemm(ConvFwdA<true>{a, ci, lci, lw}, WeightTap{params + lay.conv_w[i], K, lci},
-               ConvReluPoolOut{act.p[i], params + lay.conv_b[i], co, lw - 1}, M, co, K, 1, st, true);
-      if (e != hipSuccess) return e;
-    }
+    // each convolution pools in its epilogue: only the pooled maps (and, in
+    // training, the gradient positions) are written
+    e = gemm(ConvFwdA{a, ci, lci, lw}, WeightTap{params + lay.conv_w[i], K, lci},
+             ConvReluPoolOut{act.p[i], params + lay.conv_b[i], co, lw - 1, train ? act.arg[i] : nullptr}, M, co, K,
+             1, st, true);
+    if (e != hipSuccess) return e;
     a = act.p[i];
     ci = co;
     w /= 2;
@@ -914,7 +887,7 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
   for (int i = 3; i >= 0; --i) {
     const int co = kChannels[i], ci = i ? kChannels[i - 1] : 1, lw = ilog2(w);
     const float* in = i ? act.p[i - 1] : x;
-    hipLaunchKernelGGL(k_pool_bwd, dim3(nb(bsz * co * (w / 2) * (w / 2))), dim3(256), 0, st, act.r[i], act.p[i],
+    hipLaunchKernelGGL(k_unpool_bwd, dim3(nb(bsz * co * (w / 2) * (w / 2))), dim3(256), 0, st, act.arg[i],
                        act.dp[i], (int64_t)(bsz * co), lw - 1, act.g[i]);
     // weight gradient, split over (b, y, x)
     const int K = (int)(bsz * w * w), N = ci * 9;
