@@ -435,15 +435,18 @@ static void split_sum(const float* part, int z, int64_t mn, float* out, hipStrea
   else hipLaunchKernelGGL(k_split_sum<1>, dim3(blocks), dim3(64), 0, st, part, z, mn, out);
 }
 
-// partial sums over (b, pixel) of g[b][c][pixel]: block (c, z) sums images
-// z, z + Z, ... (bias gradient, first stage)
-__global__ __launch_bounds__(256) void k_channel_part(const float* __restrict__ g, int bsz, int c, int hw,
-                                                      int zs, double* __restrict__ part) {
+// Bias gradient of a convolution, the sum over (b, pixel) of g[b][c][pixel].
+// g is zero except at the recorded quad position of each pooled output,
+// where it is the pooled gradient, so the sum runs over the pooled maps:
+// block (c, z) sums images z, z + Z, ... of dpool where arg < 4 (first
+// stage, in double)
+__global__ __launch_bounds__(256) void k_channel_part(const uint8_t* __restrict__ arg, const float* __restrict__ dpool,
+                                                      int bsz, int c, int hw, int zs, double* __restrict__ part) {
   const int ch = blockIdx.x, z = blockIdx.y;
   double s = 0.0;
   for (int bb = z; bb < bsz; bb += zs) {
-    const float* p = g + ((size_t)bb * c + ch) * hw;
-    for (int i = threadIdx.x; i < hw; i += 256) s += p[i];
+    const size_t o = ((size_t)bb * c + ch) * hw;
+    for (int i = threadIdx.x; i < hw; i += 256) s += arg[o + i] < 4 ? dpool[o + i] : 0.0f;
   }
   s = wave_sum(s);
   __shared__ double red[4];
@@ -452,22 +455,34 @@ __global__ __launch_bounds__(256) void k_channel_part(const float* __restrict__ 
   if (threadIdx.x == 0) part[(size_t)ch * zs + z] = red[0] + red[1] + red[2] + red[3];
 }
 
-// second stage, in a fixed order: out[c] = sum_z part[c][z]
-__global__ void k_channel_sum(const double* __restrict__ part, int c, int zs, float* __restrict__ out) {
-  const int ch = blockIdx.x * 256 + threadIdx.x;
-  if (ch >= c) return;
-  double s = 0.0;
-  for (int z = 0; z < zs; ++z) s += part[(size_t)ch * zs + z];
-  out[ch] = (float)s;
+// second stage, one wave per channel (zs <= 64): out[c] = sum_z part[c][z]
+// by a fixed butterfly
+__global__ __launch_bounds__(64) void k_channel_sum(const double* __restrict__ part, int zs,
+                                                    float* __restrict__ out) {
+  const int ch = blockIdx.x, z = threadIdx.x;
+  const double s = wave_sum(z < zs ? part[(size_t)ch * zs + z] : 0.0);
+  if (z == 0) out[ch] = (float)s;
 }
 
-// column sums of a [rows][cols] matrix
-__global__ void k_col_sum(const float* __restrict__ a, int rows, int cols, float* __restrict__ out) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= cols) return;
+// column sums of a [rows][cols] matrix: a block takes 64 columns, thread
+// (x, y) of its 64 x 16 sums rows y, y + 16, ..., then the 16 partials are
+// added in order
+__global__ __launch_bounds__(1024) void k_col_sum(const float* __restrict__ a, int rows, int cols,
+                                                  float* __restrict__ out) {
+  __shared__ float red[16][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + tx;
   float s = 0.0f;
-  for (int r = 0; r < rows; ++r) s += a[(size_t)r * cols + j];
-  out[j] = s;
+  if (j < cols)
+    for (int r = ty; r < rows; r += 16) s += a[(size_t)r * cols + j];
+  red[ty][tx] = s;
+  __syncthreads();
+  if (ty == 0 && j < cols) {
+    float t = red[0][tx];
+#pragma unroll
+    for (int y = 1; y < 16; ++y) t += red[y][tx];
+    out[j] = t;
+  }
 }
 
 // gradient through the ReLU and the 2 x 2 max pool: the pooled gradient goes to the
@@ -487,39 +502,45 @@ __global__ void k_unpool_bwd(const uint8_t* __restrict__ arg, const float* __res
 }
 
 // softmax cross-entropy per row: loss_row[b], dz = (softmax - onehot) / B
-__global__ __launch_bounds__(256) void k_softmax_xent(const float* __restrict__ z, const int32_t* __restrict__ y,
-                                                      int l, int bsz, float* __restrict__ dz,
-                                                      double* __restrict__ loss_row) {
+__global__ __launch_bounds__(1024) void k_softmax_xent(const float* __restrict__ z, const int32_t* __restrict__ y,
+                                                       int l, int bsz, float* __restrict__ dz,
+                                                       double* __restrict__ loss_row) {
   const int bb = blockIdx.x;
   const float* zr = z + (size_t)bb * l;
-  __shared__ float redf[4];
-  __shared__ double redd[4];
+  __shared__ float redf[16];
+  __shared__ double redd[16];
   float mx = -INFINITY;
-  for (int i = threadIdx.x; i < l; i += 256) mx = fmaxf(mx, zr[i]);
+  for (int i = threadIdx.x; i < l; i += 1024) mx = fmaxf(mx, zr[i]);
   mx = wave_max(mx);
   if ((threadIdx.x & 63) == 0) redf[threadIdx.x >> 6] = mx;
   __syncthreads();
-  mx = fmaxf(fmaxf(redf[0], redf[1]), fmaxf(redf[2], redf[3]));
+  mx = redf[0];
+#pragma unroll
+  for (int k = 1; k < 16; ++k) mx = fmaxf(mx, redf[k]);
   double s = 0.0;
-  for (int i = threadIdx.x; i < l; i += 256) s += exp((double)(zr[i] - mx));
+  for (int i = threadIdx.x; i < l; i += 1024) s += exp((double)(zr[i] - mx));
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) redd[threadIdx.x >> 6] = s;
   __syncthreads();
-  s = redd[0] + redd[1] + redd[2] + redd[3];
+  s = redd[0];
+#pragma unroll
+  for (int k = 1; k < 16; ++k) s += redd[k];
   const int lab = y[bb];
   const float inv = 1.0f / (float)bsz;
-  for (int i = threadIdx.x; i < l; i += 256) {
+  for (int i = threadIdx.x; i < l; i += 1024) {
     const float p = (float)(exp((double)(zr[i] - mx)) / s);
     dz[(size_t)bb * l + i] = (p - (i == lab ? 1.0f : 0.0f)) * inv;
   }
   if (threadIdx.x == 0) loss_row[bb] = log(s) - (double)(zr[lab] - mx);
 }
 
-__global__ void k_mean_loss(const double* __restrict__ loss_row, int bsz, float* __restrict__ loss) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// mean of the per-row losses (lane sums, then a fixed butterfly)
+__global__ __launch_bounds__(64) void k_mean_loss(const double* __restrict__ loss_row, int bsz,
+                                                  float* __restrict__ loss) {
   double s = 0.0;
-  for (int i = 0; i < bsz; ++i) s += loss_row[i];
-  *loss = (float)(s / bsz);
+  for (int i = threadIdx.x; i < bsz; i += 64) s += loss_row[i];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) *loss = (float)(s / bsz);
 }
 
 // Adam (Kingma and Ba), bias-corrected step sizes precomputed on the host;
@@ -861,14 +882,14 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
                     hipStream_t st) {
   hipError_t e;
   const int L = lay.classes;
-  hipLaunchKernelGGL(k_softmax_xent, dim3((unsigned)bsz), dim3(256), 0, st, act.logits, labels, L, (int)bsz,
+  hipLaunchKernelGGL(k_softmax_xent, dim3((unsigned)bsz), dim3(1024), 0, st, act.logits, labels, L, (int)bsz,
                      act.dz, loss_row);
   hipLaunchKernelGGL(k_mean_loss, dim3(1), dim3(64), 0, st, loss_row, (int)bsz, loss);
   // fc: dW = dz^T f, db = column sums of dz, df = dz W
   e = gemm(ColK{act.dz, L}, BRowN{act.p[3], kFeatures}, RowOut{grad + lay.fc_w, nullptr, kFeatures}, L, kFeatures,
            (int)bsz, 1, st, true);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_col_sum, dim3(nb(L)), dim3(256), 0, st, act.dz, (int)bsz, L, grad + lay.fc_b);
+  hipLaunchKernelGGL(k_col_sum, dim3((L + 63) / 64), dim3(1024), 0, st, act.dz, (int)bsz, L, grad + lay.fc_b);
   {
     // df = dz W: few output tiles and a long K (= L), so K is split and the
     // partials are summed in a fixed order
@@ -901,8 +922,9 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
     {
       const int zs = (int)(bsz < 64 ? bsz : 64);
       double* cpart = reinterpret_cast<double*>(part);  // the weight-gradient partials are summed already
-      hipLaunchKernelGGL(k_channel_part, dim3(co, zs), dim3(256), 0, st, act.g[i], (int)bsz, co, w * w, zs, cpart);
-      hipLaunchKernelGGL(k_channel_sum, dim3(nb(co)), dim3(256), 0, st, cpart, co, zs, grad + lay.conv_b[i]);
+      hipLaunchKernelGGL(k_channel_part, dim3(co, zs), dim3(256), 0, st, act.arg[i], act.dp[i], (int)bsz, co,
+                         (w / 2) * (w / 2), zs, cpart);
+      hipLaunchKernelGGL(k_channel_sum, dim3(co), dim3(64), 0, st, cpart, zs, grad + lay.conv_b[i]);
     }
     if (i > 0) {
       e = gemm(ConvBwdDataA{act.g[i], ilog2(co), lw}, WeightBwdData{params + lay.conv_w[i], ci, ilog2(co)},
