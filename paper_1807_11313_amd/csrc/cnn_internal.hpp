@@ -30,7 +30,7 @@ Layout layout_of(int n_classes);
 struct Acts {
   uint8_t* arg[4];  // per pooled output: the quad position its gradient goes to (4: none)
   float* p[4];
-  float* g[4];
+  float* g[4];  // gradient maps of layers 1..3 (g[0] is never formed)
   float* dp[4];
   float* logits;
   float* dz;

@@ -151,7 +151,7 @@ int ensure_ws(ebsd_cnn_s* c, int64_t bsz, hipStream_t st) {
     const size_t full = (size_t)bsz * cnn::kChannels[i] * w * w;
     const size_t half = full / 4;
     o_arg[i] = take((half + 3) / 4);  // one byte per pooled output
-    o_g[i] = take(full);
+    o_g[i] = i ? take(full) : 0;  // the first layer's gradient map is never formed
     o_p[i] = take(half);
     o_dp[i] = take(half);
     w /= 2;
@@ -165,7 +165,7 @@ int ensure_ws(ebsd_cnn_s* c, int64_t bsz, hipStream_t st) {
   float* base = (float*)c->ws;
   for (int i = 0; i < 4; ++i) {
     c->act.arg[i] = reinterpret_cast<uint8_t*>(base + o_arg[i]);
-    c->act.g[i] = base + o_g[i];
+    c->act.g[i] = i ? base + o_g[i] : nullptr;
     c->act.p[i] = base + o_p[i];
     c->act.dp[i] = base + o_dp[i];
   }

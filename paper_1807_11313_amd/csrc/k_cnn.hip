@@ -485,6 +485,58 @@ __global__ __launch_bounds__(1024) void k_col_sum(const float* __restrict__ a, i
   }
 }
 
+// Weight gradient of the first convolution (one input channel, 64 x 64):
+// dW[o][t] = sum over (b, y, x) of g[b][o][y][x] in[b][y + dy - 1][x + dx - 1],
+// t = 3 dy + dx.  g is the pooled gradient at each pooled output's recorded
+// quad position and zero elsewhere, so the sum runs over the pooled maps.
+// Block (b, group of OG channels) stages image b with a zero border in LDS;
+// a thread takes pooled positions i, i + 256, ... of each channel, and the
+// block's nine sums per channel go to part[b][o][t] (fixed order: lanes,
+// then waves), summed over b afterwards.
+template <int OG>
+__global__ __launch_bounds__(256) void k_wgrad_first(const float* __restrict__ x, const uint8_t* __restrict__ arg,
+                                                     const float* __restrict__ dpool, int co,
+                                                     float* __restrict__ part) {
+  constexpr int W = kInSize, WP = W / 2, S = W + 2;
+  __shared__ float xs[S * S];
+  __shared__ float red[4][9];
+  const int bb = blockIdx.x, o0 = blockIdx.y * OG, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = tid; i < S * S; i += 256) {
+    const int yy = i / S - 1, xx = i % S - 1;
+    xs[i] = ((unsigned)yy < (unsigned)W && (unsigned)xx < (unsigned)W) ? x[((size_t)bb * W + yy) * W + xx] : 0.0f;
+  }
+  __syncthreads();
+  for (int oi = 0; oi < OG; ++oi) {
+    const int o = o0 + oi;
+    const size_t pl = ((size_t)bb * co + o) * (WP * WP);
+    float acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < WP * WP / 256; ++r) {
+      const int i = tid + 256 * r;
+      const int q = arg[pl + i];
+      const float d = q < 4 ? dpool[pl + i] : 0.0f;
+      // full-resolution pixel of the quad position (any position when q = 4:
+      // d = 0 there), shifted by the border
+      const int py = 2 * (i / WP) + ((q >> 1) & 1), px = 2 * (i % WP) + (q & 1);
+      const float* xp = xs + py * S + px;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) acc[t] = fmaf(d, xp[(t / 3) * S + t % 3], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      float v = acc[t];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) red[w][t] = v;
+    }
+    __syncthreads();
+    if (tid < 9) part[((size_t)bb * co + o) * 9 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+    __syncthreads();
+  }
+}
+
 // gradient through the ReLU and the 2 x 2 max pool: the pooled gradient goes to the
 // quad position arg recorded by the forward pass (4: to none of them)
 __global__ void k_unpool_bwd(const uint8_t* __restrict__ arg, const float* __restrict__ dpool, int64_t planes,
@@ -908,17 +960,27 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
   for (int i = 3; i >= 0; --i) {
     const int co = kChannels[i], ci = i ? kChannels[i - 1] : 1, lw = ilog2(w);
     const float* in = i ? act.p[i - 1] : x;
-    hipLaunchKernelGGL(k_unpool_bwd, dim3(nb(bsz * co * (w / 2) * (w / 2))), dim3(256), 0, st, act.arg[i],
-                       act.dp[i], (int64_t)(bsz * co), lw - 1, act.g[i]);
-    // weight gradient, split over (b, y, x)
-    const int K = (int)(bsz * w * w), N = ci * 9;
-    const int64_t tiles = (int64_t)((co + 63) / 64) * ((N + 63) / 64);
-    int s = splits_for(K, tiles);
-    while ((size_t)s * co * N > part_floats && s > 1) s = (s + 1) / 2;
-    const int z = k_slices(K, s);
-    e = gemm(ConvBwdWA{act.g[i], co, lw}, ConvBwdWB{in, ci, lw}, SplitOut{part, co, N}, co, N, K, s, st);
-    if (e != hipSuccess) return e;
-    split_sum(part, z, (int64_t)co * N, grad + lay.conv_w[i], st);
+    if (i == 0) {
+      // the first layer needs no input gradient: its weight gradient reads
+      // the pooled gradient directly, and g_0 is never formed
+      static_assert(kChannels[0] % 8 == 0 && (kInSize / 2) * (kInSize / 2) % 256 == 0, "first-layer shape");
+      if ((size_t)bsz * co * 9 > part_floats) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_wgrad_first<8>, dim3((unsigned)bsz, co / 8), dim3(256), 0, st, x, act.arg[0], act.dp[0],
+                         co, part);
+      split_sum(part, (int)bsz, (int64_t)co * 9, grad + lay.conv_w[0], st);
+    } else {
+      hipLaunchKernelGGL(k_unpool_bwd, dim3(nb(bsz * co * (w / 2) * (w / 2))), dim3(256), 0, st, act.arg[i],
+                         act.dp[i], (int64_t)(bsz * co), lw - 1, act.g[i]);
+      // weight gradient, split over (b, y, x)
+      const int K = (int)(bsz * w * w), N = ci * 9;
+      const int64_t tiles = (int64_t)((co + 63) / 64) * ((N + 63) / 64);
+      int s = splits_for(K, tiles);
+      while ((size_t)s * co * N > part_floats && s > 1) s = (s + 1) / 2;
+      const int z = k_slices(K, s);
+      e = gemm(ConvBwdWA{act.g[i], co, lw}, ConvBwdWB{in, ci, lw}, SplitOut{part, co, N}, co, N, K, s, st);
+      if (e != hipSuccess) return e;
+      split_sum(part, z, (int64_t)co * N, grad + lay.conv_w[i], st);
+    }
     {
       const int zs = (int)(bsz < 64 ? bsz : 64);
       double* cpart = reinterpret_cast<double*>(part);  // the weight-gradient partials are summed already
