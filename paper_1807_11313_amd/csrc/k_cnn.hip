@@ -36,13 +36,14 @@ template <class T>
 struct OutQuad<T, std::void_t<decltype(T::QUAD)>> : std::bool_constant<T::QUAD> {};
 template <class Out>
 constexpr bool out_quad() { return OutQuad<Out>::value; }
-// A operand maps with a whole-step fetch (STEP): the values k0 + kw + ks r of
-// one row m (with KFAST false a thread holds one row of the A tile and
-// k = kw + ks r, ks = 256 / TM)
+// operand maps with a whole-step fetch (STEP).  A with KFAST false: the
+// values k0 + kw + ks r of one row m (a thread holds one row of the A tile,
+// k = kw + ks r, ks = 256 / TM), step().  KFAST operands (A or B): the values
+// of one k at rows (columns) m, m + 256 / KS, ..., stepk()
 template <class T, class = void>
-struct AStep : std::false_type {};
+struct HasStep : std::false_type {};
 template <class T>
-struct AStep<T, std::void_t<decltype(T::STEP)>> : std::bool_constant<T::STEP> {};
+struct HasStep<T, std::void_t<decltype(T::STEP)>> : std::bool_constant<T::STEP> {};
 
 template <int TM, int TN, class A, class Bm, class Out>
 __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N, int K, int kslice) {
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
   float ra[KRA], rb[KRB];
   auto fetch = [&](int k0) {
     bool done = false;
-    if constexpr (AStep<A>::value && !A::KFAST) {
+    if constexpr (HasStep<A>::value && !A::KFAST) {
       // am[r] = tid % TM and ak[r] = tid / TM + (256 / TM) r for every r
       if (a.stepwise() && k0 + KS <= ke) {
         const int m = m0 + am[0];
@@ -95,6 +96,13 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
         done = true;
       }
     }
+    if constexpr (HasStep<A>::value && A::KFAST) {
+      // am[r] = tid / KS + (256 / KS) r and ak[r] = tid % KS for every r
+      if (k0 + KS <= ke && m0 + TM <= M && a.stepwise(TM)) {
+        a.template stepk<KRA>(m0 + am[0], k0 + ak[0], 256 / KS, ra);
+        done = true;
+      }
+    }
     if (!done) {
 #pragma unroll
       for (int r = 0; r < KRA; ++r) {
@@ -102,10 +110,20 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
         ra[r] = (m < M && k < ke) ? a(m, k) : 0.0f;
       }
     }
+    bool bdone = false;
+    if constexpr (HasStep<Bm>::value && Bm::KFAST) {
+      // bn[r] = tid / KS + (256 / KS) r and bk[r] = tid % KS for every r
+      if (k0 + KS <= ke && n0 + TN <= N && b.stepwise(TN)) {
+        b.template stepk<KRB>(n0 + bn[0], k0 + bk[0], 256 / KS, rb);
+        bdone = true;
+      }
+    }
+    if (!bdone) {
 #pragma unroll
-    for (int r = 0; r < KRB; ++r) {
-      const int n = n0 + bn[r], k2 = k0 + bk[r];
-      rb[r] = (n < N && k2 < ke) ? b(k2, n) : 0.0f;
+      for (int r = 0; r < KRB; ++r) {
+        const int n = n0 + bn[r], k2 = k0 + bk[r];
+        rb[r] = (n < N && k2 < ke) ? b(k2, n) : 0.0f;
+      }
     }
   };
   auto stash = [&](int st) {
@@ -303,29 +321,57 @@ struct NchwOut {
   }
 };
 
-// weight gradient, A(m = o, k = (b, y, x)) = g[b][o][y][x]
+// weight gradient, A(m = o, k = (b, y, x)) = g[b][o][y][x] (32-bit offsets:
+// gradients below 2^31 elements).  Whole-step fetch: a thread's values of a
+// step share k and lie ms rows apart.
 struct ConvBwdWA {
   static constexpr bool KFAST = true;
+  static constexpr bool STEP = true;
   const float* g;
   int co, lw;
   __device__ float operator()(int m, int k) const {
     const int hw = 1 << (2 * lw);
-    const int bb = k >> (2 * lw), p = k & (hw - 1);
-    return g[((size_t)bb * co + m) * hw + p];
+    return g[((unsigned)((k >> (2 * lw)) * co + m) << (2 * lw)) + (unsigned)(k & (hw - 1))];
+  }
+  __device__ bool stepwise(int) const { return true; }
+  template <int CNT>
+  __device__ void stepk(int m, int k, int ms, float* v) const {
+    const int hw = 1 << (2 * lw);
+    const unsigned base = ((unsigned)((k >> (2 * lw)) * co + m) << (2 * lw)) + (unsigned)(k & (hw - 1));
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) v[r] = g[base + (unsigned)(r * ms) * (unsigned)hw];
   }
 };
-// B(k = (b, y, x), n = (c, r)) = in[b][c][y + dy - 1][x + dx - 1]
+// B(k = (b, y, x), n) = in[b][c][y + dy - 1][x + dx - 1] with N tap-major,
+// n = t ci + c, t = 3 dy + dx (the partial sums are put back into the stored
+// [co][ci][3][3] order by the split sum).  When ci is a multiple of the tile
+// width, a thread's values of a step (n, n + ns, ...) share one tap: one
+// bounds test, channels ns planes apart.
 struct ConvBwdWB {
   static constexpr bool KFAST = true;
+  static constexpr bool STEP = true;
   const float* in;
-  int ci, lw;
+  int lci, lw;  // lci = log2 ci
   __device__ float operator()(int k, int n) const {
     const int w = 1 << lw;
     const int x = k & (w - 1), y = (k >> lw) & (w - 1), bb = k >> (2 * lw);
-    const int c = n / 9, r = n - 9 * c;
-    const int yy = y + r / 3 - 1, xx = x + r % 3 - 1;
+    const int t = n >> lci, c = n & ((1 << lci) - 1);
+    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
     if ((unsigned)yy >= (unsigned)w || (unsigned)xx >= (unsigned)w) return 0.0f;
-    return in[(((size_t)bb * ci + c) << (2 * lw)) + (yy << lw) + xx];
+    return in[(unsigned)(((((bb << lci) + c) << lw) + yy) << lw) + (unsigned)xx];
+  }
+  __device__ bool stepwise(int tn) const { return (1 << lci) >= tn; }
+  template <int CNT>
+  __device__ void stepk(int n, int k, int ns, float* v) const {
+    const int w = 1 << lw;
+    const int x = k & (w - 1), y = (k >> lw) & (w - 1), bb = k >> (2 * lw);
+    const int t = n >> lci, c = n & ((1 << lci) - 1);
+    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+    const bool inside = (unsigned)yy < (unsigned)w && (unsigned)xx < (unsigned)w;
+    const unsigned base = (unsigned)(((((bb << lci) + c) << lw) + yy) << lw) + (unsigned)xx;
+    const unsigned plane = (unsigned)ns << (2 * lw);
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) v[r] = inside ? in[base + r * plane] : 0.0f;
   }
 };
 // partial[z][m][n] = acc (split K, summed in a fixed order afterwards)
@@ -406,18 +452,25 @@ static hipError_t gemm(A a, Bm b, Out out, int M, int N, int K, int splits, hipS
 // groups of 64 threads, group g taking the partials k = g, g + G, ...; the
 // groups' sums are then added in group order (a fixed order, as the split
 // itself is fixed).  G = 16 when the split is long (few outputs, many
-// partials: the first layer's weight gradient), else 1.
+// partials), else 1.  With nt > 0 the columns of part are tap-major, n =
+// t ci + c (ci = 2^lci, nt = 9 ci), and go out in [c][t] order.
 template <int G>
 __global__ __launch_bounds__(64 * G) void k_split_sum(const float* __restrict__ part, int z, int64_t mn,
-                                                      float* __restrict__ out) {
+                                                      float* __restrict__ out, int nt, int lci) {
   __shared__ float acc[G][64];
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   float s = 0.0f;
   if (i < mn)
     for (int k = g; k < z; k += G) s += part[(size_t)k * mn + i];
+  int64_t o = i;
+  if (nt > 0) {
+    const int64_t m = i / nt;
+    const int n = (int)(i - m * nt), t = n >> lci, c = n & ((1 << lci) - 1);
+    o = m * nt + c * 9 + t;
+  }
   if constexpr (G == 1) {
-    if (i < mn) out[i] = s;
+    if (i < mn) out[o] = s;
   } else {
     acc[g][lane] = s;
     __syncthreads();
@@ -425,14 +478,14 @@ __global__ __launch_bounds__(64 * G) void k_split_sum(const float* __restrict__ 
       float t = acc[0][lane];
 #pragma unroll
       for (int h = 1; h < G; ++h) t += acc[h][lane];
-      out[i] = t;
+      out[o] = t;
     }
   }
 }
-static void split_sum(const float* part, int z, int64_t mn, float* out, hipStream_t st) {
+static void split_sum(const float* part, int z, int64_t mn, float* out, hipStream_t st, int nt = 0, int lci = 0) {
   const unsigned blocks = (unsigned)((mn + 63) / 64);
-  if (z >= 64) hipLaunchKernelGGL(k_split_sum<16>, dim3(blocks), dim3(1024), 0, st, part, z, mn, out);
-  else hipLaunchKernelGGL(k_split_sum<1>, dim3(blocks), dim3(64), 0, st, part, z, mn, out);
+  if (z >= 64) hipLaunchKernelGGL(k_split_sum<16>, dim3(blocks), dim3(1024), 0, st, part, z, mn, out, nt, lci);
+  else hipLaunchKernelGGL(k_split_sum<1>, dim3(blocks), dim3(64), 0, st, part, z, mn, out, nt, lci);
 }
 
 // Bias gradient of a convolution, the sum over (b, pixel) of g[b][c][pixel].
@@ -977,9 +1030,9 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
       int s = splits_for(K, tiles);
       while ((size_t)s * co * N > part_floats && s > 1) s = (s + 1) / 2;
       const int z = k_slices(K, s);
-      e = gemm(ConvBwdWA{act.g[i], co, lw}, ConvBwdWB{in, ci, lw}, SplitOut{part, co, N}, co, N, K, s, st);
+      e = gemm(ConvBwdWA{act.g[i], co, lw}, ConvBwdWB{in, ilog2(ci), lw}, SplitOut{part, co, N}, co, N, K, s, st);
       if (e != hipSuccess) return e;
-      split_sum(part, z, (int64_t)co * N, grad + lay.conv_w[i], st);
+      split_sum(part, z, (int64_t)co * N, grad + lay.conv_w[i], st, N, ilog2(ci));
     }
     {
       const int zs = (int)(bsz < 64 ? bsz : 64);
