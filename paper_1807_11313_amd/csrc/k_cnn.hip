@@ -137,8 +137,13 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
   __syncthreads();
   int st = 0;
   for (int k0 = kb; k0 < ke; k0 += KS) {
-    const bool more = k0 + KS < ke;
-    if (more) fetch(k0 + KS);
+    // the next step's fetch and stash run unconditionally: past the end of
+    // the slice every bounds test fails and zeros go to the stage nobody
+    // reads again.  With a conditional stash the loads of one step could
+    // still count as outstanding at the next step's zero-filled registers,
+    // and each step would wait for its own A loads before it issued the B
+    // loads and its products.
+    fetch(k0 + KS);
 #pragma unroll
     for (int k4 = 0; k4 < KS; k4 += 4) {
       float av[TI], bv[TJ];
@@ -151,7 +156,7 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
 #pragma unroll
         for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
-    if (more) stash(st ^ 1);
+    stash(st ^ 1);
     __syncthreads();
     st ^= 1;
   }
