@@ -24,9 +24,19 @@ struct Layout {
 };
 Layout layout_of(int n_classes);
 
-// Activations of a batch: r[i] conv i output after ReLU, p[i] after the
-// pool, g[i] gradient at conv i's output (through ReLU), dp[i] gradient at
-// p[i]; logits and their gradient dz.
+// The convolution weights in tap-major rows, wt_i[o][t ci + c] = w_i[o][c][t]
+// (t = 3 dy + dx), layers one after another: offset of layer i and the total.
+constexpr int64_t tap_weights_offset(int i) {
+  int64_t off = 0;
+  for (int l = 0, ci = 1; l < i; ci = kChannels[l], ++l) off += (int64_t)kChannels[l] * ci * 9;
+  return off;
+}
+constexpr int64_t kTapWeights = tap_weights_offset(4);
+
+// Activations of a batch: p[i] conv i output after ReLU and the pool,
+// arg[i] the gradient positions of its pool, g[i] gradient at conv i's
+// output (through ReLU), dp[i] gradient at p[i]; logits and their gradient
+// dz; wt the tap-major copy of the convolution weights.
 struct Acts {
   uint8_t* arg[4];  // per pooled output: the quad position its gradient goes to (4: none)
   float* p[4];
@@ -34,14 +44,17 @@ struct Acts {
   float* dp[4];
   float* logits;
   float* dz;
+  float* wt;
 };
 
 hipError_t init_params(float* params, const Layout& lay, uint64_t seed, hipStream_t st);
-// Each convolution writes its pooled map act.p; train: also the gradient
-// positions act.arg that the backward pass needs
+// Writes the tap-major weights act.wt, then each convolution its pooled map
+// act.p; train: also the gradient positions act.arg that the backward pass
+// needs
 hipError_t forward(const float* params, const Layout& lay, const float* x, int64_t bsz, const Acts& act,
                    hipStream_t st, bool train = true);
-// Gradient of the mean cross-entropy into grad (all of it overwritten);
+// Gradient of the mean cross-entropy into grad (all of it overwritten), from
+// act as the training forward pass on the same parameters left it;
 // part: split-K scratch of part_floats floats; loss_row: [bsz] doubles.
 hipError_t backward(const float* params, const Layout& lay, const float* x, const int32_t* labels, int64_t bsz,
                     const Acts& act, float* grad, float* part, size_t part_floats, double* loss_row, float* loss,

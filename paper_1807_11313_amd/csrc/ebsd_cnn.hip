@@ -159,6 +159,7 @@ int ensure_ws(ebsd_cnn_s* c, int64_t bsz, hipStream_t st) {
   const size_t o_logits = take((size_t)bsz * c->lay.classes);
   const size_t o_dz = take((size_t)bsz * c->lay.classes);
   const size_t o_part = take(kPartFloats);
+  const size_t o_wt = take((size_t)cnn::kTapWeights);
   const size_t loss_bytes = sizeof(double) * (size_t)bsz;
   if (hipMalloc(&c->ws, off * sizeof(float) + loss_bytes) != hipSuccess)
     return fail(EBSD_E_NOMEM, "cnn workspace allocation failed");
@@ -172,6 +173,7 @@ int ensure_ws(ebsd_cnn_s* c, int64_t bsz, hipStream_t st) {
   c->act.logits = base + o_logits;
   c->act.dz = base + o_dz;
   c->part = base + o_part;
+  c->act.wt = base + o_wt;
   c->part_floats = kPartFloats;
   c->loss_row = (double*)(base + off);
   c->ws_batch = bsz;

@@ -29,6 +29,14 @@ typedef float f4c __attribute__((ext_vector_type(4)));
 #endif
 constexpr int KS = EBSD_TGEMM_KS;  // K depth of one step
 
+// p[i] through a 32-bit byte offset from the (uniform) base, so that the
+// load takes the base from scalar registers and one 32-bit offset per lane.
+// Operands stay below 2^30 elements: batches of at most 4,096 patterns make
+// the largest (the second layer's gradient map) 2^28.
+__device__ __forceinline__ float ld32(const float* p, unsigned i) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(p) + (i << 2));
+}
+
 // output maps that take a lane's four consecutive rows at once (QUAD)
 template <class T, class = void>
 struct OutQuad : std::false_type {};
@@ -36,10 +44,11 @@ template <class T>
 struct OutQuad<T, std::void_t<decltype(T::QUAD)>> : std::bool_constant<T::QUAD> {};
 template <class Out>
 constexpr bool out_quad() { return OutQuad<Out>::value; }
-// operand maps with a whole-step fetch (STEP).  A with KFAST false: the
-// values k0 + kw + ks r of one row m (a thread holds one row of the A tile,
-// k = kw + ks r, ks = 256 / TM), step().  KFAST operands (A or B): the values
-// of one k at rows (columns) m, m + 256 / KS, ..., stepk()
+// operand maps with a whole-step fetch (STEP), taken when stepwise(tile
+// width) holds and the step and tile are whole.  KFAST false: a thread holds
+// one row m (column n) of the tile and the values k0 + kw + ks r, ks = 256 /
+// TM (TN), step().  KFAST true: the values of one k at rows (columns) m,
+// m + 256 / KS, ..., stepk()
 template <class T, class = void>
 struct HasStep : std::false_type {};
 template <class T>
@@ -81,49 +90,47 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
     bk[r] = Bm::KFAST ? idx % KS : idx / TN;
   }
   float ra[KRA], rb[KRB];
-  auto fetch = [&](int k0) {
-    bool done = false;
-    if constexpr (HasStep<A>::value && !A::KFAST) {
-      // am[r] = tid % TM and ak[r] = tid / TM + (256 / TM) r for every r
-      if (a.stepwise() && k0 + KS <= ke) {
-        const int m = m0 + am[0];
-        if (m < M) {
-          a.template step<KRA>(m, k0, ak[0], 256 / TM, ra);
-        } else {
+  // Whole-step fetches (see HasStep) for both operands, taken for every step
+  // when the block's tile is whole and its K slice a whole number of steps;
+  // otherwise every value goes through the bounds-tested maps.  The two loops
+  // are compiled apart so that the bounds-tested path adds nothing (such as
+  // its strength-reduced addresses) to the whole-step loop.
+  auto fetch_steps = [&](int k0) {
+    if (k0 >= ke) {
+      // past the end: zeros for the stage nobody reads again
 #pragma unroll
-          for (int r = 0; r < KRA; ++r) ra[r] = 0.0f;
-        }
-        done = true;
-      }
+      for (int r = 0; r < KRA; ++r) ra[r] = 0.0f;
+#pragma unroll
+      for (int r = 0; r < KRB; ++r) rb[r] = 0.0f;
+      return;
     }
-    if constexpr (HasStep<A>::value && A::KFAST) {
-      // am[r] = tid / KS + (256 / KS) r and ak[r] = tid % KS for every r
-      if (k0 + KS <= ke && m0 + TM <= M && a.stepwise(TM)) {
+    if constexpr (HasStep<A>::value && HasStep<Bm>::value) {
+      if constexpr (A::KFAST) {
+        // am[r] = tid / KS + (256 / KS) r and ak[r] = tid % KS for every r
         a.template stepk<KRA>(m0 + am[0], k0 + ak[0], 256 / KS, ra);
-        done = true;
+      } else {
+        // am[r] = tid % TM and ak[r] = tid / TM + (256 / TM) r for every r
+        a.template step<KRA>(m0 + am[0], k0, ak[0], 256 / TM, ra);
       }
-    }
-    if (!done) {
-#pragma unroll
-      for (int r = 0; r < KRA; ++r) {
-        const int m = m0 + am[r], k = k0 + ak[r];
-        ra[r] = (m < M && k < ke) ? a(m, k) : 0.0f;
-      }
-    }
-    bool bdone = false;
-    if constexpr (HasStep<Bm>::value && Bm::KFAST) {
-      // bn[r] = tid / KS + (256 / KS) r and bk[r] = tid % KS for every r
-      if (k0 + KS <= ke && n0 + TN <= N && b.stepwise(TN)) {
+      if constexpr (Bm::KFAST) {
+        // bn[r] = tid / KS + (256 / KS) r and bk[r] = tid % KS for every r
         b.template stepk<KRB>(n0 + bn[0], k0 + bk[0], 256 / KS, rb);
-        bdone = true;
+      } else {
+        // bn[r] = tid % TN and bk[r] = tid / TN + (256 / TN) r for every r
+        b.template step<KRB>(n0 + bn[0], k0, bk[0], 256 / TN, rb);
       }
     }
-    if (!bdone) {
+  };
+  auto fetch_tested = [&](int k0) {
 #pragma unroll
-      for (int r = 0; r < KRB; ++r) {
-        const int n = n0 + bn[r], k2 = k0 + bk[r];
-        rb[r] = (n < N && k2 < ke) ? b(k2, n) : 0.0f;
-      }
+    for (int r = 0; r < KRA; ++r) {
+      const int m = m0 + am[r], k = k0 + ak[r];
+      ra[r] = (m < M && k < ke) ? a(m, k) : 0.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < KRB; ++r) {
+      const int n = n0 + bn[r], k2 = k0 + bk[r];
+      rb[r] = (n < N && k2 < ke) ? b(k2, n) : 0.0f;
     }
   };
   auto stash = [&](int st) {
@@ -132,34 +139,50 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
 #pragma unroll
     for (int r = 0; r < KRB; ++r) bs[st][bk[r]][bn[r]] = rb[r];
   };
-  fetch(kb);
-  stash(0);
-  __syncthreads();
-  int st = 0;
-  for (int k0 = kb; k0 < ke; k0 += KS) {
-    // the next step's fetch and stash run unconditionally: past the end of
-    // the slice every bounds test fails and zeros go to the stage nobody
-    // reads again.  With a conditional stash the loads of one step could
-    // still count as outstanding at the next step's zero-filled registers,
-    // and each step would wait for its own A loads before it issued the B
-    // loads and its products.
-    fetch(k0 + KS);
-#pragma unroll
-    for (int k4 = 0; k4 < KS; k4 += 4) {
-      float av[TI], bv[TJ];
-#pragma unroll
-      for (int i = 0; i < TI; ++i) av[i] = as[st][k4 + q4][wm + 16 * i + r16];
-#pragma unroll
-      for (int j = 0; j < TJ; ++j) bv[j] = bs[st][k4 + q4][wn + 16 * j + r16];
-#pragma unroll
-      for (int i = 0; i < TI; ++i)
-#pragma unroll
-        for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
-    }
-    stash(st ^ 1);
+  auto run = [&](auto whole) {
+    constexpr bool W = decltype(whole)::value;
+    auto fetch = [&](int k0) {
+      if constexpr (W) fetch_steps(k0);
+      else fetch_tested(k0);
+    };
+    fetch(kb);
+    stash(0);
     __syncthreads();
-    st ^= 1;
+    int st = 0;
+    for (int k0 = kb; k0 < ke; k0 += KS) {
+      // the next step's fetch and stash run unconditionally: past the end of
+      // the slice zeros go to the stage nobody reads again.  With a
+      // conditional stash the loads of one step could still count as
+      // outstanding at the next step's zero-filled registers, and each step
+      // would wait for its own A loads before it issued the B loads and its
+      // products.
+      fetch(k0 + KS);
+#pragma unroll
+      for (int k4 = 0; k4 < KS; k4 += 4) {
+        float av[TI], bv[TJ];
+#pragma unroll
+        for (int i = 0; i < TI; ++i) av[i] = as[st][k4 + q4][wm + 16 * i + r16];
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) bv[j] = bs[st][k4 + q4][wn + 16 * j + r16];
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+      }
+      stash(st ^ 1);
+      __syncthreads();
+      st ^= 1;
+    }
+  };
+  bool whole = false;
+  if constexpr (HasStep<A>::value && HasStep<Bm>::value) {
+    // a thread's A row (KFAST false) past M reads nothing: the whole tile is
+    // required for both orders
+    whole = (ke - kb) % KS == 0 && m0 + TM <= M && n0 + TN <= N && a.stepwise(TM) && b.stepwise(TN);
   }
+  if (whole) run(std::true_type{});
+  else run(std::false_type{});
   if constexpr (out_quad<Out>()) {
     // the four accumulator rows of a lane (m = 4 g .. 4 g + 3) go out together
 #pragma unroll
@@ -190,7 +213,7 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
 // weights are read in their stored [co][ci][3][3] order through WeightTap).
 // Output pixels are ordered by 2 x 2 pooling quad, m = ((b, Y, X), q), pixel
 // (2 Y + q / 2, 2 X + q % 2), so that the four accumulator rows of a lane
-// are one quad.  Offsets are 32-bit (inputs below 2^31 elements).  For
+// are one quad.  Offsets are 32-bit (inputs below 2^30 elements).  For
 // ci >= 16 the values a thread loads in one 16-deep step (k = k0 + kw + ks r,
 // r < 16 / ks) share one tap: one bounds test, and the channels are ks
 // planes apart.
@@ -213,7 +236,7 @@ struct ConvFwdA {
     if ((unsigned)yy >= (unsigned)w || (unsigned)xx >= (unsigned)w) return 0.0f;
     return in[(unsigned)(((((bb << lci) + c) << lw) + yy) << lw) + (unsigned)xx];
   }
-  __device__ bool stepwise() const { return lci >= 4; }
+  __device__ bool stepwise(int) const { return lci >= 4; }
   template <int CNT>
   __device__ void step(int m, int k0, int kw, int ks, float* v) const {
     int bb, y, x;
@@ -224,17 +247,7 @@ struct ConvFwdA {
     const unsigned base = (unsigned)(((((bb << lci) + c) << lw) + yy) << lw) + (unsigned)xx;
     const unsigned plane = (unsigned)ks << (2 * lw);
 #pragma unroll
-    for (int r = 0; r < CNT; ++r) v[r] = inside ? in[base + r * plane] : 0.0f;
-  }
-};
-// B(k, n) = weight of output channel n, input channel k % ci, tap k / ci
-// (weights [co][ci][3][3]), for the tap-major K of ConvFwdA
-struct WeightTap {
-  static constexpr bool KFAST = true;
-  const float* w;
-  int k_len, lci;
-  __device__ float operator()(int k, int n) const {
-    return w[(unsigned)(n * k_len) + (unsigned)((k & ((1 << lci) - 1)) * 9 + (k >> lci))];
+    for (int r = 0; r < CNT; ++r) v[r] = inside ? ld32(in, base + r * plane) : 0.0f;
   }
 };
 // pooled[b][n][Y][X] = max over the quad of max(acc + bias[n], 0), which is
@@ -266,17 +279,26 @@ struct ConvReluPoolOut {
   }
   __device__ void operator()(int, int, float, int) const {}
 };
-// B(k, n) = w[n][k] (weights [co][ci * 9])
+// B(k, n) = w[n][k]: the fc weights [classes][features], and the convolution
+// weights in tap-major rows [co][9 ci] (k = t ci + c, see k_weights_tap)
 struct WeightT {
   static constexpr bool KFAST = true;
+  static constexpr bool STEP = true;
   const float* w;
   int k_len;
   __device__ float operator()(int k, int n) const { return w[(size_t)n * k_len + k]; }
+  __device__ bool stepwise(int) const { return true; }
+  template <int CNT>
+  __device__ void stepk(int n, int k, int ns, float* v) const {
+    const unsigned o = (unsigned)n * (unsigned)k_len + (unsigned)k, d = (unsigned)(ns * k_len);
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) v[r] = ld32(w, o + r * d);
+  }
 };
 
 // data gradient, A(m = (b, y, x), k) = g[b][o][y - dy + 1][x - dx + 1] with
 // K tap-major as in the forward convolution: k = t co + o, t = 3 (dy + 1) +
-// (dx + 1).  32-bit offsets (gradients below 2^31 elements); for co >= 16 a
+// (dx + 1).  32-bit offsets (gradients below 2^30 elements); for co >= 16 a
 // thread's values of one 16-deep step share one tap (one bounds test).
 struct ConvBwdDataA {
   static constexpr bool KFAST = false;
@@ -291,7 +313,7 @@ struct ConvBwdDataA {
     if ((unsigned)yy >= (unsigned)w || (unsigned)xx >= (unsigned)w) return 0.0f;
     return g[(unsigned)(((((bb << lco) + o) << lw) + yy) << lw) + (unsigned)xx];
   }
-  __device__ bool stepwise() const { return lco >= 4; }
+  __device__ bool stepwise(int) const { return lco >= 4; }
   template <int CNT>
   __device__ void step(int m, int k0, int kw, int ks, float* v) const {
     const int w = 1 << lw;
@@ -302,17 +324,28 @@ struct ConvBwdDataA {
     const unsigned base = (unsigned)(((((bb << lco) + o) << lw) + yy) << lw) + (unsigned)xx;
     const unsigned plane = (unsigned)ks << (2 * lw);
 #pragma unroll
-    for (int r = 0; r < CNT; ++r) v[r] = inside ? g[base + r * plane] : 0.0f;
+    for (int r = 0; r < CNT; ++r) v[r] = inside ? ld32(g, base + r * plane) : 0.0f;
   }
 };
-// B(k = t co + o, n = c) = w[o][c][t]
+// B(k = t co + o, n = c) = w[o][c][t], read from the tap-major rows wt[o][t ci
+// + c] (contiguous in n).  For co >= 16 a thread's values of one step share
+// the tap and lie ks rows apart.
 struct WeightBwdData {
   static constexpr bool KFAST = false;
-  const float* w;
+  static constexpr bool STEP = true;
+  const float* wt;
   int ci, lco;
   __device__ float operator()(int k, int n) const {
     const int t = k >> lco, o = k & ((1 << lco) - 1);
-    return w[(unsigned)((o * ci + n) * 9 + t)];
+    return wt[(unsigned)(o * 9 * ci + t * ci + n)];
+  }
+  __device__ bool stepwise(int) const { return lco >= 4; }
+  template <int CNT>
+  __device__ void step(int n, int k0, int kw, int ks, float* v) const {
+    const int t = k0 >> lco, o = (k0 & ((1 << lco) - 1)) + kw;
+    const unsigned base = (unsigned)(o * 9 * ci + t * ci + n), stride = (unsigned)(ks * 9 * ci);
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) v[r] = ld32(wt, base + r * stride);
   }
 };
 // out[b][n][y][x] = acc
@@ -327,7 +360,7 @@ struct NchwOut {
 };
 
 // weight gradient, A(m = o, k = (b, y, x)) = g[b][o][y][x] (32-bit offsets:
-// gradients below 2^31 elements).  Whole-step fetch: a thread's values of a
+// gradients below 2^30 elements).  Whole-step fetch: a thread's values of a
 // step share k and lie ms rows apart.
 struct ConvBwdWA {
   static constexpr bool KFAST = true;
@@ -344,7 +377,7 @@ struct ConvBwdWA {
     const int hw = 1 << (2 * lw);
     const unsigned base = ((unsigned)((k >> (2 * lw)) * co + m) << (2 * lw)) + (unsigned)(k & (hw - 1));
 #pragma unroll
-    for (int r = 0; r < CNT; ++r) v[r] = g[base + (unsigned)(r * ms) * (unsigned)hw];
+    for (int r = 0; r < CNT; ++r) v[r] = ld32(g, base + (unsigned)(r * ms) * (unsigned)hw);
   }
 };
 // B(k = (b, y, x), n) = in[b][c][y + dy - 1][x + dx - 1] with N tap-major,
@@ -376,7 +409,7 @@ struct ConvBwdWB {
     const unsigned base = (unsigned)(((((bb << lci) + c) << lw) + yy) << lw) + (unsigned)xx;
     const unsigned plane = (unsigned)ns << (2 * lw);
 #pragma unroll
-    for (int r = 0; r < CNT; ++r) v[r] = inside ? in[base + r * plane] : 0.0f;
+    for (int r = 0; r < CNT; ++r) v[r] = inside ? ld32(in, base + r * plane) : 0.0f;
   }
 };
 // partial[z][m][n] = acc (split K, summed in a fixed order afterwards)
@@ -386,24 +419,49 @@ struct SplitOut {
   __device__ void operator()(int m, int n, float v, int z) const { part[((size_t)z * M + m) * N + n] = v; }
 };
 
-// row-major matrices
+// row-major matrices (the whole-step fetches use 32-bit offsets: operands
+// below 2^30 elements)
 struct RowK {  // A(m, k) = p[m * ld + k]
   static constexpr bool KFAST = true;
+  static constexpr bool STEP = true;
   const float* p;
   int ld;
   __device__ float operator()(int m, int k) const { return p[(size_t)m * ld + k]; }
+  __device__ bool stepwise(int) const { return true; }
+  template <int CNT>
+  __device__ void stepk(int m, int k, int ms, float* v) const {
+    const unsigned o = (unsigned)m * (unsigned)ld + (unsigned)k, d = (unsigned)(ms * ld);
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) v[r] = ld32(p, o + r * d);
+  }
 };
 struct ColK {  // A(m, k) = p[k * ld + m]
   static constexpr bool KFAST = false;
+  static constexpr bool STEP = true;
   const float* p;
   int ld;
   __device__ float operator()(int m, int k) const { return p[(size_t)k * ld + m]; }
+  __device__ bool stepwise(int) const { return true; }
+  template <int CNT>
+  __device__ void step(int m, int k0, int kw, int ks, float* v) const {
+    const unsigned o = (unsigned)(k0 + kw) * (unsigned)ld + (unsigned)m, d = (unsigned)(ks * ld);
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) v[r] = ld32(p, o + r * d);
+  }
 };
 struct BRowN {  // B(k, n) = p[k * ld + n]
   static constexpr bool KFAST = false;
+  static constexpr bool STEP = true;
   const float* p;
   int ld;
   __device__ float operator()(int k, int n) const { return p[(size_t)k * ld + n]; }
+  __device__ bool stepwise(int) const { return true; }
+  template <int CNT>
+  __device__ void step(int n, int k0, int kw, int ks, float* v) const {
+    const unsigned o = (unsigned)(k0 + kw) * (unsigned)ld + (unsigned)n, d = (unsigned)(ks * ld);
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) v[r] = ld32(p, o + r * d);
+  }
 };
 struct RowOut {  // C[m * ld + n] = acc (+ bias[n])
   float* out;
@@ -593,6 +651,20 @@ __global__ __launch_bounds__(256) void k_wgrad_first(const float* __restrict__ x
     if (tid < 9) part[((size_t)bb * co + o) * 9 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
     __syncthreads();
   }
+}
+
+// Convolution weights [co][ci][3][3] -> tap-major rows wt[o][t ci + c] =
+// w[o][c][t], the four layers in one launch
+__global__ void k_weights_tap(const float* __restrict__ params, Layout lay, float* __restrict__ wt) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= kTapWeights) return;
+  int l = 0;
+  while (l < 3 && j >= tap_weights_offset(l + 1)) ++l;
+  const int ci = l ? kChannels[l - 1] : 1;
+  const int64_t i = j - tap_weights_offset(l);
+  const int64_t o = i / (9 * ci);
+  const int rem = (int)(i - o * 9 * ci), t = rem / ci, c = rem - t * ci;
+  wt[j] = params[lay.conv_w[l] + (o * ci + c) * 9 + t];
 }
 
 // gradient through the ReLU and the 2 x 2 max pool: the pooled gradient goes to the
@@ -957,6 +1029,7 @@ hipError_t init_params(float* params, const Layout& lay, uint64_t seed, hipStrea
 // forward; act holds p_i (i = 0..3), in training arg_i, and the logits
 hipError_t forward(const float* params, const Layout& lay, const float* x, int64_t bsz, const Acts& act,
                    hipStream_t st, bool train) {
+  hipLaunchKernelGGL(k_weights_tap, dim3(nb(kTapWeights)), dim3(256), 0, st, params, lay, act.wt);
   const float* a = x;
   int ci = 1, w = kInSize;
   hipError_t e;
@@ -966,7 +1039,7 @@ hipError_t forward(const float* params, const Layout& lay, const float* x, int64
     const int lci = ilog2(ci);
     // each convolution pools in its epilogue: only the pooled maps (and, in
     // training, the gradient positions) are written
-    e = gemm(ConvFwdA{a, ci, lci, lw}, WeightTap{params + lay.conv_w[i], K, lci},
+    e = gemm(ConvFwdA{a, ci, lci, lw}, WeightT{act.wt + tap_weights_offset(i), K},
              ConvReluPoolOut{act.p[i], params + lay.conv_b[i], co, lw - 1, train ? act.arg[i] : nullptr}, M, co, K,
              1, st, true);
     if (e != hipSuccess) return e;
@@ -1047,7 +1120,7 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
       hipLaunchKernelGGL(k_channel_sum, dim3(co), dim3(64), 0, st, cpart, zs, grad + lay.conv_b[i]);
     }
     if (i > 0) {
-      e = gemm(ConvBwdDataA{act.g[i], ilog2(co), lw}, WeightBwdData{params + lay.conv_w[i], ci, ilog2(co)},
+      e = gemm(ConvBwdDataA{act.g[i], ilog2(co), lw}, WeightBwdData{act.wt + tap_weights_offset(i), ci, ilog2(co)},
                NchwOut{act.dp[i - 1], ci, lw}, (int)(bsz * w * w), ci, co * 9, 1, st, true);
       if (e != hipSuccess) return e;
     }
