@@ -486,7 +486,8 @@ static int k_slices(int K, int splits) {
 }
 
 template <class A, class Bm, class Out>
-static hipError_t gemm(A a, Bm b, Out out, int M, int N, int K, int splits, hipStream_t st, bool wide = false) {
+static hipError_t gemm(A a, Bm b, Out out, int M, int N, int K, int splits, hipStream_t st, bool wide = false,
+                       bool narrow = false) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int kslice = k_slice(K, splits);
   const int z = k_slices(K, splits) < 1 ? 1 : k_slices(K, splits);
@@ -504,6 +505,11 @@ static hipError_t gemm(A a, Bm b, Out out, int M, int N, int K, int splits, hipS
   } else if (wide) {
     hipLaunchKernelGGL((k_tgemm<128, 128, A, Bm, Out>), dim3((N + 127) / 128, (M + 127) / 128, z), dim3(256), 0,
                        st, a, b, out, M, N, K, kslice);
+  } else if (narrow) {
+    // narrow: 64 x 32 tiles (operands whose whole-step fetch needs tiles at
+    // most 32 wide)
+    hipLaunchKernelGGL((k_tgemm<64, 32, A, Bm, Out>), dim3((N + 31) / 32, (M + 63) / 64, z), dim3(256), 0, st, a, b,
+                       out, M, N, K, kslice);
   } else {
     hipLaunchKernelGGL((k_tgemm<64, 64, A, Bm, Out>), dim3((N + 63) / 64, (M + 63) / 64, z), dim3(256), 0, st, a, b,
                        out, M, N, K, kslice);
@@ -605,51 +611,62 @@ __global__ __launch_bounds__(1024) void k_col_sum(const float* __restrict__ a, i
 // dW[o][t] = sum over (b, y, x) of g[b][o][y][x] in[b][y + dy - 1][x + dx - 1],
 // t = 3 dy + dx.  g is the pooled gradient at each pooled output's recorded
 // quad position and zero elsewhere, so the sum runs over the pooled maps.
-// Block (b, group of OG channels) stages image b with a zero border in LDS;
-// a thread takes pooled positions i, i + 256, ... of each channel, and the
-// block's nine sums per channel go to part[b][o][t] (fixed order: lanes,
-// then waves), summed over b afterwards.
+// Block (b, group of OG channels) loads its pooled gradients and positions
+// first, then stages image b with a zero border in LDS; a thread takes
+// pooled positions i, i + 256, ... of each channel, and the block's nine sums
+// per channel go to part[b][o][t] (fixed order: lanes, then waves), summed
+// over b afterwards.
 template <int OG>
 __global__ __launch_bounds__(256) void k_wgrad_first(const float* __restrict__ x, const uint8_t* __restrict__ arg,
                                                      const float* __restrict__ dpool, int co,
                                                      float* __restrict__ part) {
-  constexpr int W = kInSize, WP = W / 2, S = W + 2;
+  constexpr int W = kInSize, WP = W / 2, S = W + 2, PR = WP * WP / 256;
   __shared__ float xs[S * S];
-  __shared__ float red[4][9];
+  __shared__ float red[4][OG][9];
   const int bb = blockIdx.x, o0 = blockIdx.y * OG, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int q[OG][PR];
+  float d[OG][PR];
+#pragma unroll
+  for (int oi = 0; oi < OG; ++oi)
+#pragma unroll
+    for (int r = 0; r < PR; ++r) {
+      const size_t o = ((size_t)bb * co + o0 + oi) * (WP * WP) + tid + 256 * r;
+      q[oi][r] = arg[o];
+      d[oi][r] = dpool[o];
+    }
   for (int i = tid; i < S * S; i += 256) {
     const int yy = i / S - 1, xx = i % S - 1;
     xs[i] = ((unsigned)yy < (unsigned)W && (unsigned)xx < (unsigned)W) ? x[((size_t)bb * W + yy) * W + xx] : 0.0f;
   }
   __syncthreads();
+#pragma unroll
   for (int oi = 0; oi < OG; ++oi) {
-    const int o = o0 + oi;
-    const size_t pl = ((size_t)bb * co + o) * (WP * WP);
     float acc[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t] = 0.0f;
 #pragma unroll
-    for (int r = 0; r < WP * WP / 256; ++r) {
-      const int i = tid + 256 * r;
-      const int q = arg[pl + i];
-      const float d = q < 4 ? dpool[pl + i] : 0.0f;
+    for (int r = 0; r < PR; ++r) {
+      const int i = tid + 256 * r, qq = q[oi][r];
+      const float dv = qq < 4 ? d[oi][r] : 0.0f;
       // full-resolution pixel of the quad position (any position when q = 4:
-      // d = 0 there), shifted by the border
-      const int py = 2 * (i / WP) + ((q >> 1) & 1), px = 2 * (i % WP) + (q & 1);
+      // dv = 0 there), shifted by the border
+      const int py = 2 * (i / WP) + ((qq >> 1) & 1), px = 2 * (i % WP) + (qq & 1);
       const float* xp = xs + py * S + px;
 #pragma unroll
-      for (int t = 0; t < 9; ++t) acc[t] = fmaf(d, xp[(t / 3) * S + t % 3], acc[t]);
+      for (int t = 0; t < 9; ++t) acc[t] = fmaf(dv, xp[(t / 3) * S + t % 3], acc[t]);
     }
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       float v = acc[t];
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      if (lane == 0) red[w][t] = v;
+      if (lane == 0) red[w][oi][t] = v;
     }
-    __syncthreads();
-    if (tid < 9) part[((size_t)bb * co + o) * 9 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-    __syncthreads();
+  }
+  __syncthreads();
+  if (tid < OG * 9) {
+    const int oi = tid / 9, t = tid % 9;
+    part[((size_t)bb * co + o0 + oi) * 9 + t] = ((red[0][oi][t] + red[1][oi][t]) + red[2][oi][t]) + red[3][oi][t];
   }
 }
 
@@ -1102,13 +1119,17 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
     } else {
       hipLaunchKernelGGL(k_unpool_bwd, dim3(nb(bsz * co * (w / 2) * (w / 2))), dim3(256), 0, st, act.arg[i],
                          act.dp[i], (int64_t)(bsz * co), lw - 1, act.g[i]);
-      // weight gradient, split over (b, y, x)
+      // weight gradient, split over (b, y, x); 32-wide tiles when ci < 64
+      // (the tap-major columns of a tile then share a tap)
       const int K = (int)(bsz * w * w), N = ci * 9;
-      const int64_t tiles = (int64_t)((co + 63) / 64) * ((N + 63) / 64);
+      const bool narrow = ci < 64;
+      const int tn = narrow ? 32 : 64;
+      const int64_t tiles = (int64_t)((co + 63) / 64) * ((N + tn - 1) / tn);
       int s = splits_for(K, tiles);
       while ((size_t)s * co * N > part_floats && s > 1) s = (s + 1) / 2;
       const int z = k_slices(K, s);
-      e = gemm(ConvBwdWA{act.g[i], co, lw}, ConvBwdWB{in, ilog2(ci), lw}, SplitOut{part, co, N}, co, N, K, s, st);
+      e = gemm(ConvBwdWA{act.g[i], co, lw}, ConvBwdWB{in, ilog2(ci), lw}, SplitOut{part, co, N}, co, N, K, s, st,
+               false, narrow);
       if (e != hipSuccess) return e;
       split_sum(part, z, (int64_t)co * N, grad + lay.conv_w[i], st, N, ilog2(ci));
     }
