@@ -104,6 +104,65 @@ def test_forward_and_gradients_match_oracle():
     net.close()
 
 
+def test_forward_at_full_width_matches_oracle_on_sampled_patterns():
+    # 2,896 patterns (a pass of 2,048 and one of 848) and 8,000 classes: the
+    # convolutions and the fc run on 128-row tiles with whole-step fetches,
+    # the last fc row block on the bounds-tested path (the small case above
+    # takes the 64 x 64 tiles).  A pattern's scores depend on that pattern
+    # alone, so sampled rows are compared with the oracle's forward of them.
+    banner("cnn forward at 2896 x 8000 vs oracle on sampled patterns")
+    t = tm()
+    n_cls, bsz = 8000, 2048 + 848
+    rng = np.random.default_rng(11)
+    net = t.Cnn(n_cls, seed=7)
+    params = _seeded_params(rng, n_cls)
+    net.set_params(dev(params))
+    xs = rng.normal(size=(bsz, 64, 64)).astype(np.float32)
+    logits = host(net.forward(dev(xs)))
+    rows = [0, 1, 127, 128, 1023, 2047, 2048, 2815, 2816, bsz - 1]
+    ref, _ = ocnn.forward(params.astype(np.float64), xs[rows].astype(np.float64), n_cls)
+    err = np.max(np.abs(logits[rows] - ref)) / np.max(np.abs(ref))
+    print("[gpu]   sampled logits relative error %.2e" % err, flush=True)
+    assert err <= 1e-4
+    net.close()
+
+
+def test_gradients_of_a_batch_are_the_mean_over_its_slices():
+    # A batch of 256 at 8,000 classes takes the 128-row and 64 x 32 tiles and
+    # the whole-step fetches; the gradient of its mean loss is the mean of
+    # the gradients over its 64 slices of 4, which take the paths the oracle
+    # test above checks.  FP32 sums in another order: 1e-5 relative per
+    # parameter tensor, the loss 1e-6.
+    banner("cnn gradients: batch of 256 vs the mean over slices of 4")
+    t = tm()
+    n_cls, bsz, sl = 8000, 256, 4
+    rng = np.random.default_rng(13)
+    net = t.Cnn(n_cls, seed=7)
+    params = _seeded_params(rng, n_cls)
+    net.set_params(dev(params))
+    x = dev(rng.normal(size=(bsz, 64, 64)).astype(np.float32))
+    y = dev(rng.integers(0, n_cls, size=bsz).astype(np.int32))
+    g, loss = net.gradients(x, y)
+    g_big, loss_big = host(g).astype(np.float64), float(host(loss)[0])
+    acc, lacc = np.zeros_like(g_big), 0.0
+    for i in range(0, bsz, sl):
+        g, loss = net.gradients(x[i:i + sl], y[i:i + sl])
+        acc += host(g)
+        lacc += float(host(loss)[0])
+    acc /= bsz // sl
+    lacc /= bsz // sl
+    assert abs(loss_big - lacc) <= 1e-6 * abs(lacc)
+    k = 0
+    for name, s in ocnn.param_shapes(n_cls):
+        m = int(np.prod(s))
+        a, b = g_big[k:k + m], acc[k:k + m]
+        err = np.linalg.norm(a - b) / np.linalg.norm(b)
+        print("[gpu]   %s relative difference %.2e" % (name, err), flush=True)
+        assert err < 1e-5, name
+        k += m
+    net.close()
+
+
 def test_adam_steps_match_oracle():
     # three Adam steps from seeded gradients spanning eight decades (and a few
     # exact zeros) against the FP64 oracle: 1e-6 relative to max(|w|, lr)
