@@ -995,6 +995,135 @@ __global__ __launch_bounds__(256) void k_topk(const float* __restrict__ z, int l
   }
 }
 
+// The same selection for k <= kTopKWave by a threshold.  Lane j of wave 0
+// takes the largest of threads 4j .. 4j + 3's entries (i = t + 256 r); T =
+// the k-th largest of these 64 group maxima (ranked by value, then lane), so
+// at least k entries are >= T and the k best are among them.  The entries
+// >= T (typically a few dozen of thousands) are collected and wave 0 orders
+// them by (score, then index), the total order of k_topk: a bitonic sort in
+// registers for at most 64 of them, else k rounds of a wave argmax; more
+// than kTopKCand (heavy ties at T) falls back to k_topk's block argmax.
+constexpr int kTopKWave = 64, kTopKCand = 1024;
+__device__ __forceinline__ bool topk_before(float va, int ia, float vb, int ib) {
+  return va > vb || (va == vb && ia < ib);
+}
+__global__ __launch_bounds__(256) void k_topk_wave(const float* __restrict__ z, int l, int k,
+                                                   int32_t* __restrict__ idx) {
+  extern __shared__ float row[];
+  __shared__ float tmax[256];
+  __shared__ float cv[kTopKCand];
+  __shared__ int ci[kTopKCand];
+  __shared__ int ncand;
+  __shared__ float thr;
+  const int64_t b = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  float mt = -INFINITY;
+  for (int i = tid; i < l; i += 256) {
+    const float v = z[(size_t)b * l + i];
+    const float vv = v != v ? -INFINITY : v;
+    row[i] = vv;
+    mt = fmaxf(mt, vv);
+  }
+  tmax[tid] = mt;
+  if (tid == 0) ncand = 0;
+  __syncthreads();
+  if (w == 0) {
+    const float g = fmaxf(fmaxf(tmax[4 * lane], tmax[4 * lane + 1]), fmaxf(tmax[4 * lane + 2], tmax[4 * lane + 3]));
+    int rank = 0;
+    for (int u = 0; u < 64; ++u) {
+      const float o = __shfl(g, u, 64);
+      rank += (o > g || (o == g && u < lane)) ? 1 : 0;
+    }
+    if (rank == k - 1) thr = g;  // ranks are a permutation of 0 .. 63
+  }
+  __syncthreads();
+  const float t = thr;
+  for (int i = tid; i < l; i += 256) {
+    const float v = row[i];
+    if (v >= t) {
+      const int p = atomicAdd(&ncand, 1);
+      if (p < kTopKCand) {
+        cv[p] = v;
+        ci[p] = i;
+      }
+    }
+  }
+  __syncthreads();
+  const int m = ncand;
+  if (m <= 64) {
+    if (w == 0) {
+      float v = lane < m ? cv[lane] : -INFINITY;
+      int i = lane < m ? ci[lane] : 0x7fffffff;
+      for (int size = 2; size <= 64; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+          const float ov = __shfl_xor(v, stride, 64);
+          const int oi = __shfl_xor(i, stride, 64);
+          // runs of `size` lanes alternate direction until the last pass;
+          // the lower lane of a pair keeps the earlier entry of its run
+          const bool fwd = (lane & size) == 0 || size == 64;
+          const bool lower = (lane & stride) == 0;
+          const bool other_first = topk_before(ov, oi, v, i);
+          if (lower == fwd ? other_first : topk_before(v, i, ov, oi)) {
+            v = ov;
+            i = oi;
+          }
+        }
+      if (lane < k) idx[b * k + lane] = i;
+    }
+  } else if (m <= kTopKCand) {
+    if (w == 0) {
+      // a lane caches its best candidate; only the owner of a pick rescans
+      auto best = [&](float& bv, int& bi, int& slot) {
+        bv = -INFINITY;
+        bi = 0x7fffffff;
+        slot = -1;
+        for (int e = lane; e < m; e += 64)
+          if (topk_before(cv[e], ci[e], bv, bi)) {
+            bv = cv[e];
+            bi = ci[e];
+            slot = e;
+          }
+      };
+      float mv;
+      int mi, ms;
+      best(mv, mi, ms);
+      for (int r = 0; r < k; ++r) {
+        float bv = mv;
+        int bi = mi;
+        wave_argmax(bv, bi);
+        if (lane == 0) idx[b * k + r] = bi;
+        if (bi == mi && ms >= 0) {
+          cv[ms] = __int_as_float(0x7fc00000);  // NaN never wins a comparison
+          best(mv, mi, ms);
+        }
+      }
+    }
+  } else {
+    __shared__ float rv[4];
+    __shared__ int ri[4];
+    __shared__ int pick;
+    for (int r = 0; r < k; ++r) {
+      float bv = -INFINITY;
+      int bi = 0x7fffffff;
+      for (int i = tid; i < l; i += 256) argmax_merge(bv, bi, row[i], i);
+      wave_argmax(bv, bi);
+      if (lane == 0) {
+        rv[w] = bv;
+        ri[w] = bi;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        for (int u = 1; u < 4; ++u) argmax_merge(bv, bi, rv[u], ri[u]);
+        pick = bi;
+        idx[b * k + r] = bi;
+      }
+      __syncthreads();
+      if (tid == 0) row[pick] = __int_as_float(0x7fc00000);
+      __syncthreads();
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 
@@ -1199,6 +1328,14 @@ hipError_t topk(const float* z, int64_t rows, int l, int k, int32_t* idx, hipStr
   if (rows > (int64_t(1) << 31) / 256) return hipErrorInvalidValue;  // one dispatch below 2^31 items
   const size_t shm = sizeof(float) * (size_t)l;
   if (shm > 160 * 1024) return hipErrorInvalidValue;
+  // (the threshold form adds 9 KB of its own to the row in LDS)
+  if (k <= kTopKWave && shm + 1024 * (size_t)(1 + 2 * kTopKCand / 256) + 64 <= 160 * 1024) {
+    const hipError_t e =
+        hipFuncSetAttribute((const void*)k_topk_wave, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_topk_wave, dim3((unsigned)rows), dim3(256), shm, st, z, l, k, idx);
+    return hipGetLastError();
+  }
   const hipError_t e = hipFuncSetAttribute((const void*)k_topk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_topk, dim3((unsigned)rows), dim3(256), shm, st, z, l, k, idx);

@@ -225,14 +225,24 @@ def test_set_params_round_trip_and_train_step_lowers_loss():
     net.close()
 
 
-def test_topk_order_and_ties():
+@pytest.mark.parametrize("l,k", [(300, 32), (300, 1), (300, 64), (300, 65), (50, 32), (40, 40), (8000, 32),
+                                 (3000, 32)])
+def test_topk_order_and_ties(l, k):
+    # k <= 64 takes the threshold kernel: few entries at or above the
+    # threshold (random rows), up to 1,024 (the coarse row 0: ties), more
+    # (the constant rows 1 and 5: its block-argmax fallback); k = 65 the
+    # block-argmax kernel; l = 50 and l = k leave threads without entries
     t = tm()
-    rng = np.random.default_rng(2)
-    z = np.round(rng.normal(size=(5, 300)), 1).astype(np.float32)   # many ties
+    rng = np.random.default_rng(2 + l + k)
+    z = np.round(rng.normal(size=(7, l)), 1).astype(np.float32)   # many ties
+    z[0, :] = np.round(rng.normal(size=l), 0)
     z[1, :] = 0.0
     z[2, 7] = np.nan
-    idx = host(t.cnn_topk(dev(z), 32))
-    for r in range(5):
+    z[3, ::3] = -0.0                                             # ties with +0.0 by value
+    z[4, ::5] = -np.inf
+    z[5, :] = -np.inf
+    idx = host(t.cnn_topk(dev(z), k))
+    for r in range(z.shape[0]):
         v = np.where(np.isnan(z[r]), -np.inf, z[r])
-        want = sorted(range(300), key=lambda i: (-v[i], i))[:32]
-        assert list(idx[r]) == want
+        want = sorted(range(l), key=lambda i: (-v[i], i))[:k]
+        assert list(idx[r]) == want, r
