@@ -17,7 +17,11 @@ __all__ = ["lib", "Params", "index_patterns", "refine_orientations", "project_te
            "pattern_spectra", "spectrum_floats", "xcf_peak", "xcf_scores", "xcf_scores_cand", "xcf_subpixel",
            "measure_rotation", "params_default", "version", "RaggedPlan", "Cnn", "cnn_make_batch", "cnn_topk",
            "index_proposed", "refine_from_match", "pc_map", "PcModel", "capture_range", "so3_library",
-           "nn_disorientation", "LibraryPlan", "LIB_PATH", "EXPORTS"]
+           "nn_disorientation", "LibraryPlan", "LIB_PATH", "EXPORTS", "PREC_FP32", "PREC_FP16X2", "PREC_BF16X2",
+           "PREC_BF16"]
+
+# precision constants of the header (ebsd_params.precision, Cnn.set_precision)
+PREC_FP32, PREC_FP16X2, PREC_BF16X2, PREC_BF16 = 0, 1, 2, 3
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libebsd_tm.so")
@@ -29,8 +33,8 @@ EXPORTS = ("ebsd_params_default", "ebsd_version", "ebsd_last_error", "ebsd_index
            "ebsd_measure_rotation", "ebsd_timing_enable", "ebsd_timing_read", "ebsd_ragged_plan_create",
            "ebsd_ragged_run", "ebsd_ragged_plan_tiles", "ebsd_ragged_plan_destroy", "ebsd_cnn_param_count",
            "ebsd_cnn_create", "ebsd_cnn_destroy", "ebsd_cnn_get_params", "ebsd_cnn_set_params", "ebsd_cnn_input",
-           "ebsd_cnn_forward", "ebsd_cnn_gradients", "ebsd_cnn_train_step", "ebsd_cnn_apply_gradient",
-           "ebsd_cnn_make_batch", "ebsd_cnn_topk",
+           "ebsd_cnn_forward", "ebsd_cnn_set_precision", "ebsd_cnn_gradients", "ebsd_cnn_train_step",
+           "ebsd_cnn_apply_gradient", "ebsd_cnn_make_batch", "ebsd_cnn_topk",
            "ebsd_index_proposed", "ebsd_pc_map", "ebsd_refine_from_match", "ebsd_capture_range",
            "ebsd_so3_library", "ebsd_nn_disorientation", "ebsd_plan_create", "ebsd_index_patterns_plan",
            "ebsd_plan_destroy")
@@ -128,6 +132,7 @@ def lib():
     L.ebsd_cnn_set_params.argtypes = [vp, vp, vp]
     L.ebsd_cnn_input.argtypes = [vp, i64, i32, vp, vp]
     L.ebsd_cnn_forward.argtypes = [vp, vp, i64, vp, vp]
+    L.ebsd_cnn_set_precision.argtypes = [vp, i32]
     L.ebsd_cnn_gradients.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     L.ebsd_cnn_train_step.argtypes = [vp, vp, vp, i64, f32, vp, vp]
     L.ebsd_cnn_apply_gradient.argtypes = [vp, vp, f32, vp]
@@ -690,6 +695,10 @@ class Cnn:
         _check(lib().ebsd_cnn_forward(self._h, _ptr(x, torch.float32, "x"), x.shape[0], _ptr(out), _stream()),
                "ebsd_cnn_forward")
         return out
+
+    def set_precision(self, precision):
+        """Precision of the inference products: PREC_BF16X2 (default) or PREC_FP32."""
+        _check(lib().ebsd_cnn_set_precision(self._h, int(precision)), "ebsd_cnn_set_precision")
 
     def gradients(self, x, labels):
         import torch

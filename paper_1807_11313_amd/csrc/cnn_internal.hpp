@@ -50,9 +50,10 @@ struct Acts {
 hipError_t init_params(float* params, const Layout& lay, uint64_t seed, hipStream_t st);
 // Writes the tap-major weights act.wt, then each convolution its pooled map
 // act.p; train: also the gradient positions act.arg that the backward pass
-// needs
+// needs.  split (inference only; training is FP32): the products take BF16
+// hi + lo halves of their FP32 operands, three products per tile.
 hipError_t forward(const float* params, const Layout& lay, const float* x, int64_t bsz, const Acts& act,
-                   hipStream_t st, bool train = true);
+                   hipStream_t st, bool train = true, bool split = false);
 // Gradient of the mean cross-entropy into grad (all of it overwritten), from
 // act as the training forward pass on the same parameters left it;
 // part: split-K scratch of part_floats floats; loss_row: [bsz] doubles.

@@ -112,6 +112,7 @@ __global__ void k_scatter_best(const int32_t* __restrict__ list, int64_t f, cons
 
 struct ebsd_cnn_s {
   int device = 0;
+  int32_t infer_prec = EBSD_PREC_BF16X2;  // precision of the inference products
   cnn::Layout lay{};
   float* params = nullptr;
   float* grad = nullptr;
@@ -196,7 +197,9 @@ int forward_chunks(ebsd_cnn_s* c, const float* x, int64_t bsz, float* logits, hi
     const int64_t b = std::min(kChunk, bsz - s);
     cnn::Acts a = c->act;
     a.logits = logits + s * L;
-    CN_TRY(cnn::forward(c->params, c->lay, x + s * cnn::kInSize * cnn::kInSize, b, a, st, false), "cnn forward");
+    CN_TRY(cnn::forward(c->params, c->lay, x + s * cnn::kInSize * cnn::kInSize, b, a, st, false,
+                        c->infer_prec == EBSD_PREC_BF16X2),
+           "cnn forward");
   }
   return EBSD_OK;
 }
@@ -301,6 +304,16 @@ int ebsd_cnn_forward(ebsd_cnn c, const float* x, int64_t B, float* logits, void*
   if (B == 0) return EBSD_OK;
   if (!x || !logits) return fail(EBSD_E_INVALID, "null pointer");
   return forward_chunks(c, x, B, logits, (hipStream_t)stream);
+}
+
+int ebsd_cnn_set_precision(ebsd_cnn c, int32_t precision) {
+  g_last_error.clear();
+  if (!c) return fail(EBSD_E_INVALID, "null network");
+  if (precision == EBSD_PREC_FP16X2 || precision == EBSD_PREC_BF16)
+    return fail(EBSD_E_UNSUPPORTED, "the network's inference runs in FP32 or BF16X2");
+  if (precision != EBSD_PREC_FP32 && precision != EBSD_PREC_BF16X2) return fail(EBSD_E_INVALID, "unknown precision");
+  c->infer_prec = precision;
+  return EBSD_OK;
 }
 
 int ebsd_cnn_gradients(ebsd_cnn c, const float* x, const int32_t* labels, int64_t B, float* grad, float* loss,

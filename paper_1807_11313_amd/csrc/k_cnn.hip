@@ -208,15 +208,216 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
 // --- operand maps ---------------------------------------------------------
 // Images are NCHW with H = W = 1 << lw.
 
+// ---------------------------------------------------------------------------
+// The same product with BF16 split operands on v_mfma_f32_16x16x32_bf16:
+// every FP32 value x is split into x_hi = bf16(x) and x_lo = bf16(x - x_hi)
+// (x - x_hi is exact), and a 16 x 16 x 32 tile takes the three products
+// hi hi + hi lo + lo hi into an FP32 accumulator (the dropped lo lo term and
+// the rounding of x_lo leave about 2^-16 of each product).  32-deep K steps
+// through two LDS stages of hi / lo tiles stored [row][k] (80-byte rows, so
+// the 16-byte fragment reads of 16 lanes meet 16 distinct bank quads);
+// operand fragments: lane l holds row (column) l % 16, k = 8 (l / 16) + j.
+// A thread of a KFAST-false operand holds KR consecutive k of one row (one
+// tap of a convolution: one bounds test), so it stores its halves as
+// 16-byte vectors; KFAST operands store single halves.  Used for the
+// forward products (the backward ones stay FP32).
+constexpr int KS2 = 32, LROW = 40;  // step depth; LDS row of 32 halves + 8 of padding
+typedef __bf16 cnn_b8 __attribute__((ext_vector_type(8)));
+typedef __bf16 cnn_bf2 __attribute__((ext_vector_type(2)));
+typedef float cnn_f2 __attribute__((ext_vector_type(2)));
+typedef unsigned cnn_u4 __attribute__((ext_vector_type(4)));
+// two floats -> packed (hi, hi) and (lo, lo), round to nearest even
+__device__ __forceinline__ void bf16_split2(float a, float b, unsigned& hi, unsigned& lo) {
+  hi = __builtin_bit_cast(unsigned, __builtin_convertvector(cnn_f2{a, b}, cnn_bf2));
+  const float ha = __builtin_bit_cast(float, hi << 16), hb = __builtin_bit_cast(float, hi & 0xffff0000u);
+  lo = __builtin_bit_cast(unsigned, __builtin_convertvector(cnn_f2{a - ha, b - hb}, cnn_bf2));
+}
+
+template <int TM, int TN, class A, class Bm, class Out>
+__global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int N, int K, int kslice) {
+  static_assert((TM == 64 || TM == 128) && (TN == 32 || TN == 64 || TN == 128), "tile");
+  constexpr int KRA = TM * KS2 / 256, KRB = TN * KS2 / 256;  // operand values per thread and step
+  constexpr int TI = TM / 32, TJ = TN / 32;                   // 16 x 16 tiles per wave
+  static_assert((A::KFAST || KRA % 8 == 0) && (Bm::KFAST || KRB % 8 == 0) && KRA % 2 == 0 && KRB % 2 == 0,
+                "whole 16-byte vectors (KFAST false) or pairs (KFAST) per thread");
+  __shared__ __attribute__((aligned(16))) unsigned short ah[2][TM][LROW], al[2][TM][LROW];
+  __shared__ __attribute__((aligned(16))) unsigned short bh[2][TN][LROW], bl[2][TN][LROW];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = (w & 1) * (TM / 2), wn = (w >> 1) * (TN / 2);
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int kb = blockIdx.z * kslice;
+  const int ke = min(K, kb + kslice);
+  f4c acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = f4c{0.f, 0.f, 0.f, 0.f};
+  const int r16 = lane & 15, g8 = (lane >> 4) * 8;
+  // this thread's (m, k) and (k, n) positions in a step: KFAST false, KR
+  // consecutive k of one row; KFAST true, one k of rows 256 / KS2 apart
+  int am[KRA], ak[KRA], bn[KRB], bk[KRB];
+#pragma unroll
+  for (int r = 0; r < KRA; ++r) {
+    am[r] = A::KFAST ? (tid + 256 * r) / KS2 : tid % TM;
+    ak[r] = A::KFAST ? tid % KS2 : (tid / TM) * KRA + r;
+  }
+#pragma unroll
+  for (int r = 0; r < KRB; ++r) {
+    bn[r] = Bm::KFAST ? (tid + 256 * r) / KS2 : tid % TN;
+    bk[r] = Bm::KFAST ? tid % KS2 : (tid / TN) * KRB + r;
+  }
+  float ra[KRA], rb[KRB];
+  auto fetch_steps = [&](int k0) __attribute__((always_inline)) {
+    if constexpr (HasStep<A>::value && HasStep<Bm>::value) {
+      if constexpr (A::KFAST) a.template stepk<KRA>(m0 + am[0], k0 + ak[0], 256 / KS2, ra);
+      else a.template step<KRA>(m0 + am[0], k0, ak[0], 1, ra);
+      if constexpr (Bm::KFAST) b.template stepk<KRB>(n0 + bn[0], k0 + bk[0], 256 / KS2, rb);
+      else b.template step<KRB>(n0 + bn[0], k0, bk[0], 1, rb);
+    }
+  };
+  auto fetch_tested = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int r = 0; r < KRA; ++r) {
+      const int m = m0 + am[r], k = k0 + ak[r];
+      ra[r] = (m < M && k < ke) ? a(m, k) : 0.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < KRB; ++r) {
+      const int n = n0 + bn[r], k2 = k0 + bk[r];
+      rb[r] = (n < N && k2 < ke) ? b(k2, n) : 0.0f;
+    }
+  };
+  // split and store one step's values into stage st
+  auto stash = [&](int st) __attribute__((always_inline)) {
+    if constexpr (A::KFAST) {
+#pragma unroll
+      for (int r = 0; r < KRA; r += 2) {
+        unsigned h, l;
+        bf16_split2(ra[r], ra[r + 1], h, l);
+        ah[st][am[r]][ak[r]] = (unsigned short)h;
+        al[st][am[r]][ak[r]] = (unsigned short)l;
+        ah[st][am[r + 1]][ak[r + 1]] = (unsigned short)(h >> 16);
+        al[st][am[r + 1]][ak[r + 1]] = (unsigned short)(l >> 16);
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < KRA / 8; ++v) {
+        cnn_u4 h, l;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          unsigned he, le;
+          bf16_split2(ra[8 * v + 2 * e], ra[8 * v + 2 * e + 1], he, le);
+          h[e] = he;
+          l[e] = le;
+        }
+        *reinterpret_cast<cnn_u4*>(&ah[st][am[0]][ak[0] + 8 * v]) = h;
+        *reinterpret_cast<cnn_u4*>(&al[st][am[0]][ak[0] + 8 * v]) = l;
+      }
+    }
+    if constexpr (Bm::KFAST) {
+#pragma unroll
+      for (int r = 0; r < KRB; r += 2) {
+        unsigned h, l;
+        bf16_split2(rb[r], rb[r + 1], h, l);
+        bh[st][bn[r]][bk[r]] = (unsigned short)h;
+        bl[st][bn[r]][bk[r]] = (unsigned short)l;
+        bh[st][bn[r + 1]][bk[r + 1]] = (unsigned short)(h >> 16);
+        bl[st][bn[r + 1]][bk[r + 1]] = (unsigned short)(l >> 16);
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < KRB / 8; ++v) {
+        cnn_u4 h, l;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          unsigned he, le;
+          bf16_split2(rb[8 * v + 2 * e], rb[8 * v + 2 * e + 1], he, le);
+          h[e] = he;
+          l[e] = le;
+        }
+        *reinterpret_cast<cnn_u4*>(&bh[st][bn[0]][bk[0] + 8 * v]) = h;
+        *reinterpret_cast<cnn_u4*>(&bl[st][bn[0]][bk[0] + 8 * v]) = l;
+      }
+    }
+  };
+  auto run = [&](auto whole) __attribute__((always_inline)) {
+    constexpr bool W = decltype(whole)::value;
+    auto fetch = [&](int k0) __attribute__((always_inline)) {
+      if constexpr (W) fetch_steps(k0);
+      else fetch_tested(k0);
+    };
+    fetch(kb);
+    stash(0);
+    __syncthreads();
+    int st = 0;
+    for (int k0 = kb; k0 < ke; k0 += KS2) {
+      // as in k_tgemm: the tested loop fetches and stashes unconditionally
+      // (zeros past the end), the whole-step loop skips the step past the end
+      const bool more = k0 + KS2 < ke;
+      if (!W || more) fetch(k0 + KS2);
+      cnn_u4 fa[TI][2], fb[TJ][2];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        fa[i][0] = *reinterpret_cast<const cnn_u4*>(&ah[st][wm + 16 * i + r16][g8]);
+        fa[i][1] = *reinterpret_cast<const cnn_u4*>(&al[st][wm + 16 * i + r16][g8]);
+      }
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        fb[j][0] = *reinterpret_cast<const cnn_u4*>(&bh[st][wn + 16 * j + r16][g8]);
+        fb[j][1] = *reinterpret_cast<const cnn_u4*>(&bl[st][wn + 16 * j + r16][g8]);
+      }
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(cnn_b8, fa[i][0]),
+                                                              __builtin_bit_cast(cnn_b8, fb[j][0]), acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(cnn_b8, fa[i][0]),
+                                                              __builtin_bit_cast(cnn_b8, fb[j][1]), acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(cnn_b8, fa[i][1]),
+                                                              __builtin_bit_cast(cnn_b8, fb[j][0]), acc[i][j], 0, 0, 0);
+        }
+      if (!W || more) stash(st ^ 1);
+      __syncthreads();
+      st ^= 1;
+    }
+  };
+  bool whole = false;
+  if constexpr (HasStep<A>::value && HasStep<Bm>::value) {
+    whole = (ke - kb) % KS2 == 0 && m0 + TM <= M && n0 + TN <= N && a.stepwise(TM) && b.stepwise(TN);
+  }
+  if (whole) run(std::true_type{});
+  else run(std::false_type{});
+  if constexpr (out_quad<Out>()) {
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        const int m = m0 + wm + 16 * i + 4 * (lane >> 4), n = n0 + wn + 16 * j + r16;
+        if (m < M && n < N) out.quad(m, n, acc[i][j]);
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r, n = n0 + wn + 16 * j + r16;
+          if (m < M && n < N) out(m, n, acc[i][j][r], blockIdx.z);
+        }
+  }
+}
+
 // Forward convolution, A(m, k) = the input pixel under tap t of channel c,
 // with K ordered tap-major: k = t ci + c, t = 3 (dy + 1) + (dx + 1) (the
 // weights are read in their stored [co][ci][3][3] order through WeightTap).
 // Output pixels are ordered by 2 x 2 pooling quad, m = ((b, Y, X), q), pixel
 // (2 Y + q / 2, 2 X + q % 2), so that the four accumulator rows of a lane
 // are one quad.  Offsets are 32-bit (inputs below 2^30 elements).  For
-// ci >= 16 the values a thread loads in one 16-deep step (k = k0 + kw + ks r,
-// r < 16 / ks) share one tap: one bounds test, and the channels are ks
-// planes apart.
+// ci >= 32 the values a thread loads in one 16- or 32-deep step (k = k0 +
+// kw + ks r) share one tap: one bounds test, and the channels are ks planes
+// apart.
 struct ConvFwdA {
   static constexpr bool KFAST = false;
   static constexpr bool STEP = true;
@@ -236,7 +437,7 @@ struct ConvFwdA {
     if ((unsigned)yy >= (unsigned)w || (unsigned)xx >= (unsigned)w) return 0.0f;
     return in[(unsigned)(((((bb << lci) + c) << lw) + yy) << lw) + (unsigned)xx];
   }
-  __device__ bool stepwise(int) const { return lci >= 4; }
+  __device__ bool stepwise(int) const { return lci >= 5; }  // 32-deep steps share a tap too
   template <int CNT>
   __device__ void step(int m, int k0, int kw, int ks, float* v) const {
     int bb, y, x;
@@ -298,7 +499,7 @@ struct WeightT {
 
 // data gradient, A(m = (b, y, x), k) = g[b][o][y - dy + 1][x - dx + 1] with
 // K tap-major as in the forward convolution: k = t co + o, t = 3 (dy + 1) +
-// (dx + 1).  32-bit offsets (gradients below 2^30 elements); for co >= 16 a
+// (dx + 1).  32-bit offsets (gradients below 2^30 elements); for co >= 32 a
 // thread's values of one 16-deep step share one tap (one bounds test).
 struct ConvBwdDataA {
   static constexpr bool KFAST = false;
@@ -313,7 +514,7 @@ struct ConvBwdDataA {
     if ((unsigned)yy >= (unsigned)w || (unsigned)xx >= (unsigned)w) return 0.0f;
     return g[(unsigned)(((((bb << lco) + o) << lw) + yy) << lw) + (unsigned)xx];
   }
-  __device__ bool stepwise(int) const { return lco >= 4; }
+  __device__ bool stepwise(int) const { return lco >= 5; }
   template <int CNT>
   __device__ void step(int m, int k0, int kw, int ks, float* v) const {
     const int w = 1 << lw;
@@ -328,7 +529,7 @@ struct ConvBwdDataA {
   }
 };
 // B(k = t co + o, n = c) = w[o][c][t], read from the tap-major rows wt[o][t ci
-// + c] (contiguous in n).  For co >= 16 a thread's values of one step share
+// + c] (contiguous in n).  For co >= 32 a thread's values of one step share
 // the tap and lie ks rows apart.
 struct WeightBwdData {
   static constexpr bool KFAST = false;
@@ -339,7 +540,7 @@ struct WeightBwdData {
     const int t = k >> lco, o = k & ((1 << lco) - 1);
     return wt[(unsigned)(o * 9 * ci + t * ci + n)];
   }
-  __device__ bool stepwise(int) const { return lco >= 4; }
+  __device__ bool stepwise(int) const { return lco >= 5; }
   template <int CNT>
   __device__ void step(int n, int k0, int kw, int ks, float* v) const {
     const int t = k0 >> lco, o = (k0 & ((1 << lco) - 1)) + kw;
@@ -512,6 +713,30 @@ static hipError_t gemm(A a, Bm b, Out out, int M, int N, int K, int splits, hipS
                        out, M, N, K, kslice);
   } else {
     hipLaunchKernelGGL((k_tgemm<64, 64, A, Bm, Out>), dim3((N + 63) / 64, (M + 63) / 64, z), dim3(256), 0, st, a, b,
+                       out, M, N, K, kslice);
+  }
+  return hipGetLastError();
+}
+
+// the forward products with BF16 split operands (k_tgemm_s), no K split;
+// tiles as gemm's
+template <class A, class Bm, class Out>
+static hipError_t gemm_split(A a, Bm b, Out out, int M, int N, int K, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int kslice = (K + KS2 - 1) / KS2 * KS2;
+  const int tn = N <= 32 ? 32 : N <= 64 ? 64 : 128;
+  const bool wide = (int64_t)((N + tn - 1) / tn) * ((M + 127) / 128) >= 512;
+  if (wide && N <= 32) {
+    hipLaunchKernelGGL((k_tgemm_s<128, 32, A, Bm, Out>), dim3((N + 31) / 32, (M + 127) / 128), dim3(256), 0, st,
+                       a, b, out, M, N, K, kslice);
+  } else if (wide && N <= 64) {
+    hipLaunchKernelGGL((k_tgemm_s<128, 64, A, Bm, Out>), dim3((N + 63) / 64, (M + 127) / 128), dim3(256), 0, st,
+                       a, b, out, M, N, K, kslice);
+  } else if (wide) {
+    hipLaunchKernelGGL((k_tgemm_s<128, 128, A, Bm, Out>), dim3((N + 127) / 128, (M + 127) / 128), dim3(256), 0, st,
+                       a, b, out, M, N, K, kslice);
+  } else {
+    hipLaunchKernelGGL((k_tgemm_s<64, 64, A, Bm, Out>), dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, st, a, b,
                        out, M, N, K, kslice);
   }
   return hipGetLastError();
@@ -1172,9 +1397,11 @@ hipError_t init_params(float* params, const Layout& lay, uint64_t seed, hipStrea
   return hipGetLastError();
 }
 
-// forward; act holds p_i (i = 0..3), in training arg_i, and the logits
+// forward; act holds p_i (i = 0..3), in training arg_i, and the logits; split:
+// inference products with BF16 split operands (k_tgemm_s)
 hipError_t forward(const float* params, const Layout& lay, const float* x, int64_t bsz, const Acts& act,
-                   hipStream_t st, bool train) {
+                   hipStream_t st, bool train, bool split) {
+  split = split && !train;
   hipLaunchKernelGGL(k_weights_tap, dim3(nb(kTapWeights)), dim3(256), 0, st, params, lay, act.wt);
   const float* a = x;
   int ci = 1, w = kInSize;
@@ -1185,16 +1412,19 @@ hipError_t forward(const float* params, const Layout& lay, const float* x, int64
     const int lci = ilog2(ci);
     // each convolution pools in its epilogue: only the pooled maps (and, in
     // training, the gradient positions) are written
-    e = gemm(ConvFwdA{a, ci, lci, lw}, WeightT{act.wt + tap_weights_offset(i), K},
-             ConvReluPoolOut{act.p[i], params + lay.conv_b[i], co, lw - 1, train ? act.arg[i] : nullptr}, M, co, K,
-             1, st, true);
+    const ConvReluPoolOut o{act.p[i], params + lay.conv_b[i], co, lw - 1, train ? act.arg[i] : nullptr};
+    e = split ? gemm_split(ConvFwdA{a, ci, lci, lw}, WeightT{act.wt + tap_weights_offset(i), K}, o, M, co, K, st)
+              : gemm(ConvFwdA{a, ci, lci, lw}, WeightT{act.wt + tap_weights_offset(i), K}, o, M, co, K, 1, st, true);
     if (e != hipSuccess) return e;
     a = act.p[i];
     ci = co;
     w /= 2;
   }
-  return gemm(RowK{a, kFeatures}, WeightT{params + lay.fc_w, kFeatures},
-              RowOut{act.logits, params + lay.fc_b, lay.classes}, (int)bsz, lay.classes, kFeatures, 1, st, true);
+  const RowOut o{act.logits, params + lay.fc_b, lay.classes};
+  return split ? gemm_split(RowK{a, kFeatures}, WeightT{params + lay.fc_w, kFeatures}, o, (int)bsz, lay.classes,
+                            kFeatures, st)
+               : gemm(RowK{a, kFeatures}, WeightT{params + lay.fc_w, kFeatures}, o, (int)bsz, lay.classes, kFeatures, 1,
+                      st, true);
 }
 
 static int splits_for(int64_t k_len, int64_t tiles) {

@@ -306,3 +306,10 @@ def test_plan_arguments_are_checked_on_the_host():
     b = pkg.Batch(0x3000, 4, 128)
     assert lib.ebsd_index_patterns_plan(None, ctypes.byref(b), vp(1), None, vp(2), vp(3), None, None) == -1
     assert lib.ebsd_plan_destroy(None) == 0
+
+
+def test_cnn_precision_is_checked_on_the_host():
+    import paper_1807_11313_amd as pkg
+    lib = pkg.lib()
+    assert lib.ebsd_cnn_set_precision(None, pkg.PREC_FP32) == -1
+    assert lib.ebsd_cnn_set_precision(None, pkg.PREC_BF16X2) == -1

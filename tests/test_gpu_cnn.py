@@ -127,6 +127,40 @@ def test_forward_at_full_width_matches_oracle_on_sampled_patterns():
     net.close()
 
 
+def test_inference_precisions_match_oracle():
+    # FP32 inference products within 1e-5 of the largest score, the default
+    # BF16 split (hi + lo halves, three products) within 1e-4; at 2,048
+    # patterns every layer takes its 128-row tiles
+    banner("cnn inference precisions vs oracle")
+    t = tm()
+    n_cls, bsz = 8000, 2048
+    rng = np.random.default_rng(17)
+    net = t.Cnn(n_cls, seed=7)
+    params = _seeded_params(rng, n_cls)
+    net.set_params(dev(params))
+    xs = rng.normal(size=(bsz, 64, 64)).astype(np.float32)
+    x = dev(xs)
+    rows = [0, 5, 1000, 2047]
+    ref, _ = ocnn.forward(params.astype(np.float64), xs[rows].astype(np.float64), n_cls)
+    scale = np.max(np.abs(ref))
+    split = host(net.forward(x))
+    net.set_precision(t.PREC_FP32)
+    fp32 = host(net.forward(x))
+    net.set_precision(t.PREC_BF16X2)
+    again = host(net.forward(x))
+    e32 = np.max(np.abs(fp32[rows] - ref)) / scale
+    esp = np.max(np.abs(split[rows] - ref)) / scale
+    print("[gpu]   fp32 %.2e, bf16 split %.2e (relative to the largest score)" % (e32, esp), flush=True)
+    assert e32 <= 1e-5
+    assert esp <= 1e-4
+    assert np.array_equal(split, again)
+    with pytest.raises(t.EbsdError):
+        net.set_precision(t.PREC_FP16X2)
+    with pytest.raises(t.EbsdError):
+        net.set_precision(7)
+    net.close()
+
+
 def test_gradients_of_a_batch_are_the_mean_over_its_slices():
     # A batch of 256 at 8,000 classes takes the 128-row and 64 x 32 tiles and
     # the whole-step fetches; the gradient of its mean loss is the mean of
