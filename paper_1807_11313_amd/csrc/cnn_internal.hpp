@@ -36,7 +36,8 @@ constexpr int64_t kTapWeights = tap_weights_offset(4);
 // Activations of a batch: p[i] conv i output after ReLU and the pool,
 // arg[i] the gradient positions of its pool, g[i] gradient at conv i's
 // output (through ReLU), dp[i] gradient at p[i]; logits and their gradient
-// dz; wt the tap-major copy of the convolution weights.
+// dz; wt the tap-major copy of the convolution weights and the split
+// halves of the weights for inference.
 struct Acts {
   uint8_t* arg[4];  // per pooled output: the quad position its gradient goes to (4: none)
   float* p[4];
@@ -45,13 +46,21 @@ struct Acts {
   float* logits;
   float* dz;
   float* wt;
+  // split inference: BF16 halves of wt (layer i's rows at 2 x its offset) and
+  // of the fc weights, rows interleaving groups of 8 hi and 8 lo halves
+  unsigned short* wts;
+  unsigned short* fcs;
 };
 
 hipError_t init_params(float* params, const Layout& lay, uint64_t seed, hipStream_t st);
-// Writes the tap-major weights act.wt, then each convolution its pooled map
-// act.p; train: also the gradient positions act.arg that the backward pass
-// needs.  split (inference only; training is FP32): the products take BF16
-// hi + lo halves of their FP32 operands, three products per tile.
+// Weights in the forms the products read: the tap-major copy act.wt and,
+// with split, the BF16 halves of it and of the fc weights.  Once per
+// parameter version, before forward / backward.
+hipError_t prepare(const float* params, const Layout& lay, const Acts& act, bool split, hipStream_t st);
+// Each convolution writes its pooled map act.p; train: also the gradient
+// positions act.arg that the backward pass needs.  split (inference only;
+// training is FP32): the products take BF16 hi + lo halves of their FP32
+// operands, three products per tile.
 hipError_t forward(const float* params, const Layout& lay, const float* x, int64_t bsz, const Acts& act,
                    hipStream_t st, bool train = true, bool split = false);
 // Gradient of the mean cross-entropy into grad (all of it overwritten), from

@@ -161,6 +161,9 @@ int ensure_ws(ebsd_cnn_s* c, int64_t bsz, hipStream_t st) {
   const size_t o_dz = take((size_t)bsz * c->lay.classes);
   const size_t o_part = take(kPartFloats);
   const size_t o_wt = take((size_t)cnn::kTapWeights);
+  // BF16 hi and lo halves (one float slot each) of the tap-major and the fc weights
+  const size_t o_wts = take((size_t)cnn::kTapWeights);
+  const size_t o_fcs = take((size_t)c->lay.classes * cnn::kFeatures);
   const size_t loss_bytes = sizeof(double) * (size_t)bsz;
   if (hipMalloc(&c->ws, off * sizeof(float) + loss_bytes) != hipSuccess)
     return fail(EBSD_E_NOMEM, "cnn workspace allocation failed");
@@ -175,6 +178,8 @@ int ensure_ws(ebsd_cnn_s* c, int64_t bsz, hipStream_t st) {
   c->act.dz = base + o_dz;
   c->part = base + o_part;
   c->act.wt = base + o_wt;
+  c->act.wts = reinterpret_cast<unsigned short*>(base + o_wts);
+  c->act.fcs = reinterpret_cast<unsigned short*>(base + o_fcs);
   c->part_floats = kPartFloats;
   c->loss_row = (double*)(base + off);
   c->ws_batch = bsz;
@@ -193,12 +198,13 @@ int forward_chunks(ebsd_cnn_s* c, const float* x, int64_t bsz, float* logits, hi
   int rc;
   if ((rc = ensure_ws(c, std::min(bsz, kChunk), st))) return rc;
   const int L = c->lay.classes;
+  const bool split = c->infer_prec == EBSD_PREC_BF16X2;
+  CN_TRY(cnn::prepare(c->params, c->lay, c->act, split, st), "cnn weights");
   for (int64_t s = 0; s < bsz; s += kChunk) {
     const int64_t b = std::min(kChunk, bsz - s);
     cnn::Acts a = c->act;
     a.logits = logits + s * L;
-    CN_TRY(cnn::forward(c->params, c->lay, x + s * cnn::kInSize * cnn::kInSize, b, a, st, false,
-                        c->infer_prec == EBSD_PREC_BF16X2),
+    CN_TRY(cnn::forward(c->params, c->lay, x + s * cnn::kInSize * cnn::kInSize, b, a, st, false, split),
            "cnn forward");
   }
   return EBSD_OK;
@@ -207,6 +213,7 @@ int forward_chunks(ebsd_cnn_s* c, const float* x, int64_t bsz, float* logits, hi
 int grads(ebsd_cnn_s* c, const float* x, const int32_t* labels, int64_t bsz, float* loss, hipStream_t st) {
   int rc;
   if ((rc = ensure_ws(c, bsz, st))) return rc;
+  CN_TRY(cnn::prepare(c->params, c->lay, c->act, false, st), "cnn weights");
   CN_TRY(cnn::forward(c->params, c->lay, x, bsz, c->act, st), "cnn forward");
   CN_TRY(cnn::backward(c->params, c->lay, x, labels, bsz, c->act, c->grad, c->part, c->part_floats, c->loss_row,
                        loss, st),

@@ -233,6 +233,25 @@ __device__ __forceinline__ void bf16_split2(float a, float b, unsigned& hi, unsi
   lo = __builtin_bit_cast(unsigned, __builtin_convertvector(cnn_f2{a - ha, b - hb}, cnn_bf2));
 }
 
+// B operands whose BF16 halves were split ahead of the product (PRESPLIT)
+template <class T, class = void>
+struct PreSplit : std::false_type {};
+template <class T>
+struct PreSplit<T, std::void_t<decltype(T::PRESPLIT)>> : std::bool_constant<T::PRESPLIT> {};
+// B(k, n) = the BF16 halves of w[n][k], split ahead into rows of 2 k_len
+// halves that interleave groups of 8: hi of k = 8 g .. 8 g + 7, then their
+// lo (k_len a multiple of 32, rows 16-byte aligned), so a 32-deep step of
+// one row is one 128-byte line and a thread loads its groups as vectors
+struct SplitRowsB {
+  static constexpr bool PRESPLIT = true;
+  static constexpr bool KFAST = true;
+  static constexpr bool STEP = true;
+  const unsigned short* w;
+  int k_len;
+  __device__ bool stepwise(int) const { return true; }
+  __device__ size_t hi_at(int n, int k) const { return (size_t)n * 2 * k_len + (k >> 3) * 16 + (k & 7); }
+};
+
 template <int TM, int TN, class A, class Bm, class Out>
 __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int N, int K, int kslice) {
   static_assert((TM == 64 || TM == 128) && (TN == 32 || TN == 64 || TN == 128), "tile");
@@ -267,12 +286,42 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
     bk[r] = Bm::KFAST ? tid % KS2 : (tid / TN) * KRB + r;
   }
   float ra[KRA], rb[KRB];
+  // pre-split B: 256 / TN threads per column n, KPT consecutive k each, as
+  // KPT / 2 dwords of hi and of lo halves
+  constexpr int TPN = 256 / TN, KPT = KS2 / TPN;
+  const int pn = tid / TPN, pk = (tid % TPN) * KPT;
+  unsigned bhv[KPT / 2], blv[KPT / 2];
   auto fetch_steps = [&](int k0) __attribute__((always_inline)) {
     if constexpr (HasStep<A>::value && HasStep<Bm>::value) {
       if constexpr (A::KFAST) a.template stepk<KRA>(m0 + am[0], k0 + ak[0], 256 / KS2, ra);
       else a.template step<KRA>(m0 + am[0], k0, ak[0], 1, ra);
-      if constexpr (Bm::KFAST) b.template stepk<KRB>(n0 + bn[0], k0 + bk[0], 256 / KS2, rb);
-      else b.template step<KRB>(n0 + bn[0], k0, bk[0], 1, rb);
+      if constexpr (PreSplit<Bm>::value) {
+        const size_t o = b.hi_at(n0 + pn, k0 + pk);
+        if constexpr (KPT >= 8) {
+#pragma unroll
+          for (int v = 0; v < KPT / 8; ++v) {
+            const cnn_u4 h = *reinterpret_cast<const cnn_u4*>(b.w + o + 16 * v);
+            const cnn_u4 l = *reinterpret_cast<const cnn_u4*>(b.w + o + 16 * v + 8);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              bhv[4 * v + e] = h[e];
+              blv[4 * v + e] = l[e];
+            }
+          }
+        } else {
+          typedef unsigned cnn_u2 __attribute__((ext_vector_type(2)));
+          const cnn_u2 h = *reinterpret_cast<const cnn_u2*>(b.w + o);
+          const cnn_u2 l = *reinterpret_cast<const cnn_u2*>(b.w + o + 8);
+          bhv[0] = h[0];
+          bhv[1] = h[1];
+          blv[0] = l[0];
+          blv[1] = l[1];
+        }
+      } else if constexpr (Bm::KFAST) {
+        b.template stepk<KRB>(n0 + bn[0], k0 + bk[0], 256 / KS2, rb);
+      } else {
+        b.template step<KRB>(n0 + bn[0], k0, bk[0], 1, rb);
+      }
     }
   };
   auto fetch_tested = [&](int k0) __attribute__((always_inline)) {
@@ -281,10 +330,22 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
       const int m = m0 + am[r], k = k0 + ak[r];
       ra[r] = (m < M && k < ke) ? a(m, k) : 0.0f;
     }
+    if constexpr (PreSplit<Bm>::value) {
+      const int n = n0 + pn;
 #pragma unroll
-    for (int r = 0; r < KRB; ++r) {
-      const int n = n0 + bn[r], k2 = k0 + bk[r];
-      rb[r] = (n < N && k2 < ke) ? b(k2, n) : 0.0f;
+      for (int e = 0; e < KPT / 2; ++e) {
+        const int k2 = k0 + pk + 2 * e;  // even: k2 and k2 + 1 share a group
+        const bool ok0 = n < N && k2 < ke, ok1 = n < N && k2 + 1 < ke;
+        const size_t o = ok0 ? b.hi_at(n, k2) : 0;
+        bhv[e] = (ok0 ? b.w[o] : 0u) | ((ok1 ? b.w[o + 1] : 0u) << 16);
+        blv[e] = (ok0 ? b.w[o + 8] : 0u) | ((ok1 ? b.w[o + 9] : 0u) << 16);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < KRB; ++r) {
+        const int n = n0 + bn[r], k2 = k0 + bk[r];
+        rb[r] = (n < N && k2 < ke) ? b(k2, n) : 0.0f;
+      }
     }
   };
   // split and store one step's values into stage st
@@ -314,7 +375,21 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
         *reinterpret_cast<cnn_u4*>(&al[st][am[0]][ak[0] + 8 * v]) = l;
       }
     }
-    if constexpr (Bm::KFAST) {
+    if constexpr (PreSplit<Bm>::value) {
+      if constexpr (KPT >= 8) {
+#pragma unroll
+        for (int v = 0; v < KPT / 8; ++v) {
+          *reinterpret_cast<cnn_u4*>(&bh[st][pn][pk + 8 * v]) =
+              cnn_u4{bhv[4 * v], bhv[4 * v + 1], bhv[4 * v + 2], bhv[4 * v + 3]};
+          *reinterpret_cast<cnn_u4*>(&bl[st][pn][pk + 8 * v]) =
+              cnn_u4{blv[4 * v], blv[4 * v + 1], blv[4 * v + 2], blv[4 * v + 3]};
+        }
+      } else {
+        typedef unsigned cnn_u2 __attribute__((ext_vector_type(2)));
+        *reinterpret_cast<cnn_u2*>(&bh[st][pn][pk]) = cnn_u2{bhv[0], bhv[1]};
+        *reinterpret_cast<cnn_u2*>(&bl[st][pn][pk]) = cnn_u2{blv[0], blv[1]};
+      }
+    } else if constexpr (Bm::KFAST) {
 #pragma unroll
       for (int r = 0; r < KRB; r += 2) {
         unsigned h, l;
@@ -909,6 +984,29 @@ __global__ void k_weights_tap(const float* __restrict__ params, Layout lay, floa
   wt[j] = params[lay.conv_w[l] + (o * ci + c) * 9 + t];
 }
 
+// BF16 halves (x_hi = bf16(x), x_lo = bf16(x - x_hi)) of rows floats rows of
+// k_len (a multiple of 8) into the interleaved rows of SplitRowsB: a thread
+// takes one group of 8
+__global__ void k_split_rows(const float* __restrict__ x, int64_t rows, int k_len, unsigned short* __restrict__ w) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;  // group index
+  const int gpr = k_len >> 3;
+  if (g >= rows * gpr) return;
+  const int64_t n = g / gpr;
+  const int kg = (int)(g - n * gpr);
+  const float* src = x + n * k_len + 8 * kg;
+  unsigned short* dst = w + n * 2 * k_len + 16 * kg;
+  cnn_u4 h, l;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    unsigned he, le;
+    bf16_split2(src[2 * e], src[2 * e + 1], he, le);
+    h[e] = he;
+    l[e] = le;
+  }
+  *reinterpret_cast<cnn_u4*>(dst) = h;
+  *reinterpret_cast<cnn_u4*>(dst + 8) = l;
+}
+
 // gradient through the ReLU and the 2 x 2 max pool: the pooled gradient goes to the
 // quad position arg recorded by the forward pass (4: to none of them)
 __global__ void k_unpool_bwd(const uint8_t* __restrict__ arg, const float* __restrict__ dpool, int64_t planes,
@@ -1397,12 +1495,29 @@ hipError_t init_params(float* params, const Layout& lay, uint64_t seed, hipStrea
   return hipGetLastError();
 }
 
-// forward; act holds p_i (i = 0..3), in training arg_i, and the logits; split:
-// inference products with BF16 split operands (k_tgemm_s)
+// forward (after prepare on the same parameters); act holds p_i (i = 0..3),
+// in training arg_i, and the logits; split: inference products with BF16
+// split operands (k_tgemm_s), the weights' halves made by prepare
+hipError_t prepare(const float* params, const Layout& lay, const Acts& act, bool split, hipStream_t st) {
+  hipLaunchKernelGGL(k_weights_tap, dim3(nb(kTapWeights)), dim3(256), 0, st, params, lay, act.wt);
+  if (split) {
+    // layers 2-4 (the first stays FP32); layer i's rows start at twice its
+    // tap-major offset
+    for (int i = 1, ci = kChannels[0]; i < 4; ci = kChannels[i], ++i) {
+      const int k_len = 9 * ci;
+      hipLaunchKernelGGL(k_split_rows, dim3(nb((int64_t)kChannels[i] * k_len / 8)), dim3(256), 0, st,
+                         act.wt + tap_weights_offset(i), (int64_t)kChannels[i], k_len,
+                         act.wts + 2 * tap_weights_offset(i));
+    }
+    hipLaunchKernelGGL(k_split_rows, dim3(nb((int64_t)lay.classes * kFeatures / 8)), dim3(256), 0, st,
+                       params + lay.fc_w, (int64_t)lay.classes, kFeatures, act.fcs);
+  }
+  return hipGetLastError();
+}
+
 hipError_t forward(const float* params, const Layout& lay, const float* x, int64_t bsz, const Acts& act,
                    hipStream_t st, bool train, bool split) {
   split = split && !train;
-  hipLaunchKernelGGL(k_weights_tap, dim3(nb(kTapWeights)), dim3(256), 0, st, params, lay, act.wt);
   const float* a = x;
   int ci = 1, w = kInSize;
   hipError_t e;
@@ -1413,7 +1528,11 @@ hipError_t forward(const float* params, const Layout& lay, const float* x, int64
     // each convolution pools in its epilogue: only the pooled maps (and, in
     // training, the gradient positions) are written
     const ConvReluPoolOut o{act.p[i], params + lay.conv_b[i], co, lw - 1, train ? act.arg[i] : nullptr};
-    e = split ? gemm_split(ConvFwdA{a, ci, lci, lw}, WeightT{act.wt + tap_weights_offset(i), K}, o, M, co, K, st)
+    // the first layer (K = 9, one input channel) stays FP32: a 32-deep step
+    // would be mostly padding
+    e = split && i > 0
+            ? gemm_split(ConvFwdA{a, ci, lci, lw},
+                         SplitRowsB{act.wts + 2 * tap_weights_offset(i), K}, o, M, co, K, st)
               : gemm(ConvFwdA{a, ci, lci, lw}, WeightT{act.wt + tap_weights_offset(i), K}, o, M, co, K, 1, st, true);
     if (e != hipSuccess) return e;
     a = act.p[i];
@@ -1421,7 +1540,7 @@ hipError_t forward(const float* params, const Layout& lay, const float* x, int64
     w /= 2;
   }
   const RowOut o{act.logits, params + lay.fc_b, lay.classes};
-  return split ? gemm_split(RowK{a, kFeatures}, WeightT{params + lay.fc_w, kFeatures}, o, (int)bsz, lay.classes,
+  return split ? gemm_split(RowK{a, kFeatures}, SplitRowsB{act.fcs, kFeatures}, o, (int)bsz, lay.classes,
                             kFeatures, st)
                : gemm(RowK{a, kFeatures}, WeightT{params + lay.fc_w, kFeatures}, o, (int)bsz, lay.classes, kFeatures, 1,
                       st, true);
