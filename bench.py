@@ -912,7 +912,10 @@ def learned_proposal(tm, library, n_train, epochs, n_test, k=32, bsz=256, n=128)
     ex, t_ex = timed(lambda: tm.index_patterns(test, master, pc, lq))
     pr, t_pr = timed(lambda: tm.index_proposed(test, master, pc, lq, net, top_k=k, fallback_tau=tau))
     x_test = tm.Cnn.input(test[:bsz * 8])
-    _, t_fwd = timed(lambda: net.forward(x_test), reps=5)
+    _, t_fwd = timed(lambda: net.forward(x_test), reps=5)  # default inference precision: BF16 split halves
+    net.set_precision(tm.PREC_FP32)
+    _, t_fwd32 = timed(lambda: net.forward(x_test), reps=5)
+    net.set_precision(tm.PREC_BF16X2)
     # both picks refined the same way (the library pick is only the start)
     rf_ex, t_rf = timed(lambda: tm.refine_from_match(test, master, pc, ex["best_q"], ex["shift"], pc_per=pc_per),
                         reps=1)
@@ -927,8 +930,9 @@ def learned_proposal(tm, library, n_train, epochs, n_test, k=32, bsz=256, n=128)
     rpr = np.rad2deg([rotations.disorientation_q(q_pr[i], q_test[i]) for i in pts])
     rpe = np.rad2deg([rotations.disorientation_q(q_pr[i], q_ex[i]) for i in pts])
     pairs_pr = n_test * k + int(fb.sum()) * library
-    res = {"workload": "proposal: CNN (4 conv 32-128 ch on 64x64 binned input, fc to %d) trained on the GPU on "
-                       "%d projected noisy patterns x %.1f epochs; %d test patterns at 128x128 fp32, top-%d "
+    res = {"workload": "proposal: CNN (4 conv 32-128 ch on 64x64 binned input, fc to %d) trained on the GPU (FP32) "
+                       "on %d projected noisy patterns x %.1f epochs; inference products on BF16 split halves "
+                       "(hi*hi + hi*lo + lo*hi, FP32 sums); %d test patterns at 128x128 fp32, top-%d "
                        "correlation with exhaustive fallback below tau" % (library, n_train, epochs, n_test, k),
            "train_s": t_train, "train_steps": steps, "batch": bsz, "final_loss": final_loss,
            "train_samples_per_s": steps * bsz / t_train,
@@ -937,6 +941,8 @@ def learned_proposal(tm, library, n_train, epochs, n_test, k=32, bsz=256, n=128)
                                    "frac": train_flops / t_step / PEAK_MFMA_FP32,
                                    "flops_per_sample_forward": cnn_flops_per_sample(library)},
            "forward_patterns_per_s": bsz * 8 / t_fwd,
+           "forward_patterns_per_s_fp32": bsz * 8 / t_fwd32,
+           "forward_tflops_network": cnn_flops_per_sample(library) * bsz * 8 / t_fwd / 1e12,
            "tau": tau, "tau_rule": "1st percentile of the exhaustive integer peak height among the correctly "
                                    "indexed of 10,000 validation patterns (refined within 1 deg of the truth)",
            "validation_correctly_indexed": float(ok_val.mean()), "tau_over_all_validation": tau_all,
