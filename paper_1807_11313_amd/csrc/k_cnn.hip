@@ -291,9 +291,17 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
   constexpr int TPN = 256 / TN, KPT = KS2 / TPN;
   const int pn = tid / TPN, pk = (tid % TPN) * KPT;
   unsigned bhv[KPT / 2], blv[KPT / 2];
-  auto fetch_steps = [&](int k0) __attribute__((always_inline)) {
+  // pre-split A likewise: 256 / TM threads per row m, KPTA consecutive k each
+  constexpr int TPM = 256 / TM, KPTA = KS2 / TPM;
+  const int pm = tid / TPM, pka = (tid % TPM) * KPTA;
+  unsigned ahv[KPTA / 2], alv[KPTA / 2];
+  // the fetches return whether the A values are valid (a pre-split A's tap
+  // outside the image: the stash stores zeros)
+  auto fetch_steps = [&](int k0) __attribute__((always_inline)) -> int {
+    int ok = 1;
     if constexpr (HasStep<A>::value && HasStep<Bm>::value) {
-      if constexpr (A::KFAST) a.template stepk<KRA>(m0 + am[0], k0 + ak[0], 256 / KS2, ra);
+      if constexpr (PreSplit<A>::value) ok = a.template split_at<KPTA>(m0 + pm, k0 + pka, ahv, alv) ? 1 : 0;
+      else if constexpr (A::KFAST) a.template stepk<KRA>(m0 + am[0], k0 + ak[0], 256 / KS2, ra);
       else a.template step<KRA>(m0 + am[0], k0, ak[0], 1, ra);
       if constexpr (PreSplit<Bm>::value) {
         const size_t o = b.hi_at(n0 + pn, k0 + pk);
@@ -323,12 +331,22 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
         b.template step<KRB>(n0 + bn[0], k0, bk[0], 1, rb);
       }
     }
+    return ok;
   };
-  auto fetch_tested = [&](int k0) __attribute__((always_inline)) {
+  auto fetch_tested = [&](int k0) __attribute__((always_inline)) -> int {
+    if constexpr (PreSplit<A>::value) {
+      const int m = m0 + pm;
 #pragma unroll
-    for (int r = 0; r < KRA; ++r) {
-      const int m = m0 + am[r], k = k0 + ak[r];
-      ra[r] = (m < M && k < ke) ? a(m, k) : 0.0f;
+      for (int e = 0; e < KPTA / 2; ++e) {
+        const int k2 = k0 + pka + 2 * e;  // even: k2 and k2 + 1 share a group and a tap (ci even)
+        a.pair_at(m, k2, m < M && k2 < ke, m < M && k2 + 1 < ke, ahv[e], alv[e]);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < KRA; ++r) {
+        const int m = m0 + am[r], k = k0 + ak[r];
+        ra[r] = (m < M && k < ke) ? a(m, k) : 0.0f;
+      }
     }
     if constexpr (PreSplit<Bm>::value) {
       const int n = n0 + pn;
@@ -347,10 +365,21 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
         rb[r] = (n < N && k2 < ke) ? b(k2, n) : 0.0f;
       }
     }
+    return 1;
   };
   // split and store one step's values into stage st
-  auto stash = [&](int st) __attribute__((always_inline)) {
-    if constexpr (A::KFAST) {
+  auto stash = [&](int st, int ok) __attribute__((always_inline)) {
+    if constexpr (PreSplit<A>::value) {
+      if constexpr (KPTA >= 8) {
+#pragma unroll
+        for (int v = 0; v < KPTA / 8; ++v) {
+          *reinterpret_cast<cnn_u4*>(&ah[st][pm][pka + 8 * v]) =
+              ok ? cnn_u4{ahv[4 * v], ahv[4 * v + 1], ahv[4 * v + 2], ahv[4 * v + 3]} : cnn_u4{0u, 0u, 0u, 0u};
+          *reinterpret_cast<cnn_u4*>(&al[st][pm][pka + 8 * v]) =
+              ok ? cnn_u4{alv[4 * v], alv[4 * v + 1], alv[4 * v + 2], alv[4 * v + 3]} : cnn_u4{0u, 0u, 0u, 0u};
+        }
+      }
+    } else if constexpr (A::KFAST) {
 #pragma unroll
       for (int r = 0; r < KRA; r += 2) {
         unsigned h, l;
@@ -417,19 +446,19 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
   };
   auto run = [&](auto whole) __attribute__((always_inline)) {
     constexpr bool W = decltype(whole)::value;
-    auto fetch = [&](int k0) __attribute__((always_inline)) {
-      if constexpr (W) fetch_steps(k0);
-      else fetch_tested(k0);
+    auto fetch = [&](int k0) __attribute__((always_inline)) -> int {
+      if constexpr (W) return fetch_steps(k0);
+      else return fetch_tested(k0);
     };
-    fetch(kb);
-    stash(0);
+    stash(0, fetch(kb));
     __syncthreads();
     int st = 0;
     for (int k0 = kb; k0 < ke; k0 += KS2) {
       // as in k_tgemm: the tested loop fetches and stashes unconditionally
       // (zeros past the end), the whole-step loop skips the step past the end
       const bool more = k0 + KS2 < ke;
-      if (!W || more) fetch(k0 + KS2);
+      int ok = 1;
+      if (!W || more) ok = fetch(k0 + KS2);
       cnn_u4 fa[TI][2], fb[TJ][2];
 #pragma unroll
       for (int i = 0; i < TI; ++i) {
@@ -452,7 +481,7 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(cnn_b8, fa[i][1]),
                                                               __builtin_bit_cast(cnn_b8, fb[j][0]), acc[i][j], 0, 0, 0);
         }
-      if (!W || more) stash(st ^ 1);
+      if (!W || more) stash(st ^ 1, ok);
       __syncthreads();
       st ^= 1;
     }
@@ -525,6 +554,86 @@ struct ConvFwdA {
 #pragma unroll
     for (int r = 0; r < CNT; ++r) v[r] = inside ? ld32(in, base + r * plane) : 0.0f;
   }
+};
+// Forward convolution reading an input already split for the BF16 products
+// (k_tgemm_s): in[b][y][x] holds the ci channels' BF16 halves in groups of
+// 8, hi of channels 8 g .. 8 g + 7 then their lo (2 ci halves per pixel,
+// written by ConvReluPoolSplitOut).  K tap-major and output pixels
+// quad-ordered as ConvFwdA.  split_at: a thread's KP consecutive k (one tap,
+// channels c .. c + KP - 1, c a multiple of KP) as KP / 2 dwords of hi and
+// of lo halves, loaded from the clamped pixel; false outside the image.
+struct ConvFwdSA {
+  static constexpr bool PRESPLIT = true;
+  static constexpr bool KFAST = false;
+  static constexpr bool STEP = true;
+  const unsigned short* in;
+  int ci, lci, lw;  // lci = log2 ci
+  __device__ bool stepwise(int) const { return lci >= 5; }
+  __device__ void pix(int m, int& bb, int& y, int& x) const {
+    const int lo = lw - 1, q = m & 3;
+    x = 2 * ((m >> 2) & ((1 << lo) - 1)) + (q & 1);
+    y = 2 * ((m >> (2 + lo)) & ((1 << lo) - 1)) + (q >> 1);
+    bb = m >> (2 * lw);
+  }
+  // hi half of channel c at pixel (bb, y, x); its lo is 8 halves on
+  __device__ unsigned at(int bb, int y, int x, int c) const {
+    return (((((unsigned)bb << lw) + (unsigned)y) << lw) + (unsigned)x) * (unsigned)(2 * ci) + (unsigned)((c >> 3) * 16 + (c & 7));
+  }
+  template <int KP>
+  __device__ bool split_at(int m, int k, unsigned* h, unsigned* l) const {
+    int bb, y, x;
+    pix(m, bb, y, x);
+    const int t = k >> lci, c = k & ((1 << lci) - 1);
+    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1, w = 1 << lw;
+    const bool inside = (unsigned)yy < (unsigned)w && (unsigned)xx < (unsigned)w;
+    const unsigned o = at(bb, min(max(yy, 0), w - 1), min(max(xx, 0), w - 1), c);
+#pragma unroll
+    for (int v = 0; v < KP / 8; ++v) {
+      const cnn_u4 hv = *reinterpret_cast<const cnn_u4*>(in + o + 16 * v);
+      const cnn_u4 lv = *reinterpret_cast<const cnn_u4*>(in + o + 16 * v + 8);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        h[4 * v + e] = hv[e];
+        l[4 * v + e] = lv[e];
+      }
+    }
+    return inside;
+  }
+  // channels c, c + 1 (c even) of tap k / ci at pixel m as (hi, lo) dwords;
+  // ok0 / ok1: whether the two k are inside the product at all
+  __device__ void pair_at(int m, int k, bool ok0, bool ok1, unsigned& h, unsigned& l) const {
+    h = l = 0u;
+    if (!ok0) return;
+    int bb, y, x;
+    pix(m, bb, y, x);
+    const int t = k >> lci, c = k & ((1 << lci) - 1);
+    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1, w = 1 << lw;
+    if ((unsigned)yy >= (unsigned)w || (unsigned)xx >= (unsigned)w) return;
+    const unsigned o = at(bb, yy, xx, c);
+    h = (unsigned)in[o] | (ok1 ? (unsigned)in[o + 1] << 16 : 0u);
+    l = (unsigned)in[o + 8] | (ok1 ? (unsigned)in[o + 9] << 16 : 0u);
+  }
+};
+// The pooled value of ConvReluPoolOut written split for the next layer's
+// ConvFwdSA: out[b][Y][X] holds the co channels' halves in groups of 8
+// (split inference only: no gradient positions)
+struct ConvReluPoolSplitOut {
+  static constexpr bool QUAD = true;
+  unsigned short* out;
+  const float* bias;
+  int co, lw;  // lw: log2 of the pooled side
+  __device__ void quad(int m, int n, const f4c& v) const {
+    const int hw = 1 << (2 * lw);
+    const int bb = (m >> 2) >> (2 * lw), p = (m >> 2) & (hw - 1);
+    const float mx = fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3]));
+    const float pv = fmaxf(mx + bias[n], 0.0f);
+    unsigned h, l;
+    bf16_split2(pv, 0.0f, h, l);
+    const unsigned o = ((unsigned)bb * (unsigned)hw + (unsigned)p) * (unsigned)(2 * co) + (unsigned)((n >> 3) * 16 + (n & 7));
+    out[o] = (unsigned short)h;
+    out[o + 8] = (unsigned short)l;
+  }
+  __device__ void operator()(int, int, float, int) const {}
 };
 // pooled[b][n][Y][X] = max over the quad of max(acc + bias[n], 0), which is
 // max(max over the quad of acc + bias[n], 0): adding the bias and clamping
@@ -1527,13 +1636,26 @@ hipError_t forward(const float* params, const Layout& lay, const float* x, int64
     const int lci = ilog2(ci);
     // each convolution pools in its epilogue: only the pooled maps (and, in
     // training, the gradient positions) are written
-    const ConvReluPoolOut o{act.p[i], params + lay.conv_b[i], co, lw - 1, train ? act.arg[i] : nullptr};
-    // the first layer (K = 9, one input channel) stays FP32: a 32-deep step
-    // would be mostly padding
-    e = split && i > 0
-            ? gemm_split(ConvFwdA{a, ci, lci, lw},
-                         SplitRowsB{act.wts + 2 * tap_weights_offset(i), K}, o, M, co, K, st)
-              : gemm(ConvFwdA{a, ci, lci, lw}, WeightT{act.wt + tap_weights_offset(i), K}, o, M, co, K, 1, st, true);
+    const float* bias = params + lay.conv_b[i];
+    if (!split) {
+      const ConvReluPoolOut o{act.p[i], bias, co, lw - 1, train ? act.arg[i] : nullptr};
+      e = gemm(ConvFwdA{a, ci, lci, lw}, WeightT{act.wt + tap_weights_offset(i), K}, o, M, co, K, 1, st, true);
+    } else {
+      // split inference: the first layer (K = 9, one input channel) in FP32,
+      // a 32-deep step would be mostly padding; layers 1-3 write their pooled
+      // maps split for the next layer's BF16 products (in the FP32 maps'
+      // buffers, the same bytes), the last one FP32 features for the fc
+      const unsigned short* sa = reinterpret_cast<const unsigned short*>(a);
+      const ConvReluPoolSplitOut so{reinterpret_cast<unsigned short*>(act.p[i]), bias, co, lw - 1};
+      const SplitRowsB wb{act.wts + 2 * tap_weights_offset(i), K};
+      if (i == 0)
+        e = gemm(ConvFwdA{a, ci, lci, lw}, WeightT{act.wt, K}, so, M, co, K, 1, st, true);
+      else if (i < 3)
+        e = gemm_split(ConvFwdSA{sa, ci, lci, lw}, wb, so, M, co, K, st);
+      else
+        e = gemm_split(ConvFwdSA{sa, ci, lci, lw}, wb, ConvReluPoolOut{act.p[3], bias, co, lw - 1, nullptr}, M, co,
+                       K, st);
+    }
     if (e != hipSuccess) return e;
     a = act.p[i];
     ci = co;
