@@ -233,17 +233,25 @@ __device__ __forceinline__ void bf16_split2(float a, float b, unsigned& hi, unsi
   lo = __builtin_bit_cast(unsigned, __builtin_convertvector(cnn_f2{a - ha, b - hb}, cnn_bf2));
 }
 
-// B operands whose BF16 halves were split ahead of the product (PRESPLIT)
+// operands whose BF16 halves were split ahead of the product (PRESPLIT),
+// and among them the row-major ones (ROWS: SplitRows, used for B)
 template <class T, class = void>
 struct PreSplit : std::false_type {};
 template <class T>
 struct PreSplit<T, std::void_t<decltype(T::PRESPLIT)>> : std::bool_constant<T::PRESPLIT> {};
-// B(k, n) = the BF16 halves of w[n][k], split ahead into rows of 2 k_len
-// halves that interleave groups of 8: hi of k = 8 g .. 8 g + 7, then their
-// lo (k_len a multiple of 32, rows 16-byte aligned), so a 32-deep step of
-// one row is one 128-byte line and a thread loads its groups as vectors
-struct SplitRowsB {
+template <class T, class = void>
+struct SplitRowsOp : std::false_type {};
+template <class T>
+struct SplitRowsOp<T, std::void_t<decltype(T::ROWS)>> : std::bool_constant<T::ROWS> {};
+// B(k, n) = the BF16 halves of w[n][k], split ahead
+// into rows of 2 k_len halves that interleave groups of 8: hi of k = 8 g ..
+// 8 g + 7, then their lo (k_len a multiple of 32, rows 16-byte aligned), so
+// a 32-deep step of one row is one 128-byte line of 8 16-byte chunks (chunk
+// q: group q / 2, hi for even q, lo for odd).  k_tgemm_s gives each row 8
+// lanes, lane q loading chunk q: a load instruction reads 8 whole lines.
+struct SplitRows {
   static constexpr bool PRESPLIT = true;
+  static constexpr bool ROWS = true;
   static constexpr bool KFAST = true;
   static constexpr bool STEP = true;
   const unsigned short* w;
@@ -286,11 +294,22 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
     bk[r] = Bm::KFAST ? tid % KS2 : (tid / TN) * KRB + r;
   }
   float ra[KRA], rb[KRB];
-  // pre-split B: 256 / TN threads per column n, KPT consecutive k each, as
-  // KPT / 2 dwords of hi and of lo halves
-  constexpr int TPN = 256 / TN, KPT = KS2 / TPN;
-  const int pn = tid / TPN, pk = (tid % TPN) * KPT;
-  unsigned bhv[KPT / 2], blv[KPT / 2];
+  // a row-major pre-split B: 8 lanes per row, lane cq loading the row's
+  // 16-byte chunk cq of the step, rows cr, cr + 32, ...
+  const int cq = tid & 7, cr = tid >> 3;
+  cnn_u4 bc[TN / 32];
+  // a row's chunk cq of the step at k0 (bounds-tested: rows past R, k past ke
+  // give zeros)
+  auto chunk_at = [&](const SplitRows& w, int row, int R, int k0, cnn_u4& c) __attribute__((always_inline)) {
+    const int kg = k0 + (cq >> 1) * 8;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k2 = kg + 2 * e;
+      const bool ok0 = row < R && k2 < ke, ok1 = row < R && k2 + 1 < ke;
+      const size_t o = ok0 ? w.hi_at(row, k2) + (cq & 1) * 8 : 0;
+      c[e] = (ok0 ? (unsigned)w.w[o] : 0u) | (ok1 ? (unsigned)w.w[o + 1] << 16 : 0u);
+    }
+  };
   // pre-split A likewise: 256 / TM threads per row m, KPTA consecutive k each
   constexpr int TPM = 256 / TM, KPTA = KS2 / TPM;
   const int pm = tid / TPM, pka = (tid % TPM) * KPTA;
@@ -303,28 +322,10 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
       if constexpr (PreSplit<A>::value) ok = a.template split_at<KPTA>(m0 + pm, k0 + pka, ahv, alv) ? 1 : 0;
       else if constexpr (A::KFAST) a.template stepk<KRA>(m0 + am[0], k0 + ak[0], 256 / KS2, ra);
       else a.template step<KRA>(m0 + am[0], k0, ak[0], 1, ra);
-      if constexpr (PreSplit<Bm>::value) {
-        const size_t o = b.hi_at(n0 + pn, k0 + pk);
-        if constexpr (KPT >= 8) {
+      if constexpr (SplitRowsOp<Bm>::value) {
 #pragma unroll
-          for (int v = 0; v < KPT / 8; ++v) {
-            const cnn_u4 h = *reinterpret_cast<const cnn_u4*>(b.w + o + 16 * v);
-            const cnn_u4 l = *reinterpret_cast<const cnn_u4*>(b.w + o + 16 * v + 8);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              bhv[4 * v + e] = h[e];
-              blv[4 * v + e] = l[e];
-            }
-          }
-        } else {
-          typedef unsigned cnn_u2 __attribute__((ext_vector_type(2)));
-          const cnn_u2 h = *reinterpret_cast<const cnn_u2*>(b.w + o);
-          const cnn_u2 l = *reinterpret_cast<const cnn_u2*>(b.w + o + 8);
-          bhv[0] = h[0];
-          bhv[1] = h[1];
-          blv[0] = l[0];
-          blv[1] = l[1];
-        }
+        for (int j = 0; j < TN / 32; ++j)
+          bc[j] = *reinterpret_cast<const cnn_u4*>(b.w + b.hi_at(n0 + cr + 32 * j, k0) + 8 * cq);
       } else if constexpr (Bm::KFAST) {
         b.template stepk<KRB>(n0 + bn[0], k0 + bk[0], 256 / KS2, rb);
       } else {
@@ -348,16 +349,9 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
         ra[r] = (m < M && k < ke) ? a(m, k) : 0.0f;
       }
     }
-    if constexpr (PreSplit<Bm>::value) {
-      const int n = n0 + pn;
+    if constexpr (SplitRowsOp<Bm>::value) {
 #pragma unroll
-      for (int e = 0; e < KPT / 2; ++e) {
-        const int k2 = k0 + pk + 2 * e;  // even: k2 and k2 + 1 share a group
-        const bool ok0 = n < N && k2 < ke, ok1 = n < N && k2 + 1 < ke;
-        const size_t o = ok0 ? b.hi_at(n, k2) : 0;
-        bhv[e] = (ok0 ? b.w[o] : 0u) | ((ok1 ? b.w[o + 1] : 0u) << 16);
-        blv[e] = (ok0 ? b.w[o + 8] : 0u) | ((ok1 ? b.w[o + 9] : 0u) << 16);
-      }
+      for (int j = 0; j < TN / 32; ++j) chunk_at(b, n0 + cr + 32 * j, N, k0, bc[j]);
     } else {
 #pragma unroll
       for (int r = 0; r < KRB; ++r) {
@@ -404,20 +398,10 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
         *reinterpret_cast<cnn_u4*>(&al[st][am[0]][ak[0] + 8 * v]) = l;
       }
     }
-    if constexpr (PreSplit<Bm>::value) {
-      if constexpr (KPT >= 8) {
+    if constexpr (SplitRowsOp<Bm>::value) {
+      unsigned short(*dst)[LROW] = (cq & 1) ? bl[st] : bh[st];
 #pragma unroll
-        for (int v = 0; v < KPT / 8; ++v) {
-          *reinterpret_cast<cnn_u4*>(&bh[st][pn][pk + 8 * v]) =
-              cnn_u4{bhv[4 * v], bhv[4 * v + 1], bhv[4 * v + 2], bhv[4 * v + 3]};
-          *reinterpret_cast<cnn_u4*>(&bl[st][pn][pk + 8 * v]) =
-              cnn_u4{blv[4 * v], blv[4 * v + 1], blv[4 * v + 2], blv[4 * v + 3]};
-        }
-      } else {
-        typedef unsigned cnn_u2 __attribute__((ext_vector_type(2)));
-        *reinterpret_cast<cnn_u2*>(&bh[st][pn][pk]) = cnn_u2{bhv[0], bhv[1]};
-        *reinterpret_cast<cnn_u2*>(&bl[st][pn][pk]) = cnn_u2{blv[0], blv[1]};
-      }
+      for (int j = 0; j < TN / 32; ++j) *reinterpret_cast<cnn_u4*>(&dst[cr + 32 * j][(cq >> 1) * 8]) = bc[j];
     } else if constexpr (Bm::KFAST) {
 #pragma unroll
       for (int r = 0; r < KRB; r += 2) {
@@ -1094,7 +1078,7 @@ __global__ void k_weights_tap(const float* __restrict__ params, Layout lay, floa
 }
 
 // BF16 halves (x_hi = bf16(x), x_lo = bf16(x - x_hi)) of rows floats rows of
-// k_len (a multiple of 8) into the interleaved rows of SplitRowsB: a thread
+// k_len (a multiple of 8) into the interleaved rows of SplitRows: a thread
 // takes one group of 8
 __global__ void k_split_rows(const float* __restrict__ x, int64_t rows, int k_len, unsigned short* __restrict__ w) {
   const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;  // group index
@@ -1647,7 +1631,7 @@ hipError_t forward(const float* params, const Layout& lay, const float* x, int64
       // buffers, the same bytes), the last one FP32 features for the fc
       const unsigned short* sa = reinterpret_cast<const unsigned short*>(a);
       const ConvReluPoolSplitOut so{reinterpret_cast<unsigned short*>(act.p[i]), bias, co, lw - 1};
-      const SplitRowsB wb{act.wts + 2 * tap_weights_offset(i), K};
+      const SplitRows wb{act.wts + 2 * tap_weights_offset(i), K};
       if (i == 0)
         e = gemm(ConvFwdA{a, ci, lci, lw}, WeightT{act.wt, K}, so, M, co, K, 1, st, true);
       else if (i < 3)
@@ -1662,7 +1646,7 @@ hipError_t forward(const float* params, const Layout& lay, const float* x, int64
     w /= 2;
   }
   const RowOut o{act.logits, params + lay.fc_b, lay.classes};
-  return split ? gemm_split(RowK{a, kFeatures}, SplitRowsB{act.fcs, kFeatures}, o, (int)bsz, lay.classes,
+  return split ? gemm_split(RowK{a, kFeatures}, SplitRows{act.fcs, kFeatures}, o, (int)bsz, lay.classes,
                             kFeatures, st)
                : gemm(RowK{a, kFeatures}, WeightT{params + lay.fc_w, kFeatures}, o, (int)bsz, lay.classes, kFeatures, 1,
                       st, true);
