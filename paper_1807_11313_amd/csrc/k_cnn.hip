@@ -217,10 +217,12 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
 // through two LDS stages of hi / lo tiles stored [row][k] (80-byte rows, so
 // the 16-byte fragment reads of 16 lanes meet 16 distinct bank quads);
 // operand fragments: lane l holds row (column) l % 16, k = 8 (l / 16) + j.
-// A thread of a KFAST-false operand holds KR consecutive k of one row (one
-// tap of a convolution: one bounds test), so it stores its halves as
-// 16-byte vectors; KFAST operands store single halves.  Used for the
-// forward products (the backward ones stay FP32).
+// Operands split here: a thread of a KFAST-false one holds KR consecutive k
+// of one row (one tap of a convolution: one bounds test) and stores its
+// halves as 16-byte vectors; KFAST ones store single halves.  Operands split
+// ahead (PRESPLIT: the layer input ConvFwdSA, the weight rows SplitRows) are
+// loaded and stored as halves, 16-byte vectors.  Used for the inference
+// products (training stays FP32).
 constexpr int KS2 = 32, LROW = 40;  // step depth; LDS row of 32 halves + 8 of padding
 typedef __bf16 cnn_b8 __attribute__((ext_vector_type(8)));
 typedef __bf16 cnn_bf2 __attribute__((ext_vector_type(2)));
