@@ -501,7 +501,7 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
 
 // Forward convolution, A(m, k) = the input pixel under tap t of channel c,
 // with K ordered tap-major: k = t ci + c, t = 3 (dy + 1) + (dx + 1) (the
-// weights are read in their stored [co][ci][3][3] order through WeightTap).
+// weights are read from their tap-major copy, k_weights_tap, as WeightT).
 // Output pixels are ordered by 2 x 2 pooling quad, m = ((b, Y, X), q), pixel
 // (2 Y + q / 2, 2 X + q % 2), so that the four accumulator rows of a lane
 // are one quad.  Offsets are 32-bit (inputs below 2^30 elements).  For
