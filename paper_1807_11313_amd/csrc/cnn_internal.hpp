@@ -59,16 +59,17 @@ hipError_t init_params(float* params, const Layout& lay, uint64_t seed, hipStrea
 hipError_t prepare(const float* params, const Layout& lay, const Acts& act, bool split, hipStream_t st);
 // Each convolution writes its pooled map act.p; train: also the gradient
 // positions act.arg that the backward pass needs.  split (inference only;
-// training is FP32): the products take BF16 hi + lo halves of their FP32
+// the training forward is FP32): the products take BF16 hi + lo halves of their FP32
 // operands, three products per tile.
 hipError_t forward(const float* params, const Layout& lay, const float* x, int64_t bsz, const Acts& act,
                    hipStream_t st, bool train = true, bool split = false);
 // Gradient of the mean cross-entropy into grad (all of it overwritten), from
 // act as the training forward pass on the same parameters left it;
 // part: split-K scratch of part_floats floats; loss_row: [bsz] doubles.
+// split: the products take BF16 split operands.
 hipError_t backward(const float* params, const Layout& lay, const float* x, const int32_t* labels, int64_t bsz,
                     const Acts& act, float* grad, float* part, size_t part_floats, double* loss_row, float* loss,
-                    hipStream_t st);
+                    hipStream_t st, bool split = false);
 hipError_t adam(float* params, const float* grad, float* m, float* v, int64_t n, int64_t step, float lr,
                 hipStream_t st);
 

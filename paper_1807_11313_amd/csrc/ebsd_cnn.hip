@@ -112,7 +112,7 @@ __global__ void k_scatter_best(const int32_t* __restrict__ list, int64_t f, cons
 
 struct ebsd_cnn_s {
   int device = 0;
-  int32_t infer_prec = EBSD_PREC_BF16X2;  // precision of the inference products
+  int32_t prec = EBSD_PREC_BF16X2;  // precision of the inference and backward products
   cnn::Layout lay{};
   float* params = nullptr;
   float* grad = nullptr;
@@ -198,7 +198,7 @@ int forward_chunks(ebsd_cnn_s* c, const float* x, int64_t bsz, float* logits, hi
   int rc;
   if ((rc = ensure_ws(c, std::min(bsz, kChunk), st))) return rc;
   const int L = c->lay.classes;
-  const bool split = c->infer_prec == EBSD_PREC_BF16X2;
+  const bool split = c->prec == EBSD_PREC_BF16X2;
   CN_TRY(cnn::prepare(c->params, c->lay, c->act, split, st), "cnn weights");
   for (int64_t s = 0; s < bsz; s += kChunk) {
     const int64_t b = std::min(kChunk, bsz - s);
@@ -216,7 +216,7 @@ int grads(ebsd_cnn_s* c, const float* x, const int32_t* labels, int64_t bsz, flo
   CN_TRY(cnn::prepare(c->params, c->lay, c->act, false, st), "cnn weights");
   CN_TRY(cnn::forward(c->params, c->lay, x, bsz, c->act, st), "cnn forward");
   CN_TRY(cnn::backward(c->params, c->lay, x, labels, bsz, c->act, c->grad, c->part, c->part_floats, c->loss_row,
-                       loss, st),
+                       loss, st, c->prec == EBSD_PREC_BF16X2),
          "cnn backward");
   return EBSD_OK;
 }
@@ -317,9 +317,9 @@ int ebsd_cnn_set_precision(ebsd_cnn c, int32_t precision) {
   g_last_error.clear();
   if (!c) return fail(EBSD_E_INVALID, "null network");
   if (precision == EBSD_PREC_FP16X2 || precision == EBSD_PREC_BF16)
-    return fail(EBSD_E_UNSUPPORTED, "the network's inference runs in FP32 or BF16X2");
+    return fail(EBSD_E_UNSUPPORTED, "the network's products run in FP32 or BF16X2");
   if (precision != EBSD_PREC_FP32 && precision != EBSD_PREC_BF16X2) return fail(EBSD_E_INVALID, "unknown precision");
-  c->infer_prec = precision;
+  c->prec = precision;
   return EBSD_OK;
 }
 

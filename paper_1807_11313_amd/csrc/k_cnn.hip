@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
 // halves as 16-byte vectors; KFAST ones store single halves.  Operands split
 // ahead (PRESPLIT: the layer input ConvFwdSA, the weight rows SplitRows) are
 // loaded and stored as halves, 16-byte vectors.  Used for the inference
-// products (training stays FP32).
+// products and the backward products (the training's forward stays FP32).
 constexpr int KS2 = 32, LROW = 40;  // step depth; LDS row of 32 halves + 8 of padding
 typedef __bf16 cnn_b8 __attribute__((ext_vector_type(8)));
 typedef __bf16 cnn_bf2 __attribute__((ext_vector_type(2)));
@@ -267,8 +267,9 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
   static_assert((TM == 64 || TM == 128) && (TN == 32 || TN == 64 || TN == 128), "tile");
   constexpr int KRA = TM * KS2 / 256, KRB = TN * KS2 / 256;  // operand values per thread and step
   constexpr int TI = TM / 32, TJ = TN / 32;                   // 16 x 16 tiles per wave
-  static_assert((A::KFAST || KRA % 8 == 0) && (Bm::KFAST || KRB % 8 == 0) && KRA % 2 == 0 && KRB % 2 == 0,
-                "whole 16-byte vectors (KFAST false) or pairs (KFAST) per thread");
+  static_assert((A::KFAST || KRA % 8 == 0) && (Bm::KFAST || KRB % 8 == 0 || KRB == 4) && KRA % 2 == 0 &&
+                    KRB % 2 == 0,
+                "whole 16-byte vectors (or one 8-byte one) (KFAST false) or pairs (KFAST) per thread");
   __shared__ __attribute__((aligned(16))) unsigned short ah[2][TM][LROW], al[2][TM][LROW];
   __shared__ __attribute__((aligned(16))) unsigned short bh[2][TN][LROW], bl[2][TN][LROW];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -414,6 +415,14 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
         bh[st][bn[r + 1]][bk[r + 1]] = (unsigned short)(h >> 16);
         bl[st][bn[r + 1]][bk[r + 1]] = (unsigned short)(l >> 16);
       }
+    } else if constexpr (KRB == 4) {
+      // 32-wide tiles: 4 consecutive k per thread, one 8-byte vector
+      typedef unsigned cnn_u2 __attribute__((ext_vector_type(2)));
+      unsigned h0, l0, h1, l1;
+      bf16_split2(rb[0], rb[1], h0, l0);
+      bf16_split2(rb[2], rb[3], h1, l1);
+      *reinterpret_cast<cnn_u2*>(&bh[st][bn[0]][bk[0]]) = cnn_u2{h0, h1};
+      *reinterpret_cast<cnn_u2*>(&bl[st][bn[0]][bk[0]]) = cnn_u2{l0, l1};
     } else {
 #pragma unroll
       for (int v = 0; v < KRB / 8; ++v) {
@@ -888,26 +897,43 @@ static hipError_t gemm(A a, Bm b, Out out, int M, int N, int K, int splits, hipS
   return hipGetLastError();
 }
 
-// the forward products with BF16 split operands (k_tgemm_s), no K split;
-// tiles as gemm's
+// K slice of a split into `splits` parts for k_tgemm_s (a whole number of its
+// 32-deep steps) and the number of slices z it launches
+static int k_slice_s(int K, int splits) {
+  splits = splits < 1 ? 1 : splits;
+  const int kslice = (K + splits - 1) / splits;
+  return (kslice + KS2 - 1) / KS2 * KS2;
+}
+static int k_slices_s(int K, int splits) {
+  const int kslice = k_slice_s(K, splits);
+  return (K + kslice - 1) / kslice;
+}
+
+// products with BF16 split operands (k_tgemm_s); tiles as gemm's (wide only
+// where allowed and the grid fills the chip, narrow 64 x 32 on request)
 template <class A, class Bm, class Out>
-static hipError_t gemm_split(A a, Bm b, Out out, int M, int N, int K, hipStream_t st) {
+static hipError_t gemm_split(A a, Bm b, Out out, int M, int N, int K, hipStream_t st, int splits = 1,
+                             bool wide_ok = true, bool narrow = false) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  const int kslice = (K + KS2 - 1) / KS2 * KS2;
+  const int kslice = k_slice_s(K, splits);
+  const int z = k_slices_s(K, splits) < 1 ? 1 : k_slices_s(K, splits);
   const int tn = N <= 32 ? 32 : N <= 64 ? 64 : 128;
-  const bool wide = (int64_t)((N + tn - 1) / tn) * ((M + 127) / 128) >= 512;
+  const bool wide = wide_ok && (int64_t)((N + tn - 1) / tn) * ((M + 127) / 128) * z >= 512;
   if (wide && N <= 32) {
-    hipLaunchKernelGGL((k_tgemm_s<128, 32, A, Bm, Out>), dim3((N + 31) / 32, (M + 127) / 128), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_tgemm_s<128, 32, A, Bm, Out>), dim3((N + 31) / 32, (M + 127) / 128, z), dim3(256), 0, st,
                        a, b, out, M, N, K, kslice);
   } else if (wide && N <= 64) {
-    hipLaunchKernelGGL((k_tgemm_s<128, 64, A, Bm, Out>), dim3((N + 63) / 64, (M + 127) / 128), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_tgemm_s<128, 64, A, Bm, Out>), dim3((N + 63) / 64, (M + 127) / 128, z), dim3(256), 0, st,
                        a, b, out, M, N, K, kslice);
   } else if (wide) {
-    hipLaunchKernelGGL((k_tgemm_s<128, 128, A, Bm, Out>), dim3((N + 127) / 128, (M + 127) / 128), dim3(256), 0, st,
-                       a, b, out, M, N, K, kslice);
+    hipLaunchKernelGGL((k_tgemm_s<128, 128, A, Bm, Out>), dim3((N + 127) / 128, (M + 127) / 128, z), dim3(256), 0,
+                       st, a, b, out, M, N, K, kslice);
+  } else if (narrow) {
+    hipLaunchKernelGGL((k_tgemm_s<64, 32, A, Bm, Out>), dim3((N + 31) / 32, (M + 63) / 64, z), dim3(256), 0, st, a,
+                       b, out, M, N, K, kslice);
   } else {
-    hipLaunchKernelGGL((k_tgemm_s<64, 64, A, Bm, Out>), dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, st, a, b,
-                       out, M, N, K, kslice);
+    hipLaunchKernelGGL((k_tgemm_s<64, 64, A, Bm, Out>), dim3((N + 63) / 64, (M + 63) / 64, z), dim3(256), 0, st, a,
+                       b, out, M, N, K, kslice);
   }
   return hipGetLastError();
 }
@@ -1665,15 +1691,19 @@ static int splits_for(int64_t k_len, int64_t tiles) {
 
 hipError_t backward(const float* params, const Layout& lay, const float* x, const int32_t* labels, int64_t bsz,
                     const Acts& act, float* grad, float* part, size_t part_floats, double* loss_row, float* loss,
-                    hipStream_t st) {
+                    hipStream_t st, bool split) {
   hipError_t e;
   const int L = lay.classes;
   hipLaunchKernelGGL(k_softmax_xent, dim3((unsigned)bsz), dim3(1024), 0, st, act.logits, labels, L, (int)bsz,
                      act.dz, loss_row);
   hipLaunchKernelGGL(k_mean_loss, dim3(1), dim3(64), 0, st, loss_row, (int)bsz, loss);
   // fc: dW = dz^T f, db = column sums of dz, df = dz W
-  e = gemm(ColK{act.dz, L}, BRowN{act.p[3], kFeatures}, RowOut{grad + lay.fc_w, nullptr, kFeatures}, L, kFeatures,
-           (int)bsz, 1, st, true);
+  {
+    const ColK fa{act.dz, L};
+    const BRowN fb{act.p[3], kFeatures};
+    const RowOut fo{grad + lay.fc_w, nullptr, kFeatures};
+    e = split ? gemm_split(fa, fb, fo, L, kFeatures, (int)bsz, st) : gemm(fa, fb, fo, L, kFeatures, (int)bsz, 1, st, true);
+  }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_col_sum, dim3((L + 63) / 64), dim3(1024), 0, st, act.dz, (int)bsz, L, grad + lay.fc_b);
   {
@@ -1684,9 +1714,12 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
     const int smax = (L + 255) / 256;
     s = s > smax ? smax : (s < 1 ? 1 : s);
     while ((size_t)s * bsz * kFeatures > part_floats && s > 1) s = (s + 1) / 2;
-    const int z = k_slices(L, s);
-    e = gemm(RowK{act.dz, L}, BRowN{params + lay.fc_w, kFeatures}, SplitOut{part, (int)bsz, kFeatures}, (int)bsz,
-             kFeatures, L, s, st);
+    const int z = split ? k_slices_s(L, s) : k_slices(L, s);
+    const RowK da{act.dz, L};
+    const BRowN db{params + lay.fc_w, kFeatures};
+    const SplitOut dout{part, (int)bsz, kFeatures};
+    e = split ? gemm_split(da, db, dout, (int)bsz, kFeatures, L, st, s)
+              : gemm(da, db, dout, (int)bsz, kFeatures, L, s, st);
     if (e != hipSuccess) return e;
     split_sum(part, z, (int64_t)bsz * kFeatures, act.dp[3], st);
   }
@@ -1713,9 +1746,11 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
       const int64_t tiles = (int64_t)((co + 63) / 64) * ((N + tn - 1) / tn);
       int s = splits_for(K, tiles);
       while ((size_t)s * co * N > part_floats && s > 1) s = (s + 1) / 2;
-      const int z = k_slices(K, s);
-      e = gemm(ConvBwdWA{act.g[i], co, lw}, ConvBwdWB{in, ilog2(ci), lw}, SplitOut{part, co, N}, co, N, K, s, st,
-               false, narrow);
+      const int z = split ? k_slices_s(K, s) : k_slices(K, s);
+      const ConvBwdWA wa{act.g[i], co, lw};
+      const ConvBwdWB wb{in, ilog2(ci), lw};
+      const SplitOut wo{part, co, N};
+      e = split ? gemm_split(wa, wb, wo, co, N, K, st, s, false, narrow) : gemm(wa, wb, wo, co, N, K, s, st, false, narrow);
       if (e != hipSuccess) return e;
       split_sum(part, z, (int64_t)co * N, grad + lay.conv_w[i], st, N, ilog2(ci));
     }
@@ -1727,8 +1762,11 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
       hipLaunchKernelGGL(k_channel_sum, dim3(co), dim3(64), 0, st, cpart, zs, grad + lay.conv_b[i]);
     }
     if (i > 0) {
-      e = gemm(ConvBwdDataA{act.g[i], ilog2(co), lw}, WeightBwdData{act.wt + tap_weights_offset(i), ci, ilog2(co)},
-               NchwOut{act.dp[i - 1], ci, lw}, (int)(bsz * w * w), ci, co * 9, 1, st, true);
+      const ConvBwdDataA ga{act.g[i], ilog2(co), lw};
+      const WeightBwdData gb{act.wt + tap_weights_offset(i), ci, ilog2(co)};
+      const NchwOut go{act.dp[i - 1], ci, lw};
+      e = split ? gemm_split(ga, gb, go, (int)(bsz * w * w), ci, co * 9, st)
+                : gemm(ga, gb, go, (int)(bsz * w * w), ci, co * 9, 1, st, true);
       if (e != hipSuccess) return e;
     }
     w *= 2;
