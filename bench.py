@@ -931,7 +931,7 @@ def learned_proposal(tm, library, n_train, epochs, n_test, k=32, bsz=256, n=128)
     rpe = np.rad2deg([rotations.disorientation_q(q_pr[i], q_ex[i]) for i in pts])
     pairs_pr = n_test * k + int(fb.sum()) * library
     res = {"workload": "proposal: CNN (4 conv 32-128 ch on 64x64 binned input, fc to %d) trained on the GPU "
-                       "(forward FP32, backward products on BF16 split halves) on %d projected noisy patterns x %.1f epochs; inference products on BF16 split halves "
+                       "(convolutions FP32, fc and backward products on BF16 split halves) on %d projected noisy patterns x %.1f epochs; inference products on BF16 split halves "
                        "(hi*hi + hi*lo + lo*hi, FP32 sums); %d test patterns at 128x128 fp32, top-%d "
                        "correlation with exhaustive fallback below tau" % (library, n_train, epochs, n_test, k),
            "train_s": t_train, "train_steps": steps, "batch": bsz, "final_loss": final_loss,
@@ -941,8 +941,8 @@ def learned_proposal(tm, library, n_train, epochs, n_test, k=32, bsz=256, n=128)
                                    "frac": train_flops / t_step / PEAK_MFMA_FP32,
                                    "flops_per_sample_forward": cnn_flops_per_sample(library),
                                    "note": "network flops (one product per multiply-add) against the FP32 "
-                                           "matrix peak; the backward's products run as three BF16 products "
-                                           "on split halves"},
+                                           "matrix peak; the fc and backward products run as three BF16 "
+                                           "products on split halves"},
            "forward_patterns_per_s": bsz * 8 / t_fwd,
            "forward_patterns_per_s_fp32": bsz * 8 / t_fwd32,
            "forward_tflops_network": cnn_flops_per_sample(library) * bsz * 8 / t_fwd / 1e12,

@@ -504,10 +504,10 @@ int ebsd_ragged_plan_destroy(ebsd_ragged_plan plan);
  * each followed by a 2 x 2 max pool; a fully connected layer from the
  * 128 x 4 x 4 features to the L library orientations; softmax
  * cross-entropy against the library orientation nearest (cubic
- * disorientation) to the true one.  The forward pass of training
- * (ebsd_cnn_gradients, ebsd_cnn_train_step) runs in FP32; inference
- * (ebsd_cnn_forward, ebsd_index_proposed) and the backward products in the
- * precision ebsd_cnn_set_precision chose.  Parameters are one
+ * disorientation) to the true one.  The convolutions of the training
+ * forward pass (ebsd_cnn_gradients, ebsd_cnn_train_step) run in FP32; its
+ * fc product, the backward products and inference (ebsd_cnn_forward,
+ * ebsd_index_proposed) in the precision ebsd_cnn_set_precision chose.  Parameters are one
  * flat float vector: conv_i.w [co][ci][3][3], conv_i.b [co] for i = 1..4,
  * fc.w [L][2048], fc.b [L].  A network object owns its parameters, Adam
  * state and workspace on the device it was created on.
@@ -533,9 +533,9 @@ int ebsd_cnn_forward(ebsd_cnn cnn, const float* x, int64_t B, float* logits, voi
  * BF16 matrix cores (scores within about 1e-5 of the largest, gradients
  * about 1e-5, relative); EBSD_PREC_FP32 uses FP32 operands throughout.
  * EBSD_E_UNSUPPORTED for FP16X2 and BF16, EBSD_E_INVALID for other values.
- * The forward pass of training is FP32 either way: it decides which ReLU
- * and pooling inputs carry the gradient, and split rounding would move that
- * choice for near ties. */
+ * The convolutions of the training forward are FP32 either way: they decide
+ * which ReLU and pooling inputs carry the gradient, and split rounding would
+ * move that choice for near ties. */
 int ebsd_cnn_set_precision(ebsd_cnn cnn, int32_t precision);
 /* Mean cross-entropy of the batch (device float *loss) and its gradient
  * (device [count], parameter order); B in [1, 4096]. */

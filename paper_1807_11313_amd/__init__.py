@@ -697,7 +697,7 @@ class Cnn:
         return out
 
     def set_precision(self, precision):
-        """Precision of the inference and backward products: PREC_BF16X2 (default) or PREC_FP32."""
+        """Precision of the inference, training fc and backward products: PREC_BF16X2 (default) or PREC_FP32."""
         _check(lib().ebsd_cnn_set_precision(self._h, int(precision)), "ebsd_cnn_set_precision")
 
     def gradients(self, x, labels):

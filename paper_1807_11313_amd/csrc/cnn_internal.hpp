@@ -58,9 +58,10 @@ hipError_t init_params(float* params, const Layout& lay, uint64_t seed, hipStrea
 // parameter version, before forward / backward.
 hipError_t prepare(const float* params, const Layout& lay, const Acts& act, bool split, hipStream_t st);
 // Each convolution writes its pooled map act.p; train: also the gradient
-// positions act.arg that the backward pass needs.  split (inference only;
-// the training forward is FP32): the products take BF16 hi + lo halves of their FP32
-// operands, three products per tile.
+// positions act.arg that the backward pass needs.  split: the products take
+// BF16 hi + lo halves of their FP32 operands, three products per tile (with
+// train, the fc's only: the convolutions, whose outputs decide the ReLU and
+// pool choices, stay FP32).
 hipError_t forward(const float* params, const Layout& lay, const float* x, int64_t bsz, const Acts& act,
                    hipStream_t st, bool train = true, bool split = false);
 // Gradient of the mean cross-entropy into grad (all of it overwritten), from

@@ -214,7 +214,7 @@ int grads(ebsd_cnn_s* c, const float* x, const int32_t* labels, int64_t bsz, flo
   int rc;
   if ((rc = ensure_ws(c, bsz, st))) return rc;
   CN_TRY(cnn::prepare(c->params, c->lay, c->act, false, st), "cnn weights");
-  CN_TRY(cnn::forward(c->params, c->lay, x, bsz, c->act, st), "cnn forward");
+  CN_TRY(cnn::forward(c->params, c->lay, x, bsz, c->act, st, true, c->prec == EBSD_PREC_BF16X2), "cnn forward");
   CN_TRY(cnn::backward(c->params, c->lay, x, labels, bsz, c->act, c->grad, c->part, c->part_floats, c->loss_row,
                        loss, st, c->prec == EBSD_PREC_BF16X2),
          "cnn backward");

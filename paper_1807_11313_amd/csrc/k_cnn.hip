@@ -222,7 +222,8 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
 // halves as 16-byte vectors; KFAST ones store single halves.  Operands split
 // ahead (PRESPLIT: the layer input ConvFwdSA, the weight rows SplitRows) are
 // loaded and stored as halves, 16-byte vectors.  Used for the inference
-// products and the backward products (the training's forward stays FP32).
+// products, the training's fc and backward products (its convolutions stay
+// FP32).
 constexpr int KS2 = 32, LROW = 40;  // step depth; LDS row of 32 halves + 8 of padding
 typedef __bf16 cnn_b8 __attribute__((ext_vector_type(8)));
 typedef __bf16 cnn_bf2 __attribute__((ext_vector_type(2)));
@@ -1638,6 +1639,9 @@ hipError_t prepare(const float* params, const Layout& lay, const Acts& act, bool
 
 hipError_t forward(const float* params, const Layout& lay, const float* x, int64_t bsz, const Acts& act,
                    hipStream_t st, bool train, bool split) {
+  // training: only the fc takes split operands (its output feeds the smooth
+  // softmax, while a convolution's output decides the ReLU and pool choices)
+  const bool fc_split = split;
   split = split && !train;
   const float* a = x;
   int ci = 1, w = kInSize;
@@ -1674,6 +1678,9 @@ hipError_t forward(const float* params, const Layout& lay, const float* x, int64
     w /= 2;
   }
   const RowOut o{act.logits, params + lay.fc_b, lay.classes};
+  if (fc_split && train)
+    return gemm_split(RowK{a, kFeatures}, WeightT{params + lay.fc_w, kFeatures}, o, (int)bsz, lay.classes, kFeatures,
+                      st);
   return split ? gemm_split(RowK{a, kFeatures}, SplitRows{act.fcs, kFeatures}, o, (int)bsz, lay.classes,
                             kFeatures, st)
                : gemm(RowK{a, kFeatures}, WeightT{params + lay.fc_w, kFeatures}, o, (int)bsz, lay.classes, kFeatures, 1,
