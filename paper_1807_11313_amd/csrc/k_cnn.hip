@@ -36,6 +36,39 @@ constexpr int KS = EBSD_TGEMM_KS;  // K depth of one step
 __device__ __forceinline__ float ld32(const float* p, unsigned i) {
   return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(p) + (i << 2));
 }
+// p[i .. i + 3] in one 16-byte load (p 16-byte aligned, i a multiple of 4)
+__device__ __forceinline__ f4c ld32x4(const float* p, unsigned i) {
+  return *reinterpret_cast<const f4c*>(reinterpret_cast<const char*>(p) + (i << 2));
+}
+// p[(m + r ms) ld + k .. + 3] for r < CNT of a row-major matrix (k a
+// multiple of 4): 16-byte loads when p is 16-byte aligned and ld a multiple
+// of 4, else single ones
+template <int CNT>
+__device__ __forceinline__ void rows4(const float* p, int ld, int m, int k, int ms, f4c* v) {
+  const unsigned o = (unsigned)m * (unsigned)ld + (unsigned)k, d = (unsigned)(ms * ld);
+  if ((ld & 3) == 0 && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) v[r] = ld32x4(p, o + r * d);
+  } else {
+#pragma unroll
+    for (int r = 0; r < CNT; ++r)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[r][j] = ld32(p, o + r * d + j);
+  }
+}
+
+// The block's tile (x, y, z), numbered so that each XCD takes one run of
+// consecutive tiles: the dispatcher hands block b to XCD b % 8, and tiles
+// that share operand rows (the N tiles of one K slice) then meet in one L2.
+__device__ __forceinline__ void xcd_tile(int& bx, int& by, int& bz) {
+  const unsigned nx = gridDim.x, ny = gridDim.y, total = nx * ny * gridDim.z;
+  const unsigned lin = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+  const unsigned xcd = lin & 7, q = lin >> 3, per = total >> 3, rem = total & 7;
+  const unsigned item = xcd * per + min(xcd, rem) + q;
+  bx = (int)(item % nx);
+  by = (int)((item / nx) % ny);
+  bz = (int)(item / (nx * ny));
+}
 
 // output maps that take a lane's four consecutive rows at once (QUAD)
 template <class T, class = void>
@@ -66,8 +99,10 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
   __shared__ float bs[2][KS][TN + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = (w & 1) * (TM / 2), wn = (w >> 1) * (TN / 2);
-  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-  const int kb = blockIdx.z * kslice;
+  int bx, by, bz;
+  xcd_tile(bx, by, bz);
+  const int m0 = by * TM, n0 = bx * TN;
+  const int kb = bz * kslice;
   const int ke = min(K, kb + kslice);
   f4c acc[TI][TJ];
 #pragma unroll
@@ -200,7 +235,7 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int m = m0 + wm + 16 * i + 4 * q4 + r, n = n0 + wn + 16 * j + r16;
-          if (m < M && n < N) out(m, n, acc[i][j][r], blockIdx.z);
+          if (m < M && n < N) out(m, n, acc[i][j][r], bz);
         }
   }
 }
@@ -219,7 +254,9 @@ __global__ __launch_bounds__(256) void k_tgemm(A a, Bm b, Out out, int M, int N,
 // operand fragments: lane l holds row (column) l % 16, k = 8 (l / 16) + j.
 // Operands split here: a thread of a KFAST-false one holds KR consecutive k
 // of one row (one tap of a convolution: one bounds test) and stores its
-// halves as 16-byte vectors; KFAST ones store single halves.  Operands split
+// halves as 16-byte vectors; a thread of a KFAST one holds 4 consecutive k
+// of each of its rows (16-byte loads where aligned) and stores 8-byte
+// vectors.  Tiles may be 96 wide for a KFAST B.  Operands split
 // ahead (PRESPLIT: the layer input ConvFwdSA, the weight rows SplitRows) are
 // loaded and stored as halves, 16-byte vectors.  Used for the inference
 // products, the training's fc and backward products (its convolutions stay
@@ -229,6 +266,7 @@ typedef __bf16 cnn_b8 __attribute__((ext_vector_type(8)));
 typedef __bf16 cnn_bf2 __attribute__((ext_vector_type(2)));
 typedef float cnn_f2 __attribute__((ext_vector_type(2)));
 typedef unsigned cnn_u4 __attribute__((ext_vector_type(4)));
+typedef unsigned cnn_u2 __attribute__((ext_vector_type(2)));
 // two floats -> packed (hi, hi) and (lo, lo), round to nearest even
 __device__ __forceinline__ void bf16_split2(float a, float b, unsigned& hi, unsigned& lo) {
   hi = __builtin_bit_cast(unsigned, __builtin_convertvector(cnn_f2{a, b}, cnn_bf2));
@@ -265,7 +303,8 @@ struct SplitRows {
 
 template <int TM, int TN, class A, class Bm, class Out>
 __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int N, int K, int kslice) {
-  static_assert((TM == 64 || TM == 128) && (TN == 32 || TN == 64 || TN == 128), "tile");
+  static_assert((TM == 64 || TM == 128) && (TN == 32 || TN == 64 || TN == 128 || (TN == 96 && Bm::KFAST)),
+                "tile (96 wide: K-fast B only)");
   constexpr int KRA = TM * KS2 / 256, KRB = TN * KS2 / 256;  // operand values per thread and step
   constexpr int TI = TM / 32, TJ = TN / 32;                   // 16 x 16 tiles per wave
   static_assert((A::KFAST || KRA % 8 == 0) && (Bm::KFAST || KRB % 8 == 0 || KRB == 4) && KRA % 2 == 0 &&
@@ -275,8 +314,10 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
   __shared__ __attribute__((aligned(16))) unsigned short bh[2][TN][LROW], bl[2][TN][LROW];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = (w & 1) * (TM / 2), wn = (w >> 1) * (TN / 2);
-  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-  const int kb = blockIdx.z * kslice;
+  int bx, by, bz;
+  xcd_tile(bx, by, bz);
+  const int m0 = by * TM, n0 = bx * TN;
+  const int kb = bz * kslice;
   const int ke = min(K, kb + kslice);
   f4c acc[TI][TJ];
 #pragma unroll
@@ -298,6 +339,11 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
     bk[r] = Bm::KFAST ? tid % KS2 : (tid / TN) * KRB + r;
   }
   float ra[KRA], rb[KRB];
+  // a KFAST operand here: 4 consecutive k per thread (k0 + 4 (tid % 8)) of
+  // rows tid / 8 + 32 r, fetched as 16-byte vectors where the operand allows
+  // and stored as one 8-byte vector of hi and one of lo halves per row
+  const int qk = 4 * (tid & 7), qr = tid >> 3;
+  f4c va[A::KFAST ? TM / 32 : 1], vb[Bm::KFAST ? TN / 32 : 1];
   // a row-major pre-split B: 8 lanes per row, lane cq loading the row's
   // 16-byte chunk cq of the step, rows cr, cr + 32, ...
   const int cq = tid & 7, cr = tid >> 3;
@@ -324,14 +370,14 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
     int ok = 1;
     if constexpr (HasStep<A>::value && HasStep<Bm>::value) {
       if constexpr (PreSplit<A>::value) ok = a.template split_at<KPTA>(m0 + pm, k0 + pka, ahv, alv) ? 1 : 0;
-      else if constexpr (A::KFAST) a.template stepk<KRA>(m0 + am[0], k0 + ak[0], 256 / KS2, ra);
+      else if constexpr (A::KFAST) a.template stepk4<TM / 32>(m0 + qr, k0 + qk, 32, va);
       else a.template step<KRA>(m0 + am[0], k0, ak[0], 1, ra);
       if constexpr (SplitRowsOp<Bm>::value) {
 #pragma unroll
         for (int j = 0; j < TN / 32; ++j)
           bc[j] = *reinterpret_cast<const cnn_u4*>(b.w + b.hi_at(n0 + cr + 32 * j, k0) + 8 * cq);
       } else if constexpr (Bm::KFAST) {
-        b.template stepk<KRB>(n0 + bn[0], k0 + bk[0], 256 / KS2, rb);
+        b.template stepk4<TN / 32>(n0 + qr, k0 + qk, 32, vb);
       } else {
         b.template step<KRB>(n0 + bn[0], k0, bk[0], 1, rb);
       }
@@ -346,6 +392,14 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
         const int k2 = k0 + pka + 2 * e;  // even: k2 and k2 + 1 share a group and a tap (ci even)
         a.pair_at(m, k2, m < M && k2 < ke, m < M && k2 + 1 < ke, ahv[e], alv[e]);
       }
+    } else if constexpr (A::KFAST) {
+#pragma unroll
+      for (int r = 0; r < TM / 32; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int m = m0 + qr + 32 * r, k = k0 + qk + j;
+          va[r][j] = (m < M && k < ke) ? a(m, k) : 0.0f;
+        }
     } else {
 #pragma unroll
       for (int r = 0; r < KRA; ++r) {
@@ -356,6 +410,14 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
     if constexpr (SplitRowsOp<Bm>::value) {
 #pragma unroll
       for (int j = 0; j < TN / 32; ++j) chunk_at(b, n0 + cr + 32 * j, N, k0, bc[j]);
+    } else if constexpr (Bm::KFAST) {
+#pragma unroll
+      for (int r = 0; r < TN / 32; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int n = n0 + qr + 32 * r, k2 = k0 + qk + j;
+          vb[r][j] = (n < N && k2 < ke) ? b(k2, n) : 0.0f;
+        }
     } else {
 #pragma unroll
       for (int r = 0; r < KRB; ++r) {
@@ -379,13 +441,12 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
       }
     } else if constexpr (A::KFAST) {
 #pragma unroll
-      for (int r = 0; r < KRA; r += 2) {
-        unsigned h, l;
-        bf16_split2(ra[r], ra[r + 1], h, l);
-        ah[st][am[r]][ak[r]] = (unsigned short)h;
-        al[st][am[r]][ak[r]] = (unsigned short)l;
-        ah[st][am[r + 1]][ak[r + 1]] = (unsigned short)(h >> 16);
-        al[st][am[r + 1]][ak[r + 1]] = (unsigned short)(l >> 16);
+      for (int r = 0; r < TM / 32; ++r) {
+        unsigned h0, l0, h1, l1;
+        bf16_split2(va[r][0], va[r][1], h0, l0);
+        bf16_split2(va[r][2], va[r][3], h1, l1);
+        *reinterpret_cast<cnn_u2*>(&ah[st][qr + 32 * r][qk]) = cnn_u2{h0, h1};
+        *reinterpret_cast<cnn_u2*>(&al[st][qr + 32 * r][qk]) = cnn_u2{l0, l1};
       }
     } else {
 #pragma unroll
@@ -408,17 +469,15 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
       for (int j = 0; j < TN / 32; ++j) *reinterpret_cast<cnn_u4*>(&dst[cr + 32 * j][(cq >> 1) * 8]) = bc[j];
     } else if constexpr (Bm::KFAST) {
 #pragma unroll
-      for (int r = 0; r < KRB; r += 2) {
-        unsigned h, l;
-        bf16_split2(rb[r], rb[r + 1], h, l);
-        bh[st][bn[r]][bk[r]] = (unsigned short)h;
-        bl[st][bn[r]][bk[r]] = (unsigned short)l;
-        bh[st][bn[r + 1]][bk[r + 1]] = (unsigned short)(h >> 16);
-        bl[st][bn[r + 1]][bk[r + 1]] = (unsigned short)(l >> 16);
+      for (int r = 0; r < TN / 32; ++r) {
+        unsigned h0, l0, h1, l1;
+        bf16_split2(vb[r][0], vb[r][1], h0, l0);
+        bf16_split2(vb[r][2], vb[r][3], h1, l1);
+        *reinterpret_cast<cnn_u2*>(&bh[st][qr + 32 * r][qk]) = cnn_u2{h0, h1};
+        *reinterpret_cast<cnn_u2*>(&bl[st][qr + 32 * r][qk]) = cnn_u2{l0, l1};
       }
     } else if constexpr (KRB == 4) {
       // 32-wide tiles: 4 consecutive k per thread, one 8-byte vector
-      typedef unsigned cnn_u2 __attribute__((ext_vector_type(2)));
       unsigned h0, l0, h1, l1;
       bf16_split2(rb[0], rb[1], h0, l0);
       bf16_split2(rb[2], rb[3], h1, l1);
@@ -484,7 +543,9 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
   };
   bool whole = false;
   if constexpr (HasStep<A>::value && HasStep<Bm>::value) {
-    whole = (ke - kb) % KS2 == 0 && m0 + TM <= M && n0 + TN <= N && a.stepwise(TM) && b.stepwise(TN);
+    // K-fast operands are fetched in groups of 32 rows (stepk4)
+    whole = (ke - kb) % KS2 == 0 && m0 + TM <= M && n0 + TN <= N && a.stepwise(A::KFAST ? 32 : TM) &&
+            b.stepwise(Bm::KFAST ? 32 : TN);
   }
   if (whole) run(std::true_type{});
   else run(std::false_type{});
@@ -504,7 +565,7 @@ __global__ __launch_bounds__(256) void k_tgemm_s(A a, Bm b, Out out, int M, int 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r, n = n0 + wn + 16 * j + r16;
-          if (m < M && n < N) out(m, n, acc[i][j][r], blockIdx.z);
+          if (m < M && n < N) out(m, n, acc[i][j][r], bz);
         }
   }
 }
@@ -675,6 +736,8 @@ struct WeightT {
 #pragma unroll
     for (int r = 0; r < CNT; ++r) v[r] = ld32(w, o + r * d);
   }
+  template <int CNT>
+  __device__ void stepk4(int n, int k, int ns, f4c* v) const { rows4<CNT>(w, k_len, n, k, ns, v); }
 };
 
 // data gradient, A(m = (b, y, x), k) = g[b][o][y - dy + 1][x - dx + 1] with
@@ -760,6 +823,15 @@ struct ConvBwdWA {
 #pragma unroll
     for (int r = 0; r < CNT; ++r) v[r] = ld32(g, base + (unsigned)(r * ms) * (unsigned)hw);
   }
+  // k_tgemm_s: k .. k + 3 (k a multiple of 4, one row of one plane) of rows
+  // m + r ms, 16-byte loads
+  template <int CNT>
+  __device__ void stepk4(int m, int k, int ms, f4c* v) const {
+    const int hw = 1 << (2 * lw);
+    const unsigned base = ((unsigned)((k >> (2 * lw)) * co + m) << (2 * lw)) + (unsigned)(k & (hw - 1));
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) v[r] = ld32x4(g, base + (unsigned)(r * ms) * (unsigned)hw);
+  }
 };
 // B(k = (b, y, x), n) = in[b][c][y + dy - 1][x + dx - 1] with N tap-major,
 // n = t ci + c, t = 3 dy + dx (the partial sums are put back into the stored
@@ -792,6 +864,30 @@ struct ConvBwdWB {
 #pragma unroll
     for (int r = 0; r < CNT; ++r) v[r] = inside ? ld32(in, base + r * plane) : 0.0f;
   }
+  // k_tgemm_s: k .. k + 3 (k a multiple of 4: pixels x .. x + 3 of one image
+  // row) of columns n + r ns, each its own tap (ci >= 32: the 32 columns of a
+  // group n0 + 32 r .. share one); a centre column of taps reads a 16-byte
+  // vector, the side ones test their first or last pixel
+  template <int CNT>
+  __device__ void stepk4(int n, int k, int ns, f4c* v) const {
+    const int w = 1 << lw;
+    const int x = k & (w - 1), y = (k >> lw) & (w - 1), bb = k >> (2 * lw);
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) {
+      const int nr = n + r * ns, t = nr >> lci, c = nr & ((1 << lci) - 1);
+      const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+      const bool iy = (unsigned)yy < (unsigned)w, i0 = iy && xx >= 0, i3 = iy && xx + 3 < w;
+      const unsigned o = (unsigned)(((((bb << lci) + c) << lw) + yy) << lw) + (unsigned)xx;
+      if (t % 3 == 1) {
+        v[r] = iy ? ld32x4(in, o) : f4c{0.f, 0.f, 0.f, 0.f};
+      } else {
+        v[r][0] = i0 ? ld32(in, o) : 0.0f;
+        v[r][1] = iy ? ld32(in, o + 1) : 0.0f;
+        v[r][2] = iy ? ld32(in, o + 2) : 0.0f;
+        v[r][3] = i3 ? ld32(in, o + 3) : 0.0f;
+      }
+    }
+  }
 };
 // partial[z][m][n] = acc (split K, summed in a fixed order afterwards)
 struct SplitOut {
@@ -815,6 +911,10 @@ struct RowK {  // A(m, k) = p[m * ld + k]
 #pragma unroll
     for (int r = 0; r < CNT; ++r) v[r] = ld32(p, o + r * d);
   }
+  // k_tgemm_s: k .. k + 3 of rows m + r ms (16-byte loads when ld is a
+  // multiple of 4)
+  template <int CNT>
+  __device__ void stepk4(int m, int k, int ms, f4c* v) const { rows4<CNT>(p, ld, m, k, ms, v); }
 };
 struct ColK {  // A(m, k) = p[k * ld + m]
   static constexpr bool KFAST = false;
@@ -1748,6 +1848,31 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
       // weight gradient, split over (b, y, x); 32-wide tiles when ci < 64
       // (the tap-major columns of a tile then share a tap)
       const int K = (int)(bsz * w * w), N = ci * 9;
+      if (split && ci % 32 == 0) {
+        // 96-wide tiles (three taps of 32 channels; N = 9 ci divides into
+        // them): each K slice of the gradient is read N / 96 times
+#ifdef EBSD_WG_TM64
+        const int tm = 64;
+#else
+        const int tm = co >= 128 ? 128 : 64;
+#endif
+        const int64_t tiles = (int64_t)((co + tm - 1) / tm) * (N / 96);
+        int s = splits_for(K, tiles);
+        while ((size_t)s * co * N > part_floats && s > 1) s = (s + 1) / 2;
+        const int z = k_slices_s(K, s), kslice = k_slice_s(K, s);
+        const ConvBwdWA wa{act.g[i], co, lw};
+        const ConvBwdWB wb{in, ilog2(ci), lw};
+        const SplitOut wo{part, co, N};
+        const dim3 grid(N / 96, (co + tm - 1) / tm, z);
+        if (tm == 64)
+          hipLaunchKernelGGL((k_tgemm_s<64, 96, ConvBwdWA, ConvBwdWB, SplitOut>), grid, dim3(256), 0, st, wa, wb, wo,
+                             co, N, K, kslice);
+        else
+          hipLaunchKernelGGL((k_tgemm_s<128, 96, ConvBwdWA, ConvBwdWB, SplitOut>), grid, dim3(256), 0, st, wa, wb,
+                             wo, co, N, K, kslice);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        split_sum(part, z, (int64_t)co * N, grad + lay.conv_w[i], st, N, ilog2(ci));
+      } else {
       const bool narrow = ci < 64;
       const int tn = narrow ? 32 : 64;
       const int64_t tiles = (int64_t)((co + 63) / 64) * ((N + tn - 1) / tn);
@@ -1760,6 +1885,7 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
       e = split ? gemm_split(wa, wb, wo, co, N, K, st, s, false, narrow) : gemm(wa, wb, wo, co, N, K, s, st, false, narrow);
       if (e != hipSuccess) return e;
       split_sum(part, z, (int64_t)co * N, grad + lay.conv_w[i], st, N, ilog2(ci));
+      }
     }
     {
       const int zs = (int)(bsz < 64 ? bsz : 64);

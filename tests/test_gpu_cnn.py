@@ -75,12 +75,16 @@ def _seeded_params(rng, n_cls):
     return np.concatenate(parts).astype(np.float32)
 
 
-def test_forward_and_gradients_match_oracle():
-    banner("cnn forward / backward vs oracle")
+@pytest.mark.parametrize("prec", ["bf16x2", "fp32"])
+def test_forward_and_gradients_match_oracle(prec):
+    # both precisions of the products (the default splits the inference, the
+    # training fc and the backward products into BF16 halves)
+    banner("cnn forward / backward vs oracle, %s products" % prec)
     t = tm()
     n_cls, bsz = 50, 4
     rng = np.random.default_rng(5)
     net = t.Cnn(n_cls, seed=7)
+    net.set_precision(t.PREC_FP32 if prec == "fp32" else t.PREC_BF16X2)
     params = _seeded_params(rng, n_cls)
     net.set_params(dev(params))
     xs = rng.normal(size=(bsz, 64, 64)).astype(np.float32)
@@ -161,17 +165,19 @@ def test_inference_precisions_match_oracle():
     net.close()
 
 
-def test_gradients_of_a_batch_are_the_mean_over_its_slices():
-    # A batch of 256 at 8,000 classes takes the 128-row and 64 x 32 tiles and
-    # the whole-step fetches; the gradient of its mean loss is the mean of
-    # the gradients over its 64 slices of 4, which take the paths the oracle
-    # test above checks.  FP32 sums in another order: 1e-5 relative per
-    # parameter tensor, the loss 1e-6.
-    banner("cnn gradients: batch of 256 vs the mean over slices of 4")
+@pytest.mark.parametrize("prec", ["bf16x2", "fp32"])
+def test_gradients_of_a_batch_are_the_mean_over_its_slices(prec):
+    # A batch of 256 at 8,000 classes takes the 128-row and wide tiles, K
+    # split over many slices and the whole-step fetches; the gradient of its
+    # mean loss is the mean of the gradients over its 64 slices of 4, which
+    # take the paths the oracle test above checks.  Sums in another order:
+    # 1e-5 relative per parameter tensor, the loss 1e-6.
+    banner("cnn gradients: batch of 256 vs the mean over slices of 4, %s products" % prec)
     t = tm()
     n_cls, bsz, sl = 8000, 256, 4
     rng = np.random.default_rng(13)
     net = t.Cnn(n_cls, seed=7)
+    net.set_precision(t.PREC_FP32 if prec == "fp32" else t.PREC_BF16X2)
     params = _seeded_params(rng, n_cls)
     net.set_params(dev(params))
     x = dev(rng.normal(size=(bsz, 64, 64)).astype(np.float32))
