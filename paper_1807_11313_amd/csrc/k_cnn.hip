@@ -1085,12 +1085,16 @@ static void split_sum(const float* part, int z, int64_t mn, float* out, hipStrea
 // block (c, z) sums images z, z + Z, ... of dpool where arg < 4 (first
 // stage, in double)
 __global__ __launch_bounds__(256) void k_channel_part(const uint8_t* __restrict__ arg, const float* __restrict__ dpool,
-                                                      int bsz, int c, int hw, int zs, double* __restrict__ part) {
-  const int ch = blockIdx.x, z = blockIdx.y;
+                                                      int bsz, int c, int lhw, int zs, double* __restrict__ part) {
+  // the block's images bb = z, z + zs, ... and their hw = 2^lhw pixels as one
+  // range, spread over all threads (the pooled maps of the last layers hold
+  // 16 and 64 pixels)
+  const int ch = blockIdx.x, z = blockIdx.y, hw = 1 << lhw;
+  const int n = ((bsz - z + zs - 1) / zs) << lhw;
   double s = 0.0;
-  for (int bb = z; bb < bsz; bb += zs) {
-    const size_t o = ((size_t)bb * c + ch) * hw;
-    for (int i = threadIdx.x; i < hw; i += 256) s += arg[o + i] < 4 ? dpool[o + i] : 0.0f;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const size_t o = ((size_t)(z + zs * (j >> lhw)) * c + ch) * hw + (j & (hw - 1));
+    s += arg[o] < 4 ? dpool[o] : 0.0f;
   }
   s = wave_sum(s);
   __shared__ double red[4];
@@ -1891,7 +1895,7 @@ hipError_t backward(const float* params, const Layout& lay, const float* x, cons
       const int zs = (int)(bsz < 64 ? bsz : 64);
       double* cpart = reinterpret_cast<double*>(part);  // the weight-gradient partials are summed already
       hipLaunchKernelGGL(k_channel_part, dim3(co, zs), dim3(256), 0, st, act.arg[i], act.dp[i], (int)bsz, co,
-                         (w / 2) * (w / 2), zs, cpart);
+                         2 * (lw - 1), zs, cpart);
       hipLaunchKernelGGL(k_channel_sum, dim3(co), dim3(64), 0, st, cpart, zs, grad + lay.conv_b[i]);
     }
     if (i > 0) {
