@@ -1233,6 +1233,77 @@ __global__ void k_split_rows(const float* __restrict__ x, int64_t rows, int k_le
   *reinterpret_cast<cnn_u4*>(dst + 8) = l;
 }
 
+// The first convolution (one input channel: K = 9) with its bias, ReLU and
+// 2 x 2 max pool on the vector ALUs, which suit a 9-deep product better
+// than 16- or 32-deep matrix steps: a thread takes one pooled pixel, its
+// 4 x 4 input patch in registers and every channel (the weights, the same
+// for every lane, come through the scalar cache).  Pooled value and
+// gradient position as ConvReluPoolOut; SPLIT: the pooled map written in
+// ConvReluPoolSplitOut's split layout instead.  w: [32][9], x: [bsz][64][64].
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void k_conv1_pool(const float* __restrict__ x, const float* __restrict__ w,
+                                                    const float* __restrict__ bias, int64_t bsz,
+                                                    float* __restrict__ out, uint8_t* __restrict__ arg,
+                                                    unsigned short* __restrict__ sout) {
+  constexpr int S = kInSize, PS = S / 2, C = kChannels[0];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= bsz * PS * PS) return;
+  const int X = (int)(i & (PS - 1)), Y = (int)((i / PS) & (PS - 1));
+  const int64_t bb = i / (PS * PS);
+  const float* img = x + bb * S * S;
+  float pt[4][4];  // input rows 2 Y - 1 .. 2 Y + 2, columns 2 X - 1 .. 2 X + 2 (zero padding)
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int yy = 2 * Y - 1 + r, xx = 2 * X - 1 + s;
+      pt[r][s] = ((unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S) ? img[yy * S + xx] : 0.0f;
+    }
+  for (int c0 = 0; c0 < C; c0 += 8) {
+    float pv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int c = c0 + e;
+      float wt[9];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) wt[t] = w[c * 9 + t];
+      float v[4];  // quad positions (0, 0), (0, 1), (1, 0), (1, 1)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float a = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) a = __builtin_fmaf(pt[(q >> 1) + t / 3][(q & 1) + t % 3], wt[t], a);
+        v[q] = a;
+      }
+      const float b = bias[c];
+      const float mx = fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3]));
+      const float pool = fmaxf(mx + b, 0.0f);
+      pv[e] = pool;
+      if constexpr (!SPLIT) {
+        const int64_t o = ((bb * C + c) * PS + Y) * PS + X;
+        out[o] = pool;
+        if (arg) {
+          const int q = !(pool > 0.0f) ? 4 : v[0] + b == pool ? 0 : v[1] + b == pool ? 1 : v[2] + b == pool ? 2 : 3;
+          arg[o] = (uint8_t)q;
+        }
+      }
+    }
+    if constexpr (SPLIT) {
+      cnn_u4 h, l;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        unsigned he, le;
+        bf16_split2(pv[2 * e], pv[2 * e + 1], he, le);
+        h[e] = he;
+        l[e] = le;
+      }
+      unsigned short* dst = sout + ((bb * PS + Y) * PS + X) * (2 * C) + 2 * c0;
+      *reinterpret_cast<cnn_u4*>(dst) = h;
+      *reinterpret_cast<cnn_u4*>(dst + 8) = l;
+    }
+  }
+}
+
 // gradient through the ReLU and the 2 x 2 max pool: the pooled gradient goes to the
 // quad position arg recorded by the forward pass (4: to none of them)
 __global__ void k_unpool_bwd(const uint8_t* __restrict__ arg, const float* __restrict__ dpool, int64_t planes,
@@ -1757,20 +1828,27 @@ hipError_t forward(const float* params, const Layout& lay, const float* x, int64
     // each convolution pools in its epilogue: only the pooled maps (and, in
     // training, the gradient positions) are written
     const float* bias = params + lay.conv_b[i];
-    if (!split) {
+    if (i == 0) {
+      static_assert(kChannels[0] % 8 == 0, "first layer: channel groups of 8");
+      const unsigned blocks = nb(bsz * (kInSize / 2) * (kInSize / 2));
+      if (split)
+        hipLaunchKernelGGL(k_conv1_pool<true>, dim3(blocks), dim3(256), 0, st, x, params + lay.conv_w[0], bias, bsz,
+                           nullptr, nullptr, reinterpret_cast<unsigned short*>(act.p[0]));
+      else
+        hipLaunchKernelGGL(k_conv1_pool<false>, dim3(blocks), dim3(256), 0, st, x, params + lay.conv_w[0], bias,
+                           bsz, act.p[0], train ? act.arg[0] : nullptr, nullptr);
+      e = hipGetLastError();
+    } else if (!split) {
       const ConvReluPoolOut o{act.p[i], bias, co, lw - 1, train ? act.arg[i] : nullptr};
       e = gemm(ConvFwdA{a, ci, lci, lw}, WeightT{act.wt + tap_weights_offset(i), K}, o, M, co, K, 1, st, true);
     } else {
-      // split inference: the first layer (K = 9, one input channel) in FP32,
-      // a 32-deep step would be mostly padding; layers 1-3 write their pooled
-      // maps split for the next layer's BF16 products (in the FP32 maps'
-      // buffers, the same bytes), the last one FP32 features for the fc
+      // split inference: the pooled maps are written split for the next
+      // layer's BF16 products (in the FP32 maps' buffers, the same bytes; the
+      // first layer's by k_conv1_pool), the last one as FP32 features for the fc
       const unsigned short* sa = reinterpret_cast<const unsigned short*>(a);
       const ConvReluPoolSplitOut so{reinterpret_cast<unsigned short*>(act.p[i]), bias, co, lw - 1};
       const SplitRows wb{act.wts + 2 * tap_weights_offset(i), K};
-      if (i == 0)
-        e = gemm(ConvFwdA{a, ci, lci, lw}, WeightT{act.wt, K}, so, M, co, K, 1, st, true);
-      else if (i < 3)
+      if (i < 3)
         e = gemm_split(ConvFwdSA{sa, ci, lci, lw}, wb, so, M, co, K, st);
       else
         e = gemm_split(ConvFwdSA{sa, ci, lci, lw}, wb, ConvReluPoolOut{act.p[3], bias, co, lw - 1, nullptr}, M, co,
