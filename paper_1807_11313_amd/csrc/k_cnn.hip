@@ -1010,8 +1010,8 @@ static int k_slices_s(int K, int splits) {
   return (K + kslice - 1) / kslice;
 }
 
-// products with BF16 split operands (k_tgemm_s); tiles as gemm's (wide only
-// where allowed and the grid fills the chip, narrow 64 x 32 on request)
+// products with BF16 split operands (k_tgemm_s): 128-row tiles where allowed
+// and the grid stays large, narrow 64 x 32 on request, else 64 x 64
 template <class A, class Bm, class Out>
 static hipError_t gemm_split(A a, Bm b, Out out, int M, int N, int K, hipStream_t st, int splits = 1,
                              bool wide_ok = true, bool narrow = false) {
@@ -1019,7 +1019,10 @@ static hipError_t gemm_split(A a, Bm b, Out out, int M, int N, int K, hipStream_
   const int kslice = k_slice_s(K, splits);
   const int z = k_slices_s(K, splits) < 1 ? 1 : k_slices_s(K, splits);
   const int tn = N <= 32 ? 32 : N <= 64 ? 64 : 128;
-  const bool wide = wide_ok && (int64_t)((N + tn - 1) / tn) * ((M + 127) / 128) * z >= 512;
+  // 128-row tiles once they still give 1,024 blocks (four per CU: timed
+  // against 256, 512 and 2,048, the fc of a 2,048-pattern pass with its
+  // 1,008 such blocks runs faster on 64 x 64 tiles)
+  const bool wide = wide_ok && (int64_t)((N + tn - 1) / tn) * ((M + 127) / 128) * z >= 1024;
   if (wide && N <= 32) {
     hipLaunchKernelGGL((k_tgemm_s<128, 32, A, Bm, Out>), dim3((N + 31) / 32, (M + 127) / 128, z), dim3(256), 0, st,
                        a, b, out, M, N, K, kslice);
